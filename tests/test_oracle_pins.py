@@ -1,0 +1,338 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula: each checks a property,
+special case, published known answer or theorem that a plausible mistake in
+the oracle (a dropped term, a wrong sign or index, a transposed operand)
+would violate.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import philox, rsvd as orc
+from workloads import gen
+
+
+def _low_rank(m, n, sigma, seed, noise=0.0):
+    return gen.low_rank_matrix(m, n, np.asarray(sigma, float), noise, seed)
+
+
+# ---------------------------------------------------------------- generator
+
+def test_philox_known_answers(golden_dir):
+    rows = []
+    with open(os.path.join(golden_dir, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(w, 16) for w in line.split()])
+    for r in rows:
+        out = philox.philox4x32_10(np.array(r[0:4], dtype=np.uint32), (r[4], r[5]))
+        assert [int(x) for x in out] == r[6:10]
+
+
+def test_gaussian_moments_and_prefix_stability():
+    g = philox.gaussian(200_001, 10, seed=12345, stream=philox.STREAM_OMEGA)
+    x = g.ravel()
+    n = x.size
+    assert abs(x.mean()) < 5 / math.sqrt(n)
+    assert abs(x.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    kurt = np.mean(x ** 4)
+    assert abs(kurt - 3.0) < 5 * math.sqrt(96.0 / n)
+    # columns are independent of how many are drawn; rows of a shorter draw
+    # are a prefix of a longer one (odd row counts included)
+    a = philox.gaussian(37, 9, seed=7, stream=4)
+    b = philox.gaussian(38, 4, seed=7, stream=4, col0=5)
+    assert np.array_equal(a[:, 5:9], b[:37])
+    # different streams and seeds differ
+    assert not np.allclose(philox.gaussian(8, 2, 7, 4), philox.gaussian(8, 2, 7, 6))
+    assert not np.allclose(philox.gaussian(8, 2, 7, 4), philox.gaussian(8, 2, 8, 4))
+    # columns uncorrelated
+    c = np.corrcoef(g[:, :4].T)
+    assert np.max(np.abs(c - np.eye(4))) < 5 / math.sqrt(g.shape[0])
+
+
+# ---------------------------------------------------------------- primitives
+
+def test_orth_is_an_unpivoted_qr_with_positive_diagonal():
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((120, 17))
+    Q = orc.orth(X)
+    assert np.linalg.norm(Q.T @ Q - np.eye(17)) < 1e-13
+    R = Q.T @ X
+    assert np.linalg.norm(np.tril(R, -1)) < 1e-12 * np.linalg.norm(X)
+    assert np.all(np.diag(R) > 0)
+    assert np.linalg.norm(Q @ R - X) < 1e-13 * np.linalg.norm(X)
+    # special case: an orthonormal, upper-trapezoidal X is returned unchanged
+    E = np.eye(30)[:, :6]
+    assert np.array_equal(orc.orth(E), E)
+    # unpivoted: the first column of Q is the normalised first column of X
+    assert np.allclose(Q[:, 0], X[:, 0] / np.linalg.norm(X[:, 0]), atol=1e-14)
+
+
+def test_svd_small_recovers_a_planted_factorisation():
+    rng = np.random.default_rng(1)
+    U0 = orc.orth(rng.standard_normal((25, 25)))
+    V0 = orc.orth(rng.standard_normal((90, 25)))
+    d0 = np.sort(rng.uniform(0.1, 3.0, 25))[::-1]
+    B = (U0 * d0) @ V0.T
+    uh, d, v = orc.svd_small(B)
+    assert np.allclose(d, d0, rtol=1e-13, atol=0)
+    for j in range(25):
+        s = np.sign(U0[np.argmax(np.abs(U0[:, j])), j])
+        assert np.allclose(uh[:, j], s * U0[:, j], atol=1e-12)
+        assert np.allclose(v[:, j], s * V0[:, j], atol=1e-12)
+        assert uh[np.argmax(np.abs(uh[:, j])), j] > 0
+    # a diagonal matrix with known entries
+    D = np.diag([1.0, 5.0, 3.0])
+    uh, d, v = orc.svd_small(np.hstack([D, np.zeros((3, 2))]))
+    assert np.array_equal(d, [5.0, 3.0, 1.0])
+    assert np.array_equal(np.abs(uh), np.eye(3)[:, [1, 2, 0]])
+
+
+# ---------------------------------------------------------------- Section 3/4
+
+def test_exact_rank_is_recovered_exactly():
+    """Section 4: when A has exact rank k, A G spans its range with probability 1."""
+    sigma = np.array([3.0, 2.0, 1.0, 0.5, 0.25, 0.1])
+    A = _low_rank(200, 150, sigma, seed=3)
+    G = gen.gaussian_matrix(150, 8, seed=4)
+    r = orc.rsvd_basic(A, G)
+    assert np.allclose(r.D[:6], sigma, rtol=1e-12)
+    assert np.all(r.D[6:] < 1e-13)
+    assert np.linalg.norm(A - (r.U * r.D) @ r.V.T, 2) < 1e-13
+
+
+def test_full_width_sketch_equals_the_full_svd():
+    """Brute force on a tiny input: with l = n the RSVD is the exact SVD."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((14, 9))
+    r = orc.rsvd(A, gen.gaussian_matrix(9, 9, seed=6), q=1)
+    s = np.linalg.svd(A, compute_uv=False)
+    assert np.allclose(r.D, s, rtol=1e-12)
+    assert np.linalg.norm(A - (r.U * r.D) @ r.V.T) < 1e-12
+
+
+def test_eckart_young_floor_and_stage_b_identity():
+    """Section 2.2: sigma_{k+1} (spectral) and the tail norm (Frobenius) are the
+    smallest rank-k errors.  Remark in Section 3: Stage B adds no error, so at
+    rank l the factorisation error equals ||A - Q Q^T A||.  Second remark:
+    |sigma_i - D_ii| <= ||A - Q Q^T A||."""
+    sigma = gen.spectrum("poly", 60, alpha=1.0)
+    A = _low_rank(300, 220, sigma, seed=9)
+    k, p = 12, 6
+    r = orc.rsvd(A, gen.gaussian_matrix(220, k + p, seed=10), q=0)
+    t = r.truncate(k)
+    err_k = np.linalg.norm(A - (t.U * t.D) @ t.V.T, 2)
+    assert err_k >= sigma[k] * (1 - 1e-12)
+    assert np.linalg.norm(A - (t.U * t.D) @ t.V.T) >= np.sqrt(np.sum(sigma[k:] ** 2)) * (1 - 1e-12)
+    resid = A - r.Q @ (r.Q.T @ A)
+    e_qq = np.linalg.norm(resid, 2)
+    e_full = np.linalg.norm(A - (r.U * r.D) @ r.V.T, 2)
+    assert abs(e_full - e_qq) < 1e-12
+    assert abs(np.linalg.norm(A - (r.U * r.D) @ r.V.T) - np.linalg.norm(resid)) < 1e-12
+    assert np.all(np.abs(sigma[:k + p] - r.D) <= e_qq * (1 + 1e-12))
+    # U and V orthonormal
+    assert np.linalg.norm(r.U.T @ r.U - np.eye(k + p)) < 1e-13
+    assert np.linalg.norm(r.V.T @ r.V - np.eye(k + p)) < 1e-13
+
+
+# ---------------------------------------------------------------- Section 7, 8
+
+def _errors(A, k, p, q, seeds, fig=orc.rsvd):
+    fro, spec = [], []
+    for s in seeds:
+        G = gen.gaussian_matrix(A.shape[1], k + p, seed=1000 + s)
+        r = fig(A, G, q)
+        R = A - r.Q @ (r.Q.T @ A)
+        fro.append(np.linalg.norm(R))
+        spec.append(np.linalg.norm(R, 2))
+    return np.array(fro), np.array(spec)
+
+
+def test_expectation_bounds_q0():
+    """Theorem of Section 7.1 (both norms) at q = 0, mean over 200 draws."""
+    sigma = gen.spectrum("poly", 150, alpha=1.0)
+    A = _low_rank(260, 180, sigma, seed=21)
+    k, p = 10, 5
+    fro, spec = _errors(A, k, p, 0, range(200))
+    bf = orc.thm_expectation_frobenius(sigma, k, p)
+    bs = orc.thm_expectation_spectral(sigma, k, p, 0)
+    assert fro.mean() + 3 * fro.std() / math.sqrt(len(fro)) <= bf
+    assert spec.mean() + 3 * spec.std() / math.sqrt(len(spec)) <= bs
+    # and never below the Eckart-Young floor
+    assert spec.min() >= sigma[k] * (1 - 1e-12)
+    assert fro.min() >= math.sqrt(np.sum(sigma[k:] ** 2)) * (1 - 1e-12)
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_expectation_bound_with_power_steps(q):
+    """Theorem of Section 8.2 for the power scheme (the re-orthonormalised
+    Figure 5 spans the same space in exact arithmetic)."""
+    sigma = gen.spectrum("poly", 150, alpha=0.5)
+    A = _low_rank(260, 180, sigma, seed=22)
+    k, p = 10, 4
+    _, spec = _errors(A, k, p, q, range(150))
+    assert spec.mean() + 3 * spec.std() / math.sqrt(len(spec)) <= orc.thm_expectation_spectral(sigma, k, p, q)
+    # more power steps, smaller mean error on a slowly decaying spectrum
+    _, spec0 = _errors(A, k, p, 0, range(150))
+    assert spec.mean() < spec0.mean()
+
+
+def test_tail_bound_frequency():
+    """Section 7.2: the deviation bound fails with probability <= 3 e^-p."""
+    sigma = gen.spectrum("poly", 120, alpha=0.7)
+    A = _low_rank(200, 150, sigma, seed=23)
+    k, p = 8, 4
+    _, spec = _errors(A, k, p, 0, range(300))
+    bound = orc.thm_tail_spectral(sigma, k, p)
+    freq = np.mean(spec > bound)
+    assert freq <= 3 * math.exp(-p) + 3 * math.sqrt(3 * math.exp(-p) / 300)
+
+
+def test_power_scheme_targets_the_spectrum_of_A_q():
+    """Section 8.1: (A A^T)^q A = U D^(2q+1) V^T.  Build A^(q) from the
+    generator's factors (no product with A) and check that the oracle's
+    Figure 5 basis spans orth(A^(q) G) for the same G."""
+    r_ = 40
+    sigma = gen.spectrum("exp", r_, tau=8.0)
+    m, n = 180, 140
+    U = gen.orthonormal_factor(m, r_, 31, 1)
+    V = gen.orthonormal_factor(n, r_, 31, 2)
+    A = (U * sigma) @ V.T
+    G = gen.gaussian_matrix(n, 12, seed=32)
+    for q in (1, 2):
+        Aq = (U * sigma ** (2 * q + 1)) @ V.T
+        Qref = orc.orth(Aq @ G)
+        Q = orc.rsvd(A, G, q).Q
+        # principal angles between the two 12-dim subspaces
+        cosines = np.linalg.svd(Qref.T @ Q, compute_uv=False)
+        assert np.min(cosines) > 1 - 1e-9
+        # and Figure 4 (no re-orthonormalisation) agrees in float64 here
+        Q4 = orc.rsvd_power(A, G, q).Q
+        assert np.min(np.linalg.svd(Q4.T @ Q, compute_uv=False)) > 1 - 1e-9
+
+
+def test_without_reorthonormalisation_information_is_lost():
+    """Remark after Figure 4: directions with sigma_j / sigma_1 <=
+    eps_mach^(1/(2q+1)) are lost without re-orthonormalisation; Figure 5
+    keeps them."""
+    q = 3
+    sigma = np.logspace(0, -6, 40)          # reaches 1e-6 << eps^(1/7) ~ 5e-3
+    A = _low_rank(150, 120, sigma, seed=41)
+    G = gen.gaussian_matrix(120, 40, seed=42)
+    good = orc.rsvd(A, G, q)
+    bad = orc.rsvd_power(A, G, q)
+    j = 30                                   # sigma_j ~ 2.5e-5
+    thresh = np.finfo(float).eps ** (1 / (2 * q + 1))
+    assert sigma[j] / sigma[0] < thresh
+    assert abs(good.D[j] - sigma[j]) / sigma[j] < 1e-6
+    assert abs(bad.D[j] - sigma[j]) / sigma[j] > 1e-2
+
+
+# ---------------------------------------------------------------- Sections 12-14
+
+def test_probe_lemma_failure_rate_and_mean_square():
+    """Lemma of Section 13: P(bound < ||T||) <= alpha^r; remark after Figure 14:
+    E||T g||^2 = ||T||_F^2."""
+    rng = np.random.default_rng(50)
+    T = rng.standard_normal((40, 30)) * np.logspace(0, -2, 30)
+    t2 = np.linalg.norm(T, 2)
+    trials = 4000
+    G = rng.standard_normal((30, trials))
+    norms = np.linalg.norm(T @ G, axis=0)
+    # r = 1, alpha = 1/2: failure probability <= 1/2
+    fails = np.mean([orc.probe_bound(norms[i:i + 1], 0.5) < t2 for i in range(trials)])
+    assert fails <= 0.5 + 3 * math.sqrt(0.25 / trials)
+    # r = 2, alpha = 0.1: <= 0.01
+    fails2 = np.mean([orc.probe_bound(norms[i:i + 2], 0.1) < t2 for i in range(0, trials, 2)])
+    assert fails2 <= 0.01 + 3 * math.sqrt(0.01 / (trials / 2))
+    ms = np.mean(norms ** 2)
+    f2 = np.linalg.norm(T) ** 2
+    assert abs(ms - f2) < 4 * np.std(norms ** 2) / math.sqrt(trials)
+
+
+@pytest.mark.parametrize("s", [0, 1, 2])
+def test_certificate_bounds_the_true_error(s):
+    """Section 14: 10 probes, alpha = 0.1, bound valid w.p. >= 1 - 1e-10; the
+    powered variant bounds ||T|| through ||(T T^T)^s T|| = ||T||^(2s+1)."""
+    sigma = gen.spectrum("poly", 80, alpha=1.0)
+    A = _low_rank(160, 120, sigma, seed=60)
+    r = orc.rsvd(A, gen.gaussian_matrix(120, 16, seed=61), 1).truncate(10)
+    true = np.linalg.norm(A - (r.U * r.D) @ r.V.T, 2)
+    ratios = []
+    for t in range(40):
+        Gc = gen.gaussian_matrix(120, 10, seed=100 + t)
+        b = orc.certificate(A, r.U, r.D, r.V, Gc, s)
+        assert b >= true
+        ratios.append(b / true)
+    if s > 0:   # the powered estimate is tighter on average
+        b0 = np.mean([orc.certificate(A, r.U, r.D, r.V, gen.gaussian_matrix(120, 10, seed=100 + t), 0) / true
+                      for t in range(40)])
+        assert np.mean(ratios) < b0
+
+
+def test_frobenius_downdating_identity():
+    """Section 12.4: ||A - Q B||_F^2 = ||A||_F^2 - ||B||_F^2 for B = Q^T A."""
+    rng = np.random.default_rng(70)
+    A = rng.standard_normal((90, 70)) @ np.diag(np.logspace(0, -3, 70))
+    Q = orc.orth(A @ rng.standard_normal((70, 15)))
+    B = Q.T @ A
+    direct = np.linalg.norm(A - Q @ B)
+    assert abs(orc.frobenius_downdate(np.linalg.norm(A), B) - direct) < 1e-12 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("b", [1, 4])
+def test_blocked_growth_spans_the_same_space_as_the_basic_sketch(b):
+    """Caption of Figure 13: building Q a few vectors at a time from the
+    columns of G gives an orthonormal basis of A G(:, 1:j), as the basic
+    RSVD does."""
+    sigma = gen.spectrum("poly", 60, alpha=1.0)
+    A = _low_rank(150, 100, sigma, seed=80)
+    G = gen.gaussian_matrix(100, 24, seed=81)
+    Q0 = orc.orth(A @ G[:, :8])
+    steps_wanted = 16 // b
+
+    def draw(j):
+        return G[:, 8 + j * b: 8 + (j + 1) * b]
+    Q, B, steps, hist = orc.blocked_growth(A, Q0, Q0.T @ A, draw,
+                                           lambda Q_, B_: Q_.shape[1] >= 24, b, 24)
+    assert steps == steps_wanted and Q.shape[1] == 24
+    assert np.linalg.norm(Q.T @ Q - np.eye(24)) < 1e-12
+    Qref = orc.orth(A @ G)
+    assert np.min(np.linalg.svd(Qref.T @ Q, compute_uv=False)) > 1 - 1e-10
+    assert np.all(np.diff(hist) <= 1e-12)   # residual never grows
+
+
+def test_adaptive_vector_finder_meets_its_tolerance():
+    """Figure 14: the output Q satisfies ||A - Q Q^T A|| <= eps (w.p. >= 1 -
+    min(m,n) 10^-r)."""
+    sigma = gen.spectrum("exp", 80, tau=5.0)
+    A = _low_rank(120, 100, sigma, seed=90)
+    eps = 1e-4
+    Q = orc.adaptive_vector(A, eps, r=10, draw=lambda j: gen.gaussian_matrix(100, 1, seed=2000 + j)[:, 0])
+    err = np.linalg.norm(A - Q @ (Q.T @ A), 2)
+    assert err <= eps
+    assert Q.shape[1] < 80
+    assert np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1])) < 1e-12
+
+
+def test_factor_with_fallback_reaches_the_tolerance():
+    """The certificate (Section 14) rejects the rank-k result, the blocked
+    range finder (Figure 12) grows the basis until the certificate holds, and
+    the true error then meets the tolerance."""
+    sigma = gen.spectrum("exp", 120, tau=10.0)
+    A = _low_rank(200, 160, sigma, seed=95)
+    out = orc.factor(A, k=10, p=5, q=1, seed=96, eps=1e-3, block=8, max_rank=120)
+    assert out.certified and out.fallback_steps > 0
+    assert out.rank > 15
+    true = np.linalg.norm(A - (out.U * out.D) @ out.V.T, 2)
+    assert true <= 1e-3 * out.sigma1
+    assert out.bound >= true
+    # the fixed-rank path alone (eps = 0) returns rank k
+    plain = orc.factor(A, k=10, p=5, q=1, seed=96)
+    assert plain.rank == 10 and plain.U.shape == (200, 10)
+    # singular values of Q^T A interlace those of A from below
+    assert np.all(plain.D <= sigma[:10] * (1 + 1e-12))
+    assert np.allclose(plain.D, sigma[:10], rtol=1e-2)
