@@ -1,0 +1,156 @@
+"""MI355X (gfx950) randomized range finder and randomized SVD.
+
+Python binding of the C ABI in include/rsvd.h.  The functions named like the
+C entry points marshal torch tensors (device memory) and the current HIP
+stream into the library; all computation runs in the HIP kernels of
+``librsvd.so``.  There is no CPU fallback: if the library is not built,
+importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    RSVD_BF16, RSVD_E_ARG, RSVD_E_BREAKDOWN, RSVD_E_HIP, RSVD_E_NONFINITE, RSVD_E_UNSUPPORTED, RSVD_E_WORKSPACE,
+    RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RSVD_NOT_CERTIFIED, RSVD_OK, RSVD_RETURN_RANK_L, RSVD_TIMING, RSVDError,
+    STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info, status_str,
+)
+
+_DTYPES = {"f64": RSVD_F64, "f32": RSVD_F32, "bf16": RSVD_BF16, "fp8": RSVD_FP8_E4M3}
+_TORCH = {RSVD_F64: torch.float64, RSVD_F32: torch.float32}
+
+
+def _code(dt) -> int:
+    if isinstance(dt, str):
+        return _DTYPES[dt]
+    if dt is torch.float64:
+        return RSVD_F64
+    if dt is torch.float32:
+        return RSVD_F32
+    return int(dt)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(device=None, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_desc(m, n, k, p=10, q=1, a_dtype="f32", sketch_dtype=None, proj_dtype=None, seed=0, eps=0.0,
+              n_probe=0, est_power=0, fallback_block=0, max_rank=0, flags=0) -> rsvd_desc:
+    a = _code(a_dtype)
+    d = rsvd_desc()
+    d.m, d.n, d.k, d.p, d.q = int(m), int(n), int(k), int(p), int(q)
+    d.a_dtype = a
+    d.sketch_dtype = a if sketch_dtype is None else _code(sketch_dtype)
+    d.proj_dtype = a if proj_dtype is None else _code(proj_dtype)
+    d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    d.eps = float(eps)
+    d.n_probe, d.est_power = int(n_probe), int(est_power)
+    d.fallback_block, d.max_rank = int(fallback_block), int(max_rank)
+    d.flags = int(flags)
+    return d
+
+
+def rsvd_status_str(status: int) -> str:
+    return status_str(status)
+
+
+def rsvd_workspace_size(desc: rsvd_desc) -> int:
+    out = ctypes.c_size_t(0)
+    st = _lib.lib().rsvd_workspace_size(ctypes.byref(desc), ctypes.byref(out))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_workspace_size")
+    return int(out.value)
+
+
+def rsvd_plan(desc: rsvd_desc, workspace: torch.Tensor, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    st = _lib.lib().rsvd_plan(ctypes.byref(desc), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                              _stream_handle(workspace.device, stream), ctypes.byref(h))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_plan")
+    return h
+
+
+def rsvd_factor(plan, A: torch.Tensor, U: torch.Tensor, S: torch.Tensor, V: Optional[torch.Tensor],
+                omega: Optional[torch.Tensor] = None, want_info: bool = True):
+    """Returns (status, rsvd_info or None).  A, U, V row-major (2-D, unit
+    column stride); omega, if given, n x (k+p) float64 row-major."""
+    info = rsvd_info() if want_info else None
+    st = _lib.lib().rsvd_factor(plan, _ptr(A), A.stride(0), _ptr(omega), _ptr(U), U.stride(0), _ptr(S), _ptr(V),
+                                V.stride(0) if V is not None else 0, ctypes.byref(info) if info is not None else None)
+    return st, info
+
+
+def rsvd_destroy(plan) -> None:
+    _lib.lib().rsvd_destroy(plan)
+
+
+def rsvd_gaussian(seed: int, stream_id: int, out: torch.Tensor, col0: int = 0, stream=None) -> None:
+    rows, cols = out.shape
+    st = _lib.lib().rsvd_gaussian(int(seed), int(stream_id), rows, cols, int(col0), _code(out.dtype), _ptr(out),
+                                  out.stride(0), _stream_handle(out.device, stream))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_gaussian")
+
+
+def rsvd_philox4x32_10(ctr: torch.Tensor, k0: int, k1: int, out: torch.Tensor, stream=None) -> None:
+    """ctr, out: int32 device tensors of shape (count, 4) holding uint32 words."""
+    st = _lib.lib().rsvd_philox4x32_10(ctr.shape[0], _ptr(ctr), int(k0) & 0xFFFFFFFF, int(k1) & 0xFFFFFFFF,
+                                       _ptr(out), _stream_handle(out.device, stream))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_philox4x32_10")
+
+
+class RSVD:
+    """A plan plus its torch-allocated workspace for one problem shape.
+
+    ``RSVD(m, n, k, p, q, dtype)(A)`` returns (U, S, V, info) with U (m x r),
+    S (r, float64, descending), V (n x r) on A's device."""
+
+    def __init__(self, m, n, k, p=10, q=1, dtype="f32", device="cuda", **kw):
+        self.desc = make_desc(m, n, k, p, q, a_dtype=dtype, **kw)
+        self.device = torch.device(device)
+        nbytes = rsvd_workspace_size(self.desc)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.workspace = self.workspace[off:off + nbytes]
+        self.plan = rsvd_plan(self.desc, self.workspace)
+        l = self.desc.k + self.desc.p
+        self.rank_cap = max(l, self.desc.max_rank) if self.desc.eps > 0 else (
+            l if (self.desc.flags & RSVD_RETURN_RANK_L) else self.desc.k)
+        self.tdtype = _TORCH[self.desc.a_dtype]
+
+    def __call__(self, A: torch.Tensor, omega: Optional[torch.Tensor] = None, want_info: bool = True,
+                 out=None):
+        r = self.rank_cap
+        if out is None:
+            U = torch.empty(self.desc.m, r, dtype=self.tdtype, device=self.device)
+            S = torch.empty(r, dtype=torch.float64, device=self.device)
+            V = torch.empty(self.desc.n, r, dtype=self.tdtype, device=self.device)
+        else:
+            U, S, V = out
+        st, info = rsvd_factor(self.plan, A, U, S, V, omega, want_info)
+        if st < 0:
+            raise RSVDError(st, "rsvd_factor")
+        if info is not None:
+            k = info.rank_out
+            return U[:, :k], S[:k], V[:, :k], info
+        return U, S, V, None
+
+    def __del__(self):
+        p = getattr(self, "plan", None)
+        if p is not None:
+            try:
+                rsvd_destroy(p)
+            except Exception:
+                pass
+            self.plan = None

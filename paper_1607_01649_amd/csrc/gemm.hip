@@ -1,0 +1,343 @@
+// Skinny products with the large matrix A on MFMA (gfx950).
+//
+// Every heavy step of the method is a product of the m x n matrix A (or a
+// tall l-column panel) with a thin panel of at most a few hundred columns:
+//   sketch   Y = A Omega,  power step  Y = A W          (nn_kernel, K = n)
+//   power    Z = A^T Q,    projection  B^T = A^T Q      (tn_kernel, K = m)
+//   Gram     G = Y^T Y   (nn_kernel with A := Y^T, split over the rows)
+//   triangular apply Q = Y R^-1 and the lifts U = Q U_hat, V = B^T (U_hat D^-1)
+//                       (tn_kernel with A := Y^T)
+// Thin panels live in HBM in "panel" layout: column c is contiguous
+// (element (r, c) at p[c * ld + r], ld a multiple of 64), so a panel is the
+// row-major transpose of the tall matrix.
+//
+// Design (both kernels):
+//   * 256 threads = 4 wave64s; the thin panel's K-chunk (64 rows) is staged in
+//     LDS in MFMA-fragment order, so each lane reads its B operand with one
+//     16-byte ds_read and every wave of the block shares it;
+//   * A is read straight from HBM into registers, 16 bytes per lane per load:
+//     the contraction index is permuted within each 16-wide K group so a lane
+//     holds four consecutive K entries of one row (nn) or four consecutive
+//     output rows of one K entry (tn), exactly what the 16x16x4 MFMA consumes
+//     over four instructions;
+//   * each block covers a full panel-column group (up to 128 columns), so A is
+//     read once per group; the K range is split over grid.y and partial
+//     results are summed afterwards in a fixed order (deterministic, no
+//     atomics).
+#include "internal.hpp"
+
+namespace rsvd {
+
+constexpr int KC = 64;   // K rows staged per iteration
+
+// Stage panel rows [k0, k0+64) of columns [cg0, cg0+NB*16) of a panel P
+// (column c contiguous, stride ldp) into LDS fragment order:
+//   ps[(cb*4 + kq)*64 + (c%16) + 16*g].x[t] = P(c, k0 + 16*kq + 4*g + t).
+template <int NB, typename TP, typename TC>
+__device__ __forceinline__ void stage_panel(V4<TC>* ps, const TP* __restrict__ P, int64_t ldp, int cg0, int ncols,
+                                            int64_t k0, int64_t kend) {
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    int it = threadIdx.x + 256 * u;
+    int cl = it >> 4, jq = it & 15;
+    int c = cg0 + cl;
+    V4<TP> v = (c < ncols) ? load4_guarded<true>(P, ldp, (int64_t)c, k0 + 4 * jq, (int64_t)ncols, kend)
+                           : v4_zero<TP>();
+    int cb = cl >> 4, cli = cl & 15, kq = jq >> 2, g = jq & 3;
+    ps[(cb * 4 + kq) * 64 + cli + 16 * g] = v4_cast<TC>(v);
+  }
+}
+
+// out[split][c][r] = sum_{j in split} A[r][j] * X(j, c)      (X in panel layout: X[c*ldx + j])
+template <typename TA, typename TX, typename TC, typename TO, int NB, bool VEC>
+__global__ __launch_bounds__(256) void nn_kernel(const TA* __restrict__ A, int64_t lda, int64_t rows, int64_t K,
+                                                 const TX* __restrict__ X, int64_t ldx, int ncols,
+                                                 TO* __restrict__ out, int64_t ldo, int64_t part_stride,
+                                                 int64_t kchunk) {
+  __shared__ V4<TC> xs[NB * 4 * 64];
+  typedef Mma<TC> M;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int split = blockIdx.y;
+  const int cg0 = blockIdx.z * NB * 16;
+  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kend = min(K, kbeg + kchunk);
+
+  typename M::acc acc[2][NB];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = M::zero();
+
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+    stage_panel<NB>(xs, X, ldx, cg0, ncols, k0, kend);
+    V4<TA> a[2][4];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq)
+        a[rb][kq] = load4_guarded<VEC>(A, lda, rbase + 16 * rb + li, k0 + 16 * kq + 4 * g, rows, kend);
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      V4<TC> b[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) b[cb] = xs[(cb * 4 + kq) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          TC av = static_cast<TC>(a[rb][kq].x[t]);
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = M::op(av, b[cb].x[t], acc[rb][cb]);
+        }
+    }
+    __syncthreads();
+  }
+
+  TO* o = out + (int64_t)split * part_stride;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      int c = cg0 + cb * 16 + li;
+      if (c >= ncols) continue;
+      int64_t r = rbase + rb * 16 + 4 * g;
+      TO* p = o + (int64_t)c * ldo + r;
+      if (r + 4 <= rows) {
+        V4<TO> v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v.x[e] = static_cast<TO>(acc[rb][cb][e]);
+        v4_store(p, v);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (r + e < rows) p[e] = static_cast<TO>(acc[rb][cb][e]);
+      }
+    }
+}
+
+// out[split][c][j] = sum_{i in split} A[i][j] * P(i, c)      (P in panel layout: P[c*ldp + i])
+// OUT_RM: write out[j*ldo + c] instead (row-major result, no split).
+template <typename TA, typename TP, typename TC, typename TO, int NB, bool VEC, bool OUT_RM>
+__global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64_t lda, int64_t K, int64_t N,
+                                                 const TP* __restrict__ P, int64_t ldp, int ncols,
+                                                 TO* __restrict__ out, int64_t ldo, int64_t part_stride,
+                                                 int64_t kchunk) {
+  __shared__ V4<TC> ps[NB * 4 * 64];
+  typedef Mma<TC> M;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t jw = (int64_t)blockIdx.x * 256 + wave * 64;   // this wave's 64 output rows
+  const int split = blockIdx.y;
+  const int cg0 = blockIdx.z * NB * 16;
+  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kend = min(K, kbeg + kchunk);
+
+  // acc[bb][cb]: MFMA tile row m <-> output row jw + 4*m + bb
+  typename M::acc acc[4][NB];
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[bb][cb] = M::zero();
+
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+    stage_panel<NB>(ps, P, ldp, cg0, ncols, k0, kend);
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      V4<TA> a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        a[t] = load4_guarded<VEC>(A, lda, k0 + 16 * kq + 4 * g + t, jw + 4 * li, kend, N);
+      V4<TC> b[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) b[cb] = ps[(cb * 4 + kq) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+          TC av = static_cast<TC>(a[t].x[bb]);
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) acc[bb][cb] = M::op(av, b[cb].x[t], acc[bb][cb]);
+        }
+    }
+    __syncthreads();
+  }
+
+  TO* o = out + (int64_t)split * part_stride;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    int c = cg0 + cb * 16 + li;
+    if (c >= ncols) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int64_t j = jw + 16 * g + 4 * r;   // rows j .. j+3 <-> bb = 0..3
+      if (OUT_RM) {
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+          if (j + bb < N) o[(j + bb) * ldo + c] = static_cast<TO>(acc[bb][cb][r]);
+      } else {
+        TO* p = o + (int64_t)c * ldo + j;
+        if (j + 4 <= N) {
+          V4<TO> v;
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb) v.x[bb] = static_cast<TO>(acc[bb][cb][r]);
+          v4_store(p, v);
+        } else {
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb)
+            if (j + bb < N) p[bb] = static_cast<TO>(acc[bb][cb][r]);
+        }
+      }
+    }
+  }
+}
+
+// out[c*ldo + r] = sum_{s < S} part[s*ps + c*ldp + r]  (fixed order), r < rows, c < ncols.
+template <typename TP, typename TO>
+__global__ __launch_bounds__(256) void reduce_kernel(const TP* __restrict__ part, int S, int64_t pstride,
+                                                     int64_t ldp, int64_t rows, int ncols, TO* __restrict__ out,
+                                                     int64_t ldo) {
+  int64_t nq = (rows + 3) / 4;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nq * ncols) return;
+  int64_t c = t / nq, r = 4 * (t % nq);
+  const TP* p = part + c * ldp + r;
+  TO* o = out + c * ldo + r;
+  if (r + 4 <= rows) {
+    V4<TP> s = v4_load(p);
+    for (int k = 1; k < S; ++k) {
+      V4<TP> v = v4_load(p + k * pstride);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s.x[e] += v.x[e];
+    }
+    v4_store(o, v4_cast<TO>(s));
+  } else {
+    for (int e = 0; r + e < rows; ++e) {
+      TP s = p[e];
+      for (int k = 1; k < S; ++k) s += p[k * pstride + e];
+      o[e] = static_cast<TO>(s);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline int nb_for(int ncols) { int nb = (ncols + 15) / 16; return nb > 8 ? 8 : (nb < 1 ? 1 : nb); }
+
+#define RSVD_NB_SWITCH(NBV, ...)                          \
+  switch (NBV) {                                          \
+    case 1: { constexpr int NB = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int NB = 2; __VA_ARGS__; } break; \
+    case 3: { constexpr int NB = 3; __VA_ARGS__; } break; \
+    case 4: { constexpr int NB = 4; __VA_ARGS__; } break; \
+    case 5: { constexpr int NB = 5; __VA_ARGS__; } break; \
+    case 6: { constexpr int NB = 6; __VA_ARGS__; } break; \
+    case 7: { constexpr int NB = 7; __VA_ARGS__; } break; \
+    default: { constexpr int NB = 8; __VA_ARGS__; } break; \
+  }
+
+template <typename TA, typename TX, typename TC, typename TO>
+hipError_t launch_nn(const TA* A, int64_t lda, int64_t rows, int64_t K, const TX* X, int64_t ldx, int ncols,
+                     TO* out, int64_t ldo, int64_t part_stride, int splits, hipStream_t s) {
+  if (rows <= 0 || ncols <= 0) return hipSuccess;
+  if (splits < 1) splits = 1;
+  int64_t kchunk = ((K + splits - 1) / splits + KC - 1) / KC * KC;
+  if (kchunk < KC) kchunk = KC;
+  int used = (int)((K + kchunk - 1) / kchunk);
+  if (used < 1) used = 1;
+  int nb = nb_for(ncols);
+  int groups = (ncols + nb * 16 - 1) / (nb * 16);
+  dim3 grid((unsigned)((rows + 127) / 128), (unsigned)used, (unsigned)groups);
+  bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  RSVD_NB_SWITCH(nb, {
+    if (vec)
+      hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, true>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
+                         ncols, out, ldo, part_stride, kchunk);
+    else
+      hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, false>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
+                         ncols, out, ldo, part_stride, kchunk);
+  });
+  return hipGetLastError();
+}
+
+int nn_splits_used(int64_t K, int splits) {
+  if (splits < 1) splits = 1;
+  int64_t kchunk = ((K + splits - 1) / splits + KC - 1) / KC * KC;
+  if (kchunk < KC) kchunk = KC;
+  int used = (int)((K + kchunk - 1) / kchunk);
+  return used < 1 ? 1 : used;
+}
+
+template <typename TA, typename TP, typename TC, typename TO>
+hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols, TO* out,
+                     int64_t ldo, int64_t part_stride, int splits, bool out_rowmajor, hipStream_t s) {
+  if (N <= 0 || ncols <= 0) return hipSuccess;
+  if (splits < 1 || out_rowmajor) splits = 1;
+  int64_t kchunk = ((K + splits - 1) / splits + KC - 1) / KC * KC;
+  if (kchunk < KC) kchunk = KC;
+  int used = (int)((K + kchunk - 1) / kchunk);
+  if (used < 1) used = 1;
+  int nb = nb_for(ncols);
+  int groups = (ncols + nb * 16 - 1) / (nb * 16);
+  dim3 grid((unsigned)((N + 255) / 256), (unsigned)used, (unsigned)groups);
+  bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  RSVD_NB_SWITCH(nb, {
+    if (out_rowmajor) {
+      if (vec)
+        hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                           ldp, ncols, out, ldo, part_stride, kchunk);
+      else
+        hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                           ldp, ncols, out, ldo, part_stride, kchunk);
+    } else {
+      if (vec)
+        hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                           ldp, ncols, out, ldo, part_stride, kchunk);
+      else
+        hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                           ldp, ncols, out, ldo, part_stride, kchunk);
+    }
+  });
+  return hipGetLastError();
+}
+
+template <typename TP, typename TO>
+hipError_t launch_reduce(const TP* part, int S, int64_t pstride, int64_t ldp, int64_t rows, int ncols, TO* out,
+                         int64_t ldo, hipStream_t s) {
+  int64_t work = ((rows + 3) / 4) * ncols;
+  if (work <= 0) return hipSuccess;
+  hipLaunchKernelGGL((reduce_kernel<TP, TO>), dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, part, S,
+                     pstride, ldp, rows, ncols, out, ldo);
+  return hipGetLastError();
+}
+
+// Explicit instantiations used by the host orchestration.
+template hipError_t launch_nn<float, float, float, float>(const float*, int64_t, int64_t, int64_t, const float*,
+                                                          int64_t, int, float*, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_nn<double, double, double, double>(const double*, int64_t, int64_t, int64_t,
+                                                              const double*, int64_t, int, double*, int64_t,
+                                                              int64_t, int, hipStream_t);
+template hipError_t launch_nn<float, float, double, double>(const float*, int64_t, int64_t, int64_t, const float*,
+                                                            int64_t, int, double*, int64_t, int64_t, int,
+                                                            hipStream_t);
+template hipError_t launch_tn<float, float, float, float>(const float*, int64_t, int64_t, int64_t, const float*,
+                                                          int64_t, int, float*, int64_t, int64_t, int, bool,
+                                                          hipStream_t);
+template hipError_t launch_tn<double, double, double, double>(const double*, int64_t, int64_t, int64_t,
+                                                              const double*, int64_t, int, double*, int64_t,
+                                                              int64_t, int, bool, hipStream_t);
+template hipError_t launch_tn<float, double, double, double>(const float*, int64_t, int64_t, int64_t,
+                                                             const double*, int64_t, int, double*, int64_t,
+                                                             int64_t, int, bool, hipStream_t);
+template hipError_t launch_tn<double, double, double, float>(const double*, int64_t, int64_t, int64_t,
+                                                             const double*, int64_t, int, float*, int64_t, int64_t,
+                                                             int, bool, hipStream_t);
+template hipError_t launch_reduce<float, float>(const float*, int, int64_t, int64_t, int64_t, int, float*, int64_t,
+                                                hipStream_t);
+template hipError_t launch_reduce<double, double>(const double*, int, int64_t, int64_t, int64_t, int, double*,
+                                                  int64_t, hipStream_t);
+
+}  // namespace rsvd

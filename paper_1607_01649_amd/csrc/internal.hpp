@@ -1,0 +1,47 @@
+// Internal launch wrappers of the HIP kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+
+namespace rsvd {
+
+// rng.hip
+hipError_t launch_philox(int64_t count, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t s);
+template <typename T>
+hipError_t launch_gaussian(uint64_t seed, uint32_t stream, int64_t rows, int64_t cols, int64_t col0, T* out,
+                           int64_t row_stride, int64_t col_stride, hipStream_t s);
+
+// gemm.hip -- see the file comment for the panel layout.
+// nn: out[s][c][r] = sum_{j in split s} A[r][j] X(j, c); A rows x K row-major, X panel (X[c*ldx + j]).
+template <typename TA, typename TX, typename TC, typename TO>
+hipError_t launch_nn(const TA* A, int64_t lda, int64_t rows, int64_t K, const TX* X, int64_t ldx, int ncols, TO* out,
+                     int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
+// tn: out[s][c][j] = sum_{i in split s} A[i][j] P(i, c); A K x N row-major, P panel (P[c*ldp + i]).
+template <typename TA, typename TP, typename TC, typename TO>
+hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols, TO* out,
+                     int64_t ldo, int64_t part_stride, int splits, bool out_rowmajor, hipStream_t s);
+int nn_splits_used(int64_t K, int splits);
+template <typename TP, typename TO>
+hipError_t launch_reduce(const TP* part, int S, int64_t pstride, int64_t ldp, int64_t rows, int ncols, TO* out,
+                         int64_t ldo, hipStream_t s);
+
+// chol.hip
+template <typename TQ>
+hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_rel, TQ* rinv_p, double* r_out,
+                       const double* r_prev, double* scratch, int* flags, hipStream_t s);
+
+// jacobi.hip
+template <typename TU>
+hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma, double* uhat_d,
+                         TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s);
+
+// misc.hip
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+template <typename TO>
+hipError_t launch_rowmajor_to_panel(const double* src, int64_t rows, int64_t cols, int64_t ld_src, TO* dst,
+                                    int64_t ld_dst, hipStream_t s);
+
+}  // namespace rsvd

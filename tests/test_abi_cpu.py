@@ -1,0 +1,111 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/rsvd.h declares, and rejects invalid arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsvd.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(rsvd_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1607_01649_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("librsvd.so is not built; run __graft_entry__.build()")
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for want in ("rsvd_workspace_size", "rsvd_plan", "rsvd_factor", "rsvd_destroy", "rsvd_status_str",
+                 "rsvd_gaussian", "rsvd_philox4x32_10"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1607_01649_amd import _lib
+    bound = {name for name, _, _ in _lib.SIGNATURES}
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+        assert name in bound, f"{name} has no Python binding"
+
+
+def test_struct_layouts_match_the_header(lib):
+    from paper_1607_01649_amd._lib import rsvd_desc, rsvd_info
+    assert ctypes.sizeof(rsvd_desc) == 80
+    assert ctypes.sizeof(rsvd_info) == 88
+    assert rsvd_desc.seed.offset == 40 and rsvd_desc.eps.offset == 48 and rsvd_desc.flags.offset == 72
+    assert rsvd_info.err_bound.offset == 24 and rsvd_info.stage_ms.offset == 40 and rsvd_info.nn_launches.offset == 80
+
+
+def _desc(**kw):
+    from paper_1607_01649_amd import make_desc
+    base = dict(m=1000, n=800, k=20, p=10, q=1, a_dtype="f32")
+    base.update(kw)
+    return make_desc(**base)
+
+
+def _ws(lib, d):
+    n = ctypes.c_size_t(0)
+    st = lib.rsvd_workspace_size(ctypes.byref(d), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_for_valid_descriptions(lib):
+    for kw in (dict(), dict(a_dtype="f64"), dict(m=50000, n=20000, k=100, p=10, q=2),
+               dict(m=517, n=389, k=7, p=6, q=0)):
+        st, n = _ws(lib, _desc(**kw))
+        assert st == 0 and n > 0
+    # larger problems need more workspace
+    assert _ws(lib, _desc(m=4000))[1] > _ws(lib, _desc(m=1000))[1]
+
+
+@pytest.mark.parametrize("kw", [
+    dict(k=0), dict(p=-1), dict(q=-1), dict(m=0), dict(n=-5),
+    dict(k=790, p=20),                 # k + p > min(m, n)
+    dict(eps=-1.0), dict(eps=float("nan")),
+    dict(a_dtype=7), dict(max_rank=5),  # max_rank below k + p
+    dict(n_probe=-1), dict(est_power=-2),
+])
+def test_invalid_descriptions_are_rejected_on_the_host(lib, kw):
+    st, _ = _ws(lib, _desc(**kw))
+    assert st == -1
+    h = ctypes.c_void_p()
+    d = _desc(**kw)
+    assert lib.rsvd_plan(ctypes.byref(d), ctypes.c_void_p(1 << 20), 1 << 30, None, ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_unsupported_combinations(lib):
+    st, _ = _ws(lib, _desc(a_dtype="f64", sketch_dtype="f32"))
+    assert st == -5
+
+
+def test_plan_checks_workspace_before_touching_the_device(lib):
+    d = _desc()
+    st, need = _ws(lib, d)
+    h = ctypes.c_void_p()
+    assert lib.rsvd_plan(ctypes.byref(d), None, need, None, ctypes.byref(h)) == -2
+    assert lib.rsvd_plan(ctypes.byref(d), ctypes.c_void_p(4096), need - 1, None, ctypes.byref(h)) == -2
+    assert lib.rsvd_plan(ctypes.byref(d), ctypes.c_void_p(4096 + 8), need, None, ctypes.byref(h)) == -2
+
+
+def test_null_arguments(lib):
+    assert lib.rsvd_workspace_size(None, None) == -1
+    assert lib.rsvd_factor(None, None, 0, None, None, 0, None, None, 0, None) == -1
+    assert lib.rsvd_gaussian(0, 4, 10, 10, 0, 1, None, 10, None) == -1
+    assert lib.rsvd_gaussian(0, 4, 10, 10, 0, 9, ctypes.c_void_p(4096), 10, None) == -1
+    assert lib.rsvd_philox4x32_10(-1, None, 0, 0, None, None) == -1
+    lib.rsvd_destroy(None)
+    assert lib.rsvd_status_str(-3) == b"RSVD_E_HIP"

@@ -1,0 +1,175 @@
+"""Parity of the HIP path (through the C ABI) with the float64 CPU oracle.
+
+Tolerances
+  FP64 path: singular values relative error <= 1e-10; U and V columns within
+             1e-8 (the oracle and the GPU use the same sign rule), which is
+             u64 * kappa / gap with a wide margin for these spectra.
+  FP32 path: singular values relative error <= 1e-4 against the FP64 oracle;
+             rank-k subspaces within sin(theta) <= 50 * sqrt(n) * u32 / relgap,
+             relgap = (sigma_k - sigma_{k+1}) / sigma_1 of the oracle's factors
+             (a Wedin-type bound with the FP32 rounding of the data as the
+             perturbation).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import philox, rsvd as orc
+from workloads import gen
+
+from tests.gpu_helpers import column_errors, device, max_rel_sigma, orth_error, run_factor, subspace_sin
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _kat_rows(golden_dir):
+    import os
+    rows = []
+    for line in open(os.path.join(golden_dir, "philox4x32_10_kat.txt")):
+        if line.strip() and not line.startswith("#"):
+            rows.append([int(w, 16) for w in line.split()])
+    return rows
+
+
+def test_philox_known_answers_on_device(golden_dir):
+    import torch
+    from paper_1607_01649_amd import rsvd_philox4x32_10
+    dev = device()
+    for r in _kat_rows(golden_dir):
+        ctr = torch.tensor(np.array(r[0:4], dtype=np.uint32).view(np.int32)[None, :], device=dev)
+        out = torch.empty_like(ctr)
+        rsvd_philox4x32_10(ctr, r[4], r[5], out)
+        got = out.cpu().numpy().view(np.uint32)[0].tolist()
+        assert got == r[6:10]
+    # a batch of counters against the oracle's integers, bit for bit
+    rng = np.random.default_rng(0)
+    c = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr = torch.tensor(c.view(np.int32), device=dev)
+    out = torch.empty_like(ctr)
+    rsvd_philox4x32_10(ctr, 0x12345678, 0x9ABCDEF0, out)
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), philox.philox4x32_10(c, (0x12345678, 0x9ABCDEF0)))
+
+
+@pytest.mark.parametrize("rows,cols,col0", [(1001, 7, 0), (64, 33, 5), (2, 1, 1000)])
+def test_gaussian_matches_the_oracle_generator(rows, cols, col0):
+    import torch
+    from paper_1607_01649_amd import rsvd_gaussian
+    dev = device()
+    ref = philox.gaussian(rows, cols, 987654321123, 4, col0=col0)
+    out = torch.empty(rows, cols, dtype=torch.float64, device=dev)
+    rsvd_gaussian(987654321123, 4, out, col0=col0)
+    got = out.cpu().numpy()
+    # same integers; log/cos/sin of the two math libraries agree to a few ulp
+    assert np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref))) < 1e-14
+    out32 = torch.empty(rows, cols, dtype=torch.float32, device=dev)
+    rsvd_gaussian(987654321123, 4, out32, col0=col0)
+    assert np.max(np.abs(out32.cpu().numpy() - ref.astype(np.float32))) <= 2 * U32 * np.max(np.abs(ref))
+
+
+F64_CASES = [
+    # m, n, rank, alpha, k, p, q
+    (600, 500, 120, 2.0, 20, 10, 1),
+    (517, 389, 100, 1.0, 7, 6, 0),     # ragged tails everywhere, q = 0
+    (300, 300, 300, 1.0, 290, 10, 2),  # k + p = min(m, n)
+    (128, 96, 60, 1.5, 16, 0, 1),      # p = 0
+    (1000, 64, 64, 1.0, 40, 24, 1),    # l = n
+    (70, 900, 70, 1.0, 20, 15, 2),     # wide A
+]
+
+
+@pytest.mark.parametrize("m,n,rank,alpha,k,p,q", F64_CASES)
+def test_factor_f64_matches_the_oracle_given_omega(m, n, rank, alpha, k, p, q):
+    sigma = gen.spectrum("poly", rank, alpha=alpha)
+    A = gen.low_rank_matrix(m, n, sigma, 1e-8, seed=m * 7 + n)
+    G = gen.gaussian_matrix(n, k + p, seed=m + n)
+    ref = orc.rsvd(A, G, q).truncate(k)
+    U, S, V, info = run_factor(A, k, p, q, "f64", omega=G)
+    assert info.status == 0 and info.rank_out == k
+    assert max_rel_sigma(S, ref.D, k) <= 1e-10
+    gaps = np.abs(np.diff(ref.D))
+    good = [j for j in range(k) if (j == 0 or gaps[j - 1] > 1e-6 * ref.D[0]) and (j >= len(gaps) or gaps[j] > 1e-6 * ref.D[0])]
+    assert column_errors(U[:, good], ref.U[:, good]) <= 1e-8
+    assert column_errors(V[:, good], ref.V[:, good]) <= 1e-8
+
+
+def test_factor_f64_plain_2000_from_seed():
+    """The 2000 x 2000 float64 workload (sigma_j = j^-2 over 200 modes, noise
+    1e-8, k=20, p=10, q=1) with Omega drawn on the device from the seed and
+    independently by the oracle's own Philox generator."""
+    cfg = gen.config("plain_f64_2000")
+    A = cfg.matrix(seed=11)
+    ref = orc.rsvd_seeded(A, cfg.k, cfg.p, cfg.q, seed=2024).truncate(cfg.k)
+    U, S, V, info = run_factor(A, cfg.k, cfg.p, cfg.q, "f64", seed=2024)
+    assert max_rel_sigma(S, ref.D, cfg.k) <= 1e-10
+    assert column_errors(U, ref.U) <= 1e-8
+    assert column_errors(V, ref.V) <= 1e-8
+    # the Eckart-Young floor holds for the returned rank-k factors
+    err = np.linalg.norm(A - (U * S) @ V.T, 2)
+    s = np.linalg.svd(A, compute_uv=False)
+    assert err >= s[cfg.k] * (1 - 1e-10)
+
+
+F32_CASES = [
+    # m, n, rank, alpha, k, p, q, lda_pad
+    (3000, 1500, 300, 0.5, 20, 10, 2, 0),
+    (1237, 901, 200, 1.0, 12, 8, 1, 0),    # n % 4 != 0: unaligned rows, scalar loads
+    (2048, 1024, 256, 0.5, 50, 14, 2, 3),  # lda = n + 3
+    (777, 2500, 150, 0.8, 30, 10, 1, 0),
+]
+
+
+@pytest.mark.parametrize("m,n,rank,alpha,k,p,q,pad", F32_CASES)
+def test_factor_f32_matches_the_f64_oracle(m, n, rank, alpha, k, p, q, pad):
+    sigma = gen.spectrum("poly", rank, alpha=alpha)
+    A64 = gen.low_rank_matrix(m, n, sigma, 1e-3 / math.sqrt(n), seed=m + 3 * n)
+    A32 = A64.astype(np.float32)
+    G = gen.gaussian_matrix(n, k + p, seed=m * n)
+    ref = orc.rsvd(A32.astype(np.float64), G, q)
+    refk = ref.truncate(k)
+    U, S, V, info = run_factor(A32, k, p, q, "f32", omega=G, lda_pad=pad)
+    assert info.status == 0
+    assert max_rel_sigma(S, refk.D, k) <= 1e-4
+    relgap = (ref.D[k - 1] - ref.D[k]) / ref.D[0]
+    tol = 50 * math.sqrt(max(m, n)) * U32 / relgap
+    assert subspace_sin(U, refk.U) <= tol
+    assert subspace_sin(V, refk.V) <= tol
+    assert orth_error(U) <= 1e-5 and orth_error(V) <= 1e-5
+
+
+def test_exact_low_rank_input_drops_dependent_directions():
+    """rank(A) = 5 < l = 16: the leading five triplets are exact (Section 4),
+    the remaining singular values are zero or at rounding level."""
+    sigma = np.array([5.0, 4.0, 3.0, 2.0, 1.0])
+    A = gen.low_rank_matrix(400, 300, sigma, 0.0, seed=5)
+    G = gen.gaussian_matrix(300, 16, seed=6)
+    U, S, V, info = run_factor(A, 10, 6, 1, "f64", omega=G)
+    assert np.allclose(S[:5], sigma, rtol=1e-12)
+    assert np.all(S[5:] <= 1e-12)
+    ref = orc.rsvd(A, G, 1)
+    assert subspace_sin(U[:, :5], ref.U[:, :5]) < 1e-10
+    assert np.linalg.norm(A - (U * S) @ V.T, 2) < 1e-12
+
+
+def test_rank_l_flag_and_determinism():
+    from paper_1607_01649_amd import RSVD_RETURN_RANK_L
+    sigma = gen.spectrum("poly", 100, alpha=1.0)
+    A = gen.low_rank_matrix(900, 700, sigma, 1e-6, seed=8).astype(np.float32)
+    G = gen.gaussian_matrix(700, 30, seed=9)
+    U1, S1, V1, info = run_factor(A, 20, 10, 1, "f32", omega=G, flags=RSVD_RETURN_RANK_L)
+    assert info.rank_out == 30 and U1.shape == (900, 30) and V1.shape == (700, 30)
+    U2, S2, V2, _ = run_factor(A, 20, 10, 1, "f32", omega=G, flags=RSVD_RETURN_RANK_L)
+    assert np.array_equal(U1, U2) and np.array_equal(S1, S2) and np.array_equal(V1, V2)
+    ref = orc.rsvd(A.astype(np.float64), G, 1)
+    assert max_rel_sigma(S1, ref.D, 30) <= 1e-4
+    # Stage B is exact (Remark in Section 3): at rank l, A^T U = V diag(S)
+    assert np.max(np.abs(A.astype(np.float64).T @ U1 - V1 * S1)) <= 1e-4 * S1[0]
+
+
+def test_nan_input_is_reported():
+    A = np.ones((200, 100), dtype=np.float32)
+    A[17, 3] = np.nan
+    with pytest.raises(RuntimeError, match="NONFINITE"):
+        run_factor(A, 5, 5, 0, "f32")
