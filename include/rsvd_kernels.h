@@ -1,0 +1,78 @@
+/*
+ * rsvd_kernels.h -- kernel-level entry points of librsvd.so, exposed so each
+ * building block of the randomized SVD can be checked on its own against a
+ * CPU reference.  Same conventions as rsvd.h (device pointers d_*, work
+ * enqueued on `stream`, RSVD_E_ARG before anything is enqueued).
+ *
+ * "Panel" layout: an r x c tall matrix P is stored column by column,
+ * element (i, j) at P[j * ld + i] (the row-major storage of P^T).  The
+ * library keeps Y = A Omega, Q, W, B^T and the other thin matrices this way.
+ *
+ * Precision codes: RSVD_F64 = inputs, arithmetic and output in FP64;
+ * RSVD_F32 = FP32 inputs, FP32 MFMA, FP32 output; and for the products
+ * only, 10 = FP32 inputs with FP64 MFMA accumulation and FP64 output (the
+ * Gram matrices of the orthonormalisation).
+ */
+#ifndef RSVD_KERNELS_H_
+#define RSVD_KERNELS_H_
+
+#include "rsvd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSVD_F32_ACC64 10
+
+/*
+ * d_out (panel, ld ldo >= rows) = A X for A rows x K row-major (lda >= K) and
+ * X a K x ncols panel (ldx >= K): the product used for the sketch Y = A Omega,
+ * the power step Y = A W (Section 8.1, Figure 5) and, with A a panel read as
+ * its transpose, the Gram matrix Y^T Y of CholeskyQR.  1 <= ncols <= 1024.
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_product_nn(int32_t precision, int64_t rows, int64_t K, const void* d_A, int64_t lda,
+                              const void* d_X, int64_t ldx, int32_t ncols, void* d_out, int64_t ldo,
+                              void* stream);
+
+/*
+ * d_out = A^T P for A K x N row-major (lda >= N) and P a K x ncols panel
+ * (ldp >= K): the power step Z = A^T Q and the projection B^T = A^T Q
+ * (Figure 5).  out_rowmajor = 0: d_out is an N x ncols panel (ldo >= N);
+ * 1: d_out is N x ncols row-major (ldo >= ncols).
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_product_tn(int32_t precision, int64_t K, int64_t N, const void* d_A, int64_t lda,
+                              const void* d_P, int64_t ldp, int32_t ncols, void* d_out, int64_t ldo,
+                              int32_t out_rowmajor, void* stream);
+
+/*
+ * FP64 Cholesky of the l x l symmetric matrix d_G (column-major, ldg >= l):
+ * G = R^T R with R upper triangular, R_jj > 0.  Writes d_Rinv (LP x LP FP64,
+ * d_Rinv[c*LP + k] = R^-1(k, c), identity outside l x l) and d_R (LP x LP
+ * FP64 row-major, identity outside l x l).  LP = l rounded up to 16.  Columns
+ * whose pivot falls to <= tau_rel * G_jj are dropped (zero row of R, zero
+ * column of R^-1) and counted in d_flags[1]; non-finite pivots in d_flags[0].
+ * d_flags: 4 device ints, accumulated (not cleared).
+ * Errors: RSVD_E_ARG (l < 1 or l > 1024), RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_cholesky(int32_t l, const double* d_G, int64_t ldg, double tau_rel, double* d_Rinv,
+                            double* d_R, int32_t* d_flags, void* stream);
+
+/*
+ * SVD of X = R^T by one-sided Jacobi in FP64 (the small SVD of Stage B,
+ * Section 3): d_R is LP x LP row-major (LP = l rounded up to 16), only its
+ * leading l x l block read.  Writes d_sigma (LP values, descending, zeros
+ * past l) and d_Uhat (LP x LP, column j of U_hat at d_Uhat[j*LP .. +LP)),
+ * each column signed so that its entry of largest magnitude is positive.
+ * d_flags[2] counts a sweep limit reached before convergence.
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_small_svd(int32_t l, const double* d_R, double* d_sigma, double* d_Uhat, int32_t* d_flags,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSVD_KERNELS_H_ */

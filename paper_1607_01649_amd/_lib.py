@@ -69,7 +69,17 @@ SIGNATURES = [
                                      _i64, _c_void_p]),
     ("rsvd_philox4x32_10", ctypes.c_int, [_i64, _c_void_p, ctypes.c_uint32, ctypes.c_uint32, _c_void_p,
                                           _c_void_p]),
+    # include/rsvd_kernels.h
+    ("rsvd_k_product_nn", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, _c_void_p, _i64,
+                                         ctypes.c_int32, _c_void_p, _i64, _c_void_p]),
+    ("rsvd_k_product_tn", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, _c_void_p, _i64,
+                                         ctypes.c_int32, _c_void_p, _i64, ctypes.c_int32, _c_void_p]),
+    ("rsvd_k_cholesky", ctypes.c_int, [ctypes.c_int32, _c_void_p, _i64, ctypes.c_double, _c_void_p, _c_void_p,
+                                       _c_void_p, _c_void_p]),
+    ("rsvd_k_small_svd", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
 ]
+
+RSVD_F32_ACC64 = 10
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -13,10 +13,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // One 16x16 MFMA tile with K = 4 per instruction.  Operand layout (both
-// precisions): lane l supplies A(row l%16, k l/16) and B(k l/16, col l%16);
-// the accumulator holds D(row 4*(l/16)+r, col l%16) in element r.
+// precisions): lane l supplies A(row l%16, k l/16) and B(k l/16, col l%16).
+// Accumulator element r of lane l holds
+//   f32: D(row 4*(l/16) + r, col l%16)
+//   f64: D(row (l/16) + 4*r, col l%16)
+// (measured on gfx950).  The kernels always want lane l to end up with four
+// consecutive data rows 4*(l/16) + r, so the lane that supplies MFMA row i
+// loads data row arow(i): the identity for f32, and the permutation
+// i = g + 4e -> 4g + e for f64.
 template <typename TC> struct Mma;
 template <> struct Mma<float> {
+  static __device__ __forceinline__ int arow(int i) { return i; }
   typedef f32x4 acc;
   static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
   static __device__ __forceinline__ acc op(float a, float b, acc c) {
@@ -24,6 +31,7 @@ template <> struct Mma<float> {
   }
 };
 template <> struct Mma<double> {
+  static __device__ __forceinline__ int arow(int i) { return ((i & 3) << 2) | (i >> 2); }
   typedef f64x4 acc;
   static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
   static __device__ __forceinline__ acc op(double a, double b, acc c) {

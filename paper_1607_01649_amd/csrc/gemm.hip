@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void nn_kernel(const TA* __restrict__ A, int64
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
       for (int kq = 0; kq < 4; ++kq)
-        a[rb][kq] = load4_guarded<VEC>(A, lda, rbase + 16 * rb + li, k0 + 16 * kq + 4 * g, rows, kend);
+        a[rb][kq] = load4_guarded<VEC>(A, lda, rbase + 16 * rb + M::arow(li), k0 + 16 * kq + 4 * g, rows, kend);
     __syncthreads();
 #pragma unroll
     for (int kq = 0; kq < 4; ++kq) {
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
 
-  // acc[bb][cb]: MFMA tile row m <-> output row jw + 4*m + bb
+  // acc[bb][cb]: MFMA tile row m <-> output row jw + 4*arow(m) + bb
   typename M::acc acc[4][NB];
 #pragma unroll
   for (int bb = 0; bb < 4; ++bb)
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64
       V4<TA> a[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        a[t] = load4_guarded<VEC>(A, lda, k0 + 16 * kq + 4 * g + t, jw + 4 * li, kend, N);
+        a[t] = load4_guarded<VEC>(A, lda, k0 + 16 * kq + 4 * g + t, jw + 4 * M::arow(li), kend, N);
       V4<TC> b[NB];
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) b[cb] = ps[(cb * 4 + kq) * 64 + lane];
@@ -196,19 +196,22 @@ __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64
 }
 
 // out[c*ldo + r] = sum_{s < S} part[s*ps + c*ldp + r]  (fixed order), r < rows, c < ncols.
+// grid.y = group: partials [group*S, min((group+1)*S, Stot)) go to out + group*ostride.
 template <typename TP, typename TO>
-__global__ __launch_bounds__(256) void reduce_kernel(const TP* __restrict__ part, int S, int64_t pstride,
+__global__ __launch_bounds__(256) void reduce_kernel(const TP* __restrict__ part, int S, int Stot, int64_t pstride,
                                                      int64_t ldp, int64_t rows, int ncols, TO* __restrict__ out,
-                                                     int64_t ldo) {
+                                                     int64_t ldo, int64_t ostride) {
   int64_t nq = (rows + 3) / 4;
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= nq * ncols) return;
+  const int s0 = blockIdx.y * S;
+  const int cnt = min(S, Stot - s0);
   int64_t c = t / nq, r = 4 * (t % nq);
-  const TP* p = part + c * ldp + r;
-  TO* o = out + c * ldo + r;
+  const TP* p = part + (int64_t)s0 * pstride + c * ldp + r;
+  TO* o = out + blockIdx.y * ostride + c * ldo + r;
   if (r + 4 <= rows) {
     V4<TP> s = v4_load(p);
-    for (int k = 1; k < S; ++k) {
+    for (int k = 1; k < cnt; ++k) {
       V4<TP> v = v4_load(p + k * pstride);
 #pragma unroll
       for (int e = 0; e < 4; ++e) s.x[e] += v.x[e];
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TP* __restrict__ part
   } else {
     for (int e = 0; r + e < rows; ++e) {
       TP s = p[e];
-      for (int k = 1; k < S; ++k) s += p[k * pstride + e];
+      for (int k = 1; k < cnt; ++k) s += p[k * pstride + e];
       o[e] = static_cast<TO>(s);
     }
   }
@@ -309,9 +312,25 @@ hipError_t launch_reduce(const TP* part, int S, int64_t pstride, int64_t ldp, in
                          int64_t ldo, hipStream_t s) {
   int64_t work = ((rows + 3) / 4) * ncols;
   if (work <= 0) return hipSuccess;
-  hipLaunchKernelGGL((reduce_kernel<TP, TO>), dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, part, S,
-                     pstride, ldp, rows, ncols, out, ldo);
+  hipLaunchKernelGGL((reduce_kernel<TP, TO>), dim3((unsigned)((work + 255) / 256), 1), dim3(256), 0, s, part, S, S,
+                     pstride, ldp, rows, ncols, out, ldo, (int64_t)0);
   return hipGetLastError();
+}
+
+// Two-level fixed-order sum for many partials: groups of `group` partials are
+// summed into `tmp` (ceil(S/group) partials with the same stride), then those.
+template <typename TP>
+hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int64_t ldp, int64_t rows, int ncols,
+                          TP* tmp, TP* out, int64_t ldo, hipStream_t s) {
+  if (S <= 2 * group) return launch_reduce<TP, TP>(part, S, pstride, ldp, rows, ncols, out, ldo, s);
+  int64_t work = ((rows + 3) / 4) * ncols;
+  if (work <= 0) return hipSuccess;
+  int ng = (S + group - 1) / group;
+  hipLaunchKernelGGL((reduce_kernel<TP, TP>), dim3((unsigned)((work + 255) / 256), (unsigned)ng), dim3(256), 0, s,
+                     part, group, S, pstride, ldp, rows, ncols, tmp, ldp, pstride);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce<TP, TP>(tmp, ng, pstride, ldp, rows, ncols, out, ldo, s);
 }
 
 // Explicit instantiations used by the host orchestration.
@@ -339,5 +358,7 @@ template hipError_t launch_reduce<float, float>(const float*, int, int64_t, int6
                                                 hipStream_t);
 template hipError_t launch_reduce<double, double>(const double*, int, int64_t, int64_t, int64_t, int, double*,
                                                   int64_t, hipStream_t);
+template hipError_t launch_reduce2<double>(const double*, int, int, int64_t, int64_t, int64_t, int, double*, double*,
+                                           int64_t, hipStream_t);
 
 }  // namespace rsvd

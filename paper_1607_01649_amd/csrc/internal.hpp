@@ -27,6 +27,9 @@ int nn_splits_used(int64_t K, int splits);
 template <typename TP, typename TO>
 hipError_t launch_reduce(const TP* part, int S, int64_t pstride, int64_t ldp, int64_t rows, int ncols, TO* out,
                          int64_t ldo, hipStream_t s);
+template <typename TP>
+hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int64_t ldp, int64_t rows, int ncols,
+                          TP* tmp, TP* out, int64_t ldo, hipStream_t s);
 
 // chol.hip
 template <typename TQ>

@@ -10,8 +10,8 @@
 // lift kernel.
 //
 // Pairs are visited in round-robin ("circle method") order: each round holds
-// floor(l/2) disjoint pairs, processed one pair per wave64 in parallel;
-// l-1 (or l) rounds make a sweep.  Sweeps repeat until no pair needs a
+// floor(l/2) disjoint pairs, processed in parallel by groups of 16 lanes (64
+// pairs at once in a 1024-thread block); l-1 (or l) rounds make a sweep.  Sweeps repeat until no pair needs a
 // rotation (|x_p . x_q| <= tol * ||x_p|| ||x_q||).  Results are sorted by
 // descending sigma and each u_hat column is signed so that its entry of
 // largest magnitude (lowest index on ties) is positive.
@@ -21,6 +21,13 @@ namespace rsvd {
 
 __device__ __forceinline__ int rr_player(int pos, int round, int le) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (le - 1);
+}
+
+// Reduction over the 16 lanes of a pair group (lanes 16*s .. 16*s+15).
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  return v;
 }
 
 template <typename TU, bool USE_LDS>
@@ -36,9 +43,10 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
   __shared__ int rotated;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
+  const int slot = tid >> 4, sub = tid & 15, nslots = nt >> 4;   // 16 lanes per column pair
 
   for (int idx = tid; idx < l * l; idx += nt) {
-    int p = idx / l, i = idx % l;
+    int p = idx / l, i = idx - (idx / l) * l;
     xs[p * LP + i] = R[(int64_t)p * LP + i];
   }
   const int le = l + (l & 1);
@@ -50,28 +58,28 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < le - 1; ++round) {
-      for (int pi = w; pi < npairs; pi += nw) {
+      for (int pi = slot; pi < npairs; pi += nslots) {
         int p = rr_player(pi, round, le), q = rr_player(le - 1 - pi, round, le);
-        if (p >= l || q >= l) continue;
+        if (p >= l || q >= l) continue;   // uniform within the 16-lane group
         double* xp = xs + p * LP;
         double* xq = xs + q * LP;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < l; i += 64) {
+        for (int i = sub; i < l; i += 16) {
           double a = xp[i], b = xq[i];
           al += a * a; be += b * b; ga += a * b;
         }
-        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+        al = group16_sum(al); be = group16_sum(be); ga = group16_sum(ga);
         if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
           double zeta = (be - al) / (2.0 * ga);
           double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double c = 1.0 / sqrt(1.0 + t * t);
           double s = c * t;
-          for (int i = lane; i < l; i += 64) {
+          for (int i = sub; i < l; i += 16) {
             double a = xp[i], b = xq[i];
             xp[i] = c * a - s * b;
             xq[i] = s * a + c * b;
           }
-          if (lane == 0) rotated = 1;
+          if (sub == 0) rotated = 1;
         }
       }
       __syncthreads();
@@ -99,8 +107,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     if (p >= l) {   // padding: zero column at the same index
       for (int i = lane; i < LP; i += 64) {
         uhat_d[(int64_t)p * LP + i] = 0.0;
-        uhat_p[(int64_t)p * LP + i] = TU(0);
-        vhat_p[(int64_t)p * LP + i] = TU(0);
+        if (uhat_p) uhat_p[(int64_t)p * LP + i] = TU(0);
+        if (vhat_p) vhat_p[(int64_t)p * LP + i] = TU(0);
       }
       if (lane == 0) sigma[p] = 0.0;
       continue;
@@ -126,8 +134,8 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     for (int i = lane; i < LP; i += 64) {
       double x = (i < l) ? xs[p * LP + i] : 0.0;
       uhat_d[(int64_t)j * LP + i] = x * inv;
-      uhat_p[(int64_t)j * LP + i] = static_cast<TU>(x * inv);
-      vhat_p[(int64_t)j * LP + i] = static_cast<TU>(x * inv2);
+      if (uhat_p) uhat_p[(int64_t)j * LP + i] = static_cast<TU>(x * inv);
+      if (vhat_p) vhat_p[(int64_t)j * LP + i] = static_cast<TU>(x * inv2);
     }
     if (lane == 0) sigma[j] = sv;
   }

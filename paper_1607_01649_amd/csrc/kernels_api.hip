@@ -1,0 +1,70 @@
+// Kernel-level C entry points (include/rsvd_kernels.h): each building block of
+// the randomized SVD callable on its own, for per-kernel parity tests.
+#include "../../include/rsvd_kernels.h"
+#include "internal.hpp"
+
+using namespace rsvd;
+
+#define K_TRY(expr)                           \
+  do {                                        \
+    if ((expr) != hipSuccess) return RSVD_E_HIP; \
+  } while (0)
+
+extern "C" {
+
+rsvd_status rsvd_k_product_nn(int32_t prec, int64_t rows, int64_t K, const void* A, int64_t lda, const void* X,
+                              int64_t ldx, int32_t ncols, void* out, int64_t ldo, void* stream) {
+  if (!A || !X || !out || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K || ldx < K || ldo < rows)
+    return RSVD_E_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (prec == RSVD_F64)
+    K_TRY((launch_nn<double, double, double, double>((const double*)A, lda, rows, K, (const double*)X, ldx, ncols,
+                                                     (double*)out, ldo, 0, 1, s)));
+  else if (prec == RSVD_F32)
+    K_TRY((launch_nn<float, float, float, float>((const float*)A, lda, rows, K, (const float*)X, ldx, ncols,
+                                                 (float*)out, ldo, 0, 1, s)));
+  else if (prec == RSVD_F32_ACC64)
+    K_TRY((launch_nn<float, float, double, double>((const float*)A, lda, rows, K, (const float*)X, ldx, ncols,
+                                                   (double*)out, ldo, 0, 1, s)));
+  else
+    return RSVD_E_ARG;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_k_product_tn(int32_t prec, int64_t K, int64_t N, const void* A, int64_t lda, const void* P,
+                              int64_t ldp, int32_t ncols, void* out, int64_t ldo, int32_t out_rowmajor,
+                              void* stream) {
+  if (!A || !P || !out || K < 1 || N < 1 || ncols < 1 || ncols > 1024 || lda < N || ldp < K) return RSVD_E_ARG;
+  if (out_rowmajor ? (ldo < ncols) : (ldo < N)) return RSVD_E_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  bool rm = out_rowmajor != 0;
+  if (prec == RSVD_F64)
+    K_TRY((launch_tn<double, double, double, double>((const double*)A, lda, K, N, (const double*)P, ldp, ncols,
+                                                     (double*)out, ldo, 0, 1, rm, s)));
+  else if (prec == RSVD_F32)
+    K_TRY((launch_tn<float, float, float, float>((const float*)A, lda, K, N, (const float*)P, ldp, ncols,
+                                                 (float*)out, ldo, 0, 1, rm, s)));
+  else
+    return RSVD_E_ARG;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_k_cholesky(int32_t l, const double* G, int64_t ldg, double tau_rel, double* Rinv, double* R,
+                            int32_t* flags, void* stream) {
+  if (l < 1 || l > 128 || !G || !Rinv || !R || !flags || ldg < l || !(tau_rel >= 0.0)) return RSVD_E_ARG;
+  int LP = (l + 15) / 16 * 16;
+  K_TRY(launch_chol<double>(G, ldg, l, LP, tau_rel, Rinv, R, nullptr, nullptr, flags,
+                            reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_k_small_svd(int32_t l, const double* R, double* sigma, double* Uhat, int32_t* flags,
+                             void* stream) {
+  if (l < 1 || l > 128 || !R || !sigma || !Uhat || !flags) return RSVD_E_ARG;
+  int LP = (l + 15) / 16 * 16;
+  K_TRY(launch_jacobi<double>(R, l, LP, (double)l * 2.220446049250313e-16, 60, sigma, Uhat, (double*)nullptr,
+                              (double*)nullptr, nullptr, flags, reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
+}
+
+}  // extern "C"

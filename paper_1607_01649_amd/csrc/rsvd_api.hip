@@ -16,6 +16,7 @@ using namespace rsvd;
 
 namespace {
 
+constexpr int kRedGroup = 16;   // partials summed per first-level reduction group
 constexpr int kFlags = 64;   // device status words: [0] non-finite pivot, [1] dropped columns, [2] Jacobi not converged
 
 bool log_enabled() {
@@ -40,7 +41,7 @@ struct Layout {
   int64_t ldm, ldn;
   size_t es;   // element size of panels (8 for F64, 4 otherwise)
   int s_nn, s_tn, s_gm, s_gn;
-  size_t omega, Y, T, Q, Z, W, Bt, part, gpart, G, R1, R, rinv, rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p,
+  size_t omega, Y, T, Q, Z, W, Bt, part, gpart, gpart2, G, R1, R, rinv, rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p,
       scr_chol, scr_jac, flags, total;
 };
 
@@ -86,8 +87,8 @@ Layout make_layout(const rsvd_desc* d) {
   L.s_nn = pick_splits(((d->m + 127) / 128) * cg, d->n, 2048, 512);
   L.s_tn = pick_splits(((d->n + 255) / 256) * cg, d->m, 2048, 512);
   const int64_t gt = ((L.l + 127) / 128) * cg;
-  L.s_gm = pick_splits(gt, d->m, 1024, 256);
-  L.s_gn = pick_splits(gt, d->n, 1024, 256);
+  L.s_gm = pick_splits(gt, d->m, 512, 128);
+  L.s_gn = pick_splits(gt, d->n, 512, 128);
   L.s_nn = nn_splits_used(d->n, L.s_nn);
   L.s_tn = nn_splits_used(d->m, L.s_tn);
   L.s_gm = nn_splits_used(d->m, L.s_gm);
@@ -104,6 +105,7 @@ Layout make_layout(const rsvd_desc* d) {
   L.Bt = take(LP * L.ldn * L.es);
   L.part = take(std::max((size_t)L.s_nn * LP * L.ldm, (size_t)L.s_tn * LP * L.ldn) * L.es);
   L.gpart = take((size_t)std::max(L.s_gm, L.s_gn) * LP * LP * 8);
+  L.gpart2 = take((size_t)((std::max(L.s_gm, L.s_gn) + kRedGroup - 1) / kRedGroup) * LP * LP * 8);
   L.G = take(LP * LP * 8);
   L.R1 = take(LP * LP * 8);
   L.R = take(LP * LP * 8);
@@ -164,7 +166,8 @@ template <typename T> struct Path {
   rsvd_status gram(const T* X, int64_t ldx, int64_t rows, int splits, double* G) {
     double* gp = P.at<double>(L.gpart);
     HIP_TRY((launch_nn<T, T, double, double>(X, ldx, l, rows, X, ldx, l, gp, LP, (int64_t)LP * LP, splits, st)));
-    HIP_TRY((launch_reduce<double, double>(gp, splits, (int64_t)LP * LP, LP, l, l, G, LP, st)));
+    HIP_TRY(launch_reduce2<double>(gp, splits, kRedGroup, (int64_t)LP * LP, LP, l, l, P.at<double>(L.gpart2), G, LP,
+                                   st));
     return RSVD_OK;
   }
 
@@ -259,13 +262,14 @@ template <typename T> struct Path {
       double* Q1d = P.at<double>(L.Q1d);
       double* gp = P.at<double>(L.gpart);
       double* scr = P.at<double>(L.scr_chol);
+      double* gp2 = P.at<double>(L.gpart2);
       HIP_TRY((launch_nn<T, T, double, double>(Bt, L.ldn, l, n, Bt, L.ldn, l, gp, LP, (int64_t)LP * LP, L.s_gn, st)));
-      HIP_TRY((launch_reduce<double, double>(gp, L.s_gn, (int64_t)LP * LP, LP, l, l, G, LP, st)));
+      HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LP * LP, LP, l, l, gp2, G, LP, st));
       HIP_TRY(launch_chol<double>(G, LP, l, LP, tau, rinv_d, R1, nullptr, scr, flags, st));
       HIP_TRY((launch_tn<T, double, double, double>(Bt, L.ldn, l, n, rinv_d, LP, l, Q1d, L.ldn, 0, 1, false, st)));
       HIP_TRY((launch_nn<double, double, double, double>(Q1d, L.ldn, l, n, Q1d, L.ldn, l, gp, LP, (int64_t)LP * LP,
                                                          L.s_gn, st)));
-      HIP_TRY((launch_reduce<double, double>(gp, L.s_gn, (int64_t)LP * LP, LP, l, l, G, LP, st)));
+      HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LP * LP, LP, l, l, gp2, G, LP, st));
       HIP_TRY(launch_chol<double>(G, LP, l, LP, tau, rinv_d, R, R1, scr, flags, st));
       const double tol = (double)l * 2.220446049250313e-16;
       HIP_TRY(launch_jacobi<T>(R, l, LP, tol, 60, P.at<double>(L.sigma), P.at<double>(L.uhat_d), P.at<T>(L.uhat_p),

@@ -39,9 +39,10 @@ def max_rel_sigma(s_gpu, s_ref, k):
 
 
 def subspace_sin(Ua, Ub):
-    """sine of the largest principal angle between span(Ua) and span(Ub)."""
-    c = np.linalg.svd(Ua.T @ Ub, compute_uv=False)
-    return float(math.sqrt(max(0.0, 1.0 - float(np.min(c)) ** 2)))
+    """sine of the largest principal angle between span(Ua) and span(Ub)
+    (orthonormal columns), computed as ||(I - Ua Ua^T) Ub||_2, which stays
+    accurate for tiny angles."""
+    return float(np.linalg.norm(Ub - Ua @ (Ua.T @ Ub), 2))
 
 
 def column_errors(Xa, Xb):

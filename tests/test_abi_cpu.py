@@ -8,11 +8,11 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rsvd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("rsvd.h", "rsvd_kernels.h")]
 
 
 def _declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"\b(rsvd_[a-z0-9_]+)\s*\(", text)
     return sorted(set(names))

@@ -1,0 +1,168 @@
+"""Per-kernel parity of the HIP building blocks (include/rsvd_kernels.h)
+against CPU references.
+
+Products on small-integer data are exact in every precision (all partial sums
+stay below 2^24), so those comparisons are bit for bit.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import device
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_1607_01649_amd import _lib
+    return _lib.lib()
+
+
+def _t(x, dt):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device(), dt)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+PREC = {"f64": 0, "f32": 1, "f32acc64": 10}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32acc64"])
+@pytest.mark.parametrize("rows,K,ncols,lda_pad", [(128, 64, 16, 0), (300, 517, 30, 0), (77, 1000, 110, 4),
+                                                  (1000, 129, 128, 0), (33, 70, 7, 1), (513, 2048, 200, 0)])
+def test_product_nn_is_exact_on_integers(prec, rows, K, ncols, lda_pad):
+    import torch
+    rng = np.random.default_rng(rows + K)
+    A = rng.integers(-3, 4, size=(rows, K + lda_pad)).astype(np.float64)
+    X = rng.integers(-3, 4, size=(K, ncols)).astype(np.float64)
+    ref = A[:, :K] @ X
+    tin = torch.float64 if prec == "f64" else torch.float32
+    tout = torch.float32 if prec == "f32" else torch.float64
+    dA = _t(A, tin)
+    ldx = K + 5
+    Xp = np.zeros((ncols, ldx))
+    Xp[:, :K] = X.T
+    dX = _t(Xp, tin)
+    ldo = rows + 3
+    out = torch.full((ncols, ldo), -7.0, dtype=tout, device=device())
+    st = _lib().rsvd_k_product_nn(PREC[prec], rows, K, _p(dA), K + lda_pad, _p(dX), ldx, ncols, _p(out), ldo, None)
+    assert st == 0
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[:, :rows], ref.T)
+    assert np.all(got[:, rows:] == -7.0)     # nothing written past the panel rows
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("K,N,ncols,rowmajor", [(64, 256, 16, 0), (517, 300, 30, 0), (1000, 77, 110, 1),
+                                                (30, 1000, 30, 0), (129, 513, 200, 1), (2048, 260, 9, 0)])
+def test_product_tn_is_exact_on_integers(prec, K, N, ncols, rowmajor):
+    import torch
+    rng = np.random.default_rng(K * 3 + N)
+    A = rng.integers(-3, 4, size=(K, N)).astype(np.float64)
+    P = rng.integers(-3, 4, size=(K, ncols)).astype(np.float64)
+    ref = A.T @ P
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    dA = _t(A, tdt)
+    ldp = K + 2
+    Pp = np.zeros((ncols, ldp))
+    Pp[:, :K] = P.T
+    dP = _t(Pp, tdt)
+    if rowmajor:
+        ldo = ncols + 3
+        out = torch.full((N, ldo), -7.0, dtype=tdt, device=device())
+    else:
+        ldo = N + 3
+        out = torch.full((ncols, ldo), -7.0, dtype=tdt, device=device())
+    st = _lib().rsvd_k_product_tn(PREC[prec], K, N, _p(dA), N, _p(dP), ldp, ncols, _p(out), ldo, rowmajor, None)
+    assert st == 0
+    got = out.cpu().numpy().astype(np.float64)
+    if rowmajor:
+        assert np.array_equal(got[:, :ncols], ref)
+        assert np.all(got[:, ncols:] == -7.0)
+    else:
+        assert np.array_equal(got[:, :N], ref.T)
+        assert np.all(got[:, N:] == -7.0)
+
+
+@pytest.mark.parametrize("l", [1, 5, 16, 30, 110, 128])
+def test_cholesky_and_inverse(l):
+    import torch
+    rng = np.random.default_rng(l)
+    Y = rng.standard_normal((3 * l + 5, l)) @ np.diag(np.logspace(0, -3, l))
+    G = Y.T @ Y
+    LP = (l + 15) // 16 * 16
+    dG = _t(G.T, torch.float64)                 # column-major
+    Rinv = torch.zeros(LP * LP, dtype=torch.float64, device=device())
+    R = torch.zeros(LP * LP, dtype=torch.float64, device=device())
+    flags = torch.zeros(4, dtype=torch.int32, device=device())
+    st = _lib().rsvd_k_cholesky(l, _p(dG), l, 0.0, _p(Rinv), _p(R), _p(flags), None)
+    assert st == 0
+    R = R.cpu().numpy().reshape(LP, LP)
+    Ri = Rinv.cpu().numpy().reshape(LP, LP).T     # Ri[k, c] = R^-1(k, c)
+    assert flags.cpu().numpy()[:2].tolist() == [0, 0]
+    Rl = R[:l, :l]
+    assert np.allclose(np.tril(Rl, -1), 0) and np.all(np.diag(Rl) > 0)
+    ref = np.linalg.cholesky(G).T
+    assert np.allclose(Rl, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    assert np.allclose(Ri[:l, :l] @ Rl, np.eye(l), atol=1e-9)
+    assert np.array_equal(R[l:, l:], np.eye(LP - l)) and np.array_equal(Ri[l:, l:], np.eye(LP - l))
+
+
+def test_cholesky_drops_dependent_columns():
+    import torch
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((50, 6))
+    Y[:, 3] = Y[:, 0] - 2 * Y[:, 1]          # exactly dependent column
+    G = Y.T @ Y
+    dG = _t(G.T, torch.float64)
+    Rinv = torch.zeros(256, dtype=torch.float64, device=device())
+    R = torch.zeros(256, dtype=torch.float64, device=device())
+    flags = torch.zeros(4, dtype=torch.int32, device=device())
+    # the eliminated pivot of the dependent column is rounding noise, ~u * G_jj
+    assert _lib().rsvd_k_cholesky(6, _p(dG), 6, 1e-10, _p(Rinv), _p(R), _p(flags), None) == 0
+    assert flags.cpu().numpy()[1] == 1
+    Ri = Rinv.cpu().numpy().reshape(16, 16).T[:6, :6]
+    Q = Y @ Ri
+    assert np.allclose(Q[:, 3], 0)
+    keep = [0, 1, 2, 4, 5]
+    assert np.allclose(Q[:, keep].T @ Q[:, keep], np.eye(5), atol=1e-10)
+
+
+@pytest.mark.parametrize("l", [1, 2, 7, 30, 110, 128])
+def test_small_svd_matches_lapack(l):
+    """R is the triangular factor of a matrix with singular values
+    logspace(0, -6, l), so sigma(R^T) is known; LAPACK's SVD is the reference
+    for the vectors (absolute accuracy ~ u * sigma_1)."""
+    import torch
+    from workloads import gen
+    s0 = np.logspace(0, -6, l)
+    M = (gen.orthonormal_factor(l + 7, l, 100 + l, 1) * s0) @ gen.orthonormal_factor(l, l, 100 + l, 2).T
+    R = np.linalg.qr(M, mode="r")
+    LP = (l + 15) // 16 * 16
+    Rp = np.eye(LP)
+    Rp[:l, :l] = R
+    dR = _t(Rp, torch.float64)
+    sig = torch.zeros(LP, dtype=torch.float64, device=device())
+    Uh = torch.zeros(LP * LP, dtype=torch.float64, device=device())
+    flags = torch.zeros(4, dtype=torch.int32, device=device())
+    assert _lib().rsvd_k_small_svd(l, _p(dR), _p(sig), _p(Uh), _p(flags), None) == 0
+    s = sig.cpu().numpy()
+    Uh = Uh.cpu().numpy().reshape(LP, LP).T[:l, :l]     # column j of U_hat
+    assert np.all(np.abs(s[:l] - s0) <= 1e-13 + 1e-11 * s0)
+    assert np.all(s[l:] == 0)
+    X = R.T
+    W = Uh.T @ X
+    assert np.linalg.norm(W @ W.T - np.diag(s[:l] ** 2)) <= 1e-14 * l
+    assert np.linalg.norm(Uh.T @ Uh - np.eye(l)) <= 1e-12
+    ref_u, ref_s, _ = np.linalg.svd(X)
+    for j in range(l):
+        i = np.argmax(np.abs(Uh[:, j]))
+        assert Uh[i, j] > 0
+        sgn = np.sign(ref_u[np.argmax(np.abs(ref_u[:, j])), j])
+        gap = min([abs(s0[j] - s0[i2]) for i2 in range(l) if i2 != j] + [1.0])
+        assert np.linalg.norm(Uh[:, j] - sgn * ref_u[:, j]) <= 1e-13 / gap
+    assert flags.cpu().numpy()[2] == 0
