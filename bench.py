@@ -71,14 +71,73 @@ def cpu_baseline(A_gpu, k, p, q, rows, seed):
                       f"same n, k, p, q; {dt:.1f} s; flops counted as 2*rows*n*l*(2q+2)"}
 
 
+def run_path(A, cfg, sketch, proj, steps, warmup, seed):
+    """Time `steps` factorisations with the given operand precisions; returns
+    the measurements and the last factors."""
+    import torch
+    from paper_1607_01649_amd import RSVD, RSVD_TIMING
+    m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
+    l = k + p
+    solver = RSVD(m, n, k, p, q, dtype=cfg.dtype, device=A.device, seed=seed, flags=RSVD_TIMING,
+                  sketch_dtype=sketch, proj_dtype=proj)
+    for _ in range(warmup):
+        U, S, V, info = solver(A)
+    torch.cuda.synchronize()
+    nn_ms = tn_ms = 0.0
+    nn_n = tn_n = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        U, S, V, info = solver(A)
+        nn_ms += info.nn_ms
+        tn_ms += info.tn_ms
+        nn_n += info.nn_launches
+        tn_n += info.tn_launches
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    if info.status != 0:
+        raise SystemExit(f"rsvd_factor status {info.status}")
+    flops_pass = 2.0 * m * n * l
+    passes = 2 * q + 2
+    avg_nn = nn_ms / max(nn_n, 1) * 1e-3
+    avg_tn = tn_ms / max(tn_n, 1) * 1e-3
+    names = {"f32": ("nn_kernel (Y = A X, FP32 MFMA)", "tn_kernel (Z = A^T Q, FP32 MFMA)"),
+             "bf16": ("nn_bf16_kernel (Y = bf16(A) X)", "nn_bf16_kernel (Z = bf16(A)^T Q)")}[sketch]
+    dom_nn = nn_ms >= tn_ms
+    avg = avg_nn if dom_nn else avg_tn
+    if sketch == "f32":
+        achieved = flops_pass / avg / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": MI355X_PEAK["f32"], "unit": "TFLOP/s",
+                "frac": achieved / MI355X_PEAK["f32"]}
+    else:
+        # bf16 at l = 110 is below the ridge point (2 l flop per 2-byte element of A): HBM-bound
+        bytes_launch = m * n * 2 + (m + n) * l * 4
+        achieved = bytes_launch / avg / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_launch,
+                "achieved_tflops": flops_pass / avg / 1e12}
+    roof.update({"traffic": None, "kernel": names[0] if dom_nn else names[1], "avg_launch_ms": avg * 1e3,
+                 "launches_per_step": (nn_n + tn_n) / steps,
+                 "other_kernel": {"name": names[1] if dom_nn else names[0],
+                                  "avg_launch_ms": (avg_tn if dom_nn else avg_nn) * 1e3,
+                                  "achieved_tflops": flops_pass / (avg_tn if dom_nn else avg_nn) / 1e12}})
+    sig = cfg.sigma()
+    eps_abs = 1.15 * sig[k]
+    err = spectral_residual(A, U, S, V)
+    tte = {"eps": "1.15*sigma_{k+1}", "eps_abs": eps_abs, "achieved_err": err, "reached": bool(err <= eps_abs),
+           "time_ms": dt * 1e3 if err <= eps_abs else None}
+    return {"sketch_dtype": sketch, "proj_dtype": proj, "ms_per_step": dt * 1e3,
+            "tflops": flops_pass * passes / dt / 1e12, "stage_ms": [round(x, 4) for x in info.stage_ms],
+            "jacobi_sweeps": info.jacobi_sweeps, "time_to_eps": tte, "roofline": roof}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="slowdecay_50000x20000")
-    ap.add_argument("--sketch", default="f32", choices=["f32"])
-    ap.add_argument("--cpu-rows", type=int, default=2500)
+    ap.add_argument("--paths", default="bf16,f32", help="comma list; the first one is the headline")
+    ap.add_argument("--cpu-rows", type=int, default=20000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
     args = ap.parse_args()
@@ -87,7 +146,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1607_01649_amd import RSVD, RSVD_TIMING
     from workloads import gen
 
     dev = torch.device("cuda:0")
@@ -95,60 +153,19 @@ def main():
     A = cfg.matrix(seed=args.seed, device=str(dev))
     A = A.to(torch.float32) if cfg.dtype == "f32" else A
     torch.cuda.synchronize()
-    m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
-    l = k + p
-    solver = RSVD(m, n, k, p, q, dtype=cfg.dtype, device=dev, seed=args.seed, flags=RSVD_TIMING)
-
-    for _ in range(args.warmup):
-        U, S, V, info = solver(A)
-    torch.cuda.synchronize()
-    nn_ms = tn_ms = 0.0
-    nn_n = tn_n = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        U, S, V, info = solver(A)
-        nn_ms += info.nn_ms
-        tn_ms += info.tn_ms
-        nn_n += info.nn_launches
-        tn_n += info.tn_launches
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    if info.status != 0:
-        raise SystemExit(f"rsvd_factor status {info.status}")
-
-    flops_pass = 2.0 * m * n * l
-    passes = 2 * q + 2
-    tflops = flops_pass * passes / dt / 1e12
-    avg_nn = nn_ms / max(nn_n, 1) * 1e-3
-    avg_tn = tn_ms / max(tn_n, 1) * 1e-3
-    dom_nn = nn_ms >= tn_ms
-    avg = avg_nn if dom_nn else avg_tn
-    peak = MI355X_PEAK[args.sketch]
-    achieved = flops_pass / avg / 1e12
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": "nn_kernel (Y = A X)" if dom_nn else "tn_kernel (Z = A^T Q)",
-                "avg_launch_ms": avg * 1e3,
-                "other_kernel": {"name": "tn_kernel (Z = A^T Q)" if dom_nn else "nn_kernel (Y = A X)",
-                                 "avg_launch_ms": (avg_tn if dom_nn else avg_nn) * 1e3,
-                                 "achieved_tflops": flops_pass / (avg_tn if dom_nn else avg_nn) / 1e12},
-                "hbm_gbs_of_A_read": (m * n * 4) / avg / 1e9}
-
-    # time-to-eps: untimed check that the timed factorisation reaches eps = 1.15 sigma_{k+1}
-    sig = cfg.sigma()
-    eps_abs = 1.15 * sig[k]
-    err = spectral_residual(A, U, S, V)
-    tte = {"eps": "1.15*sigma_{k+1}", "eps_abs": eps_abs, "achieved_err": err, "reached": bool(err <= eps_abs),
-           "time_ms": dt * 1e3 if err <= eps_abs else None}
-
-    out = {"metric": METRIC, "value": tflops, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": args.sketch, "data": "synthetic",
-           "config": {"workload": args.workload, "m": m, "n": n, "k": k, "p": p, "q": q,
-                      "sketch_dtype": args.sketch, "proj_dtype": args.sketch, "a_dtype": cfg.dtype},
-           "stage_ms": [round(x, 4) for x in info.stage_ms],
-           "time_to_eps": tte, "roofline": roofline}
+    paths = [p for p in args.paths.split(",") if p]
+    res = {}
+    for pth in paths:
+        res[pth] = run_path(A, cfg, pth, pth, args.steps, args.warmup, args.seed)
+    head = res[paths[0]]
+    out = {"metric": METRIC, "value": head["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": paths[0], "data": "synthetic",
+           "config": {"workload": args.workload, "m": cfg.m, "n": cfg.n, "k": cfg.k, "p": cfg.p, "q": cfg.q,
+                      "sketch_dtype": paths[0], "proj_dtype": paths[0], "a_dtype": cfg.dtype},
+           "time_to_eps": head["time_to_eps"], "roofline": head["roofline"], "paths": res}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(A, k, p, q, args.cpu_rows, args.seed)
+        out["cpu_baseline"] = cpu_baseline(A, cfg.k, cfg.p, cfg.q, args.cpu_rows, args.seed)
     print(json.dumps(out), flush=True)
 
 

@@ -115,6 +115,8 @@ typedef struct {
   float nn_ms, tn_ms;      /* with RSVD_TIMING: summed durations of the products A*X
                               and A^T*X (HIP events around each launch)              */
   int32_t nn_launches, tn_launches;
+  int32_t jacobi_sweeps;   /* sweeps of the small SVD                                 */
+  int32_t dropped_cols;    /* numerically dependent columns met by CholeskyQR          */
 } rsvd_info;
 
 typedef struct rsvd_plan_s* rsvd_plan_t;

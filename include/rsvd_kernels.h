@@ -71,6 +71,27 @@ rsvd_status rsvd_k_cholesky(int32_t l, const double* d_G, int64_t ldg, double ta
 rsvd_status rsvd_k_small_svd(int32_t l, const double* d_R, double* d_sigma, double* d_Uhat, int32_t* d_flags,
                              void* stream);
 
+/*
+ * Input preparation for the bf16 products: d_A16 (m x ld16 row-major bf16,
+ * stored as uint16) = round-to-nearest-even bf16 of A (m x n FP32, lda >= n),
+ * and d_A16T (n x ldT) = its transpose; columns past n (resp. m) are zero.
+ * ld16 >= n and ldT >= m must be multiples of 128.  *d_flag (device int) gets
+ * bit 0 set if A holds a NaN or an infinity.
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_convert_bf16(int64_t m, int64_t n, const float* d_A, int64_t lda, uint16_t* d_A16, int64_t ld16,
+                                uint16_t* d_A16T, int64_t ldT, int32_t* d_flag, void* stream);
+
+/*
+ * d_out (panel, ldo >= rows, FP32) = A16 X for A16 rows x K bf16 as written by
+ * rsvd_k_convert_bf16 (lda a multiple of 128, zero past K) and X a K x ncols
+ * FP32 panel (ldx >= K, a multiple of 4) rounded to bf16 on load; bf16 MFMA
+ * with FP32 accumulation.  1 <= ncols <= 1024.
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_product_bf16(int64_t rows, int64_t K, const uint16_t* d_A16, int64_t lda, const float* d_X,
+                                int64_t ldx, int32_t ncols, float* d_out, int64_t ldo, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,7 @@ class rsvd_info(ctypes.Structure):
         ("stage_ms", ctypes.c_float * 8),
         ("nn_ms", ctypes.c_float), ("tn_ms", ctypes.c_float),
         ("nn_launches", ctypes.c_int32), ("tn_launches", ctypes.c_int32),
+        ("jacobi_sweeps", ctypes.c_int32), ("dropped_cols", ctypes.c_int32),
     ]
 
 
@@ -77,6 +78,10 @@ SIGNATURES = [
     ("rsvd_k_cholesky", ctypes.c_int, [ctypes.c_int32, _c_void_p, _i64, ctypes.c_double, _c_void_p, _c_void_p,
                                        _c_void_p, _c_void_p]),
     ("rsvd_k_small_svd", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    ("rsvd_k_convert_bf16", ctypes.c_int, [_i64, _i64, _c_void_p, _i64, _c_void_p, _i64, _c_void_p, _i64, _c_void_p,
+                                           _c_void_p]),
+    ("rsvd_k_product_bf16", ctypes.c_int, [_i64, _i64, _c_void_p, _i64, _c_void_p, _i64, ctypes.c_int32, _c_void_p,
+                                           _i64, _c_void_p]),
 ]
 
 RSVD_F32_ACC64 = 10

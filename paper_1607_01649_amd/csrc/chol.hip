@@ -14,10 +14,9 @@
 // with d_j = U(j, j), so step j reads row j and writes only rows below it:
 // one barrier per step.  At the end R = D^-1/2 U and R^-T = D^-1/2 T.
 //
-// Storage: one LP x LP FP64 array M (LDS when LP <= 128, else global
+// Storage: one LP x LP FP64 array (registers for l <= 128, else global
 // scratch): the upper triangle including the diagonal holds U, the strict
-// lower triangle holds T (whose unit diagonal is implicit).  Each thread owns
-// the entries idx = tid + 1024 u of the l x l block.
+// lower triangle holds T (whose unit diagonal is implicit).
 //
 // Numerically dependent columns (pivot <= tau_rel * G_jj) are dropped: they
 // take no part in later eliminations, row j of R and column j of R^-1 come out
@@ -28,21 +27,138 @@
 namespace rsvd {
 
 constexpr int kCholThreads = 1024;
-constexpr int kCholOwn = 16;   // entries per thread kept in registers when l <= 128
 
-template <typename TQ, bool USE_LDS>
+// l <= 128: thread t owns the 4 x 4 register blocks U[4][4] and T[4][4] of
+// rows 4*(t/32)..+3 and columns 4*(t%32)..+3.  U starts as G's upper
+// triangle, T as the identity.  Step j, branch-free on the block:
+//     U(a, b) -= f_a U(j, b)   for a > j, b > j      (f_a = U(j, a) / d_j)
+//     T(a, b) -= f_a T(j, b)   for a > j (T(j, b) = 0 for b > j)
+// using the masked vectors f (zero for a <= j) and U(j, b) (zero for b <= j).
+// The owners of row j+1 publish U(j+1, :) and T(j+1, :) to LDS before the
+// step's barrier (double-buffered); threads whose rows are all <= j skip.
+template <typename TQ>
+__global__ __launch_bounds__(kCholThreads) void chol_reg_kernel(const double* __restrict__ g, int64_t ldg, int l,
+                                                                 int LP, double tau_rel, TQ* __restrict__ rinv_p,
+                                                                 double* __restrict__ r_out,
+                                                                 const double* __restrict__ r_prev,
+                                                                 int* __restrict__ flags) {
+  __shared__ double urow[2][128];
+  __shared__ double trow[2][128];
+  __shared__ double gdiag[128];
+  __shared__ double rsd[128];     // 1/sqrt(d_j), 0 for a dropped column
+  extern __shared__ double Ufull[];   // LP x LP, filled at the end when r_out is wanted
+  const int tid = threadIdx.x;
+  const int a0 = 4 * (tid >> 5), b0 = 4 * (tid & 31);
+  double U[4][4], T[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int a = a0 + i, b = b0 + k;
+      U[i][k] = (a < l && b < l && a <= b) ? g[(int64_t)b * ldg + a] : 0.0;
+      T[i][k] = (a == b) ? 1.0 : 0.0;
+      if (a == b && a < l) gdiag[a] = U[i][k];
+    }
+  if (a0 == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { urow[0][b0 + k] = U[0][k]; trow[0][b0 + k] = T[0][k]; }
+  }
+  __syncthreads();
+
+  int bad = 0, dropped = 0;
+  for (int j = 0; j < l; ++j) {
+    const double* uj = urow[j & 1];
+    const double* tj = trow[j & 1];
+    const double d = uj[j];
+    const double gd = gdiag[j];
+    const bool nonfinite = !isfinite(d) || !isfinite(gd);
+    const bool drop = nonfinite || !(d > tau_rel * gd) || !(d > 0.0);
+    bad += nonfinite;
+    dropped += (drop && !nonfinite);
+    if (!drop && a0 + 3 > j) {
+      const double invd = 1.0 / d;
+      double f[4], ub[4], tb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) f[i] = (a0 + i > j) ? uj[a0 + i] * invd : 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ub[k] = (b0 + k > j) ? uj[b0 + k] : 0.0;
+        tb[k] = tj[b0 + k];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          U[i][k] -= f[i] * ub[k];
+          T[i][k] -= f[i] * tb[k];
+        }
+    }
+    if (tid == 0) rsd[j] = drop ? 0.0 : 1.0 / sqrt(d);
+    // (static row index: a runtime index into U/T would move them to scratch)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (a0 + i == j + 1 && j + 1 < l) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          urow[(j + 1) & 1][b0 + k] = U[i][k];
+          trow[(j + 1) & 1][b0 + k] = T[i][k];
+        }
+      }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (bad) atomicAdd(&flags[0], bad);
+    if (dropped) atomicAdd(&flags[1], dropped);
+  }
+  // R^-1 in panel layout: rinv_p[c*LP + k] = R^-T(c, k) = T(c, k) / sqrt(d_c); identity on padding.
+  if (a0 < LP && b0 < LP) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        int c = a0 + i, kk = b0 + k;
+        double v;
+        if (c >= l || kk >= l) v = (c == kk) ? 1.0 : 0.0;
+        else v = (kk <= c) ? T[i][k] * rsd[c] : 0.0;
+        rinv_p[c * LP + kk] = static_cast<TQ>(v);
+      }
+  }
+  if (r_out) {
+    if (a0 < LP && b0 < LP) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Ufull[(a0 + i) * LP + b0 + k] = U[i][k];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < LP * LP; idx += kCholThreads) {
+      int a = idx / LP, b = idx - (idx / LP) * LP;
+      double v;
+      if (a >= l || b >= l) v = (a == b) ? 1.0 : 0.0;
+      else if (b < a || rsd[a] == 0.0) v = 0.0;
+      else if (!r_prev) v = Ufull[a * LP + b] * rsd[a];
+      else {
+        v = 0.0;
+        for (int k = a; k <= b; ++k) v += Ufull[a * LP + k] * r_prev[k * LP + b];
+        v *= rsd[a];
+      }
+      r_out[idx] = v;
+    }
+  }
+}
+
+// General l (up to 1024): the array lives in global scratch; every thread
+// loops over its entries idx = tid + 1024 u.  Same elimination as above.
+template <typename TQ>
 __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __restrict__ g, int64_t ldg, int l, int LP,
                                                              double tau_rel, TQ* __restrict__ rinv_p,
                                                              double* __restrict__ r_out,
                                                              const double* __restrict__ r_prev,
-                                                             double* __restrict__ scratch, int* __restrict__ flags) {
-  extern __shared__ double smem[];
-  double* M = USE_LDS ? smem : scratch;
-  __shared__ double gdiag[1024];   // original diagonal of G
-  __shared__ double rsd[1024];     // 1/sqrt(d_j), 0 for a dropped column
+                                                             double* __restrict__ M, int* __restrict__ flags) {
+  __shared__ double gdiag[1024];
+  __shared__ double rsd[1024];
   const int tid = threadIdx.x;
   const int ll = l * l;
-
   for (int idx = tid; idx < ll; idx += kCholThreads) {
     int a = idx / l, b = idx - (idx / l) * l;
     double v = (a <= b) ? g[(int64_t)b * ldg + a] : 0.0;
@@ -50,18 +166,6 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     if (a == b) gdiag[a] = v;
   }
   __syncthreads();
-
-  int own_a[kCholOwn], own_b[kCholOwn];
-  const int nown = USE_LDS ? (ll - tid + kCholThreads - 1) / kCholThreads : 0;
-  if (USE_LDS) {
-#pragma unroll
-    for (int u = 0; u < kCholOwn; ++u) {
-      int idx = tid + kCholThreads * u;
-      own_a[u] = idx < ll ? idx / l : -1;
-      own_b[u] = idx < ll ? idx - (idx / l) * l : 0;
-    }
-  }
-
   int bad = 0, dropped = 0;
   for (int j = 0; j < l; ++j) {
     const double d = M[j * LP + j];
@@ -72,26 +176,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     dropped += (drop && !nonfinite);
     if (!drop) {
       const double invd = 1.0 / d;
-      if (USE_LDS) {
-#pragma unroll
-        for (int u = 0; u < kCholOwn; ++u) {
-          if (u >= nown) break;
-          int a = own_a[u], b = own_b[u];
-          if (a <= j) continue;
-          double f = M[j * LP + a] * invd;
-          if (b >= a) M[a * LP + b] -= f * M[j * LP + b];
-          else if (b < j) M[a * LP + b] -= f * M[j * LP + b];
-          else if (b == j) M[a * LP + b] = -f;
-        }
-      } else {
-        for (int idx = tid; idx < ll; idx += kCholThreads) {
-          int a = idx / l, b = idx - (idx / l) * l;
-          if (a <= j) continue;
-          double f = M[j * LP + a] * invd;
-          if (b >= a) M[a * LP + b] -= f * M[j * LP + b];
-          else if (b < j) M[a * LP + b] -= f * M[j * LP + b];
-          else if (b == j) M[a * LP + b] = -f;
-        }
+      for (int idx = tid; idx < ll; idx += kCholThreads) {
+        int a = idx / l, b = idx - (idx / l) * l;
+        if (a <= j) continue;
+        double f = M[j * LP + a] * invd;
+        if (b >= a) M[a * LP + b] -= f * M[j * LP + b];
+        else if (b < j) M[a * LP + b] -= f * M[j * LP + b];
+        else if (b == j) M[a * LP + b] = -f;
       }
     }
     if (tid == j % kCholThreads) rsd[j] = drop ? 0.0 : 1.0 / sqrt(d);
@@ -101,8 +192,6 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     if (bad) atomicAdd(&flags[0], bad);
     if (dropped) atomicAdd(&flags[1], dropped);
   }
-
-  // R^-1 in panel layout: rinv_p[c*LP + k] = R^-1(k, c) = R^-T(c, k) = T(c, k) / sqrt(d_c).
   for (int idx = tid; idx < LP * LP; idx += kCholThreads) {
     int c = idx / LP, k = idx - (idx / LP) * LP;
     double v;
@@ -113,7 +202,6 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     rinv_p[idx] = static_cast<TQ>(v);
   }
   if (r_out) {
-    // R(a, b) = U(a, b) / sqrt(d_a); optionally times r_prev (both upper triangular).
     for (int idx = tid; idx < LP * LP; idx += kCholThreads) {
       int a = idx / LP, b = idx - (idx / LP) * LP;
       double v;
@@ -135,19 +223,20 @@ hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_r
                        const double* r_prev, double* scratch, int* flags, hipStream_t s) {
   if (l < 1 || l > 1024) return hipErrorInvalidValue;
   if (LP <= 128) {
-    size_t sh = (size_t)LP * LP * sizeof(double);
     static bool attr_set = false;
     if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_kernel<TQ, true>),
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_reg_kernel<TQ>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
       if (e != hipSuccess) return e;
       attr_set = true;
     }
-    hipLaunchKernelGGL((chol_kernel<TQ, true>), dim3(1), dim3(kCholThreads), sh, s, g, ldg, l, LP, tau_rel, rinv_p,
-                       r_out, r_prev, scratch, flags);
+    size_t sh = r_out ? (size_t)LP * LP * sizeof(double) : 0;
+    hipLaunchKernelGGL((chol_reg_kernel<TQ>), dim3(1), dim3(kCholThreads), sh, s, g, ldg, l, LP, tau_rel, rinv_p,
+                       r_out, r_prev, flags);
   } else {
-    hipLaunchKernelGGL((chol_kernel<TQ, false>), dim3(1), dim3(kCholThreads), 0, s, g, ldg, l, LP, tau_rel, rinv_p,
-                       r_out, r_prev, scratch, flags);
+    if (!scratch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((chol_kernel<TQ>), dim3(1), dim3(kCholThreads), 0, s, g, ldg, l, LP, tau_rel, rinv_p, r_out,
+                       r_prev, scratch, flags);
   }
   return hipGetLastError();
 }

@@ -351,9 +351,6 @@ template hipError_t launch_tn<double, double, double, double>(const double*, int
 template hipError_t launch_tn<float, double, double, double>(const float*, int64_t, int64_t, int64_t,
                                                              const double*, int64_t, int, double*, int64_t,
                                                              int64_t, int, bool, hipStream_t);
-template hipError_t launch_tn<double, double, double, float>(const double*, int64_t, int64_t, int64_t,
-                                                             const double*, int64_t, int, float*, int64_t, int64_t,
-                                                             int, bool, hipStream_t);
 template hipError_t launch_reduce<float, float>(const float*, int, int64_t, int64_t, int64_t, int, float*, int64_t,
                                                 hipStream_t);
 template hipError_t launch_reduce<double, double>(const double*, int, int64_t, int64_t, int64_t, int, double*,

@@ -41,6 +41,14 @@ template <typename TU>
 hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma, double* uhat_d,
                          TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s);
 
+// lowp.hip -- bf16 copies of A (row-major and transposed, RNE, zero-padded to
+// multiples of 128 columns) and the bf16 MFMA product with an FP32 panel.
+hipError_t launch_to_bf16(const float* A, int64_t lda, int64_t m, int64_t n, uint16_t* A16, int64_t ld16,
+                          uint16_t* A16T, int64_t ldT, int* flag, hipStream_t s);
+hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t rows, int64_t K, const float* X, int64_t ldx,
+                          int ncols, float* out, int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
+int lp_splits_used(int64_t K, int splits);
+
 // misc.hip
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 template <typename TO>

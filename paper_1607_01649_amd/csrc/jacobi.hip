@@ -10,7 +10,7 @@
 // lift kernel.
 //
 // Pairs are visited in round-robin ("circle method") order: each round holds
-// floor(l/2) disjoint pairs, processed in parallel by groups of 16 lanes (64
+// floor(l/2) disjoint pairs, processed in parallel by groups of 8 lanes (128
 // pairs at once in a 1024-thread block); l-1 (or l) rounds make a sweep.  Sweeps repeat until no pair needs a
 // rotation (|x_p . x_q| <= tol * ||x_p|| ||x_q||).  Results are sorted by
 // descending sigma and each u_hat column is signed so that its entry of
@@ -23,10 +23,14 @@ __device__ __forceinline__ int rr_player(int pos, int round, int le) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (le - 1);
 }
 
-// Reduction over the 16 lanes of a pair group (lanes 16*s .. 16*s+15).
-__device__ __forceinline__ double group16_sum(double v) {
+// Lanes per column pair.  The kernel is VALU-bound on one CU, so packing
+// several pairs into each wave (fewer waves per round) is what pays.
+constexpr int kPairLanes = 8;
+
+// Reduction over the lanes of one pair group.
+__device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+  for (int o = kPairLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kPairLanes);
   return v;
 }
 
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
   __shared__ int rotated;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
-  const int slot = tid >> 4, sub = tid & 15, nslots = nt >> 4;   // 16 lanes per column pair
+  const int slot = tid / kPairLanes, sub = tid % kPairLanes, nslots = nt / kPairLanes;
 
   for (int idx = tid; idx < l * l; idx += nt) {
     int p = idx / l, i = idx - (idx / l) * l;
@@ -60,21 +64,21 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     for (int round = 0; round < le - 1; ++round) {
       for (int pi = slot; pi < npairs; pi += nslots) {
         int p = rr_player(pi, round, le), q = rr_player(le - 1 - pi, round, le);
-        if (p >= l || q >= l) continue;   // uniform within the 16-lane group
+        if (p >= l || q >= l) continue;   // uniform within the pair group
         double* xp = xs + p * LP;
         double* xq = xs + q * LP;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = sub; i < l; i += 16) {
+        for (int i = sub; i < l; i += kPairLanes) {
           double a = xp[i], b = xq[i];
           al += a * a; be += b * b; ga += a * b;
         }
-        al = group16_sum(al); be = group16_sum(be); ga = group16_sum(ga);
+        al = group_sum(al); be = group_sum(be); ga = group_sum(ga);
         if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
           double zeta = (be - al) / (2.0 * ga);
           double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double c = 1.0 / sqrt(1.0 + t * t);
           double s = c * t;
-          for (int i = sub; i < l; i += 16) {
+          for (int i = sub; i < l; i += kPairLanes) {
             double a = xp[i], b = xq[i];
             xp[i] = c * a - s * b;
             xq[i] = s * a + c * b;
@@ -86,7 +90,10 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
     }
     converged = (rotated == 0);
   }
-  if (tid == 0 && !converged) atomicAdd(&flags[2], 1);
+  if (tid == 0) {
+    if (!converged) atomicAdd(&flags[2], 1);
+    atomicMax(&flags[3], sweep);
+  }
   __syncthreads();
 
   for (int p = w; p < l; p += nw) {

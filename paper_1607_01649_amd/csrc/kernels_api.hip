@@ -67,4 +67,21 @@ rsvd_status rsvd_k_small_svd(int32_t l, const double* R, double* sigma, double* 
   return RSVD_OK;
 }
 
+rsvd_status rsvd_k_convert_bf16(int64_t m, int64_t n, const float* A, int64_t lda, uint16_t* A16, int64_t ld16,
+                                uint16_t* A16T, int64_t ldT, int32_t* flag, void* stream) {
+  if (!A || !A16 || !A16T || !flag || m < 1 || n < 1 || lda < n || ld16 < n || ldT < m || ld16 % 128 || ldT % 128)
+    return RSVD_E_ARG;
+  K_TRY(launch_to_bf16(A, lda, m, n, A16, ld16, A16T, ldT, flag, reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_k_product_bf16(int64_t rows, int64_t K, const uint16_t* A16, int64_t lda, const float* X, int64_t ldx,
+                                int32_t ncols, float* out, int64_t ldo, void* stream) {
+  if (!A16 || !X || !out || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K || lda % 128 || ldx < K ||
+      ldx % 4 || ldo < rows)
+    return RSVD_E_ARG;
+  K_TRY(launch_nn_bf16(A16, lda, rows, K, X, ldx, ncols, out, ldo, 0, 1, reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
+}
+
 }  // extern "C"

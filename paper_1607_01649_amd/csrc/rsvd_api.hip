@@ -17,7 +17,9 @@ using namespace rsvd;
 namespace {
 
 constexpr int kRedGroup = 16;   // partials summed per first-level reduction group
-constexpr int kFlags = 64;   // device status words: [0] non-finite pivot, [1] dropped columns, [2] Jacobi not converged
+// device status words: [0] non-finite pivot, [1] dropped columns, [2] Jacobi
+// not converged, [3] Jacobi sweeps, [4] non-finite entry of A (conversion)
+constexpr int kFlags = 64;
 
 bool log_enabled() {
   static int v = -1;
@@ -40,8 +42,9 @@ struct Layout {
   int l, LP;
   int64_t ldm, ldn;
   size_t es;   // element size of panels (8 for F64, 4 otherwise)
-  int s_nn, s_tn, s_gm, s_gn;
-  size_t omega, Y, T, Q, Z, W, Bt, part, gpart, gpart2, G, R1, R, rinv, rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p,
+  int s_nn, s_tn, s_gm, s_gn, s_nn16, s_tn16;
+  int64_t ld16, ldT;   // leading dimensions of the bf16 copies of A and A^T
+  size_t a16, a16t, omega, Y, T, Q, Z, W, Bt, part, gpart, gpart2, G, R1, R, rinv, rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p,
       scr_chol, scr_jac, flags, total;
 };
 
@@ -66,11 +69,14 @@ bool validate(const rsvd_desc* d) {
   return true;
 }
 
+bool uses_bf16(const rsvd_desc* d) { return d->sketch_dtype == RSVD_BF16 || d->proj_dtype == RSVD_BF16; }
+
 rsvd_status supported(const rsvd_desc* d) {
   if (d->a_dtype == RSVD_F64) {
     if (d->sketch_dtype != RSVD_F64 || d->proj_dtype != RSVD_F64) return RSVD_E_UNSUPPORTED;
   } else {
-    if (d->sketch_dtype != RSVD_F32 || d->proj_dtype != RSVD_F32) return RSVD_E_UNSUPPORTED;
+    auto ok = [](int t) { return t == RSVD_F32 || t == RSVD_BF16; };
+    if (!ok(d->sketch_dtype) || !ok(d->proj_dtype)) return RSVD_E_UNSUPPORTED;
   }
   if (d->eps > 0.0) return RSVD_E_UNSUPPORTED;
   return RSVD_OK;
@@ -93,9 +99,16 @@ Layout make_layout(const rsvd_desc* d) {
   L.s_tn = nn_splits_used(d->m, L.s_tn);
   L.s_gm = nn_splits_used(d->m, L.s_gm);
   L.s_gn = nn_splits_used(d->n, L.s_gn);
+  L.s_nn16 = lp_splits_used(d->n, L.s_nn);
+  L.s_tn16 = lp_splits_used(d->m, L.s_tn);
+  L.ld16 = round_up(d->n, 128);
+  L.ldT = round_up(d->m, 128);
   const size_t LP = (size_t)L.LP;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };
+  const bool b16 = uses_bf16(d);
+  L.a16 = take(b16 ? (size_t)d->m * L.ld16 * 2 : 256);
+  L.a16t = take(b16 ? (size_t)d->n * L.ldT * 2 : 256);
   L.omega = take(LP * L.ldn * L.es);
   L.Y = take(LP * L.ldm * L.es);
   L.T = take(LP * std::max(L.ldm, L.ldn) * L.es);
@@ -103,7 +116,8 @@ Layout make_layout(const rsvd_desc* d) {
   L.Z = take(LP * L.ldn * L.es);
   L.W = take(LP * L.ldn * L.es);
   L.Bt = take(LP * L.ldn * L.es);
-  L.part = take(std::max((size_t)L.s_nn * LP * L.ldm, (size_t)L.s_tn * LP * L.ldn) * L.es);
+  L.part = take(std::max(std::max((size_t)L.s_nn, (size_t)L.s_nn16) * LP * L.ldm,
+                          std::max((size_t)L.s_tn, (size_t)L.s_tn16) * LP * L.ldn) * L.es);
   L.gpart = take((size_t)std::max(L.s_gm, L.s_gn) * LP * LP * 8);
   L.gpart2 = take((size_t)((std::max(L.s_gm, L.s_gn) + kRedGroup - 1) / kRedGroup) * LP * LP * 8);
   L.G = take(LP * LP * 8);
@@ -188,25 +202,43 @@ template <typename T> struct Path {
     return RSVD_OK;
   }
 
-  // Y = A X (m x l panel) for an n-row panel X.
-  rsvd_status apply_a(const T* A, int64_t lda, const T* X, T* Y) {
+  // Y = A X (m x l panel) for an n-row panel X, operands in precision `dt`.
+  rsvd_status apply_a(const T* A, int64_t lda, const T* X, T* Y, int dt) {
     T* part = P.at<T>(L.part);
     const int64_t m = P.d.m, n = P.d.n;
+    int S = L.s_nn;
     int ev = gemm_begin(0);
-    HIP_TRY((launch_nn<T, T, T, T>(A, lda, m, n, X, L.ldn, l, part, L.ldm, (int64_t)LP * L.ldm, L.s_nn, st)));
+    if (dt == RSVD_BF16) {
+      if constexpr (sizeof(T) == 4) {
+        S = L.s_nn16;
+        HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16), L.ld16, m, n, X, L.ldn, l, part, L.ldm, (int64_t)LP * L.ldm, S,
+                               st));
+      }
+    } else {
+      HIP_TRY((launch_nn<T, T, T, T>(A, lda, m, n, X, L.ldn, l, part, L.ldm, (int64_t)LP * L.ldm, S, st)));
+    }
     gemm_end(ev);
-    HIP_TRY((launch_reduce<T, T>(part, L.s_nn, (int64_t)LP * L.ldm, L.ldm, m, l, Y, L.ldm, st)));
+    HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LP * L.ldm, L.ldm, m, l, Y, L.ldm, st)));
     return RSVD_OK;
   }
 
-  // Z = A^T Q (n x l panel) for an m-row panel Q.
-  rsvd_status apply_at(const T* A, int64_t lda, const T* Qp, T* Z) {
+  // Z = A^T Q (n x l panel) for an m-row panel Q, operands in precision `dt`.
+  rsvd_status apply_at(const T* A, int64_t lda, const T* Qp, T* Z, int dt) {
     T* part = P.at<T>(L.part);
     const int64_t m = P.d.m, n = P.d.n;
+    int S = L.s_tn;
     int ev = gemm_begin(1);
-    HIP_TRY((launch_tn<T, T, T, T>(A, lda, m, n, Qp, L.ldm, l, part, L.ldn, (int64_t)LP * L.ldn, L.s_tn, false, st)));
+    if (dt == RSVD_BF16) {
+      if constexpr (sizeof(T) == 4) {
+        S = L.s_tn16;
+        HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16t), L.ldT, n, m, Qp, L.ldm, l, part, L.ldn, (int64_t)LP * L.ldn, S,
+                               st));
+      }
+    } else {
+      HIP_TRY((launch_tn<T, T, T, T>(A, lda, m, n, Qp, L.ldm, l, part, L.ldn, (int64_t)LP * L.ldn, S, false, st)));
+    }
     gemm_end(ev);
-    HIP_TRY((launch_reduce<T, T>(part, L.s_tn, (int64_t)LP * L.ldn, L.ldn, n, l, Z, L.ldn, st)));
+    HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LP * L.ldn, L.ldn, n, l, Z, L.ldn, st)));
     return RSVD_OK;
   }
 
@@ -233,25 +265,31 @@ template <typename T> struct Path {
     rsvd_status s;
     mark(0);
     HIP_TRY(launch_fill_int(flags, kFlags, 0, st));
+    const int sk = P.d.sketch_dtype, pj = P.d.proj_dtype;
+    if (uses_bf16(&P.d)) {
+      if constexpr (sizeof(T) == 4)
+        HIP_TRY(launch_to_bf16(A, lda, m, n, P.at<uint16_t>(L.a16), L.ld16, P.at<uint16_t>(L.a16t), L.ldT, flags + 4,
+                               st));
+    }
     // Figure 5 (1): Gaussian test matrix.
     if (omega_in)
       HIP_TRY(launch_rowmajor_to_panel<T>(omega_in, n, l, l, omega, L.ldn, st));
     else
       HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, l, 0, omega, 1, L.ldn, st));
     // (2): Q = orth(A Omega).
-    if ((s = apply_a(A, lda, omega, Y)) != RSVD_OK) return s;
+    if ((s = apply_a(A, lda, omega, Y, sk)) != RSVD_OK) return s;
     if ((s = orth(Y, L.ldm, m, L.s_gm, Q)) != RSVD_OK) return s;
     mark(1);
     // (3)-(6): q power steps with re-orthonormalisation.
     for (int it = 0; it < P.d.q; ++it) {
-      if ((s = apply_at(A, lda, Q, Z)) != RSVD_OK) return s;
+      if ((s = apply_at(A, lda, Q, Z, sk)) != RSVD_OK) return s;
       if ((s = orth(Z, L.ldn, n, L.s_gn, W)) != RSVD_OK) return s;
-      if ((s = apply_a(A, lda, W, Y)) != RSVD_OK) return s;
+      if ((s = apply_a(A, lda, W, Y, sk)) != RSVD_OK) return s;
       if ((s = orth(Y, L.ldm, m, L.s_gm, Q)) != RSVD_OK) return s;
     }
     mark(2);
     // (7): B = Q^T A, held as B^T (n x l panel).
-    if ((s = apply_at(A, lda, Q, Bt)) != RSVD_OK) return s;
+    if ((s = apply_at(A, lda, Q, Bt, pj)) != RSVD_OK) return s;
     mark(3);
     // (8): SVD of B in FP64: B^T = Q_B R by CholeskyQR2, then Jacobi on R^T.
     {
@@ -388,7 +426,9 @@ rsvd_status rsvd_factor(rsvd_plan_t p, const void* d_A, int64_t lda, const doubl
         else { h_info->tn_ms += ms; h_info->tn_launches++; }
       }
     }
-    if (flags[0] > 0) s = RSVD_E_NONFINITE;
+    h_info->jacobi_sweeps = flags[3];
+    h_info->dropped_cols = flags[1];
+    if (flags[0] > 0 || flags[4] != 0) s = RSVD_E_NONFINITE;
     h_info->status = s;
     RSVD_LOGF("factor done: nonfinite=%d dropped=%d jacobi_nonconv=%d", flags[0], flags[1], flags[2]);
   }

@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_the_header(lib):
     from paper_1607_01649_amd._lib import rsvd_desc, rsvd_info
     assert ctypes.sizeof(rsvd_desc) == 80
-    assert ctypes.sizeof(rsvd_info) == 88
+    assert ctypes.sizeof(rsvd_info) == 96
     assert rsvd_desc.seed.offset == 40 and rsvd_desc.eps.offset == 48 and rsvd_desc.flags.offset == 72
     assert rsvd_info.err_bound.offset == 24 and rsvd_info.stage_ms.offset == 40 and rsvd_info.nn_launches.offset == 80
 

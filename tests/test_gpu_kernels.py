@@ -166,3 +166,68 @@ def test_small_svd_matches_lapack(l):
         gap = min([abs(s0[j] - s0[i2]) for i2 in range(l) if i2 != j] + [1.0])
         assert np.linalg.norm(Uh[:, j] - sgn * ref_u[:, j]) <= 1e-13 / gap
     assert flags.cpu().numpy()[2] == 0
+
+
+def test_convert_bf16_is_bit_exact():
+    import torch
+    from oracle import quant
+    rng = np.random.default_rng(11)
+    m, n = 300, 517
+    A = (rng.standard_normal((m, n)) * 10).astype(np.float32)
+    # exact ties and tiny values
+    A[0, :8] = ((np.arange(8, dtype=np.uint32) * 0x10000 + 0x3F808000).view(np.float32))
+    A[1, :3] = np.array([1e-40, -3e-39, 1e-45], dtype=np.float32)
+    ld16, ldT = 640, 384
+    dA = _t(A, torch.float32)
+    A16 = torch.full((m, ld16), -1, dtype=torch.int16, device=device())
+    A16T = torch.full((n, ldT), -1, dtype=torch.int16, device=device())
+    flag = torch.zeros(1, dtype=torch.int32, device=device())
+    assert _lib().rsvd_k_convert_bf16(m, n, _p(dA), n, _p(A16), ld16, _p(A16T), ldT, _p(flag), None) == 0
+    got = A16.cpu().numpy().view(np.uint16)
+    want = quant.bf16_bits(A)
+    assert np.array_equal(got[:, :n], want)
+    assert np.all(got[:, n:] == 0)
+    gt = A16T.cpu().numpy().view(np.uint16)
+    assert np.array_equal(gt[:, :m], want.T)
+    assert np.all(gt[:, m:] == 0)
+    assert int(flag.cpu()[0]) == 0
+    A[5, 7] = np.inf
+    dA = _t(A, torch.float32)
+    assert _lib().rsvd_k_convert_bf16(m, n, _p(dA), n, _p(A16), ld16, _p(A16T), ldT, _p(flag), None) == 0
+    assert int(flag.cpu()[0]) == 1
+
+
+@pytest.mark.parametrize("rows,K,ncols", [(128, 128, 16), (300, 517, 30), (77, 1000, 110), (1000, 129, 128),
+                                          (33, 70, 7), (513, 2048, 200)])
+def test_product_bf16_is_exact_on_integers(rows, K, ncols):
+    import torch
+    rng = np.random.default_rng(rows * 7 + K)
+    A = rng.integers(-16, 17, size=(rows, K)).astype(np.float32)
+    X = rng.integers(-16, 17, size=(K, ncols)).astype(np.float32)
+    ref = A.astype(np.float64) @ X.astype(np.float64)
+    lda = (K + 127) // 128 * 128
+    ldT = (rows + 127) // 128 * 128
+    dA = _t(A, torch.float32)
+    A16 = torch.zeros((rows, lda), dtype=torch.int16, device=device())
+    A16T = torch.zeros((K, ldT), dtype=torch.int16, device=device())
+    flag = torch.zeros(1, dtype=torch.int32, device=device())
+    assert _lib().rsvd_k_convert_bf16(rows, K, _p(dA), K, _p(A16), lda, _p(A16T), ldT, _p(flag), None) == 0
+    ldx = (K + 3) // 4 * 4 + 4
+    Xp = np.zeros((ncols, ldx), dtype=np.float32)
+    Xp[:, :K] = X.T
+    dX = _t(Xp, torch.float32)
+    ldo = rows + 3
+    out = torch.full((ncols, ldo), -7.0, dtype=torch.float32, device=device())
+    assert _lib().rsvd_k_product_bf16(rows, K, _p(A16), lda, _p(dX), ldx, ncols, _p(out), ldo, None) == 0
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[:, :rows], ref.T)
+    assert np.all(got[:, rows:] == -7.0)
+    # and the transposed copy gives A^T P
+    P = rng.integers(-16, 17, size=(rows, 9)).astype(np.float32)
+    ldp = ldT
+    Pp = np.zeros((9, ldp), dtype=np.float32)
+    Pp[:, :rows] = P.T
+    dP = _t(Pp, torch.float32)
+    out2 = torch.zeros((9, K), dtype=torch.float32, device=device())
+    assert _lib().rsvd_k_product_bf16(K, rows, _p(A16T), ldT, _p(dP), ldp, 9, _p(out2), K, None) == 0
+    assert np.array_equal(out2.cpu().numpy().astype(np.float64), (A.astype(np.float64).T @ P).T)

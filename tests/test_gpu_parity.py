@@ -173,3 +173,31 @@ def test_nan_input_is_reported():
     A[17, 3] = np.nan
     with pytest.raises(RuntimeError, match="NONFINITE"):
         run_factor(A, 5, 5, 0, "f32")
+
+
+BF16_CASES = [
+    # m, n, rank, alpha, k, p, q, sketch, proj
+    (3000, 1500, 300, 0.5, 20, 10, 2, "bf16", "bf16"),
+    (1237, 901, 200, 1.0, 12, 8, 1, "bf16", "f32"),
+    (2048, 1024, 256, 0.5, 50, 14, 2, "bf16", "bf16"),
+]
+
+
+@pytest.mark.parametrize("m,n,rank,alpha,k,p,q,sk,pj", BF16_CASES)
+def test_factor_bf16_matches_the_quantisation_aware_oracle(m, n, rank, alpha, k, p, q, sk, pj):
+    """bf16 operands, FP32 accumulation: parity against the oracle run on the
+    identically rounded operands (differences are accumulation error only);
+    the error of the format itself against the plain oracle is reported."""
+    from oracle import quant
+    sigma = gen.spectrum("poly", rank, alpha=alpha)
+    A32 = gen.low_rank_matrix(m, n, sigma, 1e-3 / math.sqrt(n), seed=m + 5 * n).astype(np.float32)
+    G = gen.gaussian_matrix(n, k + p, seed=m * n + 1)
+    qa = quant.rsvd_quantized(A32, G, q, sk, pj)
+    plain = orc.rsvd(A32.astype(np.float64), G, q)
+    U, S, V, info = run_factor(A32, k, p, q, "f32", omega=G, sketch_dtype=sk, proj_dtype=pj)
+    assert info.status == 0
+    assert max_rel_sigma(S, qa.D, k) <= 1e-4
+    relgap = (qa.D[k - 1] - qa.D[k]) / qa.D[0]
+    assert subspace_sin(U, qa.U[:, :k]) <= 50 * math.sqrt(max(m, n)) * U32 / relgap
+    print(f"bf16 format error vs plain oracle: max rel sigma {max_rel_sigma(S, plain.D, k):.2e}")
+    assert max_rel_sigma(S, plain.D, k) <= 2e-2

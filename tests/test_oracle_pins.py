@@ -336,3 +336,51 @@ def test_factor_with_fallback_reaches_the_tolerance():
     # singular values of Q^T A interlace those of A from below
     assert np.all(plain.D <= sigma[:10] * (1 + 1e-12))
     assert np.allclose(plain.D, sigma[:10], rtol=1e-2)
+
+
+# ---------------------------------------------------------------- quantisation
+
+def test_bf16_rounding_exhaustive():
+    """Every bfloat16 code is a fixed point; the midpoint between neighbouring
+    codes rounds to the even one; the result agrees with torch's (CPU) RNE
+    conversion on random binary32 values, subnormals, infinities and NaN."""
+    import torch
+    from oracle import quant
+    codes = np.arange(65536, dtype=np.uint32)
+    vals = (codes << 16).view(np.float32)
+    finite = np.isfinite(vals)
+    assert np.array_equal(quant.bf16_bits(vals[finite]), codes[finite].astype(np.uint16))
+    # midpoints: code | 0x8000 rounds to the even neighbour
+    mids = ((codes << 16) | 0x8000).view(np.float32)
+    ok = np.isfinite(mids) & np.isfinite(((codes + 1) << 16).view(np.float32)) & (codes < 0x7F7F) | (
+        (codes >= 0x8000) & (codes < 0xFF7F))
+    got = quant.bf16_bits(mids[ok]).astype(np.uint32)
+    c = codes[ok]
+    want = np.where(c % 2 == 0, c, c + 1)
+    assert np.array_equal(got, want)
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(200000).astype(np.float32) * np.float32(1e3),
+                        (rng.integers(0, 2 ** 32, 200000, dtype=np.uint64).astype(np.uint32)).view(np.float32),
+                        np.array([np.inf, -np.inf, 1e-45, -1e-40, 3.4e38], dtype=np.float32)])
+    x = x[np.isfinite(x) | np.isinf(x)]
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ref, quant.bf16_round(x))
+    assert np.isnan(quant.bf16_round(np.array([np.nan], dtype=np.float32)))[0]
+
+
+def test_quantised_rsvd_reduces_to_the_plain_oracle_on_representable_data():
+    """Integers of magnitude <= 256 are exact in bfloat16; with such A and
+    Omega the first product is unchanged, so the quantisation-aware run and
+    the plain one share Y exactly and differ only through the rounding of the
+    later thin operands, which is small."""
+    from oracle import quant
+    rng = np.random.default_rng(3)
+    A = rng.integers(-8, 9, size=(60, 40)).astype(np.float64)
+    G = rng.integers(-4, 5, size=(40, 12)).astype(np.float64)
+    a = orc.rsvd(A, G, 0)
+    b = quant.rsvd_quantized(A, G, 0, "bf16", "f32")
+    assert np.allclose(a.Q, b.Q, atol=1e-12)       # same Y -> same orth
+    c = quant.rsvd_quantized(A, G, 0, "f32", "f32")
+    assert np.allclose(a.D, c.D, rtol=1e-6)
+    d = quant.rsvd_quantized(A, G, 1, "bf16", "bf16")
+    assert np.max(np.abs(d.D - orc.rsvd(A, G, 1).D) / orc.rsvd(A, G, 1).D[0]) < 1e-2
