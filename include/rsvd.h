@@ -85,7 +85,9 @@ typedef enum {
  *   est_power   s >= 0: the certificate is taken of (T T^T)^s T, T = A - U D V^T,
  *               and its (2s+1)-th root returned (0 = the paper's form).
  *   fallback_block  b, columns added per growth step (0 -> 32).
- *   max_rank    capacity of U and V in columns when eps > 0 (>= k+p; 0 -> k+p).
+ *   max_rank    when eps > 0: largest basis the fallback may grow to, and the
+ *               column capacity U and V must have (>= k+p; 0 -> k+p, i.e. no
+ *               growth).
  *   flags       RSVD_RETURN_RANK_L | RSVD_TIMING.
  */
 typedef struct {
@@ -117,6 +119,8 @@ typedef struct {
   int32_t nn_launches, tn_launches;
   int32_t jacobi_sweeps;   /* sweeps of the small SVD                                 */
   int32_t dropped_cols;    /* numerically dependent columns met by CholeskyQR          */
+  double frob_residual;    /* after a fallback: sqrt(||A||_F^2 - ||B||_F^2) (Section 12.4
+                              downdating) of the grown basis; -1 otherwise            */
 } rsvd_info;
 
 typedef struct rsvd_plan_s* rsvd_plan_t;
@@ -155,7 +159,15 @@ rsvd_status rsvd_plan(const rsvd_desc* d, void* d_ws, size_t ws_bytes, void* str
  *   Columns are signed so that the entry of largest magnitude of each column
  *   of U_hat (the small SVD's left vectors) is positive.
  * Asynchronous when eps == 0 and h_info == NULL.  With eps > 0 the host reads
- * the certificate once per growth step (stream synchronised).
+ * the certificate after the fixed-rank pass and once per growth step (stream
+ * synchronised); ldu and ldv must then be >= max(k or k+p, max_rank).
+ * Certificate (eps > 0): r = n_probe Gaussian vectors g_i (stream 6),
+ * bound = 10 sqrt(2/pi) max_i ||(A - U D V^T) g_i|| (alpha = 1/10), which
+ * exceeds ||A - U D V^T|| with probability at most 10^-r; accepted when
+ * bound <= eps * D(1).  Otherwise the basis grows by fallback_block columns
+ * per step (Figure 12, residual applied implicitly, each new block projected
+ * against the basis twice) until the bound holds or max_rank is reached; all
+ * columns of the grown basis are then returned (rank_out = its width).
  * Errors: RSVD_E_ARG (nothing enqueued), RSVD_E_HIP, RSVD_E_NONFINITE,
  * RSVD_E_BREAKDOWN; RSVD_NOT_CERTIFIED (> 0) when eps is missed at max_rank.
  * Reported only when h_info != NULL or eps > 0: device-side conditions

@@ -130,7 +130,7 @@ class RSVD:
         self.tdtype = _TORCH[self.desc.a_dtype]
 
     def __call__(self, A: torch.Tensor, omega: Optional[torch.Tensor] = None, want_info: bool = True,
-                 out=None):
+                 out=None, allow_not_certified: bool = True):
         r = self.rank_cap
         if out is None:
             U = torch.empty(self.desc.m, r, dtype=self.tdtype, device=self.device)
@@ -138,8 +138,8 @@ class RSVD:
             V = torch.empty(self.desc.n, r, dtype=self.tdtype, device=self.device)
         else:
             U, S, V = out
-        st, info = rsvd_factor(self.plan, A, U, S, V, omega, want_info)
-        if st < 0:
+        st, info = rsvd_factor(self.plan, A, U, S, V, omega, want_info or self.desc.eps > 0)
+        if st < 0 or (st == RSVD_NOT_CERTIFIED and not allow_not_certified):
             raise RSVDError(st, "rsvd_factor")
         if info is not None:
             k = info.rank_out

@@ -51,6 +51,7 @@ class rsvd_info(ctypes.Structure):
         ("nn_ms", ctypes.c_float), ("tn_ms", ctypes.c_float),
         ("nn_launches", ctypes.c_int32), ("tn_launches", ctypes.c_int32),
         ("jacobi_sweeps", ctypes.c_int32), ("dropped_cols", ctypes.c_int32),
+        ("frob_residual", ctypes.c_double),
     ]
 
 

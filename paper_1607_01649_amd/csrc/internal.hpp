@@ -51,6 +51,13 @@ int lp_splits_used(int64_t K, int splits);
 
 // misc.hip
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+template <typename T>
+hipError_t launch_axpy_panel(T* Y, int64_t ldy, const T* X, int64_t ldx, int64_t rows, int ncols, T alpha,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_colnorm(const T* X, int64_t ld, int64_t rows, int ncols, double* norms, hipStream_t s);
+template <typename T>
+hipError_t launch_frob2(const T* A, int64_t lda, int64_t m, int64_t n, double* partials, double* out, hipStream_t s);
 template <typename TO>
 hipError_t launch_rowmajor_to_panel(const double* src, int64_t rows, int64_t cols, int64_t ld_src, TO* dst,
                                     int64_t ld_dst, hipStream_t s);

@@ -42,3 +42,99 @@ template hipError_t launch_rowmajor_to_panel<double>(const double*, int64_t, int
                                                      hipStream_t);
 
 }  // namespace rsvd
+
+namespace rsvd {
+
+// Y[c*ldy + r] += alpha * X[c*ldx + r] for r < rows, c < ncols.
+template <typename T>
+__global__ void axpy_panel_kernel(T* __restrict__ Y, int64_t ldy, const T* __restrict__ X, int64_t ldx, int64_t rows,
+                                  int ncols, T alpha) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= rows * ncols) return;
+  int64_t c = t / rows, r = t % rows;
+  Y[c * ldy + r] += alpha * X[c * ldx + r];
+}
+
+template <typename T>
+hipError_t launch_axpy_panel(T* Y, int64_t ldy, const T* X, int64_t ldx, int64_t rows, int ncols, T alpha,
+                             hipStream_t s) {
+  int64_t work = rows * ncols;
+  if (work <= 0) return hipSuccess;
+  hipLaunchKernelGGL((axpy_panel_kernel<T>), dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, Y, ldy, X, ldx,
+                     rows, ncols, alpha);
+  return hipGetLastError();
+}
+
+// norms[c] = || X[c*ld + 0 .. rows) ||_2, accumulated in FP64; one block per column.
+template <typename T>
+__global__ __launch_bounds__(256) void colnorm_kernel(const T* __restrict__ X, int64_t ld, int64_t rows,
+                                                      double* __restrict__ norms) {
+  __shared__ double red[4];
+  const T* x = X + (int64_t)blockIdx.x * ld;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += 256) {
+    double v = (double)x[r];
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) norms[blockIdx.x] = sqrt(red[0] + red[1] + red[2] + red[3]);
+}
+
+template <typename T>
+hipError_t launch_colnorm(const T* X, int64_t ld, int64_t rows, int ncols, double* norms, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((colnorm_kernel<T>), dim3((unsigned)ncols), dim3(256), 0, s, X, ld, rows, norms);
+  return hipGetLastError();
+}
+
+// out[b] = sum of squares of rows [b*chunk, (b+1)*chunk) of A (m x n, lda), FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_rows_kernel(const T* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                         int64_t chunk, double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(m, r0 + chunk);
+  for (int64_t r = r0; r < r1; ++r)
+    for (int64_t c = threadIdx.x; c < n; c += 256) {
+      double v = (double)A[r * lda + c];
+      s += v * v;
+    }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void sum_doubles_kernel(const double* __restrict__ in, int n, double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += in[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+}
+
+// *out = ||A||_F^2 (FP64); partials: >= 1024 doubles of scratch.
+template <typename T>
+hipError_t launch_frob2(const T* A, int64_t lda, int64_t m, int64_t n, double* partials, double* out, hipStream_t s) {
+  int64_t chunk = (m + 1023) / 1024;
+  int nb = (int)((m + chunk - 1) / chunk);
+  hipLaunchKernelGGL((sumsq_rows_kernel<T>), dim3((unsigned)nb), dim3(256), 0, s, A, lda, m, n, chunk, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_doubles_kernel, dim3(1), dim3(256), 0, s, partials, nb, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_axpy_panel<float>(float*, int64_t, const float*, int64_t, int64_t, int, float, hipStream_t);
+template hipError_t launch_axpy_panel<double>(double*, int64_t, const double*, int64_t, int64_t, int, double,
+                                              hipStream_t);
+template hipError_t launch_colnorm<float>(const float*, int64_t, int64_t, int, double*, hipStream_t);
+template hipError_t launch_colnorm<double>(const double*, int64_t, int64_t, int, double*, hipStream_t);
+template hipError_t launch_frob2<float>(const float*, int64_t, int64_t, int64_t, double*, double*, hipStream_t);
+template hipError_t launch_frob2<double>(const double*, int64_t, int64_t, int64_t, double*, double*, hipStream_t);
+
+}  // namespace rsvd

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <new>
+#include <vector>
 
 #include "../../include/rsvd.h"
 #include "internal.hpp"
@@ -39,13 +40,17 @@ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 // Byte offsets of the workspace regions (all 256-byte aligned).
 struct Layout {
-  int l, LP;
+  int l, LP;          // sketch width k+p and its 16-multiple
+  int lmax, LPmax;    // capacity of Q and B^T (max_rank when certifying), and its 16-multiple
+  int b, bw;          // fallback block and its 16-multiple
+  int r;              // certificate probes
+  int W;              // width of the sketch-side panels: max(LP, bw)
   int64_t ldm, ldn;
   size_t es;   // element size of panels (8 for F64, 4 otherwise)
   int s_nn, s_tn, s_gm, s_gn, s_nn16, s_tn16;
   int64_t ld16, ldT;   // leading dimensions of the bf16 copies of A and A^T
-  size_t a16, a16t, omega, Y, T, Q, Z, W, Bt, part, gpart, gpart2, G, R1, R, rinv, rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p,
-      scr_chol, scr_jac, flags, total;
+  size_t a16, a16t, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
+      rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, total;
 };
 
 int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
@@ -62,7 +67,8 @@ bool validate(const rsvd_desc* d) {
   if (l > std::min(d->m, d->n) || l > 1024) return false;
   if (d->a_dtype != RSVD_F64 && d->a_dtype != RSVD_F32) return false;
   if (!(d->eps >= 0.0) || !isfinite(d->eps)) return false;
-  if (d->n_probe < 0 || d->est_power < 0 || d->fallback_block < 0 || d->max_rank < 0) return false;
+  if (d->n_probe < 0 || d->n_probe > 64 || d->est_power < 0 || d->est_power > 8) return false;
+  if (d->fallback_block < 0 || d->fallback_block > 256 || d->max_rank < 0) return false;
   if (d->max_rank > 0 && d->max_rank < l) return false;
   if (d->max_rank > std::min<int64_t>(std::min(d->m, d->n), 1024)) return false;
   if (d->m > (int64_t)1 << 40 || d->n > (int64_t)1 << 40) return false;
@@ -78,14 +84,20 @@ rsvd_status supported(const rsvd_desc* d) {
     auto ok = [](int t) { return t == RSVD_F32 || t == RSVD_BF16; };
     if (!ok(d->sketch_dtype) || !ok(d->proj_dtype)) return RSVD_E_UNSUPPORTED;
   }
-  if (d->eps > 0.0) return RSVD_E_UNSUPPORTED;
   return RSVD_OK;
 }
 
 Layout make_layout(const rsvd_desc* d) {
   Layout L{};
+  const bool cert = d->eps > 0.0;
   L.l = d->k + d->p;
   L.LP = (int)round_up(L.l, 16);
+  L.lmax = cert ? std::max(L.l, (int)d->max_rank) : L.l;
+  L.LPmax = (int)round_up(L.lmax, 16);
+  L.b = cert ? (d->fallback_block ? d->fallback_block : 32) : 0;
+  L.bw = (int)round_up(L.b, 16);
+  L.r = cert ? (d->n_probe ? d->n_probe : 10) : 0;
+  L.W = std::max({L.LP, L.bw, (int)round_up(std::max(L.r, 1), 16)});
   L.ldm = round_up(d->m, 64);
   L.ldn = round_up(d->n, 64);
   L.es = (d->a_dtype == RSVD_F64) ? 8 : 4;
@@ -103,35 +115,47 @@ Layout make_layout(const rsvd_desc* d) {
   L.s_tn16 = lp_splits_used(d->m, L.s_tn);
   L.ld16 = round_up(d->n, 128);
   L.ldT = round_up(d->m, 128);
-  const size_t LP = (size_t)L.LP;
+  const size_t LP = (size_t)L.LP, LPM = (size_t)L.LPmax, Wd = (size_t)L.W;
+  const size_t R = (size_t)std::max(L.r, 1);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };
   const bool b16 = uses_bf16(d);
   L.a16 = take(b16 ? (size_t)d->m * L.ld16 * 2 : 256);
   L.a16t = take(b16 ? (size_t)d->n * L.ldT * 2 : 256);
-  L.omega = take(LP * L.ldn * L.es);
-  L.Y = take(LP * L.ldm * L.es);
-  L.T = take(LP * std::max(L.ldm, L.ldn) * L.es);
-  L.Q = take(LP * L.ldm * L.es);
+  L.omega = take(Wd * L.ldn * L.es);
+  L.gc = take(R * L.ldn * L.es);
+  L.Y = take(Wd * L.ldm * L.es);
+  L.T = take(std::max(Wd, LPM) * std::max(L.ldm, L.ldn) * L.es);
+  L.Q = take(LPM * L.ldm * L.es);
   L.Z = take(LP * L.ldn * L.es);
-  L.W = take(LP * L.ldn * L.es);
-  L.Bt = take(LP * L.ldn * L.es);
-  L.part = take(std::max(std::max((size_t)L.s_nn, (size_t)L.s_nn16) * LP * L.ldm,
-                          std::max((size_t)L.s_tn, (size_t)L.s_tn16) * LP * L.ldn) * L.es);
-  L.gpart = take((size_t)std::max(L.s_gm, L.s_gn) * LP * LP * 8);
-  L.gpart2 = take((size_t)((std::max(L.s_gm, L.s_gn) + kRedGroup - 1) / kRedGroup) * LP * LP * 8);
-  L.G = take(LP * LP * 8);
-  L.R1 = take(LP * LP * 8);
-  L.R = take(LP * LP * 8);
-  L.rinv = take(LP * LP * L.es);
-  L.rinv_d = take(LP * LP * 8);
-  L.Q1d = take(LP * L.ldn * 8);
-  L.sigma = take(LP * 8);
-  L.uhat_d = take(LP * LP * 8);
-  L.uhat_p = take(LP * LP * L.es);
-  L.vhat_p = take(LP * LP * L.es);
-  L.scr_chol = take(LP > 128 ? LP * LP * 8 : 256);
-  L.scr_jac = take(LP > 128 ? LP * LP * 8 : 256);
+  L.Wp = take(LP * L.ldn * L.es);
+  L.Bt = take(LPM * L.ldn * L.es);
+  L.agc = take(R * L.ldm * L.es);
+  L.E = take(R * L.ldm * L.es);
+  L.tmpr = take(std::max(R, (size_t)L.bw) * L.ldm * L.es);
+  L.zr = take(R * L.ldn * L.es);
+  L.tmpn = take(R * L.ldn * L.es);
+  L.small = take(LPM * std::max(LPM, R) * 8);
+  L.small2 = take(LPM * std::max(LPM, R) * 8);
+  const size_t sa = std::max({(size_t)L.s_nn, (size_t)L.s_nn16}), sb = std::max({(size_t)L.s_tn, (size_t)L.s_tn16});
+  L.part = take(std::max(sa * Wd * L.ldm, sb * Wd * L.ldn) * L.es);
+  const size_t sg = (size_t)std::max(L.s_gm, L.s_gn);
+  L.gpart = take(sg * LPM * std::max(LPM, R) * 8);
+  L.gpart2 = take(((sg + kRedGroup - 1) / kRedGroup) * LPM * LPM * 8);
+  L.G = take(LPM * LPM * 8);
+  L.R1 = take(LPM * LPM * 8);
+  L.R = take(LPM * LPM * 8);
+  L.rinv = take(LPM * LPM * L.es);
+  L.rinv_d = take(LPM * LPM * 8);
+  L.Q1d = take(LPM * L.ldn * 8);
+  L.sigma = take(LPM * 8);
+  L.uhat_d = take(LPM * LPM * 8);
+  L.uhat_p = take(LPM * LPM * L.es);
+  L.vhat_p = take(LPM * LPM * L.es);
+  L.scr_chol = take(LPM > 128 ? LPM * LPM * 8 : 256);
+  L.scr_jac = take(LPM > 128 ? LPM * LPM * 8 : 256);
+  L.norms = take(64 * 8);
+  L.frob = take(1040 * 8);
   L.flags = take(kFlags * sizeof(int));
   L.total = off;
   return L;
@@ -147,10 +171,13 @@ struct rsvd_plan_s {
   int device;
   bool timing;
   hipEvent_t ev[8];
-  static constexpr int kGemmEv = 64;          // event pairs around A-products (RSVD_TIMING)
+  static constexpr int kGemmEv = 256;          // event pairs around A-products (RSVD_TIMING)
   hipEvent_t gev[2 * kGemmEv];
-  int gkind[kGemmEv];                         // 0 = A*X, 1 = A^T*X
-  mutable int ngemm = 0;
+  int gkind[kGemmEv];                          // 0 = A*X, 1 = A^T*X
+  int ngemm = 0;
+  // results of the last call (host side)
+  int rank_out = 0, fallback_steps = 0;
+  double err_bound = 0.0, frob_res = -1.0;
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
 };
 
@@ -165,104 +192,240 @@ namespace {
     }                                                                        \
   } while (0)
 
+#define RS_TRY(expr)                        \
+  do {                                      \
+    rsvd_status s_ = (expr);                \
+    if (s_ != RSVD_OK) return s_;           \
+  } while (0)
+
+inline int lp16(int nc) { return (int)round_up(nc, 16); }
+
 template <typename T> struct Path {
-  const rsvd_plan_s& P;
+  rsvd_plan_s& P;
   const Layout& L;
   hipStream_t st;
-  int l, LP;
   double tau;
-  explicit Path(const rsvd_plan_s& p) : P(p), L(p.L), st(p.st), l(p.L.l), LP(p.L.LP) {
+  explicit Path(rsvd_plan_s& p) : P(p), L(p.L), st(p.st) {
     const double u = sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
-    tau = (double)l * u * u;
-  }
-
-  // G = X^T X for an l-column panel X with `rows` rows (FP64 accumulation).
-  rsvd_status gram(const T* X, int64_t ldx, int64_t rows, int splits, double* G) {
-    double* gp = P.at<double>(L.gpart);
-    HIP_TRY((launch_nn<T, T, double, double>(X, ldx, l, rows, X, ldx, l, gp, LP, (int64_t)LP * LP, splits, st)));
-    HIP_TRY(launch_reduce2<double>(gp, splits, kRedGroup, (int64_t)LP * LP, LP, l, l, P.at<double>(L.gpart2), G, LP,
-                                   st));
-    return RSVD_OK;
-  }
-
-  // out = orth(X): CholeskyQR2 (two passes of G = X^T X = R^T R, X <- X R^-1).
-  rsvd_status orth(const T* X, int64_t ld, int64_t rows, int splits, T* out) {
-    double* G = P.at<double>(L.G);
-    T* rinv = P.at<T>(L.rinv);
-    T* tmp = P.at<T>(L.T);
-    int* flags = P.at<int>(L.flags);
-    double* scr = P.at<double>(L.scr_chol);
-    rsvd_status s;
-    if ((s = gram(X, ld, rows, splits, G)) != RSVD_OK) return s;
-    HIP_TRY(launch_chol<T>(G, LP, l, LP, tau, rinv, nullptr, nullptr, scr, flags, st));
-    HIP_TRY((launch_tn<T, T, T, T>(X, ld, l, rows, rinv, LP, l, tmp, ld, 0, 1, false, st)));
-    if ((s = gram(tmp, ld, rows, splits, G)) != RSVD_OK) return s;
-    HIP_TRY(launch_chol<T>(G, LP, l, LP, tau, rinv, nullptr, nullptr, scr, flags, st));
-    HIP_TRY((launch_tn<T, T, T, T>(tmp, ld, l, rows, rinv, LP, l, out, ld, 0, 1, false, st)));
-    return RSVD_OK;
-  }
-
-  // Y = A X (m x l panel) for an n-row panel X, operands in precision `dt`.
-  rsvd_status apply_a(const T* A, int64_t lda, const T* X, T* Y, int dt) {
-    T* part = P.at<T>(L.part);
-    const int64_t m = P.d.m, n = P.d.n;
-    int S = L.s_nn;
-    int ev = gemm_begin(0);
-    if (dt == RSVD_BF16) {
-      if constexpr (sizeof(T) == 4) {
-        S = L.s_nn16;
-        HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16), L.ld16, m, n, X, L.ldn, l, part, L.ldm, (int64_t)LP * L.ldm, S,
-                               st));
-      }
-    } else {
-      HIP_TRY((launch_nn<T, T, T, T>(A, lda, m, n, X, L.ldn, l, part, L.ldm, (int64_t)LP * L.ldm, S, st)));
-    }
-    gemm_end(ev);
-    HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LP * L.ldm, L.ldm, m, l, Y, L.ldm, st)));
-    return RSVD_OK;
-  }
-
-  // Z = A^T Q (n x l panel) for an m-row panel Q, operands in precision `dt`.
-  rsvd_status apply_at(const T* A, int64_t lda, const T* Qp, T* Z, int dt) {
-    T* part = P.at<T>(L.part);
-    const int64_t m = P.d.m, n = P.d.n;
-    int S = L.s_tn;
-    int ev = gemm_begin(1);
-    if (dt == RSVD_BF16) {
-      if constexpr (sizeof(T) == 4) {
-        S = L.s_tn16;
-        HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16t), L.ldT, n, m, Qp, L.ldm, l, part, L.ldn, (int64_t)LP * L.ldn, S,
-                               st));
-      }
-    } else {
-      HIP_TRY((launch_tn<T, T, T, T>(A, lda, m, n, Qp, L.ldm, l, part, L.ldn, (int64_t)LP * L.ldn, S, false, st)));
-    }
-    gemm_end(ev);
-    HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LP * L.ldn, L.ldn, n, l, Z, L.ldn, st)));
-    return RSVD_OK;
+    tau = (double)L.lmax * u * u;
   }
 
   void mark(int i) { if (P.timing) (void)hipEventRecord(P.ev[i], st); }
   int gemm_begin(int kind) {
     if (!P.timing || P.ngemm >= rsvd_plan_s::kGemmEv) return -1;
     int i = P.ngemm++;
-    const_cast<rsvd_plan_s&>(P).gkind[i] = kind;
+    P.gkind[i] = kind;
     (void)hipEventRecord(P.gev[2 * i], st);
     return i;
   }
   void gemm_end(int i) { if (i >= 0) (void)hipEventRecord(P.gev[2 * i + 1], st); }
 
+  // G (nc x nc, column-major, ld lp16(nc)) = X^T X for a nc-column panel X with `rows` rows, FP64 accumulation.
+  rsvd_status gram(const T* X, int64_t ldx, int64_t rows, int nc, int splits, double* G) {
+    const int LPc = lp16(nc);
+    double* gp = P.at<double>(L.gpart);
+    HIP_TRY((launch_nn<T, T, double, double>(X, ldx, nc, rows, X, ldx, nc, gp, LPc, (int64_t)LPc * LPc, splits, st)));
+    HIP_TRY(launch_reduce2<double>(gp, splits, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, P.at<double>(L.gpart2), G,
+                                   LPc, st));
+    return RSVD_OK;
+  }
+
+  // out = orth(X) for an nc-column panel: CholeskyQR2 (two passes of G = X^T X = R^T R, X <- X R^-1).
+  rsvd_status orth(const T* X, int64_t ld, int64_t rows, int nc, int splits, T* out) {
+    const int LPc = lp16(nc);
+    double* G = P.at<double>(L.G);
+    T* rinv = P.at<T>(L.rinv);
+    T* tmp = P.at<T>(L.T);
+    int* flags = P.at<int>(L.flags);
+    double* scr = P.at<double>(L.scr_chol);
+    RS_TRY(gram(X, ld, rows, nc, splits, G));
+    HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st));
+    HIP_TRY((launch_tn<T, T, T, T>(X, ld, nc, rows, rinv, LPc, nc, tmp, ld, 0, 1, false, st)));
+    RS_TRY(gram(tmp, ld, rows, nc, splits, G));
+    HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st));
+    HIP_TRY((launch_tn<T, T, T, T>(tmp, ld, nc, rows, rinv, LPc, nc, out, ld, 0, 1, false, st)));
+    return RSVD_OK;
+  }
+
+  // Y = A X (m x nc panel) for an n-row panel X, operands in precision `dt`.
+  rsvd_status apply_a(const T* A, int64_t lda, const T* X, int nc, T* Y, int dt) {
+    T* part = P.at<T>(L.part);
+    const int64_t m = P.d.m, n = P.d.n;
+    const int LPc = lp16(nc);
+    int S = L.s_nn;
+    int ev = gemm_begin(0);
+    if (dt == RSVD_BF16) {
+      if constexpr (sizeof(T) == 4) {
+        S = L.s_nn16;
+        HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16), L.ld16, m, n, X, L.ldn, nc, part, L.ldm, (int64_t)LPc * L.ldm,
+                               S, st));
+      }
+    } else {
+      HIP_TRY((launch_nn<T, T, T, T>(A, lda, m, n, X, L.ldn, nc, part, L.ldm, (int64_t)LPc * L.ldm, S, st)));
+    }
+    gemm_end(ev);
+    HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LPc * L.ldm, L.ldm, m, nc, Y, L.ldm, st)));
+    return RSVD_OK;
+  }
+
+  // Z = A^T Q (n x nc panel) for an m-row panel Q, operands in precision `dt`.
+  rsvd_status apply_at(const T* A, int64_t lda, const T* Qp, int nc, T* Z, int dt) {
+    T* part = P.at<T>(L.part);
+    const int64_t m = P.d.m, n = P.d.n;
+    const int LPc = lp16(nc);
+    int S = L.s_tn;
+    int ev = gemm_begin(1);
+    if (dt == RSVD_BF16) {
+      if constexpr (sizeof(T) == 4) {
+        S = L.s_tn16;
+        HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16t), L.ldT, n, m, Qp, L.ldm, nc, part, L.ldn, (int64_t)LPc * L.ldn,
+                               S, st));
+      }
+    } else {
+      HIP_TRY(
+          (launch_tn<T, T, T, T>(A, lda, m, n, Qp, L.ldm, nc, part, L.ldn, (int64_t)LPc * L.ldn, S, false, st)));
+    }
+    gemm_end(ev);
+    HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LPc * L.ldn, L.ldn, n, nc, Z, L.ldn, st)));
+    return RSVD_OK;
+  }
+
+  // C (na x nb, stored C[j*ldc + i] = (Xa^T Xb)(i, j)) for panels Xa (na columns) and Xb (nb columns) of `rows`
+  // rows; split over the rows, summed in fixed order.
+  rsvd_status panel_tprod(const T* Xa, int na, const T* Xb, int nb, int64_t ld, int64_t rows, int splits, T* C,
+                          int64_t ldc) {
+    T* gp = P.at<T>(L.gpart);
+    HIP_TRY((launch_nn<T, T, T, T>(Xa, ld, na, rows, Xb, ld, nb, gp, ldc, (int64_t)ldc * nb, splits, st)));
+    HIP_TRY((launch_reduce<T, T>(gp, splits, (int64_t)ldc * nb, ldc, na, nb, C, ldc, st)));
+    return RSVD_OK;
+  }
+
+  // out (rows x nb panel) = X S for an na-column panel X and S (na x nb, S[j*lds + i]).
+  rsvd_status panel_mult(const T* X, int na, int64_t ld, int64_t rows, const T* S, int64_t lds, int nb, T* out,
+                         int64_t ldo) {
+    HIP_TRY((launch_tn<T, T, T, T>(X, ld, na, rows, S, lds, nb, out, ldo, 0, 1, false, st)));
+    return RSVD_OK;
+  }
+
+  // SVD of B (nc x n, held as the panel B^T): FP64 CholeskyQR2 of B^T, Jacobi on R^T.
+  rsvd_status small_svd(int nc) {
+    const int64_t n = P.d.n;
+    const int LPc = lp16(nc);
+    T* Bt = P.at<T>(L.Bt);
+    double* G = P.at<double>(L.G);
+    double* R1 = P.at<double>(L.R1);
+    double* R = P.at<double>(L.R);
+    double* rinv_d = P.at<double>(L.rinv_d);
+    double* Q1d = P.at<double>(L.Q1d);
+    double* gp = P.at<double>(L.gpart);
+    double* gp2 = P.at<double>(L.gpart2);
+    double* scr = P.at<double>(L.scr_chol);
+    int* flags = P.at<int>(L.flags);
+    HIP_TRY((launch_nn<T, T, double, double>(Bt, L.ldn, nc, n, Bt, L.ldn, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st)));
+    HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
+    HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R1, nullptr, scr, flags, st));
+    HIP_TRY((launch_tn<T, double, double, double>(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, 0, 1, false, st)));
+    HIP_TRY((launch_nn<double, double, double, double>(Q1d, L.ldn, nc, n, Q1d, L.ldn, nc, gp, LPc, (int64_t)LPc * LPc,
+                                                       L.s_gn, st)));
+    HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
+    HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R, R1, scr, flags, st));
+    const double tol = (double)nc * 2.220446049250313e-16;
+    HIP_TRY(launch_jacobi<T>(R, nc, LPc, tol, 60, P.at<double>(L.sigma), P.at<double>(L.uhat_d), P.at<T>(L.uhat_p),
+                             P.at<T>(L.vhat_p), P.at<double>(L.scr_jac), flags, st));
+    return RSVD_OK;
+  }
+
+  // U = Q U_hat(:, :kout), V = B^T U_hat D^-1 (:, :kout), S = sigma(:kout) for a basis of nc columns.
+  rsvd_status lift(int nc, int kout, T* U, int64_t ldu, double* S, T* V, int64_t ldv) {
+    const int64_t m = P.d.m, n = P.d.n;
+    const int LPc = lp16(nc);
+    HIP_TRY((launch_tn<T, T, T, T>(P.at<T>(L.Q), L.ldm, nc, m, P.at<T>(L.uhat_p), LPc, kout, U, ldu, 0, 1, true, st)));
+    if (V)
+      HIP_TRY((launch_tn<T, T, T, T>(P.at<T>(L.Bt), L.ldn, nc, n, P.at<T>(L.vhat_p), LPc, kout, V, ldv, 0, 1, true,
+                                     st)));
+    HIP_TRY(hipMemcpyAsync(S, P.at<double>(L.sigma), (size_t)kout * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return RSVD_OK;
+  }
+
+  // H (nc x r, ld LPmax) <- U_hat_k U_hat_k^T H, the projector onto the k kept directions of the small SVD.
+  rsvd_status apply_pk(int nc, int kk, T* H) {
+    const int LPc = lp16(nc);
+    T* W1 = P.at<T>(L.small2);
+    HIP_TRY((launch_nn<T, T, T, T>(P.at<T>(L.uhat_p), LPc, kk, nc, H, L.LPmax, L.r, W1, L.LPmax, 0, 1, st)));
+    HIP_TRY((launch_tn<T, T, T, T>(P.at<T>(L.uhat_p), LPc, kk, nc, W1, L.LPmax, L.r, H, L.LPmax, 0, 1, false, st)));
+    return RSVD_OK;
+  }
+
+  rsvd_status max_colnorm(const T* E, double* h_max) {
+    double* nrm = P.at<double>(L.norms);
+    HIP_TRY(launch_colnorm<T>(E, L.ldm, P.d.m, L.r, nrm, st));
+    double h[64];
+    HIP_TRY(hipMemcpyAsync(h, nrm, (size_t)L.r * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double mx = 0.0;
+    for (int i = 0; i < L.r; ++i) mx = std::max(mx, h[i]);
+    *h_max = mx;
+    return RSVD_OK;
+  }
+
+  // Certificate (Section 14 with the Lemma of Section 13).  T = A - Q P B with P = U_hat_k U_hat_k^T (the
+  // rank-k result, kk > 0) or P = I (the rank-nc pair (Q, B), kk == 0); U D V^T = Q P B for the factors the
+  // library returns.  E = (T T^T)^s T Gc is left in the E panel; returns max_i ||E(:, i)||.
+  rsvd_status cert_residual(const T* A, int64_t lda, int nc, int kk, double* h_max) {
+    const int64_t m = P.d.m, n = P.d.n;
+    const int r = L.r;
+    const int dt = (sizeof(T) == 8) ? RSVD_F64 : RSVD_F32;   // the certificate judges A itself
+    T* E = P.at<T>(L.E);
+    T* H = P.at<T>(L.small);
+    T* tmp = P.at<T>(L.tmpr);
+    T* Zr = P.at<T>(L.zr);
+    T* tn_ = P.at<T>(L.tmpn);
+    T* Q = P.at<T>(L.Q);
+    T* Bt = P.at<T>(L.Bt);
+    // E = A Gc - Q P (B Gc)
+    HIP_TRY(hipMemcpyAsync(E, P.at<T>(L.agc), (size_t)r * L.ldm * sizeof(T), hipMemcpyDeviceToDevice, st));
+    RS_TRY(panel_tprod(Bt, nc, P.at<T>(L.gc), r, L.ldn, n, L.s_gn, H, L.LPmax));
+    if (kk > 0) RS_TRY(apply_pk(nc, kk, H));
+    RS_TRY(panel_mult(Q, nc, L.ldm, m, H, L.LPmax, r, tmp, L.ldm));
+    HIP_TRY(launch_axpy_panel<T>(E, L.ldm, tmp, L.ldm, m, r, T(-1), st));
+    for (int t = 0; t < P.d.est_power; ++t) {
+      // Zr = T^T E = A^T E - B^T P (Q^T E)
+      RS_TRY(apply_at(A, lda, E, r, Zr, dt));
+      RS_TRY(panel_tprod(Q, nc, E, r, L.ldm, m, L.s_gm, H, L.LPmax));
+      if (kk > 0) RS_TRY(apply_pk(nc, kk, H));
+      RS_TRY(panel_mult(Bt, nc, L.ldn, n, H, L.LPmax, r, tn_, L.ldn));
+      HIP_TRY(launch_axpy_panel<T>(Zr, L.ldn, tn_, L.ldn, n, r, T(-1), st));
+      // E = T Zr = A Zr - Q P (B Zr)
+      RS_TRY(apply_a(A, lda, Zr, r, E, dt));
+      RS_TRY(panel_tprod(Bt, nc, Zr, r, L.ldn, n, L.s_gn, H, L.LPmax));
+      if (kk > 0) RS_TRY(apply_pk(nc, kk, H));
+      RS_TRY(panel_mult(Q, nc, L.ldm, m, H, L.LPmax, r, tmp, L.ldm));
+      HIP_TRY(launch_axpy_panel<T>(E, L.ldm, tmp, L.ldm, m, r, T(-1), st));
+    }
+    return max_colnorm(E, h_max);
+  }
+
+  double bound_from(double mx) const {
+    const double c_alpha = 10.0 * sqrt(2.0 / 3.14159265358979323846);   // (1/alpha) sqrt(2/pi), alpha = 1/10
+    const int s = P.d.est_power;
+    return pow(c_alpha * mx, 1.0 / (2 * s + 1));
+  }
+
   rsvd_status run(const T* A, int64_t lda, const double* omega_in, T* U, int64_t ldu, double* S, T* V, int64_t ldv,
                   int kout) {
     const int64_t m = P.d.m, n = P.d.n;
+    const int l = L.l;
     T* omega = P.at<T>(L.omega);
     T* Y = P.at<T>(L.Y);
     T* Q = P.at<T>(L.Q);
     T* Z = P.at<T>(L.Z);
-    T* W = P.at<T>(L.W);
+    T* Wp = P.at<T>(L.Wp);
     T* Bt = P.at<T>(L.Bt);
     int* flags = P.at<int>(L.flags);
-    rsvd_status s;
+    P.rank_out = kout;
+    P.fallback_steps = 0;
+    P.err_bound = 0.0;
+    P.frob_res = -1.0;
     mark(0);
     HIP_TRY(launch_fill_int(flags, kFlags, 0, st));
     const int sk = P.d.sketch_dtype, pj = P.d.proj_dtype;
@@ -277,49 +440,99 @@ template <typename T> struct Path {
     else
       HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, l, 0, omega, 1, L.ldn, st));
     // (2): Q = orth(A Omega).
-    if ((s = apply_a(A, lda, omega, Y, sk)) != RSVD_OK) return s;
-    if ((s = orth(Y, L.ldm, m, L.s_gm, Q)) != RSVD_OK) return s;
+    RS_TRY(apply_a(A, lda, omega, l, Y, sk));
+    RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q));
     mark(1);
     // (3)-(6): q power steps with re-orthonormalisation.
     for (int it = 0; it < P.d.q; ++it) {
-      if ((s = apply_at(A, lda, Q, Z, sk)) != RSVD_OK) return s;
-      if ((s = orth(Z, L.ldn, n, L.s_gn, W)) != RSVD_OK) return s;
-      if ((s = apply_a(A, lda, W, Y, sk)) != RSVD_OK) return s;
-      if ((s = orth(Y, L.ldm, m, L.s_gm, Q)) != RSVD_OK) return s;
+      RS_TRY(apply_at(A, lda, Q, l, Z, sk));
+      RS_TRY(orth(Z, L.ldn, n, l, L.s_gn, Wp));
+      RS_TRY(apply_a(A, lda, Wp, l, Y, sk));
+      RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q));
     }
     mark(2);
     // (7): B = Q^T A, held as B^T (n x l panel).
-    if ((s = apply_at(A, lda, Q, Bt, pj)) != RSVD_OK) return s;
+    RS_TRY(apply_at(A, lda, Q, l, Bt, pj));
     mark(3);
-    // (8): SVD of B in FP64: B^T = Q_B R by CholeskyQR2, then Jacobi on R^T.
-    {
-      double* G = P.at<double>(L.G);
-      double* R1 = P.at<double>(L.R1);
-      double* R = P.at<double>(L.R);
-      double* rinv_d = P.at<double>(L.rinv_d);
-      double* Q1d = P.at<double>(L.Q1d);
-      double* gp = P.at<double>(L.gpart);
-      double* scr = P.at<double>(L.scr_chol);
-      double* gp2 = P.at<double>(L.gpart2);
-      HIP_TRY((launch_nn<T, T, double, double>(Bt, L.ldn, l, n, Bt, L.ldn, l, gp, LP, (int64_t)LP * LP, L.s_gn, st)));
-      HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LP * LP, LP, l, l, gp2, G, LP, st));
-      HIP_TRY(launch_chol<double>(G, LP, l, LP, tau, rinv_d, R1, nullptr, scr, flags, st));
-      HIP_TRY((launch_tn<T, double, double, double>(Bt, L.ldn, l, n, rinv_d, LP, l, Q1d, L.ldn, 0, 1, false, st)));
-      HIP_TRY((launch_nn<double, double, double, double>(Q1d, L.ldn, l, n, Q1d, L.ldn, l, gp, LP, (int64_t)LP * LP,
-                                                         L.s_gn, st)));
-      HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LP * LP, LP, l, l, gp2, G, LP, st));
-      HIP_TRY(launch_chol<double>(G, LP, l, LP, tau, rinv_d, R, R1, scr, flags, st));
-      const double tol = (double)l * 2.220446049250313e-16;
-      HIP_TRY(launch_jacobi<T>(R, l, LP, tol, 60, P.at<double>(L.sigma), P.at<double>(L.uhat_d), P.at<T>(L.uhat_p),
-                               P.at<T>(L.vhat_p), P.at<double>(L.scr_jac), flags, st));
-    }
+    // (8): SVD of B in FP64.
+    RS_TRY(small_svd(l));
     mark(4);
-    // (9): U = Q U_hat and V = B^T U_hat D^-1, leading kout columns, row-major.
-    HIP_TRY((launch_tn<T, T, T, T>(Q, L.ldm, l, m, P.at<T>(L.uhat_p), LP, kout, U, ldu, 0, 1, true, st)));
-    if (V) HIP_TRY((launch_tn<T, T, T, T>(Bt, L.ldn, l, n, P.at<T>(L.vhat_p), LP, kout, V, ldv, 0, 1, true, st)));
-    HIP_TRY(hipMemcpyAsync(S, P.at<double>(L.sigma), (size_t)kout * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // (9): U = Q U_hat, V = B^T U_hat D^-1, leading kout columns.
+    RS_TRY(lift(l, kout, U, ldu, S, V, ldv));
     mark(5);
-    return RSVD_OK;
+    if (P.d.eps <= 0.0) return RSVD_OK;
+
+    // Certificate of Section 14 on the rank-k result, relative to sigma_hat_1.
+    const int r = L.r;
+    HIP_TRY(launch_gaussian<T>(P.d.seed, 6u, n, r, 0, P.at<T>(L.gc), 1, L.ldn, st));
+    {
+      const int dt = (sizeof(T) == 8) ? RSVD_F64 : RSVD_F32;
+      RS_TRY(apply_a(A, lda, P.at<T>(L.gc), r, P.at<T>(L.agc), dt));
+    }
+    double sig1 = 0.0;
+    HIP_TRY(hipMemcpyAsync(&sig1, P.at<double>(L.sigma), sizeof(double), hipMemcpyDeviceToHost, st));
+    double mx = 0.0;
+    RS_TRY(cert_residual(A, lda, l, kout, &mx));
+    P.err_bound = bound_from(mx);
+    const double target = P.d.eps * sig1;
+    mark(6);
+    if (P.err_bound <= target) { mark(7); return RSVD_OK; }
+
+    // Blocked adaptive range finder (Figure 12) with the residual applied implicitly.
+    int lc = l;
+    RS_TRY(cert_residual(A, lda, lc, 0, &mx));
+    P.err_bound = bound_from(mx);
+    const int b = L.b;
+    int step = 0;
+    T* tmp = P.at<T>(L.tmpr);
+    T* C = P.at<T>(L.small);
+    while (P.err_bound > target && lc + b <= L.lmax) {
+      // b more Gaussian columns: the continuation of Omega's column sequence
+      HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, b, l + (int64_t)step * b, omega, 1, L.ldn, st));
+      RS_TRY(apply_a(A, lda, omega, b, Y, sk));
+      for (int pass = 0; pass < 2; ++pass) {   // Y <- (I - Q Q^T) Y, twice
+        RS_TRY(panel_tprod(Q, lc, Y, b, L.ldm, m, L.s_gm, C, L.LPmax));
+        RS_TRY(panel_mult(Q, lc, L.ldm, m, C, L.LPmax, b, tmp, L.ldm));
+        HIP_TRY(launch_axpy_panel<T>(Y, L.ldm, tmp, L.ldm, m, b, T(-1), st));
+      }
+      T* Qn = Q + (int64_t)lc * L.ldm;
+      RS_TRY(orth(Y, L.ldm, m, b, L.s_gm, Qn));
+      T* Bn = Bt + (int64_t)lc * L.ldn;
+      RS_TRY(apply_at(A, lda, Qn, b, Bn, pj));
+      lc += b;
+      ++step;
+      if (P.d.est_power == 0) {
+        // E <- E - Q_new (B_new Gc): the residual sample follows the growth exactly
+        RS_TRY(panel_tprod(Bn, b, P.at<T>(L.gc), r, L.ldn, n, L.s_gn, C, L.LPmax));
+        RS_TRY(panel_mult(Qn, b, L.ldm, m, C, L.LPmax, r, tmp, L.ldm));
+        T* E = P.at<T>(L.E);
+        HIP_TRY(launch_axpy_panel<T>(E, L.ldm, tmp, L.ldm, m, r, T(-1), st));
+        RS_TRY(max_colnorm(E, &mx));
+      } else {
+        RS_TRY(cert_residual(A, lda, lc, 0, &mx));
+      }
+      P.err_bound = bound_from(mx);
+    }
+    P.fallback_steps = step;
+    // Section 12.4: ||A - Q B||_F^2 = ||A||_F^2 - ||B||_F^2 (reported)
+    {
+      double* fr = P.at<double>(L.frob);
+      HIP_TRY(launch_frob2<T>(A, lda, m, n, fr, fr + 1032, st));
+      RS_TRY(gram(Bt, L.ldn, n, lc, L.s_gn, P.at<double>(L.G)));
+      double a2 = 0.0;
+      HIP_TRY(hipMemcpyAsync(&a2, fr + 1032, sizeof(double), hipMemcpyDeviceToHost, st));
+      std::vector<double> g((size_t)lp16(lc) * lp16(lc));
+      HIP_TRY(hipMemcpyAsync(g.data(), P.at<double>(L.G), g.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      double b2 = 0.0;
+      for (int i = 0; i < lc; ++i) b2 += g[(size_t)i * lp16(lc) + i];
+      P.frob_res = sqrt(std::max(a2 - b2, 0.0));
+    }
+    RS_TRY(small_svd(lc));
+    RS_TRY(lift(lc, lc, U, ldu, S, V, ldv));
+    P.rank_out = lc;
+    mark(7);
+    return (P.err_bound <= target) ? RSVD_OK : RSVD_NOT_CERTIFIED;
   }
 };
 
@@ -391,7 +604,8 @@ rsvd_status rsvd_factor(rsvd_plan_t p, const void* d_A, int64_t lda, const doubl
   const rsvd_desc& d = p->d;
   const int l = d.k + d.p;
   const int kout = (d.flags & RSVD_RETURN_RANK_L) ? l : d.k;
-  if (lda < d.n || ldu < kout || (d_V && ldv < kout)) return RSVD_E_ARG;
+  const int cap = d.eps > 0.0 ? std::max(kout, p->L.lmax) : kout;
+  if (lda < d.n || ldu < cap || (d_V && ldv < cap)) return RSVD_E_ARG;
   rsvd_status s;
   p->ngemm = 0;
   if (d.a_dtype == RSVD_F64) {
@@ -403,34 +617,47 @@ rsvd_status rsvd_factor(rsvd_plan_t p, const void* d_A, int64_t lda, const doubl
     s = path.run(static_cast<const float*>(d_A), lda, d_Omega, static_cast<float*>(d_U), ldu, d_S,
                  static_cast<float*>(d_V), ldv, kout);
   }
-  if (s != RSVD_OK) return s;
-  if (h_info) {
-    memset(h_info, 0, sizeof(*h_info));
+  if (s < 0) return s;
+  const bool need_sync = h_info || d.eps > 0.0;
+  if (need_sync) {
     int flags[kFlags];
     HIP_TRY(hipMemcpyAsync(flags, p->ws + p->L.flags, sizeof(flags), hipMemcpyDeviceToHost, p->st));
     HIP_TRY(hipStreamSynchronize(p->st));
-    double s1 = 0.0;
-    HIP_TRY(hipMemcpy(&s1, d_S, sizeof(double), hipMemcpyDeviceToHost));
-    h_info->p_used = d.p;
-    h_info->q_used = d.q;
-    h_info->rank_out = kout;
-    h_info->sigma1 = s1;
-    h_info->orth_retries = 0;
-    if (p->timing) {
-      for (int i = 0; i < 5; ++i) (void)hipEventElapsedTime(&h_info->stage_ms[i], p->ev[i], p->ev[i + 1]);
-      (void)hipEventElapsedTime(&h_info->stage_ms[7], p->ev[0], p->ev[5]);
-      for (int i = 0; i < p->ngemm; ++i) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, p->gev[2 * i], p->gev[2 * i + 1]);
-        if (p->gkind[i] == 0) { h_info->nn_ms += ms; h_info->nn_launches++; }
-        else { h_info->tn_ms += ms; h_info->tn_launches++; }
-      }
-    }
-    h_info->jacobi_sweeps = flags[3];
-    h_info->dropped_cols = flags[1];
     if (flags[0] > 0 || flags[4] != 0) s = RSVD_E_NONFINITE;
-    h_info->status = s;
-    RSVD_LOGF("factor done: nonfinite=%d dropped=%d jacobi_nonconv=%d", flags[0], flags[1], flags[2]);
+    if (h_info) {
+      memset(h_info, 0, sizeof(*h_info));
+      double s1 = 0.0;
+      HIP_TRY(hipMemcpy(&s1, d_S, sizeof(double), hipMemcpyDeviceToHost));
+      h_info->p_used = d.p;
+      h_info->q_used = d.q;
+      h_info->rank_out = p->rank_out;
+      h_info->fallback_steps = p->fallback_steps;
+      h_info->err_bound = p->err_bound;
+      h_info->frob_residual = p->frob_res;
+      h_info->sigma1 = s1;
+      h_info->orth_retries = 0;
+      if (p->timing) {
+        for (int i = 0; i < 5; ++i) (void)hipEventElapsedTime(&h_info->stage_ms[i], p->ev[i], p->ev[i + 1]);
+        const int last = d.eps > 0.0 ? 7 : 5;
+        if (d.eps > 0.0) {
+          (void)hipEventElapsedTime(&h_info->stage_ms[5], p->ev[5], p->ev[6]);
+          if (p->fallback_steps > 0 || p->rank_out != kout)
+            (void)hipEventElapsedTime(&h_info->stage_ms[6], p->ev[6], p->ev[7]);
+        }
+        (void)hipEventElapsedTime(&h_info->stage_ms[7], p->ev[0], p->ev[last]);
+        for (int i = 0; i < p->ngemm; ++i) {
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, p->gev[2 * i], p->gev[2 * i + 1]);
+          if (p->gkind[i] == 0) { h_info->nn_ms += ms; h_info->nn_launches++; }
+          else { h_info->tn_ms += ms; h_info->tn_launches++; }
+        }
+      }
+      h_info->jacobi_sweeps = flags[3];
+      h_info->dropped_cols = flags[1];
+      h_info->status = s;
+    }
+    RSVD_LOGF("factor done: status=%d nonfinite=%d dropped=%d jacobi_nonconv=%d bound=%g rank=%d", (int)s, flags[0],
+              flags[1], flags[2], p->err_bound, p->rank_out);
   }
   return s;
 }

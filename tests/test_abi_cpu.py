@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_the_header(lib):
     from paper_1607_01649_amd._lib import rsvd_desc, rsvd_info
     assert ctypes.sizeof(rsvd_desc) == 80
-    assert ctypes.sizeof(rsvd_info) == 96
+    assert ctypes.sizeof(rsvd_info) == 104
     assert rsvd_desc.seed.offset == 40 and rsvd_desc.eps.offset == 48 and rsvd_desc.flags.offset == 72
     assert rsvd_info.err_bound.offset == 24 and rsvd_info.stage_ms.offset == 40 and rsvd_info.nn_launches.offset == 80
 
@@ -76,7 +76,7 @@ def test_workspace_size_for_valid_descriptions(lib):
     dict(k=790, p=20),                 # k + p > min(m, n)
     dict(eps=-1.0), dict(eps=float("nan")),
     dict(a_dtype=7), dict(max_rank=5),  # max_rank below k + p
-    dict(n_probe=-1), dict(est_power=-2),
+    dict(n_probe=-1), dict(est_power=-2), dict(n_probe=65), dict(fallback_block=300),
 ])
 def test_invalid_descriptions_are_rejected_on_the_host(lib, kw):
     st, _ = _ws(lib, _desc(**kw))

@@ -201,3 +201,72 @@ def test_factor_bf16_matches_the_quantisation_aware_oracle(m, n, rank, alpha, k,
     assert subspace_sin(U, qa.U[:, :k]) <= 50 * math.sqrt(max(m, n)) * U32 / relgap
     print(f"bf16 format error vs plain oracle: max rel sigma {max_rel_sigma(S, plain.D, k):.2e}")
     assert max_rel_sigma(S, plain.D, k) <= 2e-2
+
+
+# ---------------------------------------------------------------- certificate and fallback
+
+def _cert_case(seed=95, m=700, n=500, tau=10.0):
+    sigma = gen.spectrum("exp", 300, tau=tau)
+    return gen.low_rank_matrix(m, n, sigma, 0.0, seed=seed)
+
+
+@pytest.mark.parametrize("s", [0, 1])
+def test_certificate_matches_the_oracle(s):
+    """Section 14: bound = 10 sqrt(2/pi) max_i ||(A - U D V^T) g_i|| with the
+    probes drawn from the same seed on both sides; with eps loose enough the
+    rank-k result is accepted as is."""
+    A = _cert_case()
+    k, p, q, seed = 12, 8, 1, 5
+    # eps far above the bound: accepted at rank k on both sides, bounds compared
+    ref = orc.factor(A, k, p, q, seed, eps=100.0, n_probe=10, est_power=s)
+    assert ref.certified and ref.rank == k
+    U, S, V, info = run_factor(A, k, p, q, "f64", seed=seed, eps=100.0, n_probe=10, est_power=s)
+    assert info.status == 0 and info.rank_out == k and info.fallback_steps == 0
+    assert abs(info.err_bound - ref.bound) <= 1e-8 * ref.bound
+    assert max_rel_sigma(S, ref.D, k) <= 1e-10
+    true = np.linalg.norm(A - (U * S) @ V.T, 2)
+    assert info.err_bound >= true
+
+
+@pytest.mark.parametrize("dtype,sk,pj,b,eps", [("f64", "f64", "f64", 8, 1e-4), ("f32", "f32", "f32", 16, 1e-4),
+                                               ("f32", "bf16", "f32", 8, 1e-3)])
+def test_fallback_grows_to_the_tolerance_like_the_oracle(dtype, sk, pj, b, eps):
+    """The rank-k result misses eps; the blocked range finder of Figure 12
+    grows the basis (columns continuing Omega's sequence, two projections per
+    block) until the Section 14 certificate holds, as the oracle does.  A bf16
+    sketch only has to span; the projection B = Q^T A stays FP32 here, since
+    its rounding error enters the residual the certificate measures."""
+    A = _cert_case(seed=96)
+    k, p, q, seed = 10, 5, 1, 7
+    sk_, pj_ = sk, pj
+    ref = orc.factor(A, k, p, q, seed, eps=eps, block=b, max_rank=150)
+    assert ref.certified and ref.fallback_steps > 0
+    Ain = A if dtype == "f64" else A.astype(np.float32)
+    U, S, V, info = run_factor(Ain, k, p, q, dtype, seed=seed, eps=eps, fallback_block=b, max_rank=150,
+                               sketch_dtype=sk_, proj_dtype=pj_)
+    assert info.status == 0
+    if dtype == "f64":
+        assert info.rank_out == ref.rank and info.fallback_steps == ref.fallback_steps
+        assert abs(info.err_bound - ref.bound) <= 1e-6 * ref.bound
+        r = ref.rank
+        assert max_rel_sigma(S, ref.D, min(r, 40)) <= 1e-9
+    else:
+        assert abs(info.rank_out - ref.rank) <= b
+    true = np.linalg.norm(A - (U * S) @ V.T, 2)
+    assert true <= eps * S[0] * 1.01
+    assert info.err_bound <= eps * info.sigma1
+    assert info.err_bound >= true * (1 - 1e-6)
+    # Section 12.4: the downdated Frobenius residual matches the direct one
+    QB_res = np.linalg.norm(A - (U * S) @ V.T)
+    assert abs(info.frob_residual - QB_res) <= 1e-3 * np.linalg.norm(A) + 1e-6
+
+
+def test_not_certified_when_the_rank_cap_is_reached():
+    A = _cert_case(seed=97)
+    U, S, V, info = run_factor(A, 10, 5, 0, "f64", seed=3, eps=1e-8, fallback_block=8, max_rank=31)
+    assert info.status == 1                 # RSVD_NOT_CERTIFIED: factors written, tolerance missed
+    assert info.rank_out == 31 and info.fallback_steps == 2
+    assert info.err_bound > 1e-8 * info.sigma1
+    ref = orc.factor(A, 10, 5, 0, 3, eps=1e-8, block=8, max_rank=31)
+    assert ref.rank == 31 and not ref.certified
+    assert max_rel_sigma(S, ref.D, 31) <= 1e-9
