@@ -182,6 +182,52 @@ rsvd_status rsvd_factor(rsvd_plan_t plan, const void* d_A, int64_t lda, const do
 void rsvd_destroy(rsvd_plan_t plan);
 
 /*
+ * Batched compression of many independent blocks to a relative tolerance, in
+ * one persistent launch (the given-tolerance problem of Sections 12-14 per
+ * block).  Block b (0 <= b < nblk) is d_A[b] (device pointer), m_b x n_b FP32
+ * row-major with leading dimension lda_b >= n_b, 16 <= m_b, n_b <= 512.  Per
+ * block: l0 = 16 Gaussian columns, Q = orth(A Omega) and B = Q^T A in FP64
+ * accumulation; certificate of the pair (Q, B) with 10 probes (Section 14);
+ * while 10 sqrt(2/pi) max_i ||(A - QB) g_i|| > eps sigma_hat_1 / 2 the basis
+ * grows by 8 columns (Figure 12, Omega's continuation, projected twice);
+ * then the SVD of B and the singular values > eps sigma_hat_1 / 2 are kept,
+ * so that ||A - U S V^T|| <= eps sigma_hat_1 with the certificate's
+ * probability.  sigma_hat_1 = largest singular value of the first B.
+ * Random streams per block: 16 b + 4 (Omega), 16 b + 6 (probes), key = seed.
+ * Outputs (device): U_b at d_U + d_offU[b], m_b x rank_cap row-major (ld =
+ * rank_cap); V_b at d_V + d_offV[b], n_b x rank_cap; S_b at d_S + b*rank_cap;
+ * d_rank[b] = columns kept; d_status[b] = 0 certified, 1 not certified at the
+ * rank cap, -1 invalid block shape, -4 non-finite entries.
+ * eps in (0, 1); 16 <= rank_cap <= 64.  n_workgroups = persistent workgroups
+ * (0 = two per compute unit).  Blocks are taken largest first from an atomic
+ * queue.  Fully asynchronous; no host synchronisation; capturable.
+ * Workspace: rsvd_batched_workspace_size(nblk, n_workgroups).
+ * Errors: RSVD_E_ARG, RSVD_E_WORKSPACE, RSVD_E_HIP.
+ */
+rsvd_status rsvd_batched_workspace_size(int32_t nblk, int32_t n_workgroups, size_t* h_bytes);
+rsvd_status rsvd_batched(int32_t nblk, const int32_t* d_m, const int32_t* d_n, const float* const* d_A,
+                         const int32_t* d_lda, double eps, int32_t rank_cap, uint64_t seed, float* d_U, double* d_S,
+                         float* d_V, const int64_t* d_offU, const int64_t* d_offV, int32_t* d_rank,
+                         int32_t* d_status, int32_t n_workgroups, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Capture one rsvd_batched call (same arguments) on `stream` (not the NULL
+ * stream) into a HIP graph and instantiate it; rsvd_graph_launch replays it
+ * on any stream (the buffers named at capture are reused).  The sequence
+ * contains kernels only (no memset nodes).
+ * Errors: RSVD_E_ARG, RSVD_E_WORKSPACE, RSVD_E_HIP.
+ */
+typedef struct rsvd_graph_s* rsvd_graph_t;
+rsvd_status rsvd_batched_graph_create(int32_t nblk, const int32_t* d_m, const int32_t* d_n,
+                                      const float* const* d_A, const int32_t* d_lda, double eps, int32_t rank_cap,
+                                      uint64_t seed, float* d_U, double* d_S, float* d_V, const int64_t* d_offU,
+                                      const int64_t* d_offV, int32_t* d_rank, int32_t* d_status,
+                                      int32_t n_workgroups, void* d_ws, size_t ws_bytes, void* stream,
+                                      rsvd_graph_t* h_out);
+rsvd_status rsvd_graph_launch(rsvd_graph_t graph, void* stream);
+void rsvd_graph_destroy(rsvd_graph_t graph);
+
+/*
  * Draw columns col0 .. col0+cols-1 of the Gaussian family (seed, stream) for
  * rows 0 .. rows-1 into d_out (row-major, leading dimension ld >= cols),
  * dtype RSVD_F64 or RSVD_F32, by the Philox/Box-Muller mapping described at

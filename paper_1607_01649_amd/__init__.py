@@ -154,3 +154,87 @@ class RSVD:
             except Exception:
                 pass
             self.plan = None
+
+
+class Batched:
+    """Batched compression of a list of FP32 blocks (device tensors, 2-D,
+    unit column stride) to relative tolerance `eps`: device arrays of shapes,
+    pointers, output offsets and the workspace are built once; `run()`
+    launches rsvd_batched, `capture()` records it into a HIP graph and
+    `replay()` launches the graph.  Outputs: U (sum m_b x rank_cap),
+    V (sum n_b x rank_cap), S (nblk x rank_cap), rank, status."""
+
+    def __init__(self, blocks, eps=1e-6, rank_cap=64, seed=0, n_workgroups=0, stream=None):
+        self.blocks = list(blocks)
+        dev = self.blocks[0].device
+        self.device = dev
+        nb = len(self.blocks)
+        ms = [b.shape[0] for b in self.blocks]
+        ns = [b.shape[1] for b in self.blocks]
+        self.m = torch.tensor(ms, dtype=torch.int32, device=dev)
+        self.n = torch.tensor(ns, dtype=torch.int32, device=dev)
+        self.lda = torch.tensor([b.stride(0) for b in self.blocks], dtype=torch.int32, device=dev)
+        self.ptrs = torch.tensor([b.data_ptr() for b in self.blocks], dtype=torch.int64, device=dev)
+        offu = [0]
+        offv = [0]
+        for mm, nn in zip(ms, ns):
+            offu.append(offu[-1] + mm * rank_cap)
+            offv.append(offv[-1] + nn * rank_cap)
+        self.offU = torch.tensor(offu[:-1], dtype=torch.int64, device=dev)
+        self.offV = torch.tensor(offv[:-1], dtype=torch.int64, device=dev)
+        self.U = torch.zeros(offu[-1], dtype=torch.float32, device=dev)
+        self.V = torch.zeros(offv[-1], dtype=torch.float32, device=dev)
+        self.S = torch.zeros(nb, rank_cap, dtype=torch.float64, device=dev)
+        self.rank = torch.zeros(nb, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(nb, dtype=torch.int32, device=dev)
+        self.eps, self.rank_cap, self.seed, self.nwg = float(eps), int(rank_cap), int(seed), int(n_workgroups)
+        nbytes = ctypes.c_size_t(0)
+        st = _lib.lib().rsvd_batched_workspace_size(nb, self.nwg, ctypes.byref(nbytes))
+        if st != RSVD_OK:
+            raise RSVDError(st, "rsvd_batched_workspace_size")
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        self.ws = ws[off:off + nbytes.value]
+        self.stream = stream
+        self.graph = None
+
+    def _args(self):
+        return (len(self.blocks), _ptr(self.m), _ptr(self.n), _ptr(self.ptrs), _ptr(self.lda), self.eps,
+                self.rank_cap, self.seed, _ptr(self.U), _ptr(self.S), _ptr(self.V), _ptr(self.offU),
+                _ptr(self.offV), _ptr(self.rank), _ptr(self.status), self.nwg, _ptr(self.ws),
+                self.ws.numel())
+
+    def run(self):
+        st = _lib.lib().rsvd_batched(*self._args(), _stream_handle(self.device, self.stream))
+        if st != RSVD_OK:
+            raise RSVDError(st, "rsvd_batched")
+
+    def capture(self, stream):
+        h = ctypes.c_void_p()
+        st = _lib.lib().rsvd_batched_graph_create(*self._args(), ctypes.c_void_p(stream.cuda_stream),
+                                                  ctypes.byref(h))
+        if st != RSVD_OK:
+            raise RSVDError(st, "rsvd_batched_graph_create")
+        self.graph = h
+
+    def replay(self, stream):
+        st = _lib.lib().rsvd_graph_launch(self.graph, ctypes.c_void_p(stream.cuda_stream))
+        if st != RSVD_OK:
+            raise RSVDError(st, "rsvd_graph_launch")
+
+    def factors(self, b):
+        """(U_b, S_b, V_b) of block b (host copies, rank columns)."""
+        r = int(self.rank[b])
+        mm, nn = self.blocks[b].shape
+        ou, ov = int(self.offU[b]), int(self.offV[b])
+        U = self.U[ou:ou + mm * self.rank_cap].view(mm, self.rank_cap)[:, :r]
+        V = self.V[ov:ov + nn * self.rank_cap].view(nn, self.rank_cap)[:, :r]
+        return U, self.S[b, :r], V
+
+    def __del__(self):
+        if getattr(self, "graph", None) is not None:
+            try:
+                _lib.lib().rsvd_graph_destroy(self.graph)
+            except Exception:
+                pass
+            self.graph = None

@@ -71,6 +71,18 @@ SIGNATURES = [
                                      _i64, _c_void_p]),
     ("rsvd_philox4x32_10", ctypes.c_int, [_i64, _c_void_p, ctypes.c_uint32, ctypes.c_uint32, _c_void_p,
                                           _c_void_p]),
+    ("rsvd_batched_workspace_size", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("rsvd_batched", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, ctypes.c_double,
+                                    ctypes.c_int32, ctypes.c_uint64, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                    _c_void_p, _c_void_p, _c_void_p, ctypes.c_int32, _c_void_p, ctypes.c_size_t,
+                                    _c_void_p]),
+    ("rsvd_batched_graph_create", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                                 ctypes.c_double, ctypes.c_int32, ctypes.c_uint64, _c_void_p,
+                                                 _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                                 ctypes.c_int32, _c_void_p, ctypes.c_size_t, _c_void_p,
+                                                 ctypes.POINTER(_c_void_p)]),
+    ("rsvd_graph_launch", ctypes.c_int, [_c_void_p, _c_void_p]),
+    ("rsvd_graph_destroy", None, [_c_void_p]),
     # include/rsvd_kernels.h
     ("rsvd_k_product_nn", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, _c_void_p, _i64,
                                          ctypes.c_int32, _c_void_p, _i64, _c_void_p]),

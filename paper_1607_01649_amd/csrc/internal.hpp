@@ -49,6 +49,15 @@ hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t rows, int64_t 
                           int ncols, float* out, int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
 int lp_splits_used(int64_t K, int splits);
 
+// batched.hip
+int batched_scratch_doubles_per_wg();
+int batched_max_rank();
+int batched_max_dim();
+hipError_t launch_batched(int nblk, const int* m, const int* n, const float* const* A, const int* lda, double eps,
+                          int rank_cap, uint64_t seed, float* U, double* S, float* V, const int64_t* offU,
+                          const int64_t* offV, int* rank, int* status, int* order, int* queue, double* scratch,
+                          int nwg, hipStream_t s);
+
 // misc.hip
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 template <typename T>
