@@ -32,7 +32,9 @@ constexpr int RMAX = 64;      // max basis width
 constexpr int L0 = 16;        // initial sketch width
 constexpr int BG = 8;         // growth block
 constexpr int NP = 10;        // certificate probes
-constexpr int CH = 64;        // rows per LDS chunk
+constexpr int CH = 64;        // rows per LDS chunk of the cross-thread sums
+constexpr int KC = 16;        // columns of K per staged tile in the row-owned products
+constexpr int KLD = KC + 1;   // LDS pitch of a staged K row
 
 struct BatchedArgs {
   int nblk;
@@ -83,11 +85,11 @@ __device__ __forceinline__ void bgauss_pair(uint64_t seed, uint32_t stream, uint
   z1 = rad * sin(th);
 }
 
-// Stage rows [j0, j0+CH) of `nc` Gaussian columns into lds[jj*ldl + c] (zero past n):
+// Stage rows [j0, j0+KC) of `nc` Gaussian columns into lds[jj*ldl + c] (zero past n):
 // columns [0, nc0) from stream s0 starting at column col0, columns [nc0, nc) from stream s1.
 __device__ void stage_gauss(double* lds, int ldl, int j0, int n, int nc, int nc0, uint64_t seed, uint32_t s0,
                             int col0, uint32_t s1) {
-  const int pairs = CH / 2;
+  const int pairs = KC / 2;
   for (int t = threadIdx.x; t < pairs * nc; t += BT) {
     int c = t / pairs, i2 = t - (t / pairs) * pairs;
     int j = j0 + 2 * i2;
@@ -98,6 +100,16 @@ __device__ void stage_gauss(double* lds, int ldl, int j0, int n, int nc, int nc0
     }
     lds[(2 * i2) * ldl + c] = z0;
     lds[(2 * i2 + 1) * ldl + c] = (j + 1 < n) ? z1 : 0.0;
+  }
+}
+
+// Stage columns [j0, j0+KC) of rows [0, m) of K into tile[r*KLD + c] (zero past n).  Each
+// group of KC threads reads KC consecutive floats of one row, so the global reads are
+// contiguous; the odd LDS row pitch keeps the row-per-thread reads conflict-free.
+__device__ void stage_k(const float* __restrict__ A, int lda, int m, int n, int j0, float* tile) {
+  for (int t = threadIdx.x; t < m * KC; t += BT) {
+    const int r = t / KC, c = t - (t / KC) * KC;
+    tile[r * KLD + c] = (j0 + c < n) ? A[(int64_t)r * lda + j0 + c] : 0.0f;
   }
 }
 
@@ -176,53 +188,94 @@ __device__ void small_chol_inv(double* G, double* Tm, double* Ri, double tau) {
   __syncthreads();
 }
 
-// Eigen-decomposition of the symmetric nc x nc matrix M (LDS, ld RMAX) by cyclic Jacobi,
-// eigenvectors in Vm (ld RMAX).  Wave 0 only (lane k owns index k); the caller syncs.
-__device__ void small_eig(double* M_, double* Vm_, int nc) {
-  if (threadIdx.x >= 64) return;
-  volatile double* M = M_;
-  volatile double* Vm = Vm_;
-  const int k = threadIdx.x;
-  for (int a = 0; a < nc; ++a) Vm[a * RMAX + k] = (a == k) ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int a = 0; a < nc; ++a)
-      if (k < nc) {
-        double v = M[a * RMAX + k];
-        if (a == k) dia += v * v; else off += v * v;
+// Eigen-decomposition of the symmetric positive semi-definite nc x nc matrix M (LDS, ld
+// RMAX, nc <= RMAX) by two-sided Jacobi with the parallel round-robin ordering: with
+// N = nc rounded up to even (a zero dummy row and column when nc is odd), each of the N-1
+// rounds of a sweep rotates N/2 disjoint pairs at once, so one round is one update
+// M <- J^T M J, V <- V J by all threads.  Pairs of round r (circle method): player N-1
+// meets r, and (r + i) mod (N-1) meets (r - i) mod (N-1) for i = 1 .. N/2-1.  A pair is
+// skipped when its off-diagonal entry is negligible relative to its own diagonal (1e-15)
+// or to the largest diagonal entry (1e-16: below that it is rounding noise of M); the
+// sweeps end when one passes without a rotation (at most 30).  Eigenvectors in Vm (ld
+// RMAX); eigenvalues on the diagonal of M.  All threads call it; it ends with a sync.
+__device__ void small_eig(double* M, double* Vm, int nc) {
+  __shared__ double cf[RMAX], df[RMAX], nd[RMAX];
+  __shared__ int prt[RMAX], rot[RMAX];
+  __shared__ int any_rot;
+  __shared__ double dmax_s;
+  constexpr int PER = RMAX * RMAX / BT;
+  const int tid = threadIdx.x;
+  const int N = (nc + 1) & ~1;
+  for (int t = tid; t < N * N; t += BT) {
+    const int a = t / N, b = t - (t / N) * N;
+    Vm[a * RMAX + b] = (a == b) ? 1.0 : 0.0;
+    if (a == nc || b == nc) M[a * RMAX + b] = 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (tid == 0) {
+      double d = 0.0;
+      for (int a = 0; a < nc; ++a) d = fmax(d, M[a * RMAX + a]);
+      dmax_s = d;
+      any_rot = 0;
+    }
+    __syncthreads();
+    const double dmax = dmax_s;
+    for (int r = 0; r < N - 1; ++r) {
+      if (tid < N / 2) {
+        int p = (tid == 0) ? N - 1 : (r + tid) % (N - 1);
+        int q = (r - tid + (N - 1)) % (N - 1);
+        if (p > q) { const int x = p; p = q; q = x; }
+        const double apq = M[p * RMAX + q], app = M[p * RMAX + p], aqq = M[q * RMAX + q];
+        double c = 1.0, sn = 0.0, tapq = 0.0;
+        const bool go = !(fabs(apq) <= 1e-15 * sqrt(fabs(app * aqq)) || fabs(apq) <= 1e-16 * dmax);
+        if (go) {
+          const double th = (aqq - app) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          sn = t * c;
+          tapq = t * apq;
+          any_rot = 1;
+        }
+        prt[p] = q; prt[q] = p;
+        cf[p] = c; df[p] = -sn;
+        cf[q] = c; df[q] = sn;
+        nd[p] = app - tapq; nd[q] = aqq + tapq;
+        rot[p] = go; rot[q] = go;
       }
-    off = wave_sum(off);
-    dia = wave_sum(dia);
-    if (off <= 1e-30 * dia) break;
-    for (int p = 0; p < nc - 1; ++p)
-      for (int q = p + 1; q < nc; ++q) {
-        double apq = M[p * RMAX + q];
-        double app = M[p * RMAX + p], aqq = M[q * RMAX + q];
-        if (fabs(apq) <= 1e-300 + 1e-17 * sqrt(fabs(app * aqq))) continue;
-        double th = (aqq - app) / (2.0 * apq);
-        double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        double mkp = 0.0, mkq = 0.0;
-        if (k < nc) { mkp = M[k * RMAX + p]; mkq = M[k * RMAX + q]; }
-        double vkp = Vm[k * RMAX + p], vkq = Vm[k * RMAX + q];
-        __builtin_amdgcn_wave_barrier();
-        if (k < nc && k != p && k != q) {
-          double np_ = c * mkp - s * mkq, nq_ = s * mkp + c * mkq;
-          M[k * RMAX + p] = np_; M[p * RMAX + k] = np_;
-          M[k * RMAX + q] = nq_; M[q * RMAX + k] = nq_;
+      __syncthreads();
+      double mv[PER], vv[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int t = tid + u * BT;
+        mv[u] = 0.0;
+        vv[u] = 0.0;
+        if (t < N * N) {
+          const int x = t / N, y = t - (t / N) * N;
+          const int px = prt[x], py = prt[y];
+          const double cx = cf[x], dx = df[x], cy = cf[y], dy = df[y];
+          if (x == y) mv[u] = nd[x];
+          else if (py == x && rot[x]) mv[u] = 0.0;
+          else
+            mv[u] = cx * (cy * M[x * RMAX + y] + dy * M[x * RMAX + py]) +
+                    dx * (cy * M[px * RMAX + y] + dy * M[px * RMAX + py]);
+          vv[u] = cy * Vm[x * RMAX + y] + dy * Vm[x * RMAX + py];
         }
-        if (k == 0) {
-          M[p * RMAX + p] = app - t * apq;
-          M[q * RMAX + q] = aqq + t * apq;
-          M[p * RMAX + q] = 0.0;
-          M[q * RMAX + p] = 0.0;
-        }
-        if (k < nc) {
-          Vm[k * RMAX + p] = c * vkp - s * vkq;
-          Vm[k * RMAX + q] = s * vkp + c * vkq;
-        }
-        __builtin_amdgcn_wave_barrier();
       }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int t = tid + u * BT;
+        if (t < N * N) {
+          const int x = t / N, y = t - (t / N) * N;
+          M[x * RMAX + y] = mv[u];
+          Vm[x * RMAX + y] = vv[u];
+        }
+      }
+      __syncthreads();
+    }
+    if (!any_rot) break;
+    __syncthreads();
   }
 }
 
@@ -269,19 +322,20 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
       double y[L0 + NP];
 #pragma unroll
       for (int c = 0; c < L0 + NP; ++c) y[c] = 0.0;
-      for (int j0 = 0; j0 < n; j0 += CH) {
+      float* tile = reinterpret_cast<float*>(lds + KC * (L0 + NP));
+      for (int j0 = 0; j0 < n; j0 += KC) {
         __syncthreads();
         stage_gauss(lds, L0 + NP, j0, n, L0 + NP, L0, g.seed, s_om, 0, s_pr);
+        stage_k(A, lda, m, n, j0, tile);
         __syncthreads();
-        for (int t = tid; t < CH * NP; t += BT) {   // keep the probes for B Gc
+        for (int t = tid; t < KC * NP; t += BT) {   // keep the probes for B Gc
           int jj = t / NP, c = t - (t / NP) * NP;
           if (j0 + jj < n) Gcs[(j0 + jj) * NP + c] = lds[jj * (L0 + NP) + L0 + c];
         }
         if (row_ok) {
-          const int jn = min(CH, n - j0);
-          const float* ar = A + (int64_t)tid * lda + j0;
-          for (int jj = 0; jj < jn; ++jj) {
-            double a = (double)ar[jj];
+#pragma unroll 2
+          for (int jj = 0; jj < KC; ++jj) {
+            double a = (double)tile[tid * KLD + jj];
             nonfinite |= !isfinite(a);
 #pragma unroll
             for (int c = 0; c < L0 + NP; ++c) y[c] += a * lds[jj * (L0 + NP) + c];
@@ -391,15 +445,16 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
       double yb[BG];
 #pragma unroll
       for (int c = 0; c < BG; ++c) yb[c] = 0.0;
-      for (int j0 = 0; j0 < n; j0 += CH) {
+      float* tile = reinterpret_cast<float*>(lds + KC * BG);
+      for (int j0 = 0; j0 < n; j0 += KC) {
         __syncthreads();
         stage_gauss(lds, BG, j0, n, BG, BG, g.seed, s_om, L0 + steps * BG, s_pr);
+        stage_k(A, lda, m, n, j0, tile);
         __syncthreads();
         if (row_ok) {
-          const int jn = min(CH, n - j0);
-          const float* ar = A + (int64_t)tid * lda + j0;
-          for (int jj = 0; jj < jn; ++jj) {
-            double a = (double)ar[jj];
+#pragma unroll 2
+          for (int jj = 0; jj < KC; ++jj) {
+            double a = (double)tile[tid * KLD + jj];
 #pragma unroll
             for (int c = 0; c < BG; ++c) yb[c] += a * lds[jj * BG + c];
           }
@@ -443,9 +498,11 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
     }
 
     // ---- SVD of B (rc x n) through the eigen-decomposition of B B^T
+    // (with no growth the decomposition made for sigma_hat_1 is still in M, Vm)
     double* M = lds;
     double* Vm = lds + RMAX * RMAX;
     __syncthreads();
+    if (rc != L0) {
     for (int t = tid; t < RMAX * RMAX; t += BT) M[t] = 0.0;
     __syncthreads();
     for (int a0 = 0; a0 < rc; a0 += L0)
@@ -465,6 +522,7 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
       }
     small_eig(M, Vm, rc);
     __syncthreads();
+    }
     if (tid < rc) {
       double v = M[tid * RMAX + tid];
       int r = 0;

@@ -229,16 +229,19 @@ def test_certificate_matches_the_oracle(s):
 
 
 @pytest.mark.parametrize("dtype,sk,pj,b,eps", [("f64", "f64", "f64", 8, 1e-4), ("f32", "f32", "f32", 16, 1e-4),
-                                               ("f32", "bf16", "f32", 8, 1e-2)])
+                                               ("f32", "bf16", "f32", 8, 5e-2)])
 def test_fallback_grows_to_the_tolerance_like_the_oracle(dtype, sk, pj, b, eps):
     """The rank-k result misses eps; the blocked range finder of Figure 12
     grows the basis (columns continuing Omega's sequence, two projections per
     block) until the Section 14 certificate holds, as the oracle does.  A bf16
     sketch only has to span; the projection B = Q^T A stays FP32 here, since
     its rounding error enters the residual the certificate measures.  With a
-    bf16 sketch the basis follows bf16(A), whose rounding (about 3e-4 sigma_1
-    here) times the paper-form certificate's margin (about 8x) sets the
-    smallest eps it can certify, hence eps = 1e-2 for that case."""
+    bf16 sketch the basis follows bf16(A): the residual keeps the rounding
+    A - bf16(A), which is full rank with a flat spectrum, so a probe sees its
+    Frobenius norm (about 3.9e-3 sigma_1 here), and with the certificate's
+    factor 10 sqrt(2/pi) the bound stalls near 3e-2 sigma_1 (about 0.03 at
+    150 columns in an FP64 simulation of the bf16 sketch); that case runs at
+    eps = 5e-2 and may need more columns than the exact basis."""
     A = _cert_case(seed=96)
     k, p, q, seed = 10, 5, 1, 7
     sk_, pj_ = sk, pj
@@ -253,8 +256,11 @@ def test_fallback_grows_to_the_tolerance_like_the_oracle(dtype, sk, pj, b, eps):
         assert abs(info.err_bound - ref.bound) <= 1e-6 * ref.bound
         r = ref.rank
         assert max_rel_sigma(S, ref.D, min(r, 40)) <= 1e-9
-    else:
+    elif sk == "f32":
         assert abs(info.rank_out - ref.rank) <= b
+    else:
+        # the rounding floor makes the bf16 basis grow further than the exact one
+        assert ref.rank - b <= info.rank_out <= 150
     true = np.linalg.norm(A - (U * S) @ V.T, 2)
     assert true <= eps * S[0] * 1.01
     assert info.err_bound <= eps * info.sigma1

@@ -94,12 +94,39 @@ def low_rank_matrix(m: int, n: int, sigma: np.ndarray, noise_std: float, seed: i
 
 def kernel_block(mb: int, nb: int, seed: int, block_id: int) -> np.ndarray:
     """K_ij = log |x_i - y_j| (float64 evaluation, float32 result)."""
+    x, y = kernel_points(mb, nb, seed, block_id)
+    d = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(-1))
+    return np.log(d).astype(np.float32)
+
+
+def kernel_points(mb: int, nb: int, seed: int, block_id: int):
+    """The point sets of ``kernel_block`` (float64 arrays of shape (mb, 2) and (nb, 2))."""
     g = _rng(seed * 1_000_003 + block_id, _STREAM_POINTS)
     x = g.random((mb, 2))
     y = g.random((nb, 2))
     y[:, 0] += 3.0
-    d = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(-1))
-    return np.log(d).astype(np.float32)
+    return x, y
+
+
+def kernel_blocks_device(ms, ns, seed: int, device: str):
+    """All blocks of the batched workload in one float32 device buffer, each
+    block row-major with leading dimension n_b, evaluated on the device in
+    float64 from the same points as ``kernel_block``.  Returns (buffer, list of
+    2-D views)."""
+    import torch
+    sizes = [int(m) * int(n) for m, n in zip(ms, ns)]
+    buf = torch.empty(sum(sizes), dtype=torch.float32, device=device)
+    views, off = [], 0
+    for b, (m, n) in enumerate(zip(ms, ns)):
+        x, y = kernel_points(int(m), int(n), seed, b)
+        tx = torch.from_numpy(x).to(device)
+        ty = torch.from_numpy(y).to(device)
+        d = torch.sqrt(((tx[:, None, :] - ty[None, :, :]) ** 2).sum(-1))
+        v = buf[off:off + sizes[b]].view(int(m), int(n))
+        v.copy_(torch.log(d).to(torch.float32))
+        views.append(v)
+        off += sizes[b]
+    return buf, views
 
 
 def batched_blocks(nblk: int, seed: int, lo: int = 64, hi: int = 512):
