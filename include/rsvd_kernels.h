@@ -53,11 +53,15 @@ rsvd_status rsvd_k_product_tn(int32_t precision, int64_t K, int64_t N, const voi
  * FP64 row-major, identity outside l x l).  LP = l rounded up to 16.  Columns
  * whose pivot falls to <= tau_rel * G_jj are dropped (zero row of R, zero
  * column of R^-1) and counted in d_flags[1]; non-finite pivots in d_flags[0].
- * d_flags: 4 device ints, accumulated (not cleared).
- * Errors: RSVD_E_ARG (l < 1 or l > 1024), RSVD_E_HIP.
+ * d_flags: 4 device ints, accumulated (not cleared).  l <= 128 runs in one
+ * workgroup; larger l runs the blocked multi-workgroup form and needs
+ * d_scratch (device, rsvd_k_scratch_bytes(l) bytes, caller-owned, contents
+ * undefined afterwards); d_scratch may be NULL for l <= 128.
+ * Errors: RSVD_E_ARG (l < 1 or l > 1024, or no scratch where one is needed),
+ * RSVD_E_HIP.
  */
 rsvd_status rsvd_k_cholesky(int32_t l, const double* d_G, int64_t ldg, double tau_rel, double* d_Rinv,
-                            double* d_R, int32_t* d_flags, void* stream);
+                            double* d_R, int32_t* d_flags, void* d_scratch, void* stream);
 
 /*
  * SVD of X = R^T by one-sided Jacobi in FP64 (the small SVD of Stage B,
@@ -65,11 +69,22 @@ rsvd_status rsvd_k_cholesky(int32_t l, const double* d_G, int64_t ldg, double ta
  * leading l x l block read.  Writes d_sigma (LP values, descending, zeros
  * past l) and d_Uhat (LP x LP, column j of U_hat at d_Uhat[j*LP .. +LP)),
  * each column signed so that its entry of largest magnitude is positive.
- * d_flags[2] counts a sweep limit reached before convergence.
+ * d_flags[2] counts a sweep limit reached before convergence, d_flags[3]
+ * holds the largest sweep count.  l <= 128 runs in one workgroup with X in
+ * LDS; larger l (up to 1024) runs block one-sided Jacobi over many
+ * workgroups and needs d_scratch (rsvd_k_scratch_bytes(l) bytes; may be NULL
+ * for l <= 128); that form synchronises `stream` once per sweep.
  * Errors: RSVD_E_ARG, RSVD_E_HIP.
  */
 rsvd_status rsvd_k_small_svd(int32_t l, const double* d_R, double* d_sigma, double* d_Uhat, int32_t* d_flags,
-                             void* stream);
+                             void* d_scratch, void* stream);
+
+/*
+ * Bytes of device scratch that rsvd_k_cholesky and rsvd_k_small_svd need at
+ * size l (0 for l <= 128).  Errors: RSVD_E_ARG (l < 1 or l > 1024, NULL
+ * h_bytes).
+ */
+rsvd_status rsvd_k_scratch_bytes(int32_t l, size_t* h_bytes);
 
 /*
  * Input preparation for the bf16 products: d_A16 (m x ld16 row-major bf16,

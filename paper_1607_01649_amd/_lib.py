@@ -89,8 +89,10 @@ SIGNATURES = [
     ("rsvd_k_product_tn", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, _c_void_p, _i64,
                                          ctypes.c_int32, _c_void_p, _i64, ctypes.c_int32, _c_void_p]),
     ("rsvd_k_cholesky", ctypes.c_int, [ctypes.c_int32, _c_void_p, _i64, ctypes.c_double, _c_void_p, _c_void_p,
-                                       _c_void_p, _c_void_p]),
-    ("rsvd_k_small_svd", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+                                       _c_void_p, _c_void_p, _c_void_p]),
+    ("rsvd_k_small_svd", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                        _c_void_p]),
+    ("rsvd_k_scratch_bytes", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     ("rsvd_k_convert_bf16", ctypes.c_int, [_i64, _i64, _c_void_p, _i64, _c_void_p, _i64, _c_void_p, _i64, _c_void_p,
                                            _c_void_p]),
     ("rsvd_k_product_bf16", ctypes.c_int, [_i64, _i64, _c_void_p, _i64, _c_void_p, _i64, ctypes.c_int32, _c_void_p,

@@ -14,9 +14,8 @@
 // with d_j = U(j, j), so step j reads row j and writes only rows below it:
 // one barrier per step.  At the end R = D^-1/2 U and R^-T = D^-1/2 T.
 //
-// Storage: one LP x LP FP64 array (registers for l <= 128, else global
-// scratch): the upper triangle including the diagonal holds U, the strict
-// lower triangle holds T (whose unit diagonal is implicit).
+// Storage: register blocks, l <= 128; larger l goes to the blocked
+// multi-workgroup form in blocked.hip.
 //
 // Numerically dependent columns (pivot <= tau_rel * G_jj) are dropped: they
 // take no part in later eliminations, row j of R and column j of R^-1 come out
@@ -147,77 +146,6 @@ __global__ __launch_bounds__(kCholThreads) void chol_reg_kernel(const double* __
   }
 }
 
-// General l (up to 1024): the array lives in global scratch; every thread
-// loops over its entries idx = tid + 1024 u.  Same elimination as above.
-template <typename TQ>
-__global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __restrict__ g, int64_t ldg, int l, int LP,
-                                                             double tau_rel, TQ* __restrict__ rinv_p,
-                                                             double* __restrict__ r_out,
-                                                             const double* __restrict__ r_prev,
-                                                             double* __restrict__ M, int* __restrict__ flags) {
-  __shared__ double gdiag[1024];
-  __shared__ double rsd[1024];
-  const int tid = threadIdx.x;
-  const int ll = l * l;
-  for (int idx = tid; idx < ll; idx += kCholThreads) {
-    int a = idx / l, b = idx - (idx / l) * l;
-    double v = (a <= b) ? g[(int64_t)b * ldg + a] : 0.0;
-    M[a * LP + b] = v;
-    if (a == b) gdiag[a] = v;
-  }
-  __syncthreads();
-  int bad = 0, dropped = 0;
-  for (int j = 0; j < l; ++j) {
-    const double d = M[j * LP + j];
-    const double gd = gdiag[j];
-    const bool nonfinite = !isfinite(d) || !isfinite(gd);
-    const bool drop = nonfinite || !(d > tau_rel * gd) || !(d > 0.0);
-    bad += nonfinite;
-    dropped += (drop && !nonfinite);
-    if (!drop) {
-      const double invd = 1.0 / d;
-      for (int idx = tid; idx < ll; idx += kCholThreads) {
-        int a = idx / l, b = idx - (idx / l) * l;
-        if (a <= j) continue;
-        double f = M[j * LP + a] * invd;
-        if (b >= a) M[a * LP + b] -= f * M[j * LP + b];
-        else if (b < j) M[a * LP + b] -= f * M[j * LP + b];
-        else if (b == j) M[a * LP + b] = -f;
-      }
-    }
-    if (tid == j % kCholThreads) rsd[j] = drop ? 0.0 : 1.0 / sqrt(d);
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (bad) atomicAdd(&flags[0], bad);
-    if (dropped) atomicAdd(&flags[1], dropped);
-  }
-  for (int idx = tid; idx < LP * LP; idx += kCholThreads) {
-    int c = idx / LP, k = idx - (idx / LP) * LP;
-    double v;
-    if (c >= l || k >= l) v = (c == k) ? 1.0 : 0.0;
-    else if (k < c) v = M[c * LP + k] * rsd[c];
-    else if (k == c) v = rsd[c];
-    else v = 0.0;
-    rinv_p[idx] = static_cast<TQ>(v);
-  }
-  if (r_out) {
-    for (int idx = tid; idx < LP * LP; idx += kCholThreads) {
-      int a = idx / LP, b = idx - (idx / LP) * LP;
-      double v;
-      if (a >= l || b >= l) v = (a == b) ? 1.0 : 0.0;
-      else if (b < a || rsd[a] == 0.0) v = 0.0;
-      else if (!r_prev) v = M[a * LP + b] * rsd[a];
-      else {
-        v = 0.0;
-        for (int k = a; k <= b; ++k) v += M[a * LP + k] * r_prev[k * LP + b];
-        v *= rsd[a];
-      }
-      r_out[idx] = v;
-    }
-  }
-}
-
 template <typename TQ>
 hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_rel, TQ* rinv_p, double* r_out,
                        const double* r_prev, double* scratch, int* flags, hipStream_t s) {
@@ -235,8 +163,7 @@ hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_r
                        r_out, r_prev, flags);
   } else {
     if (!scratch) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((chol_kernel<TQ>), dim3(1), dim3(kCholThreads), 0, s, g, ldg, l, LP, tau_rel, rinv_p, r_out,
-                       r_prev, scratch, flags);
+    return launch_chol_blocked<TQ>(g, ldg, l, LP, tau_rel, rinv_p, r_out, r_prev, scratch, flags, s);
   }
   return hipGetLastError();
 }

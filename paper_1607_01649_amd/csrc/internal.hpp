@@ -36,6 +36,19 @@ template <typename TQ>
 hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_rel, TQ* rinv_p, double* r_out,
                        const double* r_prev, double* scratch, int* flags, hipStream_t s);
 
+// blocked.hip -- the same factorisations for l > 128, spread over many workgroups.
+size_t chol_blocked_scratch_doubles(int LP);
+template <typename TQ>
+hipError_t launch_chol_blocked(const double* g, int64_t ldg, int l, int LP, double tau, TQ* rinv_p, double* r_out,
+                               const double* r_prev, double* scratch, int* flags, hipStream_t s);
+size_t jacobi_blocked_scratch_bytes(int LP);
+template <typename TU>
+hipError_t launch_jacobi_blocked(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma,
+                                 double* uhat_d, TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s);
+template <typename TU>
+hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, double* sigma, double* uhat_d,
+                                  TU* uhat_p, TU* vhat_p, hipStream_t s);
+
 // jacobi.hip
 template <typename TU>
 hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma, double* uhat_d,

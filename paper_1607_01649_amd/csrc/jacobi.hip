@@ -1,5 +1,5 @@
 // SVD of the small l x l factor in FP64 by one-sided (Hestenes) Jacobi, in
-// one workgroup.
+// one workgroup for l <= 128 (larger l: the block form in blocked.hip).
 //
 // Stage B (Section 3) needs the SVD of B = Q^T A (l x n).  The library first
 // reduces B^T = Q_B R (CholeskyQR2 in FP64), so B = R^T Q_B^T and the SVD of
@@ -34,68 +34,14 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-template <typename TU, bool USE_LDS>
-__global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__ R, int l, int LP, double tol,
-                                                       int max_sweeps, double* __restrict__ sigma,
-                                                       double* __restrict__ uhat_d, TU* __restrict__ uhat_p,
-                                                       TU* __restrict__ vhat_p, double* __restrict__ scratch,
-                                                       int* __restrict__ flags) {
-  extern __shared__ double smem[];
-  double* xs = USE_LDS ? smem : scratch;   // column p of X = row p of R, at xs[p*LP + i]
-  __shared__ double nrm[1024];
-  __shared__ int rnk[1024];
-  __shared__ int rotated;
+// Norms, order, signs and outputs of the converged columns (column p of X at
+// xs[p*LP + i]): sigma descending, u_hat = x / sigma signed so that its entry
+// of largest magnitude (lowest index on ties) is positive, v_hat = u_hat / sigma.
+template <typename TU>
+__device__ void jacobi_epilogue(const double* xs, int l, int LP, double* nrm, int* rnk, double* __restrict__ sigma,
+                                double* __restrict__ uhat_d, TU* __restrict__ uhat_p, TU* __restrict__ vhat_p) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
-  const int slot = tid / kPairLanes, sub = tid % kPairLanes, nslots = nt / kPairLanes;
-
-  for (int idx = tid; idx < l * l; idx += nt) {
-    int p = idx / l, i = idx - (idx / l) * l;
-    xs[p * LP + i] = R[(int64_t)p * LP + i];
-  }
-  const int le = l + (l & 1);
-  const int npairs = le / 2;
-  int sweep = 0;
-  bool converged = (l < 2);
-  for (; sweep < max_sweeps && !converged; ++sweep) {
-    __syncthreads();
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int round = 0; round < le - 1; ++round) {
-      for (int pi = slot; pi < npairs; pi += nslots) {
-        int p = rr_player(pi, round, le), q = rr_player(le - 1 - pi, round, le);
-        if (p >= l || q >= l) continue;   // uniform within the pair group
-        double* xp = xs + p * LP;
-        double* xq = xs + q * LP;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = sub; i < l; i += kPairLanes) {
-          double a = xp[i], b = xq[i];
-          al += a * a; be += b * b; ga += a * b;
-        }
-        al = group_sum(al); be = group_sum(be); ga = group_sum(ga);
-        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-          double zeta = (be - al) / (2.0 * ga);
-          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double c = 1.0 / sqrt(1.0 + t * t);
-          double s = c * t;
-          for (int i = sub; i < l; i += kPairLanes) {
-            double a = xp[i], b = xq[i];
-            xp[i] = c * a - s * b;
-            xq[i] = s * a + c * b;
-          }
-          if (sub == 0) rotated = 1;
-        }
-      }
-      __syncthreads();
-    }
-    converged = (rotated == 0);
-  }
-  if (tid == 0) {
-    if (!converged) atomicAdd(&flags[2], 1);
-    atomicMax(&flags[3], sweep);
-  }
-  __syncthreads();
-
   for (int p = w; p < l; p += nw) {
     double s = 0.0;
     for (int i = lane; i < l; i += 64) s += xs[p * LP + i] * xs[p * LP + i];
@@ -149,23 +95,120 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
 }
 
 template <typename TU>
+__global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__ R, int l, int LP, double tol,
+                                                       int max_sweeps, double* __restrict__ sigma,
+                                                       double* __restrict__ uhat_d, TU* __restrict__ uhat_p,
+                                                       TU* __restrict__ vhat_p, int* __restrict__ flags) {
+  extern __shared__ double smem[];
+  double* xs = smem;   // column p of X = row p of R, at xs[p*LP + i]
+  __shared__ double nrm[1024];
+  __shared__ int rnk[1024];
+  __shared__ int rotated;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
+  const int slot = tid / kPairLanes, sub = tid % kPairLanes, nslots = nt / kPairLanes;
+
+  for (int idx = tid; idx < l * l; idx += nt) {
+    int p = idx / l, i = idx - (idx / l) * l;
+    xs[p * LP + i] = R[(int64_t)p * LP + i];
+  }
+  const int le = l + (l & 1);
+  const int npairs = le / 2;
+  int sweep = 0;
+  bool converged = (l < 2);
+  for (; sweep < max_sweeps && !converged; ++sweep) {
+    __syncthreads();
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < le - 1; ++round) {
+      for (int pi = slot; pi < npairs; pi += nslots) {
+        int p = rr_player(pi, round, le), q = rr_player(le - 1 - pi, round, le);
+        if (p >= l || q >= l) continue;   // uniform within the pair group
+        double* xp = xs + p * LP;
+        double* xq = xs + q * LP;
+        // the lane's slice of both columns, loaded at once (unrolled, predicated) and kept for the rotation
+        constexpr int NI = 128 / kPairLanes;
+        double av[NI], bv[NI];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+          const int i = sub + u * kPairLanes;
+          av[u] = (i < l) ? xp[i] : 0.0;
+          bv[u] = (i < l) ? xq[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+          al += av[u] * av[u]; be += bv[u] * bv[u]; ga += av[u] * bv[u];
+        }
+        al = group_sum(al); be = group_sum(be); ga = group_sum(ga);
+        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+          double zeta = (be - al) / (2.0 * ga);
+          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + t * t);
+          double s = c * t;
+#pragma unroll
+          for (int u = 0; u < NI; ++u) {
+            const int i = sub + u * kPairLanes;
+            if (i < l) {
+              xp[i] = c * av[u] - s * bv[u];
+              xq[i] = s * av[u] + c * bv[u];
+            }
+          }
+          if (sub == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    converged = (rotated == 0);
+  }
+  if (tid == 0) {
+    if (!converged) atomicAdd(&flags[2], 1);
+    atomicMax(&flags[3], sweep);
+  }
+  __syncthreads();
+
+  jacobi_epilogue<TU>(xs, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
+}
+
+template <typename TU>
+__global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* __restrict__ xs, int l, int LP,
+                                                              double* __restrict__ sigma, double* __restrict__ uhat_d,
+                                                              TU* __restrict__ uhat_p, TU* __restrict__ vhat_p) {
+  __shared__ double nrm[1024];
+  __shared__ int rnk[1024];
+  jacobi_epilogue<TU>(xs, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
+}
+
+template <typename TU>
+hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, double* sigma, double* uhat_d,
+                                  TU* uhat_p, TU* vhat_p, hipStream_t s) {
+  if (ldx != LP) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((jacobi_finish_kernel<TU>), dim3(1), dim3(1024), 0, s, xs, l, LP, sigma, uhat_d, uhat_p,
+                     vhat_p);
+  return hipGetLastError();
+}
+template hipError_t jacobi_epilogue_launch<float>(const double*, int, int, int, double*, double*, float*, float*,
+                                                  hipStream_t);
+template hipError_t jacobi_epilogue_launch<double>(const double*, int, int, int, double*, double*, double*, double*,
+                                                   hipStream_t);
+
+template <typename TU>
 hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma, double* uhat_d,
                          TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s) {
   if (l < 1 || l > 1024) return hipErrorInvalidValue;
   if (LP <= 128) {
     static bool attr_set = false;
     if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<TU, true>),
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<TU>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
       if (e != hipSuccess) return e;
       attr_set = true;
     }
     size_t sh = (size_t)LP * LP * sizeof(double);
-    hipLaunchKernelGGL((jacobi_kernel<TU, true>), dim3(1), dim3(1024), sh, s, R, l, LP, tol, max_sweeps, sigma,
-                       uhat_d, uhat_p, vhat_p, scratch, flags);
+    hipLaunchKernelGGL((jacobi_kernel<TU>), dim3(1), dim3(1024), sh, s, R, l, LP, tol, max_sweeps, sigma,
+                       uhat_d, uhat_p, vhat_p, flags);
   } else {
-    hipLaunchKernelGGL((jacobi_kernel<TU, false>), dim3(1), dim3(1024), 0, s, R, l, LP, tol, max_sweeps, sigma,
-                       uhat_d, uhat_p, vhat_p, scratch, flags);
+    return launch_jacobi_blocked<TU>(R, l, LP, tol, max_sweeps, sigma, uhat_d, uhat_p, vhat_p, scratch, flags, s);
   }
   return hipGetLastError();
 }

@@ -3,6 +3,8 @@
 #include "../../include/rsvd_kernels.h"
 #include "internal.hpp"
 
+#include <algorithm>
+
 using namespace rsvd;
 
 #define K_TRY(expr)                           \
@@ -49,21 +51,32 @@ rsvd_status rsvd_k_product_tn(int32_t prec, int64_t K, int64_t N, const void* A,
   return RSVD_OK;
 }
 
+rsvd_status rsvd_k_scratch_bytes(int32_t l, size_t* h_bytes) {
+  if (!h_bytes || l < 1 || l > 1024) return RSVD_E_ARG;
+  const int LP = (l + 15) / 16 * 16;
+  *h_bytes = LP <= 128 ? 0 : std::max(chol_blocked_scratch_doubles(LP) * sizeof(double),
+                                      jacobi_blocked_scratch_bytes(LP));
+  return RSVD_OK;
+}
+
 rsvd_status rsvd_k_cholesky(int32_t l, const double* G, int64_t ldg, double tau_rel, double* Rinv, double* R,
-                            int32_t* flags, void* stream) {
-  if (l < 1 || l > 128 || !G || !Rinv || !R || !flags || ldg < l || !(tau_rel >= 0.0)) return RSVD_E_ARG;
+                            int32_t* flags, void* scratch, void* stream) {
+  if (l < 1 || l > 1024 || !G || !Rinv || !R || !flags || ldg < l || !(tau_rel >= 0.0)) return RSVD_E_ARG;
   int LP = (l + 15) / 16 * 16;
-  K_TRY(launch_chol<double>(G, ldg, l, LP, tau_rel, Rinv, R, nullptr, nullptr, flags,
+  if (LP > 128 && !scratch) return RSVD_E_ARG;
+  K_TRY(launch_chol<double>(G, ldg, l, LP, tau_rel, Rinv, R, nullptr, reinterpret_cast<double*>(scratch), flags,
                             reinterpret_cast<hipStream_t>(stream)));
   return RSVD_OK;
 }
 
 rsvd_status rsvd_k_small_svd(int32_t l, const double* R, double* sigma, double* Uhat, int32_t* flags,
-                             void* stream) {
-  if (l < 1 || l > 128 || !R || !sigma || !Uhat || !flags) return RSVD_E_ARG;
+                             void* scratch, void* stream) {
+  if (l < 1 || l > 1024 || !R || !sigma || !Uhat || !flags) return RSVD_E_ARG;
   int LP = (l + 15) / 16 * 16;
+  if (LP > 128 && !scratch) return RSVD_E_ARG;
   K_TRY(launch_jacobi<double>(R, l, LP, (double)l * 2.220446049250313e-16, 60, sigma, Uhat, (double*)nullptr,
-                              (double*)nullptr, nullptr, flags, reinterpret_cast<hipStream_t>(stream)));
+                              (double*)nullptr, reinterpret_cast<double*>(scratch), flags,
+                              reinterpret_cast<hipStream_t>(stream)));
   return RSVD_OK;
 }
 

@@ -152,8 +152,8 @@ Layout make_layout(const rsvd_desc* d) {
   L.uhat_d = take(LPM * LPM * 8);
   L.uhat_p = take(LPM * LPM * L.es);
   L.vhat_p = take(LPM * LPM * L.es);
-  L.scr_chol = take(LPM > 128 ? LPM * LPM * 8 : 256);
-  L.scr_jac = take(LPM > 128 ? LPM * LPM * 8 : 256);
+  L.scr_chol = take(LPM > 128 ? chol_blocked_scratch_doubles((int)LPM) * 8 : 256);
+  L.scr_jac = take(LPM > 128 ? jacobi_blocked_scratch_bytes((int)LPM) : 256);
   L.norms = take(64 * 8);
   L.frob = take(1040 * 8);
   L.flags = take(kFlags * sizeof(int));
