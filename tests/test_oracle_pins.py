@@ -384,3 +384,130 @@ def test_quantised_rsvd_reduces_to_the_plain_oracle_on_representable_data():
     assert np.allclose(a.D, c.D, rtol=1e-6)
     d = quant.rsvd_quantized(A, G, 1, "bf16", "bf16")
     assert np.max(np.abs(d.D - orc.rsvd(A, G, 1).D) / orc.rsvd(A, G, 1).D[0]) < 1e-2
+
+
+# ---------------------------------------------------------------- selector network and rule
+
+def _mlp_case(seed, nb=7):
+    from oracle import mlp
+    g = np.random.default_rng(seed)
+    theta = mlp.init(seed)
+    theta[mlp.N_PARAM - 40:] = g.normal(0, 0.1, 40)          # non-zero output biases
+    X = g.normal(0, 1, (nb, mlp.N_IN))
+    Y = (g.random((nb, mlp.N_OUT)) < 0.4).astype(float)
+    M = (g.random((nb, mlp.N_OUT)) < 0.8).astype(float)
+    return theta, X, Y, M
+
+
+def test_mlp_gradient_matches_central_differences():
+    from oracle import mlp
+    theta, X, Y, M = _mlp_case(5)
+    H1, H2, Z = mlp.forward(theta, X)
+    g = mlp.backward(theta, X, H1, H2, Z, Y, M)
+
+    def loss(t):
+        return mlp.bce_loss(mlp.forward(t, X)[2], Y, M)
+    idx = np.random.default_rng(1).choice(mlp.N_PARAM, 400, replace=False)
+    idx = np.concatenate([idx, np.arange(mlp.N_PARAM - 40, mlp.N_PARAM), np.arange(1024, 1088)])
+    # h = 1e-4: truncation error ~h^2 stays below 1e-7 relative, rounding ~u L / h far below
+    h = 1e-4
+    worst = 0.0
+    for i in idx:
+        e = np.zeros_like(theta)
+        e[i] = h
+        fd = (loss(theta + e) - loss(theta - e)) / (2 * h)
+        worst = max(worst, abs(fd - g[i]) / max(abs(g[i]), 1e-3))
+    assert worst <= 1e-7
+
+
+def test_bce_closed_forms_at_zero_logits():
+    from oracle import mlp
+    theta, X, Y, M = _mlp_case(6)
+    theta[-(40 * 64 + 40):] = 0.0                 # W3 = 0, b3 = 0: every logit is 0
+    H1, H2, Z = mlp.forward(theta, X)
+    assert np.all(Z == 0.0)
+    assert abs(mlp.bce_loss(Z, Y, M) - math.log(2.0)) <= 1e-15
+    g = mlp.backward(theta, X, H1, H2, Z, Y, M)
+    gb3 = g[-40:]
+    assert np.allclose(gb3, ((0.5 - Y) * M).sum(0) / M.sum(), rtol=0, atol=1e-15)
+    # no signal reaches the hidden layers through W3 = 0
+    assert np.all(g[:1024 + 64 + 4096 + 64] == 0.0)
+
+
+def test_adam_first_step_moves_each_weight_by_lr():
+    from oracle import mlp
+    g = np.random.default_rng(2).normal(0, 1, 50)
+    th, m, v = mlp.adam_step(np.zeros(50), g, np.zeros(50), np.zeros(50), 1, lr=1e-3)
+    assert np.allclose(th, -1e-3 * np.sign(g), rtol=1e-6)
+
+
+def test_mlp_fits_a_tiny_set():
+    from oracle import mlp
+    theta, X, Y, M = _mlp_case(8, nb=8)
+    M = np.ones_like(M)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    for t in range(1, 1501):
+        H1, H2, Z = mlp.forward(theta, X)
+        theta, m, v = mlp.adam_step(theta, mlp.backward(theta, X, H1, H2, Z, Y, M), m, v, t, lr=1e-2)
+    assert mlp.bce_loss(mlp.forward(theta, X)[2], Y, M) < 0.02
+
+
+def test_selector_features_are_scale_invariant_and_reveal_rank():
+    from oracle import selector
+    A = _low_rank(300, 200, [1.0, 0.5, 0.2, 0.1, 0.05], seed=3)
+    s = selector.probe_sigma(A, seed=4)
+    x = selector.features(s, 5)
+    assert np.allclose(selector.features(selector.probe_sigma(3.0 * A, seed=4), 5), x, atol=1e-12)
+    assert np.all(x[4:15] == -2.0)            # sigma_6.. of a rank-5 sketch are clamped at 1e-12
+    assert np.all(x[:4] > -1.0) and np.all(np.diff(x[:4]) <= 0)
+    assert x[15] == pytest.approx(math.log10(5) / 3)
+
+
+def test_selector_decision_rule_by_brute_force():
+    from oracle import selector
+    g = np.random.default_rng(9)
+    for trial in range(200):
+        m, n = int(g.integers(200, 3000)), int(g.integers(200, 3000))
+        k = int(g.integers(1, min(400, m, n) + 1))
+        prob = g.random(selector.N_GRID)
+        tau = float(g.uniform(0.3, 0.95))
+        p, q = selector.choose(prob, m, n, k, tau)
+        pts = [(o, pp, qq) for qi, qq in enumerate(selector.Q_GRID) for pi, pp in enumerate(selector.P_GRID)
+               for o in [qi * 8 + pi] if k + pp <= min(m, n, 1024)]
+        feas = [t for t in pts if prob[t[0]] >= tau]
+        if feas:
+            best = min(selector.cost_ms(m, n, k, t[1], t[2]) for t in feas)
+            assert selector.cost_ms(m, n, k, p, q) == best and prob[8 * selector.Q_GRID.index(q)
+                                                                   + selector.P_GRID.index(p)] >= tau
+        else:
+            assert prob[8 * selector.Q_GRID.index(q) + selector.P_GRID.index(p)] == max(prob[t[0]] for t in pts)
+    # cost grows with p and with q
+    assert selector.cost_ms(4000, 4000, 50, 10, 1) < selector.cost_ms(4000, 4000, 50, 20, 1)
+    assert selector.cost_ms(4000, 4000, 50, 10, 1) < selector.cost_ms(4000, 4000, 50, 10, 2)
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_prefix_of_the_reorthonormalised_scheme_is_the_shorter_run(q):
+    """With prefix-stable Gaussian columns, the first k+p columns of the
+    basis of Figure 5 built from k+p_max columns span what the run with k+p
+    columns builds (CholeskyQR / QR with positive diagonal keep prefixes), so
+    every grid point's certificate follows from one run; checked against the
+    separate runs of the definition."""
+    from oracle import selector
+    sigma = gen.spectrum("polyexp", 150, alpha=1.0, tau=60.0)
+    A = _low_rank(400, 300, sigma, seed=21, noise=1e-7)
+    k, seed, ps = 12, 3, [0, 5, 10, 20, 40]
+    ref = selector.plain_certificates(A, k, q, seed, ps)
+    n = A.shape[1]
+    G = philox.gaussian(n, k + ps[-1], seed, philox.STREAM_OMEGA)
+    Q = orc.orth(A @ G)
+    for _ in range(q):
+        Q = orc.orth(A @ orc.orth(A.T @ Q))
+    Gc = philox.gaussian(n, 10, seed, philox.STREAM_CERT)
+    AG = A @ Gc
+    for p, r in zip(ps, ref):
+        Ql = Q[:, :k + p]
+        E = AG - Ql @ (Ql.T @ AG)
+        b = orc.probe_bound(np.linalg.norm(E, axis=0), 0.1)
+        assert abs(b - r) <= 1e-6 * r + 1e-12
