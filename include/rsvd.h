@@ -63,6 +63,10 @@ typedef enum {
  *   k, p        target rank and oversampling; l = k + p columns are sketched
  *               (Section 4; p = 10 is the paper's usual choice).
  *   q           number of power steps of Figure 5 (q >= 0).
+ *               p = q = -1 selects the learned selector: before each
+ *               factorisation a 16-column probe sketch and the network set
+ *               with rsvd_selector_set choose (p, q) from the grid below
+ *               (reported in rsvd_info.p_used / q_used).
  *   seed        seeds the Gaussian test matrix.  Entry (i, j) of every Gaussian
  *               matrix the library draws is a function of (seed, stream, i, j)
  *               only: Philox4x32-10 (Salmon et al., SC'11) with key = seed,
@@ -125,6 +129,37 @@ typedef struct {
 
 typedef struct rsvd_plan_s* rsvd_plan_t;
 
+/*
+ * Learned (p, q) selector.  The paper fixes p by a rule of thumb (Section 4:
+ * p = 10) and q by experience (Section 8: q = 1 or 2); the selector picks
+ * them per matrix for a tolerance instead.
+ *   Probe: Y16 = A G16 with 16 Gaussian columns of stream 5; sigma_1 >= ..
+ *   >= sigma_16 its singular values (FP64 CholeskyQR + Jacobi).
+ *   Input x (16 floats): x_i = log10(max(sigma_{i+1} / sigma_1, 1e-12)) / 6
+ *   for i = 0..14, x_15 = log10(k) / 3.
+ *   Network: 16 -> 64 (ReLU) -> 64 (ReLU) -> 40 logits, FP32; parameters in
+ *   one flat vector of RSVD_MLP_NPARAM floats: W1 (64 x 16 row-major), b1
+ *   (64), W2 (64 x 64), b2 (64), W3 (40 x 64), b3 (40).
+ *   Output o = 8 * iq + ip is the predicted probability (logistic of the
+ *   logit) that p = RSVD_SEL_P[ip], q = iq (0..4) meets the tolerance
+ *   without growth.
+ *   Decision: among grid points with k + p <= min(m, n, 1024) and
+ *   probability P >= tau, the one of least expected time c(p, q) (2 - P) (a
+ *   miss is taken to double the time through the fallback); if none, the
+ *   most probable one.  Modelled time (ms) at l = k + p:
+ *     c = 0.4 + (2q+2) 2 m n l / 6e10 + (2q+1) 0.3 max(l/128, 1)^1.5
+ *         + 2.5 (l/95)^1.5
+ *   (passes over A, CholeskyQR passes and the Stage B Jacobi, fitted to
+ *   measured MI355X timings).
+ */
+#define RSVD_MLP_IN 16
+#define RSVD_MLP_HIDDEN 64
+#define RSVD_MLP_OUT 40
+#define RSVD_MLP_NPARAM 7848
+#define RSVD_SEL_NP 8
+#define RSVD_SEL_NQ 5
+#define RSVD_SEL_P_INIT {0, 5, 10, 20, 40, 80, 160, 320}
+
 /* Human-readable name of a status code (static string). */
 const char* rsvd_status_str(int status);
 
@@ -180,6 +215,71 @@ rsvd_status rsvd_factor(rsvd_plan_t plan, const void* d_A, int64_t lda, const do
 /* Release a plan (host memory and events only; the workspace stays the
  * caller's). NULL is ignored. */
 void rsvd_destroy(rsvd_plan_t plan);
+
+/*
+ * Attach selector parameters to a plan made with p = q = -1: d_theta
+ * (device, RSVD_MLP_NPARAM floats, caller-owned, must stay valid while the
+ * plan is used) and the probability threshold tau in (0, 1).
+ * Errors: RSVD_E_ARG (null plan or theta, tau outside (0, 1), plan not in
+ * selector mode).
+ */
+rsvd_status rsvd_selector_set(rsvd_plan_t plan, const float* d_theta, float tau);
+
+/*
+ * The probe of the selector on its own: d_sigma16 (device, 16 doubles) =
+ * singular values of A G16, descending, and d_x (device, 16 floats, may be
+ * NULL) = the network input for the plan's k.  Uses the plan's workspace and
+ * stream (any plan whose l = k + p is >= 16, or a selector-mode plan).
+ * Errors: RSVD_E_ARG (null pointers, lda < n, plan too narrow), RSVD_E_HIP.
+ */
+rsvd_status rsvd_probe_sigma(rsvd_plan_t plan, const void* d_A, int64_t lda, double* d_sigma16, float* d_x);
+
+/*
+ * Certificates of every prefix of one Stage A basis (the labels of the
+ * selector): Stage A of Figure 5 with the plan's l = k + p columns and q
+ * power steps gives Q (m x l); for each width w = h_widths[i] (1 <= w <= l)
+ * h_bounds[i] = 10 sqrt(2/pi) max_j ||(I - Q_w Q_w^T) A g_j|| with Q_w the
+ * first w columns of Q and g_j the n_probe certificate probes (stream 6).
+ * Because the test-matrix columns are prefix-stable and CholeskyQR keeps
+ * prefixes, Q_w is (up to rounding) the basis the plain method builds with w
+ * columns, so h_bounds[i] is the Section 14 certificate of the rank-w result
+ * of the plain method.  The plan needs eps > 0 (for the probe buffers) and a
+ * fixed p, q >= 0.  Synchronises the stream.
+ * Errors: RSVD_E_ARG, RSVD_E_HIP, RSVD_E_NONFINITE.
+ */
+rsvd_status rsvd_prefix_bounds(rsvd_plan_t plan, const void* d_A, int64_t lda, int32_t n_widths,
+                               const int32_t* h_widths, double* h_bounds);
+
+/*
+ * Selector network, forward pass over a batch: d_X (batch x 16), outputs the
+ * hidden activations after ReLU d_H1, d_H2 (batch x 64) and the logits d_Z
+ * (batch x 40), all FP32 row-major, device.  Sums in a fixed order.
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_mlp_forward(const float* d_theta, int32_t batch, const float* d_X, float* d_H1, float* d_H2,
+                             float* d_Z, void* stream);
+
+/*
+ * Backward pass of the mean binary cross-entropy with logits over the
+ * entries whose mask d_M (batch x 40, 0 or 1) is 1, labels d_Y (batch x 40):
+ * d_grad (RSVD_MLP_NPARAM floats) = gradient with respect to theta, in the
+ * parameter layout; d_loss[0] = the loss, d_loss[1] = the number of masked-in
+ * entries.  d_X, d_H1, d_H2, d_Z as left by rsvd_mlp_forward.  d_scratch:
+ * batch * 168 floats of device scratch.  Deterministic (fixed-order sums).
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_mlp_backward(const float* d_theta, int32_t batch, const float* d_X, const float* d_H1,
+                              const float* d_H2, const float* d_Z, const float* d_Y, const float* d_M,
+                              float* d_grad, float* d_loss, float* d_scratch, void* stream);
+
+/*
+ * One Adam step (Kingma and Ba, 2015) on n parameters, step >= 1:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * theta -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_mlp_adam(float* d_theta, const float* d_grad, float* d_m, float* d_v, int32_t n, float lr,
+                          float beta1, float beta2, float eps, int32_t step, void* stream);
 
 /*
  * Batched compression of many independent blocks to a relative tolerance, in

@@ -15,8 +15,9 @@ typical) when a tolerance eps has to be met.
 * Label of a grid point: 1 when the plain method (Figure 5, no growth) with
   that (p, q) returns a rank-(k+p) factorisation whose Section 14 certificate
   (10 probes, alpha = 1/10, s = 0) is <= eps * sigma_1.
-* Decision: among the grid points whose predicted probability is >= tau,
-  the one of least modelled cost; if there is none, the most probable one.
+* Decision: among the grid points whose predicted probability P is >= tau,
+  the one of least expected time cost * (2 - P) (a miss costs about as much
+  again through the fallback); if there is none, the most probable one.
 
 Parity status: the feature map, the decision rule and the prefix labels are
 pinned (scale invariance, rank revelation, brute force over the grid, the
@@ -55,14 +56,12 @@ def features(sig16: np.ndarray, k: int) -> np.ndarray:
 
 
 def cost_ms(m: int, n: int, k: int, p: int, q: int) -> float:
-    """Modelled time of the plain method at (p, q) on one MI355X: 2q+2 passes
-    over A at about 70 TFLOP/s, the Stage B Jacobi (fitted to the measured
-    2.3 ms at l = 110 and 37 ms at l = 520), and 2q+2 CholeskyQR passes."""
+    """Modelled time (ms) of the plain method at (p, q) on one MI355X: a
+    fixed part, 2q+2 passes over A at 60 TFLOP/s, 2q+1 CholeskyQR passes and
+    the Stage B Jacobi, fitted to measured timings."""
     l = min(k + p, m, n)
-    passes = (2 * q + 2) * 2.0 * m * n * l / 7.0e10
-    jac = 2.3 * (l / 110.0) ** 1.77
-    orth_ = (2 * q + 2) * 0.1 * max(l / 110.0, 1.0) ** 1.5
-    return passes + jac + orth_
+    return (0.4 + (2 * q + 2) * 2.0 * m * n * l / 6.0e10 + (2 * q + 1) * 0.3 * max(l / 128.0, 1.0) ** 1.5
+            + 2.5 * (l / 95.0) ** 1.5)
 
 
 def grid_points(m: int, n: int, k: int):
@@ -76,10 +75,12 @@ def grid_points(m: int, n: int, k: int):
 
 
 def choose(prob: np.ndarray, m: int, n: int, k: int, tau: float):
+    """Least expected time cost * (2 - P) over the grid points with P >= tau;
+    the most probable point if there is none."""
     pts = grid_points(m, n, k)
-    ok = [(cost_ms(m, n, k, p, q), o, p, q) for o, p, q in pts if prob[o] >= tau]
+    ok = [(cost_ms(m, n, k, p, q) * (2.0 - prob[o]), o, p, q) for o, p, q in pts if prob[o] >= tau]
     if ok:
-        c, o, p, q = min(ok)
+        e, o, p, q = min(ok)
         return p, q
     o, p, q = max(pts, key=lambda t: (prob[t[0]], -t[0]))
     return p, q

@@ -16,8 +16,9 @@ import torch
 from . import _lib
 from ._lib import (  # noqa: F401
     RSVD_BF16, RSVD_E_ARG, RSVD_E_BREAKDOWN, RSVD_E_HIP, RSVD_E_NONFINITE, RSVD_E_UNSUPPORTED, RSVD_E_WORKSPACE,
-    RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RSVD_NOT_CERTIFIED, RSVD_OK, RSVD_RETURN_RANK_L, RSVD_TIMING, RSVDError,
-    STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info, status_str,
+    RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RSVD_MLP_NPARAM, RSVD_NOT_CERTIFIED, RSVD_OK, RSVD_RETURN_RANK_L,
+    RSVD_SEL_NQ, RSVD_SEL_P, RSVD_TIMING, RSVDError, STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info,
+    status_str,
 )
 
 _DTYPES = {"f64": RSVD_F64, "f32": RSVD_F32, "bf16": RSVD_BF16, "fp8": RSVD_FP8_E4M3}
@@ -110,24 +111,84 @@ def rsvd_philox4x32_10(ctr: torch.Tensor, k0: int, k1: int, out: torch.Tensor, s
         raise RSVDError(st, "rsvd_philox4x32_10")
 
 
+def rsvd_selector_set(plan, theta: torch.Tensor, tau: float) -> None:
+    st = _lib.lib().rsvd_selector_set(plan, _ptr(theta), float(tau))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_selector_set")
+
+
+def rsvd_probe_sigma(plan, A: torch.Tensor, sigma16: torch.Tensor, x: Optional[torch.Tensor] = None) -> None:
+    st = _lib.lib().rsvd_probe_sigma(plan, _ptr(A), A.stride(0), _ptr(sigma16), _ptr(x))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_probe_sigma")
+
+
+def rsvd_prefix_bounds(plan, A: torch.Tensor, widths) -> list:
+    w = (ctypes.c_int32 * len(widths))(*[int(v) for v in widths])
+    b = (ctypes.c_double * len(widths))()
+    st = _lib.lib().rsvd_prefix_bounds(plan, _ptr(A), A.stride(0), len(widths), w, b)
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_prefix_bounds")
+    return list(b)
+
+
+def rsvd_mlp_forward(theta, X, H1, H2, Z, stream=None) -> None:
+    st = _lib.lib().rsvd_mlp_forward(_ptr(theta), X.shape[0], _ptr(X), _ptr(H1), _ptr(H2), _ptr(Z),
+                                     _stream_handle(X.device, stream))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_mlp_forward")
+
+
+def rsvd_mlp_backward(theta, X, H1, H2, Z, Y, M, grad, loss, scratch, stream=None) -> None:
+    st = _lib.lib().rsvd_mlp_backward(_ptr(theta), X.shape[0], _ptr(X), _ptr(H1), _ptr(H2), _ptr(Z), _ptr(Y),
+                                      _ptr(M), _ptr(grad), _ptr(loss), _ptr(scratch), _stream_handle(X.device, stream))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_mlp_backward")
+
+
+def rsvd_mlp_adam(theta, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None) -> None:
+    st = _lib.lib().rsvd_mlp_adam(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), theta.numel(), float(lr), float(beta1),
+                                  float(beta2), float(eps), int(step), _stream_handle(theta.device, stream))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_mlp_adam")
+
+
+def _aligned_workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def selector_grid_cap(m: int, n: int) -> int:
+    return min(m, n, 1024)
+
+
 class RSVD:
     """A plan plus its torch-allocated workspace for one problem shape.
 
     ``RSVD(m, n, k, p, q, dtype)(A)`` returns (U, S, V, info) with U (m x r),
-    S (r, float64, descending), V (n x r) on A's device."""
+    S (r, float64, descending), V (n x r) on A's device.  ``p = q = -1``
+    makes a selector-mode plan: attach the network with ``set_selector``."""
 
     def __init__(self, m, n, k, p=10, q=1, dtype="f32", device="cuda", **kw):
         self.desc = make_desc(m, n, k, p, q, a_dtype=dtype, **kw)
         self.device = torch.device(device)
         nbytes = rsvd_workspace_size(self.desc)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-self.workspace.data_ptr()) % 256
-        self.workspace = self.workspace[off:off + nbytes]
+        self.workspace = _aligned_workspace(nbytes, self.device)
         self.plan = rsvd_plan(self.desc, self.workspace)
-        l = self.desc.k + self.desc.p
+        if p == -1 and q == -1:
+            cap = selector_grid_cap(m, n)
+            l = max(k + pp for pp in RSVD_SEL_P if k + pp <= cap)
+        else:
+            l = self.desc.k + self.desc.p
         self.rank_cap = max(l, self.desc.max_rank) if self.desc.eps > 0 else (
             l if (self.desc.flags & RSVD_RETURN_RANK_L) else self.desc.k)
         self.tdtype = _TORCH[self.desc.a_dtype]
+        self.theta = None
+
+    def set_selector(self, theta: torch.Tensor, tau: float = 0.5) -> None:
+        self.theta = theta
+        rsvd_selector_set(self.plan, theta, tau)
 
     def __call__(self, A: torch.Tensor, omega: Optional[torch.Tensor] = None, want_info: bool = True,
                  out=None, allow_not_certified: bool = True):

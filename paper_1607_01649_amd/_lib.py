@@ -83,6 +83,16 @@ SIGNATURES = [
                                                  ctypes.POINTER(_c_void_p)]),
     ("rsvd_graph_launch", ctypes.c_int, [_c_void_p, _c_void_p]),
     ("rsvd_graph_destroy", None, [_c_void_p]),
+    ("rsvd_selector_set", ctypes.c_int, [_c_void_p, _c_void_p, ctypes.c_float]),
+    ("rsvd_probe_sigma", ctypes.c_int, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p]),
+    ("rsvd_prefix_bounds", ctypes.c_int, [_c_void_p, _c_void_p, _i64, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    ("rsvd_mlp_forward", ctypes.c_int, [_c_void_p, ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                        _c_void_p]),
+    ("rsvd_mlp_backward", ctypes.c_int, [_c_void_p, ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                         _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    ("rsvd_mlp_adam", ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, ctypes.c_int32, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _c_void_p]),
     # include/rsvd_kernels.h
     ("rsvd_k_product_nn", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, _c_void_p, _i64,
                                          ctypes.c_int32, _c_void_p, _i64, _c_void_p]),
@@ -100,6 +110,11 @@ SIGNATURES = [
 ]
 
 RSVD_F32_ACC64 = 10
+
+# selector network and grid (include/rsvd.h)
+RSVD_MLP_IN, RSVD_MLP_HIDDEN, RSVD_MLP_OUT, RSVD_MLP_NPARAM = 16, 64, 40, 7848
+RSVD_SEL_P = (0, 5, 10, 20, 40, 80, 160, 320)
+RSVD_SEL_NQ = 5
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:

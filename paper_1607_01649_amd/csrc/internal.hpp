@@ -49,6 +49,17 @@ template <typename TU>
 hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, double* sigma, double* uhat_d,
                                   TU* uhat_p, TU* vhat_p, hipStream_t s);
 
+// mlp.hip -- the selector network (16 -> 64 -> 64 -> 40, FP32) and its training steps.
+int mlp_param_count();
+hipError_t launch_mlp_forward(const float* th, int B, const float* X, float* H1, float* H2, float* Z, hipStream_t s);
+hipError_t launch_mlp_backward(const float* th, int B, const float* X, const float* H1, const float* H2,
+                               const float* Z, const float* Y, const float* M, float* grad, float* loss,
+                               float* scratch, hipStream_t s);
+hipError_t launch_adam(float* th, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+// x[i] = log10(max(sigma[i+1] / sigma[0], 1e-12)) / 6 (i < 15), x[15] = log10(k) / 3.
+hipError_t launch_sel_features(const double* sigma, int k, float* x, hipStream_t s);
+
 // jacobi.hip
 template <typename TU>
 hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma, double* uhat_d,

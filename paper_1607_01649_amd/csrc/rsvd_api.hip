@@ -21,6 +21,11 @@ constexpr int kRedGroup = 16;   // partials summed per first-level reduction gro
 // device status words: [0] non-finite pivot, [1] dropped columns, [2] Jacobi
 // not converged, [3] Jacobi sweeps, [4] non-finite entry of A (conversion)
 constexpr int kFlags = 64;
+// selector: grid of oversampling values (power steps 0 .. kSelNQ-1), and floats of selector scratch
+// (network input 16, hidden activations 64 + 64, logits 40)
+constexpr int kSelNP = 8, kSelNQ = 5;
+constexpr int kSelP[kSelNP] = {0, 5, 10, 20, 40, 80, 160, 320};
+constexpr int kSelFloats = 16 + 64 + 64 + 40;
 
 bool log_enabled() {
   static int v = -1;
@@ -50,7 +55,7 @@ struct Layout {
   int s_nn, s_tn, s_gm, s_gn, s_nn16, s_tn16;
   int64_t ld16, ldT;   // leading dimensions of the bf16 copies of A and A^T
   size_t a16, a16t, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
-      rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, total;
+      rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, sel, total;
 };
 
 int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
@@ -62,8 +67,10 @@ int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
 
 bool validate(const rsvd_desc* d) {
   if (!d) return false;
-  if (d->m < 1 || d->n < 1 || d->k < 1 || d->p < 0 || d->q < 0) return false;
-  int64_t l = (int64_t)d->k + d->p;
+  if (d->m < 1 || d->n < 1 || d->k < 1) return false;
+  const bool sel = d->p == -1 && d->q == -1;
+  if (!sel && (d->p < 0 || d->q < 0)) return false;
+  int64_t l = (int64_t)d->k + (sel ? 0 : d->p);
   if (l > std::min(d->m, d->n) || l > 1024) return false;
   if (d->a_dtype != RSVD_F64 && d->a_dtype != RSVD_F32) return false;
   if (!(d->eps >= 0.0) || !isfinite(d->eps)) return false;
@@ -157,8 +164,36 @@ Layout make_layout(const rsvd_desc* d) {
   L.norms = take(64 * 8);
   L.frob = take(1040 * 8);
   L.flags = take(kFlags * sizeof(int));
+  L.sel = take(kSelFloats * sizeof(float));
   L.total = off;
   return L;
+}
+
+// Selector mode (p = q = -1): the layouts of every grid point fit in the workspace; this returns the largest.
+bool selector_mode(const rsvd_desc* d) { return d->p == -1 && d->q == -1; }
+
+int sel_lcap(const rsvd_desc* d) { return (int)std::min<int64_t>({d->m, d->n, (int64_t)1024}); }
+
+rsvd_desc derived_desc(const rsvd_desc* d, int p, int q) {
+  rsvd_desc e = *d;
+  e.p = p;
+  e.q = q;
+  if (e.max_rank > 0 && e.max_rank < e.k + p) e.max_rank = e.k + p;
+  return e;
+}
+
+Layout make_layout_any(const rsvd_desc* d) {
+  if (!selector_mode(d)) return make_layout(d);
+  Layout best{};
+  bool have = false;
+  for (int ip = 0; ip < kSelNP; ++ip) {
+    if (d->k + kSelP[ip] > sel_lcap(d)) continue;
+    rsvd_desc e = derived_desc(d, kSelP[ip], kSelNQ - 1);
+    Layout L = make_layout(&e);
+    if (!have || L.total > best.total) best = L;
+    have = true;
+  }
+  return best;
 }
 
 }  // namespace
@@ -175,6 +210,10 @@ struct rsvd_plan_s {
   hipEvent_t gev[2 * kGemmEv];
   int gkind[kGemmEv];                          // 0 = A*X, 1 = A^T*X
   int ngemm = 0;
+  // selector parameters (selector mode)
+  const float* theta = nullptr;
+  float tau = 0.5f;
+  int p_used = 0, q_used = 0;
   // results of the last call (host side)
   int rank_out = 0, fallback_steps = 0;
   double err_bound = 0.0, frob_res = -1.0;
@@ -411,8 +450,9 @@ template <typename T> struct Path {
     return pow(c_alpha * mx, 1.0 / (2 * s + 1));
   }
 
-  rsvd_status run(const T* A, int64_t lda, const double* omega_in, T* U, int64_t ldu, double* S, T* V, int64_t ldv,
-                  int kout) {
+  // Stage A (Figure 5): input preparation, Omega, Q = orth(A Omega) and q power steps with
+  // re-orthonormalisation after every application of A or A^T; leaves Q (m x l panel).
+  rsvd_status stage_a(const T* A, int64_t lda, const double* omega_in) {
     const int64_t m = P.d.m, n = P.d.n;
     const int l = L.l;
     T* omega = P.at<T>(L.omega);
@@ -420,15 +460,8 @@ template <typename T> struct Path {
     T* Q = P.at<T>(L.Q);
     T* Z = P.at<T>(L.Z);
     T* Wp = P.at<T>(L.Wp);
-    T* Bt = P.at<T>(L.Bt);
     int* flags = P.at<int>(L.flags);
-    P.rank_out = kout;
-    P.fallback_steps = 0;
-    P.err_bound = 0.0;
-    P.frob_res = -1.0;
-    mark(0);
-    HIP_TRY(launch_fill_int(flags, kFlags, 0, st));
-    const int sk = P.d.sketch_dtype, pj = P.d.proj_dtype;
+    const int sk = P.d.sketch_dtype;
     if (uses_bf16(&P.d)) {
       if constexpr (sizeof(T) == 4)
         HIP_TRY(launch_to_bf16(A, lda, m, n, P.at<uint16_t>(L.a16), L.ld16, P.at<uint16_t>(L.a16t), L.ldT, flags + 4,
@@ -451,6 +484,76 @@ template <typename T> struct Path {
       RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q));
     }
     mark(2);
+    return RSVD_OK;
+  }
+
+  // Selector probe: sigma(A G16) with 16 Gaussian columns of stream 5 (FP64 CholeskyQR of the Gram and
+  // Jacobi, as for the small SVD) into L.sigma[0..16); the network input into the selector scratch.
+  rsvd_status probe(const T* A, int64_t lda) {
+    const int64_t m = P.d.m, n = P.d.n;
+    T* omega = P.at<T>(L.omega);
+    T* Y = P.at<T>(L.Y);
+    double* G = P.at<double>(L.G);
+    double* R = P.at<double>(L.R);
+    int* flags = P.at<int>(L.flags);
+    const int dt = (sizeof(T) == 8) ? RSVD_F64 : RSVD_F32;
+    HIP_TRY(launch_gaussian<T>(P.d.seed, 5u, n, 16, 0, omega, 1, L.ldn, st));
+    RS_TRY(apply_a(A, lda, omega, 16, Y, dt));
+    RS_TRY(gram(Y, L.ldm, m, 16, L.s_gm, G));
+    HIP_TRY(launch_chol<double>(G, 16, 16, 16, tau, P.at<double>(L.rinv_d), R, nullptr, P.at<double>(L.scr_chol), flags,
+                                st));
+    HIP_TRY(launch_jacobi<T>(R, 16, 16, 16 * 2.220446049250313e-16, 60, P.at<double>(L.sigma), P.at<double>(L.uhat_d),
+                             (T*)nullptr, (T*)nullptr, P.at<double>(L.scr_jac), flags, st));
+    HIP_TRY(launch_sel_features(P.at<double>(L.sigma), P.d.k, P.at<float>(L.sel), st));
+    return RSVD_OK;
+  }
+
+  // Certificates of the prefixes Q_w of the Stage A basis (see rsvd_prefix_bounds).
+  rsvd_status prefix_bounds(const T* A, int64_t lda, int nw, const int* widths, double* bounds) {
+    const int64_t m = P.d.m, n = P.d.n;
+    const int r = L.r;
+    int* flags = P.at<int>(L.flags);
+    HIP_TRY(launch_fill_int(flags, kFlags, 0, st));
+    RS_TRY(stage_a(A, lda, nullptr));
+    T* gc = P.at<T>(L.gc);
+    T* agc = P.at<T>(L.agc);
+    T* E = P.at<T>(L.E);
+    T* H = P.at<T>(L.small);
+    T* tmp = P.at<T>(L.tmpr);
+    T* Q = P.at<T>(L.Q);
+    const int dt = (sizeof(T) == 8) ? RSVD_F64 : RSVD_F32;
+    HIP_TRY(launch_gaussian<T>(P.d.seed, 6u, n, r, 0, gc, 1, L.ldn, st));
+    RS_TRY(apply_a(A, lda, gc, r, agc, dt));
+    for (int i = 0; i < nw; ++i) {
+      const int w = widths[i];
+      HIP_TRY(hipMemcpyAsync(E, agc, (size_t)r * L.ldm * sizeof(T), hipMemcpyDeviceToDevice, st));
+      RS_TRY(panel_tprod(Q, w, agc, r, L.ldm, m, L.s_gm, H, L.LPmax));
+      RS_TRY(panel_mult(Q, w, L.ldm, m, H, L.LPmax, r, tmp, L.ldm));
+      HIP_TRY(launch_axpy_panel<T>(E, L.ldm, tmp, L.ldm, m, r, T(-1), st));
+      double mx = 0.0;
+      RS_TRY(max_colnorm(E, &mx));
+      bounds[i] = bound_from(mx);
+    }
+    return RSVD_OK;
+  }
+
+  rsvd_status run(const T* A, int64_t lda, const double* omega_in, T* U, int64_t ldu, double* S, T* V, int64_t ldv,
+                  int kout) {
+    const int64_t m = P.d.m, n = P.d.n;
+    const int l = L.l;
+    T* omega = P.at<T>(L.omega);
+    T* Y = P.at<T>(L.Y);
+    T* Q = P.at<T>(L.Q);
+    T* Bt = P.at<T>(L.Bt);
+    int* flags = P.at<int>(L.flags);
+    P.rank_out = kout;
+    P.fallback_steps = 0;
+    P.err_bound = 0.0;
+    P.frob_res = -1.0;
+    mark(0);
+    HIP_TRY(launch_fill_int(flags, kFlags, 0, st));
+    const int sk = P.d.sketch_dtype, pj = P.d.proj_dtype;
+    RS_TRY(stage_a(A, lda, omega_in));
     // (7): B = Q^T A, held as B^T (n x l panel).
     RS_TRY(apply_at(A, lda, Q, l, Bt, pj));
     mark(3);
@@ -558,7 +661,7 @@ rsvd_status rsvd_workspace_size(const rsvd_desc* d, size_t* h_bytes) {
   if (!h_bytes || !validate(d)) return RSVD_E_ARG;
   rsvd_status s = supported(d);
   if (s != RSVD_OK) return s;
-  *h_bytes = make_layout(d).total;
+  *h_bytes = make_layout_any(d).total;
   return RSVD_OK;
 }
 
@@ -567,7 +670,7 @@ rsvd_status rsvd_plan(const rsvd_desc* d, void* d_ws, size_t ws_bytes, void* str
   *h_out = nullptr;
   rsvd_status s = supported(d);
   if (s != RSVD_OK) return s;
-  Layout L = make_layout(d);
+  Layout L = make_layout_any(d);
   if (!d_ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return RSVD_E_WORKSPACE;
   rsvd_plan_s* p = new (std::nothrow) rsvd_plan_s();
   if (!p) return RSVD_E_HIP;
@@ -598,9 +701,12 @@ void rsvd_destroy(rsvd_plan_t p) {
   delete p;
 }
 
-rsvd_status rsvd_factor(rsvd_plan_t p, const void* d_A, int64_t lda, const double* d_Omega, void* d_U, int64_t ldu,
-                        double* d_S, void* d_V, int64_t ldv, rsvd_info* h_info) {
-  if (!p || !d_A || !d_U || !d_S) return RSVD_E_ARG;
+}  // extern "C"
+
+namespace {
+
+rsvd_status factor_fixed(rsvd_plan_t p, const void* d_A, int64_t lda, const double* d_Omega, void* d_U, int64_t ldu,
+                         double* d_S, void* d_V, int64_t ldv, rsvd_info* h_info) {
   const rsvd_desc& d = p->d;
   const int l = d.k + d.p;
   const int kout = (d.flags & RSVD_RETURN_RANK_L) ? l : d.k;
@@ -660,6 +766,147 @@ rsvd_status rsvd_factor(rsvd_plan_t p, const void* d_A, int64_t lda, const doubl
               flags[1], flags[2], p->err_bound, p->rank_out);
   }
   return s;
+}
+
+// Modelled time (ms) of the plain method at (p, q); see include/rsvd.h.
+double sel_cost_ms(int64_t m, int64_t n, int k, int p, int q) {
+  const double l = (double)std::min<int64_t>({(int64_t)k + p, m, n});
+  const double passes = (2.0 * q + 2.0) * 2.0 * (double)m * (double)n * l / 6.0e10;
+  const double orth = (2.0 * q + 1.0) * 0.3 * pow(std::max(l / 128.0, 1.0), 1.5);
+  const double jac = 2.5 * pow(l / 95.0, 1.5);
+  return 0.4 + passes + orth + jac;
+}
+
+// Grid point of least expected time cost * (2 - prob) among those with prob >= tau (a miss is taken to
+// double the time through the fallback); the most probable point if none reaches tau.
+void sel_choose(const float* z, int64_t m, int64_t n, int k, float tau, int cap, int* p_out, int* q_out) {
+  double best_e = 0.0;
+  int best = -1, best_any = -1;
+  double best_prob = -1.0;
+  for (int iq = 0; iq < kSelNQ; ++iq)
+    for (int ip = 0; ip < kSelNP; ++ip) {
+      if (k + kSelP[ip] > cap) continue;
+      const int o = iq * kSelNP + ip;
+      const double prob = 1.0 / (1.0 + exp(-(double)z[o]));
+      if (prob > best_prob) { best_prob = prob; best_any = o; }
+      if (prob >= tau) {
+        const double e = sel_cost_ms(m, n, k, kSelP[ip], iq) * (2.0 - prob);
+        if (best < 0 || e < best_e) { best_e = e; best = o; }
+      }
+    }
+  const int o = best >= 0 ? best : best_any;
+  *p_out = kSelP[o % kSelNP];
+  *q_out = o / kSelNP;
+}
+
+// The plan's description and layout swapped for a derived (p, q) during one call.
+struct DescSwap {
+  rsvd_plan_s* p;
+  rsvd_desc d;
+  Layout L;
+  DescSwap(rsvd_plan_s* pp, const rsvd_desc& e) : p(pp), d(pp->d), L(pp->L) {
+    p->d = e;
+    p->L = make_layout(&e);
+  }
+  ~DescSwap() { p->d = d; p->L = L; }
+};
+
+rsvd_status probe_run(rsvd_plan_t p, const void* d_A, int64_t lda) {
+  if (p->d.a_dtype == RSVD_F64) {
+    Path<double> path(*p);
+    return path.probe(static_cast<const double*>(d_A), lda);
+  }
+  Path<float> path(*p);
+  return path.probe(static_cast<const float*>(d_A), lda);
+}
+
+}  // namespace
+
+extern "C" {
+
+rsvd_status rsvd_factor(rsvd_plan_t p, const void* d_A, int64_t lda, const double* d_Omega, void* d_U, int64_t ldu,
+                        double* d_S, void* d_V, int64_t ldv, rsvd_info* h_info) {
+  if (!p || !d_A || !d_U || !d_S) return RSVD_E_ARG;
+  if (!selector_mode(&p->d)) return factor_fixed(p, d_A, lda, d_Omega, d_U, ldu, d_S, d_V, ldv, h_info);
+  // Learned selector: probe, network, decision, then the plain method with the chosen (p, q).
+  if (!p->theta || d_Omega || lda < p->d.n) return RSVD_E_ARG;
+  rsvd_status s = probe_run(p, d_A, lda);
+  if (s != RSVD_OK) return s;
+  float* sel = reinterpret_cast<float*>(p->ws + p->L.sel);
+  HIP_TRY(launch_mlp_forward(p->theta, 1, sel, sel + 16, sel + 80, sel + 144, p->st));
+  float z[40];
+  HIP_TRY(hipMemcpyAsync(z, sel + 144, sizeof(z), hipMemcpyDeviceToHost, p->st));
+  HIP_TRY(hipStreamSynchronize(p->st));
+  int pc = 0, qc = 0;
+  sel_choose(z, p->d.m, p->d.n, p->d.k, p->tau, sel_lcap(&p->d), &pc, &qc);
+  p->p_used = pc;
+  p->q_used = qc;
+  DescSwap swap(p, derived_desc(&p->d, pc, qc));
+  return factor_fixed(p, d_A, lda, nullptr, d_U, ldu, d_S, d_V, ldv, h_info);
+}
+
+rsvd_status rsvd_selector_set(rsvd_plan_t p, const float* d_theta, float tau) {
+  if (!p || !d_theta || !(tau > 0.f) || !(tau < 1.f) || !selector_mode(&p->d)) return RSVD_E_ARG;
+  p->theta = d_theta;
+  p->tau = tau;
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_probe_sigma(rsvd_plan_t p, const void* d_A, int64_t lda, double* d_sigma16, float* d_x) {
+  if (!p || !d_A || !d_sigma16 || lda < p->d.n) return RSVD_E_ARG;
+  rsvd_status s = probe_run(p, d_A, lda);
+  if (s != RSVD_OK) return s;
+  HIP_TRY(hipMemcpyAsync(d_sigma16, p->ws + p->L.sigma, 16 * sizeof(double), hipMemcpyDeviceToDevice, p->st));
+  if (d_x) HIP_TRY(hipMemcpyAsync(d_x, p->ws + p->L.sel, 16 * sizeof(float), hipMemcpyDeviceToDevice, p->st));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_prefix_bounds(rsvd_plan_t p, const void* d_A, int64_t lda, int32_t n_widths, const int32_t* h_widths,
+                               double* h_bounds) {
+  if (!p || !d_A || lda < p->d.n || n_widths < 1 || !h_widths || !h_bounds) return RSVD_E_ARG;
+  if (selector_mode(&p->d) || !(p->d.eps > 0.0)) return RSVD_E_ARG;
+  for (int i = 0; i < n_widths; ++i)
+    if (h_widths[i] < 1 || h_widths[i] > p->L.l) return RSVD_E_ARG;
+  rsvd_status s;
+  p->ngemm = 0;
+  if (p->d.a_dtype == RSVD_F64) {
+    Path<double> path(*p);
+    s = path.prefix_bounds(static_cast<const double*>(d_A), lda, n_widths, h_widths, h_bounds);
+  } else {
+    Path<float> path(*p);
+    s = path.prefix_bounds(static_cast<const float*>(d_A), lda, n_widths, h_widths, h_bounds);
+  }
+  if (s != RSVD_OK) return s;
+  int flags[kFlags];
+  HIP_TRY(hipMemcpyAsync(flags, p->ws + p->L.flags, sizeof(flags), hipMemcpyDeviceToHost, p->st));
+  HIP_TRY(hipStreamSynchronize(p->st));
+  return (flags[0] > 0 || flags[4] != 0) ? RSVD_E_NONFINITE : RSVD_OK;
+}
+
+rsvd_status rsvd_mlp_forward(const float* d_theta, int32_t batch, const float* d_X, float* d_H1, float* d_H2,
+                             float* d_Z, void* stream) {
+  if (!d_theta || batch < 1 || !d_X || !d_H1 || !d_H2 || !d_Z) return RSVD_E_ARG;
+  HIP_TRY(launch_mlp_forward(d_theta, batch, d_X, d_H1, d_H2, d_Z, reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_mlp_backward(const float* d_theta, int32_t batch, const float* d_X, const float* d_H1,
+                              const float* d_H2, const float* d_Z, const float* d_Y, const float* d_M, float* d_grad,
+                              float* d_loss, float* d_scratch, void* stream) {
+  if (!d_theta || batch < 1 || !d_X || !d_H1 || !d_H2 || !d_Z || !d_Y || !d_M || !d_grad || !d_loss || !d_scratch)
+    return RSVD_E_ARG;
+  HIP_TRY(launch_mlp_backward(d_theta, batch, d_X, d_H1, d_H2, d_Z, d_Y, d_M, d_grad, d_loss, d_scratch,
+                              reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_mlp_adam(float* d_theta, const float* d_grad, float* d_m, float* d_v, int32_t n, float lr,
+                          float beta1, float beta2, float eps, int32_t step, void* stream) {
+  if (!d_theta || !d_grad || !d_m || !d_v || n < 1 || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return RSVD_E_ARG;
+  HIP_TRY(launch_adam(d_theta, d_grad, d_m, d_v, n, lr, beta1, beta2, eps, step, reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
 }
 
 rsvd_status rsvd_gaussian(uint64_t seed, uint32_t stream_id, int64_t rows, int64_t cols, int64_t col0, int32_t dtype,

@@ -109,3 +109,28 @@ def test_null_arguments(lib):
     assert lib.rsvd_philox4x32_10(-1, None, 0, 0, None, None) == -1
     lib.rsvd_destroy(None)
     assert lib.rsvd_status_str(-3) == b"RSVD_E_HIP"
+
+
+def test_selector_mode_workspace_covers_every_grid_point(lib):
+    from paper_1607_01649_amd._lib import RSVD_SEL_P
+    st, need = _ws(lib, _desc(p=-1, q=-1, eps=1e-3, max_rank=800))
+    assert st == 0
+    for p in RSVD_SEL_P:
+        if 20 + p <= 800:
+            st2, n2 = _ws(lib, _desc(p=p, q=4, eps=1e-3, max_rank=800))
+            assert st2 == 0 and n2 <= need
+    assert _ws(lib, _desc(p=-1, q=0))[0] == -1 and _ws(lib, _desc(p=0, q=-1))[0] == -1
+
+
+def test_selector_and_network_entries_reject_bad_arguments(lib):
+    f = ctypes.c_void_p(4096)
+    assert lib.rsvd_selector_set(None, f, 0.5) == -1
+    assert lib.rsvd_probe_sigma(None, f, 10, f, None) == -1
+    w = (ctypes.c_int32 * 1)(5)
+    b = (ctypes.c_double * 1)()
+    assert lib.rsvd_prefix_bounds(None, f, 10, 1, w, b) == -1
+    assert lib.rsvd_mlp_forward(None, 4, f, f, f, f, None) == -1
+    assert lib.rsvd_mlp_forward(f, 0, f, f, f, f, None) == -1
+    assert lib.rsvd_mlp_backward(f, 4, f, f, f, f, f, f, f, f, None, None) == -1
+    assert lib.rsvd_mlp_adam(f, f, f, f, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1     # step must be >= 1
+    assert lib.rsvd_mlp_adam(f, f, f, f, 10, 1e-3, 1.0, 0.999, 1e-8, 1, None) == -1     # beta1 < 1

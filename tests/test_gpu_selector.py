@@ -1,0 +1,177 @@
+"""GPU parity of the learned (p, q) selector against the float64 oracle: the
+network's forward pass, gradients and Adam step, the probe features, the
+prefix certificates used as labels, the library's decision, and what the
+trained network gains over the paper's fixed choice."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from oracle import selector as osel
+from workloads import gen
+
+from tests.gpu_helpers import device
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed, nb):
+    g = np.random.default_rng(seed)
+    theta = omlp.init(seed)
+    theta[omlp.N_PARAM - 40:] = g.normal(0, 0.1, 40)
+    X = g.normal(0, 1, (nb, 16))
+    Y = (g.random((nb, 40)) < 0.4).astype(float)
+    M = (g.random((nb, 40)) < 0.8).astype(float)
+    return theta, X, Y, M
+
+
+def _dev(a, dt=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device())
+
+
+@pytest.mark.parametrize("nb", [1, 7, 300])
+def test_mlp_forward_backward_match_the_oracle(nb):
+    """FP32 kernels against the FP64 oracle at float32-rounded inputs:
+    logits to 1e-5 relative, gradients to 1e-4 (of the largest entry)."""
+    import torch
+    from paper_1607_01649_amd import rsvd_mlp_backward, rsvd_mlp_forward
+    theta, X, Y, M = _case(nb, nb)
+    theta32 = theta.astype(np.float32).astype(np.float64)
+    X32 = X.astype(np.float32).astype(np.float64)
+    H1r, H2r, Zr = omlp.forward(theta32, X32)
+    gr = omlp.backward(theta32, X32, H1r, H2r, Zr, Y, M)
+    lr_ = omlp.bce_loss(Zr, Y, M)
+    th, Xd, Yd, Md = _dev(theta), _dev(X), _dev(Y), _dev(M)
+    f = dict(dtype=torch.float32, device=device())
+    H1, H2, Z = torch.empty(nb, 64, **f), torch.empty(nb, 64, **f), torch.empty(nb, 40, **f)
+    grad, loss, scr = torch.empty(omlp.N_PARAM, **f), torch.empty(2, **f), torch.empty(nb * 168, **f)
+    rsvd_mlp_forward(th, Xd, H1, H2, Z)
+    rsvd_mlp_backward(th, Xd, H1, H2, Z, Yd, Md, grad, loss, scr)
+    torch.cuda.synchronize()
+    Z = Z.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(Z - Zr)) <= 1e-5 * max(1.0, np.max(np.abs(Zr)))
+    assert np.allclose(H1.cpu().numpy(), H1r, rtol=0, atol=1e-5 * max(1.0, np.abs(H1r).max()))
+    g = grad.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(g - gr)) <= 1e-4 * np.max(np.abs(gr))
+    assert abs(float(loss[0]) - lr_) <= 1e-5 * lr_
+    assert float(loss[1]) == M.sum()
+
+
+def test_adam_step_matches_the_oracle():
+    import torch
+    from paper_1607_01649_amd import rsvd_mlp_adam
+    g = np.random.default_rng(4)
+    n = omlp.N_PARAM
+    th0, gr = g.normal(0, 1, n), g.normal(0, 1e-2, n)
+    m0, v0 = g.normal(0, 1e-3, n), g.random(n) * 1e-4
+    th_d, m_d, v_d = _dev(th0), _dev(m0), _dev(v0)
+    rsvd_mlp_adam(th_d, _dev(gr), m_d, v_d, 1e-3, 7)
+    torch.cuda.synchronize()
+    r_th, r_m, r_v = omlp.adam_step(th0.astype(np.float32).astype(np.float64), gr.astype(np.float32).astype(np.float64),
+                                    m0.astype(np.float32).astype(np.float64), v0.astype(np.float32).astype(np.float64),
+                                    7, lr=1e-3)
+    assert np.allclose(th_d.cpu().numpy(), r_th, rtol=0, atol=2e-6 * np.abs(r_th).max())
+    assert np.allclose(m_d.cpu().numpy(), r_m, rtol=1e-5, atol=1e-9)
+    assert np.allclose(v_d.cpu().numpy(), r_v, rtol=1e-5, atol=1e-12)
+
+
+def test_gpu_training_fits_a_tiny_set():
+    from paper_1607_01649_amd import selector
+    theta, X, Y, M = _case(8, 8)
+    tr = selector.Trainer(theta.astype(np.float32), device())
+    hist = tr.fit(X.astype(np.float32), Y.astype(np.float32), np.ones_like(M, np.float32), epochs=1500, batch=8,
+                  lr=1e-2)
+    assert hist[0] > 0.5 and hist[-1] < 0.02
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_probe_features_match_the_oracle(dtype):
+    import torch
+    from paper_1607_01649_amd import RSVD, rsvd_probe_sigma
+    sigma = gen.spectrum("polyexp", 200, alpha=1.2, tau=40.0)
+    A = gen.low_rank_matrix(900, 700, sigma, 1e-9, seed=31)
+    k, seed = 23, 17
+    ref = osel.probe_sigma(A, seed)
+    Ad = torch.from_numpy(A if dtype == "f64" else A.astype(np.float32)).to(device())
+    s = RSVD(900, 700, k, 0, 0, dtype=dtype, device=device(), seed=seed)
+    sig = torch.empty(16, dtype=torch.float64, device=device())
+    x = torch.empty(16, dtype=torch.float32, device=device())
+    rsvd_probe_sigma(s.plan, Ad, sig, x)
+    torch.cuda.synchronize()
+    tol = 1e-10 if dtype == "f64" else 2e-5
+    assert np.max(np.abs(sig.cpu().numpy() - ref) / ref) <= tol
+    assert np.allclose(x.cpu().numpy(), osel.features(ref, k), atol=1e-6)
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_prefix_bounds_equal_separate_plain_runs(q):
+    """One Stage A run at k+40 columns labels every smaller oversampling: each
+    prefix certificate equals the oracle's certificate of a separate run of
+    the plain method with that many columns."""
+    import torch
+    from paper_1607_01649_amd import RSVD, rsvd_prefix_bounds
+    sigma = gen.spectrum("polyexp", 150, alpha=1.0, tau=60.0)
+    A = gen.low_rank_matrix(400, 300, sigma, 1e-7, seed=21)
+    k, seed, ps = 12, 3, [0, 5, 10, 20, 40]
+    ref = osel.plain_certificates(A, k, q, seed, ps)
+    s = RSVD(400, 300, k, ps[-1], q, dtype="f64", device=device(), seed=seed, eps=1e-3)
+    got = rsvd_prefix_bounds(s.plan, torch.from_numpy(A).to(device()), [k + p for p in ps])
+    for g_, r in zip(got, ref):
+        assert abs(g_ - r) <= 1e-6 * r
+
+
+def test_selector_mode_takes_the_oracle_decision():
+    """With fixed parameters, the library's (p, q) equals the oracle network's
+    decision on the oracle's probe features; the factorisation then meets the
+    tolerance (with the fallback where needed)."""
+    import torch
+    from paper_1607_01649_amd import RSVD
+    m, n, seed, tau = 1500, 1200, 5, 0.5
+    sigma = gen.spectrum("polyexp", 1200, alpha=1.5, tau=100.0)
+    A = gen.low_rank_matrix(m, n, sigma, 0.0, seed=41).astype(np.float32)
+    k = int(np.sum(sigma > 1e-3 * sigma[0]))
+    Ad = torch.from_numpy(A).to(device())
+    x_ref = osel.features(osel.probe_sigma(A.astype(np.float64), seed), k)
+    for tseed in range(10, 40):
+        theta = omlp.init(tseed)
+        theta[-40:] = np.random.default_rng(tseed).normal(0, 2.0, 40)
+        prob = 1.0 / (1.0 + np.exp(-omlp.forward(theta.astype(np.float32).astype(np.float64), x_ref[None])[2][0]))
+        if np.min(np.abs(prob - tau)) > 1e-3:
+            break
+    p_ref, q_ref = osel.choose(prob, m, n, k, tau)
+    s = RSVD(m, n, k, -1, -1, dtype="f32", device=device(), seed=seed, eps=1e-3, max_rank=min(m, n, 1024),
+             fallback_block=32, flags=1)
+    th = torch.from_numpy(theta.astype(np.float32)).to(device())
+    s.set_selector(th, tau)
+    U, S, V, info = s(Ad)
+    assert (info.p_used, info.q_used) == (p_ref, q_ref)
+    assert info.status == 0
+    true = np.linalg.norm(A.astype(np.float64) - (U.double().cpu().numpy() * S.cpu().numpy())
+                          @ V.double().cpu().numpy().T, 2)
+    assert true <= 1e-3 * float(S[0])
+
+
+def test_trained_selector_beats_the_fixed_choice():
+    """Time-to-eps (eps = 1e-3, certificate + fallback) on fresh items of the
+    selector stream: the trained network (weights and threshold committed with
+    the library, trained on the GPU by the library's own kernels) against the
+    paper's p = 10, q = 2.  Compared on the items the defaults certify (the
+    others end at the rank cap under every strategy)."""
+    import torch
+    from paper_1607_01649_amd import selector
+    if not os.path.exists(selector.WEIGHTS):
+        pytest.fail("selector weights missing: run python -m paper_1607_01649_amd.selector train")
+    th, tau = selector.load_weights()
+    theta = torch.from_numpy(th).to(device())
+    rows = selector.evaluate(theta, selector.SEED_TEST, 24, device(), tau=tau, start=9000, with_best=False)
+    summ = selector.summarize(rows)
+    print(summ)
+    assert summ["learned"]["certified"] >= summ["default"]["certified"] - 1e-9
+    # the robust gain: most items are certified at the first attempt (the defaults never are)
+    assert summ["learned"]["no_fallback"] >= summ["default"]["no_fallback"] + 0.3
+    # time to eps: a few percent better on the measured boxes (the fallback is cheap and both end near the
+    # same rank, so the margin is small); asserted not worse beyond timing noise
+    assert summ["learned"]["certifiable_total_ms"] <= 1.03 * summ["default"]["certifiable_total_ms"]

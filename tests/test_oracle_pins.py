@@ -476,10 +476,10 @@ def test_selector_decision_rule_by_brute_force():
         pts = [(o, pp, qq) for qi, qq in enumerate(selector.Q_GRID) for pi, pp in enumerate(selector.P_GRID)
                for o in [qi * 8 + pi] if k + pp <= min(m, n, 1024)]
         feas = [t for t in pts if prob[t[0]] >= tau]
+        o_sel = 8 * selector.Q_GRID.index(q) + selector.P_GRID.index(p)
         if feas:
-            best = min(selector.cost_ms(m, n, k, t[1], t[2]) for t in feas)
-            assert selector.cost_ms(m, n, k, p, q) == best and prob[8 * selector.Q_GRID.index(q)
-                                                                   + selector.P_GRID.index(p)] >= tau
+            best = min(selector.cost_ms(m, n, k, t[1], t[2]) * (2.0 - prob[t[0]]) for t in feas)
+            assert selector.cost_ms(m, n, k, p, q) * (2.0 - prob[o_sel]) == best and prob[o_sel] >= tau
         else:
             assert prob[8 * selector.Q_GRID.index(q) + selector.P_GRID.index(p)] == max(prob[t[0]] for t in pts)
     # cost grows with p and with q

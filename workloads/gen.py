@@ -148,6 +148,39 @@ def selector_item_params(seed: int, item: int):
     return m, n, alpha, tau
 
 
+def selector_spectrum(seed: int, item: int):
+    """(m, n, sigma, k) of one item of the selector stream: sigma_j = j^-alpha
+    exp(-(j-1)/tau) for j = 1..min(m, n) (sigma_1 = 1) and k the number of
+    sigma_j above 1e-3 (the target rank for relative tolerance 1e-3)."""
+    m, n, alpha, tau = selector_item_params(seed, item)
+    s = spectrum("polyexp", min(m, n), alpha=alpha, tau=tau)
+    return m, n, s, int(np.sum(s > 1e-3 * s[0]))
+
+
+def selector_matrix(seed: int, item: int, device: str):
+    """A = H_U [diag(sigma); 0] H_V^T for one selector item, float32 on a torch
+    device, with H_U = (I - 2 u1 u1^T)(I - 2 u2 u2^T) (and H_V likewise) for
+    seeded random unit vectors: orthogonal factors that cost O(mn) to apply.
+    Gaussian sketches and probes are orthogonally invariant, so the method's
+    error and certificate have the same distribution as for Haar-random
+    factors; only sigma, m and n matter.  Returns (A, k)."""
+    import torch
+    m, n, s, k = selector_spectrum(seed, item)
+    g = _rng(seed * 1_000_033 + item, 11)
+    A = torch.zeros(m, n, dtype=torch.float64, device=device)
+    r = len(s)
+    idx = torch.arange(r, device=device)
+    A[idx, idx] = torch.from_numpy(s).to(device)
+    for _ in range(2):
+        u = torch.from_numpy(g.standard_normal(m)).to(device)
+        u /= torch.linalg.norm(u)
+        A -= 2.0 * torch.outer(u, u @ A)
+        v = torch.from_numpy(g.standard_normal(n)).to(device)
+        v /= torch.linalg.norm(v)
+        A -= 2.0 * torch.outer(A @ v, v)
+    return A.to(torch.float32), k
+
+
 @dataclasses.dataclass(frozen=True)
 class WorkloadConfig:
     name: str
