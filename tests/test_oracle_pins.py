@@ -386,6 +386,62 @@ def test_quantised_rsvd_reduces_to_the_plain_oracle_on_representable_data():
     assert np.max(np.abs(d.D - orc.rsvd(A, G, 1).D) / orc.rsvd(A, G, 1).D[0]) < 1e-2
 
 
+def test_fp8_e4m3_codes_and_rounding():
+    """OCP E4M3 landmarks (largest 448 = 0x7E, smallest normal 2^-6 = 0x08,
+    smallest subnormal 2^-9 = 0x01, 1.0 = 0x38, NaN = 0x7F, no infinities),
+    values strictly increasing over the codes, every finite code a fixed point,
+    midpoints to the even code, saturation above 448."""
+    from oracle import quant
+    d = quant.fp8_e4m3_decode(np.arange(256))
+    assert d[0x7E] == 448.0 and d[0x08] == 2.0 ** -6 and d[0x01] == 2.0 ** -9 and d[0x38] == 1.0
+    assert d[0x07] == 7 * 2.0 ** -9 and d[0x10] == 2.0 ** -5 and d[0x3F] == 1.875
+    assert np.isnan(d[0x7F]) and np.isnan(d[0xFF]) and not np.any(np.isinf(d))
+    assert np.all(np.diff(d[:0x7F]) > 0)
+    assert np.array_equal(d[0x80:0xFF], -d[0x00:0x7F])
+    fin = np.arange(256)[np.isfinite(d)]
+    assert np.array_equal(quant.fp8_e4m3_bits(d[fin]), fin.astype(np.uint8))
+    mids = (d[0:0x7E] + d[1:0x7F]) / 2
+    got = quant.fp8_e4m3_bits(mids).astype(int)
+    want = np.where(np.arange(0x7E) % 2 == 0, np.arange(0x7E), np.arange(1, 0x7F))
+    assert np.array_equal(got, want)
+    assert np.all(quant.fp8_e4m3_bits(np.array([449.0, 1e9, -1e30])) == [0x7E, 0x7E, 0xFE])
+    # just off the midpoints: nearest wins
+    eps = np.diff(d[:0x7F]) * 1e-3
+    assert np.array_equal(quant.fp8_e4m3_bits(mids + eps).astype(int), np.arange(1, 0x7F))
+    assert np.array_equal(quant.fp8_e4m3_bits(mids - eps).astype(int), np.arange(0, 0x7E))
+
+
+def test_fp8_block_scale_rule():
+    """2^e is the least power of two with amax <= 448 2^e."""
+    from oracle import quant
+    rng = np.random.default_rng(5)
+    a = np.concatenate([[448.0, 224.0, 1.0, 16.0, 1.75, 2.0 ** -30],
+                        np.exp(rng.uniform(-40, 40, 5000))]).astype(np.float32).astype(np.float64)
+    e = quant.fp8_scale_exponent(a)
+    assert np.all(a <= 448.0 * 2.0 ** e) and np.all(a > 448.0 * 2.0 ** (e - 1))
+    assert quant.fp8_scale_exponent(0.0) == 0
+    codes, ex, deq = quant.fp8_blocks_matrix(rng.standard_normal((300, 200)) * 10, tile=128)
+    assert ex.shape == (3, 2)
+    assert np.all(np.abs(quant.fp8_e4m3_decode(codes)) <= 448)
+
+
+def test_fp8_quantised_rsvd_on_representable_data():
+    """Integers of magnitude <= 16 times a power of two are exact in E4M3 under
+    the block scale, so A is unchanged by its quantisation; with the thin
+    operands left in FP32 the quantisation-aware run equals the plain one."""
+    from oracle import quant
+    rng = np.random.default_rng(7)
+    A = rng.integers(-16, 17, size=(200, 150)).astype(np.float64)
+    A[0, 0] = 16.0
+    assert np.array_equal(quant.fp8_blocks_matrix(A)[2], A)
+    G = rng.standard_normal((150, 12))
+    a = orc.rsvd(A, G.astype(np.float32).astype(np.float64), 1)
+    b = quant.rsvd_quantized(A, G, 1, "f32", "f32")
+    assert np.allclose(a.D, b.D, rtol=1e-6)
+    c = quant.rsvd_quantized(A, G, 1, "fp8", "fp8")
+    assert np.max(np.abs(c.D - a.D) / a.D[0]) < 0.1
+
+
 # ---------------------------------------------------------------- selector network and rule
 
 def _mlp_case(seed, nb=7):
