@@ -107,6 +107,35 @@ rsvd_status rsvd_k_convert_bf16(int64_t m, int64_t n, const float* d_A, int64_t 
 rsvd_status rsvd_k_product_bf16(int64_t rows, int64_t K, const uint16_t* d_A16, int64_t lda, const float* d_X,
                                 int64_t ldx, int32_t ncols, float* d_out, int64_t ldo, void* stream);
 
+/*
+ * Input preparation for the FP8 products (OCP E4M3: bias 7, 3 mantissa bits,
+ * largest finite 448, round to nearest even, saturating): for every 128 x 128
+ * tile (ti, tj) of A (m x n FP32, lda >= n), scale[ti * (ld8/128) + tj] = 2^e
+ * with e the least integer such that max|tile| <= 448 2^e (1 for a zero
+ * tile), d_A8 (m x ld8 bytes, row-major) = E4M3 codes of A / scale and d_A8T
+ * (n x ldT) the same codes transposed; zeros past n (resp. m).  ld8 >= n and
+ * ldT >= m multiples of 128; d_A8, d_A8T 16-byte aligned.  *d_flag gets bit 0
+ * set if A holds a NaN or an infinity.  (The block-scaled format of the
+ * precision growth; tiles serve both orientations.)
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_convert_fp8(int64_t m, int64_t n, const float* d_A, int64_t lda, uint8_t* d_A8, int64_t ld8,
+                               uint8_t* d_A8T, int64_t ldT, float* d_scale, int32_t* d_flag, void* stream);
+
+/*
+ * d_out (panel, ldo >= rows, FP32) = A X for A (rows x K) given as E4M3 codes
+ * d_A8 (lda a multiple of 128, zero past K) with the scale of row block rb
+ * (128 rows) and contraction block kb (128) at d_scale[rb * s_row + kb * s_k],
+ * and X a K x ncols FP32 panel (ldx >= K, a multiple of 4, 16-byte aligned)
+ * quantised on load to E4M3 with one power-of-two scale per 128-row segment
+ * of each column.  FP8 MFMA with FP32 accumulation; each 128-wide block's
+ * partial product is scaled and added.  1 <= ncols <= 1024.
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_product_fp8(int64_t rows, int64_t K, const uint8_t* d_A8, int64_t lda, const float* d_scale,
+                               int64_t s_row, int64_t s_k, const float* d_X, int64_t ldx, int32_t ncols,
+                               float* d_out, int64_t ldo, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

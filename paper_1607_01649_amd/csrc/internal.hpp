@@ -49,6 +49,15 @@ template <typename TU>
 hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, double* sigma, double* uhat_d,
                                   TU* uhat_p, TU* vhat_p, hipStream_t s);
 
+// fp8.hip -- block-scaled OCP E4M3 copies of A (128 x 128 tile scales, shared by A8 and its transpose)
+// and the FP8 MFMA product with an FP32 panel quantised per 128-row segment of each column.
+hipError_t launch_to_fp8(const float* A, int64_t lda, int64_t m, int64_t n, uint8_t* A8, int64_t ld8, uint8_t* A8T,
+                         int64_t ldT, float* scale, int* flag, hipStream_t s);
+// scale of (row block rb, contraction block kb) at sA[rb * s_row + kb * s_k]
+hipError_t launch_nn_fp8(const uint8_t* A, int64_t lda, const float* sA, int64_t s_row, int64_t s_k, int64_t rows,
+                         int64_t K, const float* X, int64_t ldx, int ncols, float* out, int64_t ldo,
+                         int64_t part_stride, int splits, hipStream_t s);
+
 // mlp.hip -- the selector network (16 -> 64 -> 64 -> 40, FP32) and its training steps.
 int mlp_param_count();
 hipError_t launch_mlp_forward(const float* th, int B, const float* X, float* H1, float* H2, float* Z, hipStream_t s);

@@ -97,4 +97,24 @@ rsvd_status rsvd_k_product_bf16(int64_t rows, int64_t K, const uint16_t* A16, in
   return RSVD_OK;
 }
 
+rsvd_status rsvd_k_convert_fp8(int64_t m, int64_t n, const float* A, int64_t lda, uint8_t* A8, int64_t ld8,
+                               uint8_t* A8T, int64_t ldT, float* scale, int32_t* flag, void* stream) {
+  if (!A || !A8 || !A8T || !scale || !flag || m < 1 || n < 1 || lda < n || ld8 < n || ldT < m || ld8 % 128 ||
+      ldT % 128)
+    return RSVD_E_ARG;
+  K_TRY(launch_to_fp8(A, lda, m, n, A8, ld8, A8T, ldT, scale, flag, reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_k_product_fp8(int64_t rows, int64_t K, const uint8_t* A8, int64_t lda, const float* scale,
+                               int64_t s_row, int64_t s_k, const float* X, int64_t ldx, int32_t ncols, float* out,
+                               int64_t ldo, void* stream) {
+  if (!A8 || !scale || !X || !out || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K || lda % 128 ||
+      ldx < K || ldx % 4 || ldo < rows || s_row < 0 || s_k < 0)
+    return RSVD_E_ARG;
+  K_TRY(launch_nn_fp8(A8, lda, scale, s_row, s_k, rows, K, X, ldx, ncols, out, ldo, 0, 1,
+                      reinterpret_cast<hipStream_t>(stream)));
+  return RSVD_OK;
+}
+
 }  // extern "C"

@@ -54,7 +54,7 @@ struct Layout {
   size_t es;   // element size of panels (8 for F64, 4 otherwise)
   int s_nn, s_tn, s_gm, s_gn, s_nn16, s_tn16;
   int64_t ld16, ldT;   // leading dimensions of the bf16 copies of A and A^T
-  size_t a16, a16t, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
+  size_t a16, a16t, a8, a8t, s8, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
       rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, sel, total;
 };
 
@@ -83,12 +83,13 @@ bool validate(const rsvd_desc* d) {
 }
 
 bool uses_bf16(const rsvd_desc* d) { return d->sketch_dtype == RSVD_BF16 || d->proj_dtype == RSVD_BF16; }
+bool uses_fp8(const rsvd_desc* d) { return d->sketch_dtype == RSVD_FP8_E4M3 || d->proj_dtype == RSVD_FP8_E4M3; }
 
 rsvd_status supported(const rsvd_desc* d) {
   if (d->a_dtype == RSVD_F64) {
     if (d->sketch_dtype != RSVD_F64 || d->proj_dtype != RSVD_F64) return RSVD_E_UNSUPPORTED;
   } else {
-    auto ok = [](int t) { return t == RSVD_F32 || t == RSVD_BF16; };
+    auto ok = [](int t) { return t == RSVD_F32 || t == RSVD_BF16 || t == RSVD_FP8_E4M3; };
     if (!ok(d->sketch_dtype) || !ok(d->proj_dtype)) return RSVD_E_UNSUPPORTED;
   }
   return RSVD_OK;
@@ -129,6 +130,10 @@ Layout make_layout(const rsvd_desc* d) {
   const bool b16 = uses_bf16(d);
   L.a16 = take(b16 ? (size_t)d->m * L.ld16 * 2 : 256);
   L.a16t = take(b16 ? (size_t)d->n * L.ldT * 2 : 256);
+  const bool b8 = uses_fp8(d);
+  L.a8 = take(b8 ? (size_t)d->m * L.ld16 : 256);
+  L.a8t = take(b8 ? (size_t)d->n * L.ldT : 256);
+  L.s8 = take(b8 ? (size_t)(L.ld16 / 128) * (L.ldT / 128) * sizeof(float) : 256);
   L.omega = take(Wd * L.ldn * L.es);
   L.gc = take(R * L.ldn * L.es);
   L.Y = take(Wd * L.ldm * L.es);
@@ -299,6 +304,12 @@ template <typename T> struct Path {
         HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16), L.ld16, m, n, X, L.ldn, nc, part, L.ldm, (int64_t)LPc * L.ldm,
                                S, st));
       }
+    } else if (dt == RSVD_FP8_E4M3) {
+      if constexpr (sizeof(T) == 4) {
+        S = L.s_nn16;
+        HIP_TRY(launch_nn_fp8(P.at<uint8_t>(L.a8), L.ld16, P.at<float>(L.s8), L.ld16 / 128, 1, m, n, X, L.ldn, nc,
+                              part, L.ldm, (int64_t)LPc * L.ldm, S, st));
+      }
     } else {
       HIP_TRY((launch_nn<T, T, T, T>(A, lda, m, n, X, L.ldn, nc, part, L.ldm, (int64_t)LPc * L.ldm, S, st)));
     }
@@ -319,6 +330,12 @@ template <typename T> struct Path {
         S = L.s_tn16;
         HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16t), L.ldT, n, m, Qp, L.ldm, nc, part, L.ldn, (int64_t)LPc * L.ldn,
                                S, st));
+      }
+    } else if (dt == RSVD_FP8_E4M3) {
+      if constexpr (sizeof(T) == 4) {
+        S = L.s_tn16;
+        HIP_TRY(launch_nn_fp8(P.at<uint8_t>(L.a8t), L.ldT, P.at<float>(L.s8), 1, L.ld16 / 128, n, m, Qp, L.ldm, nc,
+                              part, L.ldn, (int64_t)LPc * L.ldn, S, st));
       }
     } else {
       HIP_TRY(
@@ -466,6 +483,11 @@ template <typename T> struct Path {
       if constexpr (sizeof(T) == 4)
         HIP_TRY(launch_to_bf16(A, lda, m, n, P.at<uint16_t>(L.a16), L.ld16, P.at<uint16_t>(L.a16t), L.ldT, flags + 4,
                                st));
+    }
+    if (uses_fp8(&P.d)) {
+      if constexpr (sizeof(T) == 4)
+        HIP_TRY(launch_to_fp8(A, lda, m, n, P.at<uint8_t>(L.a8), L.ld16, P.at<uint8_t>(L.a8t), L.ldT,
+                              P.at<float>(L.s8), flags + 4, st));
     }
     // Figure 5 (1): Gaussian test matrix.
     if (omega_in)

@@ -246,3 +246,99 @@ def test_product_bf16_is_exact_on_integers(rows, K, ncols):
     out2 = torch.zeros((9, K), dtype=torch.float32, device=device())
     assert _lib().rsvd_k_product_bf16(K, rows, _p(A16T), ldT, _p(dP), ldp, 9, _p(out2), K, None) == 0
     assert np.array_equal(out2.cpu().numpy().astype(np.float64), (A.astype(np.float64).T @ P).T)
+
+
+def _fp8_convert(A, torch):
+    m, n = A.shape
+    ld8, ldT = (n + 127) // 128 * 128, (m + 127) // 128 * 128
+    dA = _t(A, torch.float32)
+    A8 = torch.full((m, ld8), 0x55, dtype=torch.uint8, device=device())
+    A8T = torch.full((n, ldT), 0x55, dtype=torch.uint8, device=device())
+    sc = torch.zeros((ldT // 128) * (ld8 // 128), dtype=torch.float32, device=device())
+    flag = torch.zeros(1, dtype=torch.int32, device=device())
+    assert _lib().rsvd_k_convert_fp8(m, n, _p(dA), n, _p(A8), ld8, _p(A8T), ldT, _p(sc), _p(flag), None) == 0
+    return A8, A8T, sc, flag, ld8, ldT
+
+
+def test_convert_fp8_is_bit_exact():
+    """E4M3 codes of both copies and the power-of-two tile scales equal the
+    oracle's (ragged tiles, tiles of very different magnitude, exact ties,
+    saturation-free by construction, values that round to zero)."""
+    import torch
+    from oracle import quant
+    rng = np.random.default_rng(12)
+    m, n = 300, 517
+    A = (rng.standard_normal((m, n)) * np.exp(rng.uniform(-8, 8, (m, 1)))).astype(np.float32)
+    A[:128, :128] *= np.float32(1e-30)           # a tile far below the others
+    A[200, :8] = np.array([1.0, 1.0625, 1.1875, 3.0, 2 ** -10, -2 ** -9, 0.0, -0.0], dtype=np.float32)
+    A8, A8T, sc, flag, ld8, ldT = _fp8_convert(A, torch)
+    codes, ex, _ = quant.fp8_blocks_matrix(A)
+    got = A8.cpu().numpy()
+    assert np.array_equal(got[:, :n], codes)
+    assert np.all(got[:, n:] == 0)
+    gt = A8T.cpu().numpy()
+    assert np.array_equal(gt[:, :m], codes.T)
+    assert np.all(gt[:, m:] == 0)
+    want_sc = np.zeros((ldT // 128, ld8 // 128))
+    want_sc[:ex.shape[0], :ex.shape[1]] = 2.0 ** ex
+    assert np.array_equal(sc.cpu().numpy().reshape(want_sc.shape)[:ex.shape[0], :ex.shape[1]],
+                          want_sc[:ex.shape[0], :ex.shape[1]])
+    assert int(flag.cpu()[0]) == 0
+    A[5, 7] = np.nan
+    _, _, _, flag, _, _ = _fp8_convert(A, torch)
+    assert int(flag.cpu()[0]) == 1
+
+
+@pytest.mark.parametrize("rows,K,ncols", [(128, 128, 16), (300, 517, 30), (77, 1000, 110), (1000, 129, 128),
+                                          (33, 70, 7), (513, 2048, 200)])
+def test_product_fp8_is_exact_on_integers(rows, K, ncols):
+    """Integers of magnitude <= 16 stay exact under the block scales and the
+    FP32 sums stay below 2^24: A X and (through the transposed copy) A^T P are
+    bit-exact."""
+    import torch
+    rng = np.random.default_rng(rows * 11 + K)
+    A = rng.integers(-16, 17, size=(rows, K)).astype(np.float32)
+    X = rng.integers(-16, 17, size=(K, ncols)).astype(np.float32)
+    A8, A8T, sc, flag, lda, ldT = _fp8_convert(A, torch)
+    ntc = lda // 128
+    ldx = (K + 3) // 4 * 4 + 4
+    Xp = np.zeros((ncols, ldx), dtype=np.float32)
+    Xp[:, :K] = X.T
+    ldo = rows + 3
+    out = torch.full((ncols, ldo), -7.0, dtype=torch.float32, device=device())
+    assert _lib().rsvd_k_product_fp8(rows, K, _p(A8), lda, _p(sc), ntc, 1, _p(_t(Xp, torch.float32)), ldx, ncols,
+                                     _p(out), ldo, None) == 0
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got[:, :rows], (A.astype(np.float64) @ X.astype(np.float64)).T)
+    assert np.all(got[:, rows:] == -7.0)
+    P = rng.integers(-16, 17, size=(rows, 9)).astype(np.float32)
+    Pp = np.zeros((9, ldT), dtype=np.float32)
+    Pp[:, :rows] = P.T
+    out2 = torch.zeros((9, K), dtype=torch.float32, device=device())
+    assert _lib().rsvd_k_product_fp8(K, rows, _p(A8T), ldT, _p(sc), 1, ntc, _p(_t(Pp, torch.float32)), ldT, 9,
+                                     _p(out2), K, None) == 0
+    assert np.array_equal(out2.cpu().numpy().astype(np.float64), (A.astype(np.float64).T @ P).T)
+
+
+def test_product_fp8_matches_the_dequantised_operands():
+    """Random data: the product equals the FP64 product of the oracle's
+    dequantised operands within FP32 accumulation error."""
+    import torch
+    from oracle import quant
+    rng = np.random.default_rng(3)
+    rows, K, ncols = 700, 1300, 40
+    A = (rng.standard_normal((rows, K)) * np.exp(rng.uniform(-3, 3, (1, K)))).astype(np.float32)
+    X = rng.standard_normal((K, ncols)).astype(np.float32)
+    A8, A8T, sc, flag, lda, ldT = _fp8_convert(A, torch)
+    ldx = (K + 3) // 4 * 4
+    Xp = np.zeros((ncols, ldx), dtype=np.float32)
+    Xp[:, :K] = X.T
+    out = torch.zeros((ncols, rows), dtype=torch.float32, device=device())
+    assert _lib().rsvd_k_product_fp8(rows, K, _p(A8), lda, _p(sc), lda // 128, 1, _p(_t(Xp, torch.float32)), ldx,
+                                     ncols, _p(out), rows, None) == 0
+    Aq = quant.fp8_blocks_matrix(A)[2]
+    Xq = quant.fp8_round_thin(X)
+    ref = Aq @ Xq
+    bound = 2 * K * 2.0 ** -24 * (np.abs(Aq) @ np.abs(Xq))
+    assert np.all(np.abs(out.cpu().numpy().T - ref) <= bound)
+

@@ -203,6 +203,35 @@ def test_factor_bf16_matches_the_quantisation_aware_oracle(m, n, rank, alpha, k,
     assert max_rel_sigma(S, plain.D, k) <= 2e-2
 
 
+FP8_CASES = [
+    # m, n, rank, alpha, k, p, q, sketch, proj
+    (3000, 1500, 300, 0.5, 20, 10, 2, "fp8", "fp8"),
+    (1237, 901, 200, 1.0, 12, 8, 1, "fp8", "f32"),
+    (2048, 1024, 256, 0.5, 50, 14, 2, "fp8", "fp8"),
+]
+
+
+@pytest.mark.parametrize("m,n,rank,alpha,k,p,q,sk,pj", FP8_CASES)
+def test_factor_fp8_matches_the_quantisation_aware_oracle(m, n, rank, alpha, k, p, q, sk, pj):
+    """Block-scaled FP8 operands (128 x 128 tiles of A, 128-row segments of the
+    thin operands), FP32 accumulation: parity against the oracle run on the
+    identically quantised operands.  Beyond accumulation error, a thin-operand
+    entry whose FP32 (GPU) and FP64 (oracle) values straddle a rounding
+    boundary can land one E4M3 step apart, hence 1e-3 rather than the bf16
+    case's 1e-4; the format error against the plain oracle is reported."""
+    from oracle import quant
+    sigma = gen.spectrum("poly", rank, alpha=alpha)
+    A32 = gen.low_rank_matrix(m, n, sigma, 1e-3 / math.sqrt(n), seed=m + 5 * n).astype(np.float32)
+    G = gen.gaussian_matrix(n, k + p, seed=m * n + 1)
+    qa = quant.rsvd_quantized(A32, G, q, sk, pj)
+    plain = orc.rsvd(A32.astype(np.float64), G, q)
+    U, S, V, info = run_factor(A32, k, p, q, "f32", omega=G, sketch_dtype=sk, proj_dtype=pj)
+    assert info.status == 0
+    assert max_rel_sigma(S, qa.D, k) <= 1e-3
+    print(f"fp8 format error vs plain oracle: max rel sigma {max_rel_sigma(S, plain.D, k):.2e}")
+    assert max_rel_sigma(S, plain.D, k) <= 0.1
+
+
 # ---------------------------------------------------------------- certificate and fallback
 
 def _cert_case(seed=95, m=700, n=500, tau=10.0):
