@@ -62,8 +62,23 @@ def orthonormal_factor(rows: int, cols: int, seed: int, stream: int) -> np.ndarr
     return q * s
 
 
+def orthonormal_factor_device(rows: int, cols: int, seed: int, stream: int, device: str):
+    """Orthonormal rows x cols factor drawn and orthonormalised on a torch
+    device (float32 Gaussian from a seeded device generator, Householder QR,
+    diag(R) > 0): the recipe of ``orthonormal_factor`` for shapes too large
+    for a host QR (not bit-identical to it)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 1_000_003 + stream)
+    G = torch.randn(rows, cols, generator=g, device=device, dtype=torch.float32)
+    Q, R = torch.linalg.qr(G, mode="reduced")
+    d = torch.sign(torch.diagonal(R))
+    d[d == 0] = 1.0
+    return Q * d
+
+
 def low_rank_matrix(m: int, n: int, sigma: np.ndarray, noise_std: float, seed: int,
-                    dtype=np.float64, device: Optional[str] = None):
+                    dtype=np.float64, device: Optional[str] = None, device_factors: bool = False):
     """A = U diag(sigma) V^T + noise.
 
     With ``device`` None the matrix is formed in float64 with numpy and
@@ -73,6 +88,18 @@ def low_rank_matrix(m: int, n: int, sigma: np.ndarray, noise_std: float, seed: i
     float32 and a torch tensor is returned (large workloads).
     """
     r = len(sigma)
+    if device is not None and device_factors:
+        import torch
+        tu = orthonormal_factor_device(m, r, seed, _STREAM_U, device)
+        tu *= torch.from_numpy(np.asarray(sigma, np.float32)).to(device)
+        tv = orthonormal_factor_device(n, r, seed, _STREAM_V, device)
+        a = tu @ tv.T
+        del tu, tv
+        if noise_std > 0:
+            g = torch.Generator(device=device)
+            g.manual_seed(int(seed) * 7919 + _STREAM_NOISE)
+            a.add_(torch.randn(a.shape, generator=g, device=device, dtype=torch.float32), alpha=float(noise_std))
+        return a
     u = orthonormal_factor(m, r, seed, _STREAM_U)
     v = orthonormal_factor(n, r, seed, _STREAM_V)
     if device is None:
@@ -206,8 +233,12 @@ class WorkloadConfig:
                                    noise_std=self.noise_std if noise_std is None else noise_std)
 
     def matrix(self, seed: int = 0, device: Optional[str] = None):
+        """The workload's matrix; on a device, shapes beyond 2^15 rows draw
+        their factors on the device (``orthonormal_factor_device``)."""
         dt = np.float64 if self.dtype == "f64" else np.float32
-        return low_rank_matrix(self.m, self.n, self.sigma(), self.noise_std, seed, dt, device)
+        big = max(self.m, self.n) > 32768
+        return low_rank_matrix(self.m, self.n, self.sigma(), self.noise_std, seed, dt, device,
+                               device_factors=big and device is not None)
 
 
 CONFIGS = {
