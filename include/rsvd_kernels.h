@@ -100,12 +100,22 @@ rsvd_status rsvd_k_convert_bf16(int64_t m, int64_t n, const float* d_A, int64_t 
 /*
  * d_out (panel, ldo >= rows, FP32) = A16 X for A16 rows x K bf16 as written by
  * rsvd_k_convert_bf16 (lda a multiple of 128, zero past K) and X a K x ncols
- * FP32 panel (ldx >= K, a multiple of 4) rounded to bf16 on load; bf16 MFMA
- * with FP32 accumulation.  1 <= ncols <= 1024.
+ * FP32 panel (X[c*ldx + k], ldx >= K) rounded to bf16 (nearest even) by a
+ * conversion pass into d_scratch (device, 256-byte aligned,
+ * rsvd_k_lp_scratch_bytes(RSVD_BF16, K, ncols) bytes); bf16 MFMA with FP32
+ * accumulation.  1 <= ncols <= 1024.
  * Errors: RSVD_E_ARG, RSVD_E_HIP.
  */
 rsvd_status rsvd_k_product_bf16(int64_t rows, int64_t K, const uint16_t* d_A16, int64_t lda, const float* d_X,
-                                int64_t ldx, int32_t ncols, float* d_out, int64_t ldo, void* stream);
+                                int64_t ldx, int32_t ncols, float* d_out, int64_t ldo, void* d_scratch,
+                                void* stream);
+
+/*
+ * Bytes of the thin-operand scratch of rsvd_k_product_bf16 (dtype RSVD_BF16)
+ * and rsvd_k_product_fp8 (RSVD_FP8_E4M3) for K x ncols.
+ * Errors: RSVD_E_ARG.
+ */
+rsvd_status rsvd_k_lp_scratch_bytes(int32_t dtype, int64_t K, int32_t ncols, size_t* h_bytes);
 
 /*
  * Input preparation for the FP8 products (OCP E4M3: bias 7, 3 mantissa bits,
@@ -126,15 +136,17 @@ rsvd_status rsvd_k_convert_fp8(int64_t m, int64_t n, const float* d_A, int64_t l
  * d_out (panel, ldo >= rows, FP32) = A X for A (rows x K) given as E4M3 codes
  * d_A8 (lda a multiple of 128, zero past K) with the scale of row block rb
  * (128 rows) and contraction block kb (128) at d_scale[rb * s_row + kb * s_k],
- * and X a K x ncols FP32 panel (ldx >= K, a multiple of 4, 16-byte aligned)
- * quantised on load to E4M3 with one power-of-two scale per 128-row segment
- * of each column.  FP8 MFMA with FP32 accumulation; each 128-wide block's
- * partial product is scaled and added.  1 <= ncols <= 1024.
+ * and X a K x ncols FP32 panel (X[c*ldx + k], ldx >= K) quantised by a
+ * conversion pass into d_scratch (device, 256-byte aligned,
+ * rsvd_k_lp_scratch_bytes(RSVD_FP8_E4M3, K, ncols) bytes) to E4M3 with one
+ * power-of-two scale per 128-row segment of each column.  FP8 MFMA with FP32
+ * accumulation; each 128-wide block's partial product is scaled and added.
+ * 1 <= ncols <= 1024.
  * Errors: RSVD_E_ARG, RSVD_E_HIP.
  */
 rsvd_status rsvd_k_product_fp8(int64_t rows, int64_t K, const uint8_t* d_A8, int64_t lda, const float* d_scale,
                                int64_t s_row, int64_t s_k, const float* d_X, int64_t ldx, int32_t ncols,
-                               float* d_out, int64_t ldo, void* stream);
+                               float* d_out, int64_t ldo, void* d_scratch, void* stream);
 
 #ifdef __cplusplus
 }

@@ -106,11 +106,12 @@ SIGNATURES = [
     ("rsvd_k_convert_bf16", ctypes.c_int, [_i64, _i64, _c_void_p, _i64, _c_void_p, _i64, _c_void_p, _i64, _c_void_p,
                                            _c_void_p]),
     ("rsvd_k_product_bf16", ctypes.c_int, [_i64, _i64, _c_void_p, _i64, _c_void_p, _i64, ctypes.c_int32, _c_void_p,
-                                           _i64, _c_void_p]),
+                                           _i64, _c_void_p, _c_void_p]),
+    ("rsvd_k_lp_scratch_bytes", ctypes.c_int, [ctypes.c_int32, _i64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     ("rsvd_k_convert_fp8", ctypes.c_int, [_i64, _i64, _c_void_p, _i64, _c_void_p, _i64, _c_void_p, _i64, _c_void_p,
                                           _c_void_p, _c_void_p]),
     ("rsvd_k_product_fp8", ctypes.c_int, [_i64, _i64, _c_void_p, _i64, _c_void_p, _i64, _i64, _c_void_p, _i64,
-                                          ctypes.c_int32, _c_void_p, _i64, _c_void_p]),
+                                          ctypes.c_int32, _c_void_p, _i64, _c_void_p, _c_void_p]),
 ]
 
 RSVD_F32_ACC64 = 10

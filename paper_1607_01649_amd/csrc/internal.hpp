@@ -53,10 +53,14 @@ hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, doub
 // and the FP8 MFMA product with an FP32 panel quantised per 128-row segment of each column.
 hipError_t launch_to_fp8(const float* A, int64_t lda, int64_t m, int64_t n, uint8_t* A8, int64_t ld8, uint8_t* A8T,
                          int64_t ldT, float* scale, int* flag, hipStream_t s);
-// scale of (row block rb, contraction block kb) at sA[rb * s_row + kb * s_k]
-hipError_t launch_nn_fp8(const uint8_t* A, int64_t lda, const float* sA, int64_t s_row, int64_t s_k, int64_t rows,
-                         int64_t K, const float* X, int64_t ldx, int ncols, float* out, int64_t ldo,
-                         int64_t part_stride, int splits, hipStream_t s);
+// lpgemm.hip -- products of a low-precision copy of A (kind 0: bf16, 1: E4M3 with tile scales, scale of row
+// block rb and contraction block kb at sA[rb * s_row + kb * s_k]) with an FP32 panel converted once into
+// `scratch` (lp_scratch_bytes); output as launch_nn (split-K partials).
+size_t lp_scratch_bytes(int kind, int64_t K, int ncols);
+int lp_splits_used(int64_t K, int splits);
+hipError_t launch_nn_lp(int kind, const void* A, int64_t lda, const float* sA, int64_t s_row, int64_t s_k,
+                        int64_t rows, int64_t K, const float* X, int64_t ldx, int ncols, void* scratch, float* out,
+                        int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
 
 // mlp.hip -- the selector network (16 -> 64 -> 64 -> 40, FP32) and its training steps.
 int mlp_param_count();
@@ -75,12 +79,10 @@ hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_swe
                          TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s);
 
 // lowp.hip -- bf16 copies of A (row-major and transposed, RNE, zero-padded to
-// multiples of 128 columns) and the bf16 MFMA product with an FP32 panel.
+// multiples of 128 columns).
 hipError_t launch_to_bf16(const float* A, int64_t lda, int64_t m, int64_t n, uint16_t* A16, int64_t ld16,
                           uint16_t* A16T, int64_t ldT, int* flag, hipStream_t s);
-hipError_t launch_nn_bf16(const uint16_t* A, int64_t lda, int64_t rows, int64_t K, const float* X, int64_t ldx,
-                          int ncols, float* out, int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
-int lp_splits_used(int64_t K, int splits);
+
 
 // batched.hip
 int batched_scratch_doubles_per_wg();

@@ -88,12 +88,20 @@ rsvd_status rsvd_k_convert_bf16(int64_t m, int64_t n, const float* A, int64_t ld
   return RSVD_OK;
 }
 
-rsvd_status rsvd_k_product_bf16(int64_t rows, int64_t K, const uint16_t* A16, int64_t lda, const float* X, int64_t ldx,
-                                int32_t ncols, float* out, int64_t ldo, void* stream) {
-  if (!A16 || !X || !out || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K || lda % 128 || ldx < K ||
-      ldx % 4 || ldo < rows)
+rsvd_status rsvd_k_lp_scratch_bytes(int32_t dtype, int64_t K, int32_t ncols, size_t* h_bytes) {
+  if (!h_bytes || K < 1 || ncols < 1 || ncols > 1024 || (dtype != RSVD_BF16 && dtype != RSVD_FP8_E4M3))
     return RSVD_E_ARG;
-  K_TRY(launch_nn_bf16(A16, lda, rows, K, X, ldx, ncols, out, ldo, 0, 1, reinterpret_cast<hipStream_t>(stream)));
+  *h_bytes = lp_scratch_bytes(dtype == RSVD_BF16 ? 0 : 1, K, ncols);
+  return RSVD_OK;
+}
+
+rsvd_status rsvd_k_product_bf16(int64_t rows, int64_t K, const uint16_t* A16, int64_t lda, const float* X, int64_t ldx,
+                                int32_t ncols, float* out, int64_t ldo, void* scratch, void* stream) {
+  if (!A16 || !X || !out || !scratch || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K || lda % 128 ||
+      ldx < K || ldo < rows || (reinterpret_cast<uintptr_t>(scratch) & 255))
+    return RSVD_E_ARG;
+  K_TRY(launch_nn_lp(0, A16, lda, nullptr, 0, 0, rows, K, X, ldx, ncols, scratch, out, ldo, 0, 1,
+                     reinterpret_cast<hipStream_t>(stream)));
   return RSVD_OK;
 }
 
@@ -108,12 +116,12 @@ rsvd_status rsvd_k_convert_fp8(int64_t m, int64_t n, const float* A, int64_t lda
 
 rsvd_status rsvd_k_product_fp8(int64_t rows, int64_t K, const uint8_t* A8, int64_t lda, const float* scale,
                                int64_t s_row, int64_t s_k, const float* X, int64_t ldx, int32_t ncols, float* out,
-                               int64_t ldo, void* stream) {
-  if (!A8 || !scale || !X || !out || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K || lda % 128 ||
-      ldx < K || ldx % 4 || ldo < rows || s_row < 0 || s_k < 0)
+                               int64_t ldo, void* scratch, void* stream) {
+  if (!A8 || !scale || !X || !out || !scratch || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K ||
+      lda % 128 || ldx < K || ldo < rows || s_row < 0 || s_k < 0 || (reinterpret_cast<uintptr_t>(scratch) & 255))
     return RSVD_E_ARG;
-  K_TRY(launch_nn_fp8(A8, lda, scale, s_row, s_k, rows, K, X, ldx, ncols, out, ldo, 0, 1,
-                      reinterpret_cast<hipStream_t>(stream)));
+  K_TRY(launch_nn_lp(1, A8, lda, scale, s_row, s_k, rows, K, X, ldx, ncols, scratch, out, ldo, 0, 1,
+                     reinterpret_cast<hipStream_t>(stream)));
   return RSVD_OK;
 }
 

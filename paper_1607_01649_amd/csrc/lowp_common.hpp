@@ -1,0 +1,45 @@
+// Device helpers of the low-precision operand formats (bfloat16 and OCP FP8
+// E4M3 with power-of-two block scales), shared by the conversion and product
+// kernels.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace rsvd {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// bfloat16 of x, round to nearest even; NaN stays a quiet NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+// E4M3 code of x, round to nearest even, saturating; NaN -> 0x7F (with sign).
+__device__ __forceinline__ uint32_t f32_to_e4m3(float x) {
+  const uint32_t u = __float_as_uint(x);
+  const uint32_t sgn = (u >> 24) & 0x80u;
+  const uint32_t au = u & 0x7fffffffu;
+  if (au > 0x7f800000u) return sgn | 0x7Fu;
+  const float a = __uint_as_float(au);
+  if (a >= 448.0f) return sgn | 0x7Eu;
+  if (a < 0.015625f) return sgn | (uint32_t)rintf(a * 512.0f);   // multiples of 2^-9 (rint: ties to even)
+  const uint32_t r = au + 0x7FFFFu + ((au >> 20) & 1u);           // keep 3 mantissa bits, ties to even
+  const uint32_t e = ((r >> 23) & 0xFFu) - 127u + 7u;
+  return sgn | (e << 3) | ((r >> 20) & 7u);
+}
+
+// Least e with amax <= 448 2^e (0 for amax == 0): amax = f 2^E, f in [0.5, 1), 448 = 0.875 2^9.
+__device__ __forceinline__ int fp8_scale_exp(float amax) {
+  if (!(amax > 0.0f)) return 0;
+  int E;
+  const float f = frexpf(amax, &E);
+  return f <= 0.875f ? E - 9 : E - 8;
+}
+
+}  // namespace rsvd

@@ -54,7 +54,7 @@ struct Layout {
   size_t es;   // element size of panels (8 for F64, 4 otherwise)
   int s_nn, s_tn, s_gm, s_gn, s_nn16, s_tn16;
   int64_t ld16, ldT;   // leading dimensions of the bf16 copies of A and A^T
-  size_t a16, a16t, a8, a8t, s8, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
+  size_t a16, a16t, a8, a8t, s8, xq, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
       rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, sel, total;
 };
 
@@ -134,6 +134,8 @@ Layout make_layout(const rsvd_desc* d) {
   L.a8 = take(b8 ? (size_t)d->m * L.ld16 : 256);
   L.a8t = take(b8 ? (size_t)d->n * L.ldT : 256);
   L.s8 = take(b8 ? (size_t)(L.ld16 / 128) * (L.ldT / 128) * sizeof(float) : 256);
+  // converted thin operand of a low-precision product (widest panel, longest contraction)
+  L.xq = take((b16 || b8) ? lp_scratch_bytes(b16 ? 0 : 1, std::max(d->m, d->n), std::max({L.W, L.LPmax, 16})) : 256);
   L.omega = take(Wd * L.ldn * L.es);
   L.gc = take(R * L.ldn * L.es);
   L.Y = take(Wd * L.ldm * L.es);
@@ -301,14 +303,14 @@ template <typename T> struct Path {
     if (dt == RSVD_BF16) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_nn16;
-        HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16), L.ld16, m, n, X, L.ldn, nc, part, L.ldm, (int64_t)LPc * L.ldm,
-                               S, st));
+        HIP_TRY(launch_nn_lp(0, P.at<uint16_t>(L.a16), L.ld16, nullptr, 0, 0, m, n, X, L.ldn, nc, P.at<char>(L.xq),
+                             part, L.ldm, (int64_t)LPc * L.ldm, S, st));
       }
     } else if (dt == RSVD_FP8_E4M3) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_nn16;
-        HIP_TRY(launch_nn_fp8(P.at<uint8_t>(L.a8), L.ld16, P.at<float>(L.s8), L.ld16 / 128, 1, m, n, X, L.ldn, nc,
-                              part, L.ldm, (int64_t)LPc * L.ldm, S, st));
+        HIP_TRY(launch_nn_lp(1, P.at<uint8_t>(L.a8), L.ld16, P.at<float>(L.s8), L.ld16 / 128, 1, m, n, X, L.ldn, nc,
+                             P.at<char>(L.xq), part, L.ldm, (int64_t)LPc * L.ldm, S, st));
       }
     } else {
       HIP_TRY((launch_nn<T, T, T, T>(A, lda, m, n, X, L.ldn, nc, part, L.ldm, (int64_t)LPc * L.ldm, S, st)));
@@ -328,14 +330,14 @@ template <typename T> struct Path {
     if (dt == RSVD_BF16) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_tn16;
-        HIP_TRY(launch_nn_bf16(P.at<uint16_t>(L.a16t), L.ldT, n, m, Qp, L.ldm, nc, part, L.ldn, (int64_t)LPc * L.ldn,
-                               S, st));
+        HIP_TRY(launch_nn_lp(0, P.at<uint16_t>(L.a16t), L.ldT, nullptr, 0, 0, n, m, Qp, L.ldm, nc, P.at<char>(L.xq),
+                             part, L.ldn, (int64_t)LPc * L.ldn, S, st));
       }
     } else if (dt == RSVD_FP8_E4M3) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_tn16;
-        HIP_TRY(launch_nn_fp8(P.at<uint8_t>(L.a8t), L.ldT, P.at<float>(L.s8), 1, L.ld16 / 128, n, m, Qp, L.ldm, nc,
-                              part, L.ldn, (int64_t)LPc * L.ldn, S, st));
+        HIP_TRY(launch_nn_lp(1, P.at<uint8_t>(L.a8t), L.ldT, P.at<float>(L.s8), 1, L.ld16 / 128, n, m, Qp, L.ldm, nc,
+                             P.at<char>(L.xq), part, L.ldn, (int64_t)LPc * L.ldn, S, st));
       }
     } else {
       HIP_TRY(

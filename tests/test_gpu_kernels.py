@@ -233,7 +233,8 @@ def test_product_bf16_is_exact_on_integers(rows, K, ncols):
     dX = _t(Xp, torch.float32)
     ldo = rows + 3
     out = torch.full((ncols, ldo), -7.0, dtype=torch.float32, device=device())
-    assert _lib().rsvd_k_product_bf16(rows, K, _p(A16), lda, _p(dX), ldx, ncols, _p(out), ldo, None) == 0
+    assert _lib().rsvd_k_product_bf16(rows, K, _p(A16), lda, _p(dX), ldx, ncols, _p(out), ldo,
+                                      _p(_lp_scratch("bf16", K, ncols)), None) == 0
     got = out.cpu().numpy().astype(np.float64)
     assert np.array_equal(got[:, :rows], ref.T)
     assert np.all(got[:, rows:] == -7.0)
@@ -244,8 +245,20 @@ def test_product_bf16_is_exact_on_integers(rows, K, ncols):
     Pp[:, :rows] = P.T
     dP = _t(Pp, torch.float32)
     out2 = torch.zeros((9, K), dtype=torch.float32, device=device())
-    assert _lib().rsvd_k_product_bf16(K, rows, _p(A16T), ldT, _p(dP), ldp, 9, _p(out2), K, None) == 0
+    assert _lib().rsvd_k_product_bf16(K, rows, _p(A16T), ldT, _p(dP), ldp, 9, _p(out2), K,
+                                      _p(_lp_scratch("bf16", rows, 9)), None) == 0
     assert np.array_equal(out2.cpu().numpy().astype(np.float64), (A.astype(np.float64).T @ P).T)
+
+
+def _lp_scratch(dtype, K, ncols):
+    """Device scratch for the thin operand of a low-precision product."""
+    import torch
+    nbytes = ctypes.c_size_t(0)
+    code = {"bf16": 2, "fp8": 3}[dtype]
+    assert _lib().rsvd_k_lp_scratch_bytes(code, K, ncols, ctypes.byref(nbytes)) == 0
+    buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device())
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nbytes.value]
 
 
 def _fp8_convert(A, torch):
@@ -307,7 +320,7 @@ def test_product_fp8_is_exact_on_integers(rows, K, ncols):
     ldo = rows + 3
     out = torch.full((ncols, ldo), -7.0, dtype=torch.float32, device=device())
     assert _lib().rsvd_k_product_fp8(rows, K, _p(A8), lda, _p(sc), ntc, 1, _p(_t(Xp, torch.float32)), ldx, ncols,
-                                     _p(out), ldo, None) == 0
+                                     _p(out), ldo, _p(_lp_scratch("fp8", K, ncols)), None) == 0
     got = out.cpu().numpy().astype(np.float64)
     assert np.array_equal(got[:, :rows], (A.astype(np.float64) @ X.astype(np.float64)).T)
     assert np.all(got[:, rows:] == -7.0)
@@ -316,7 +329,7 @@ def test_product_fp8_is_exact_on_integers(rows, K, ncols):
     Pp[:, :rows] = P.T
     out2 = torch.zeros((9, K), dtype=torch.float32, device=device())
     assert _lib().rsvd_k_product_fp8(K, rows, _p(A8T), ldT, _p(sc), 1, ntc, _p(_t(Pp, torch.float32)), ldT, 9,
-                                     _p(out2), K, None) == 0
+                                     _p(out2), K, _p(_lp_scratch("fp8", rows, 9)), None) == 0
     assert np.array_equal(out2.cpu().numpy().astype(np.float64), (A.astype(np.float64).T @ P).T)
 
 
@@ -335,7 +348,7 @@ def test_product_fp8_matches_the_dequantised_operands():
     Xp[:, :K] = X.T
     out = torch.zeros((ncols, rows), dtype=torch.float32, device=device())
     assert _lib().rsvd_k_product_fp8(rows, K, _p(A8), lda, _p(sc), lda // 128, 1, _p(_t(Xp, torch.float32)), ldx,
-                                     ncols, _p(out), rows, None) == 0
+                                     ncols, _p(out), rows, _p(_lp_scratch("fp8", K, ncols)), None) == 0
     Aq = quant.fp8_blocks_matrix(A)[2]
     Xq = quant.fp8_round_thin(X)
     ref = Aq @ Xq
