@@ -87,11 +87,12 @@ def fp8_e4m3_round(x) -> np.ndarray:
 
 def fp8_scale_exponent(amax) -> np.ndarray:
     """Least e with amax <= 448 2^e (0 where amax == 0), for the binary32
-    value of amax.  With amax = f 2^E, f in [0.5, 1), and 448 = 0.875 2^9:
-    e = E - 9 when f <= 0.875, else E - 8 (exact, no logarithm)."""
+    value of amax, and at least -127 (the smallest E8M0 scale).  With
+    amax = f 2^E, f in [0.5, 1), and 448 = 0.875 2^9: e = E - 9 when
+    f <= 0.875, else E - 8 (exact, no logarithm)."""
     a = np.asarray(amax, dtype=np.float32).astype(np.float64)
     f, E = np.frexp(a)                   # a = f 2^E, f in [0.5, 1)
-    e = np.where(f <= 0.875, E - 9, E - 8)
+    e = np.maximum(np.where(f <= 0.875, E - 9, E - 8), -127)
     return np.where(a > 0, e, 0).astype(np.int64)
 
 

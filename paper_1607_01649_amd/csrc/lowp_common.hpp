@@ -35,11 +35,14 @@ __device__ __forceinline__ uint32_t f32_to_e4m3(float x) {
 }
 
 // Least e with amax <= 448 2^e (0 for amax == 0): amax = f 2^E, f in [0.5, 1), 448 = 0.875 2^9.
+// Exponents are kept in [-127, 127], the range of an E8M0 scale (the MFMA's block-scale operand); only blocks
+// whose largest magnitude is below 448 2^-127 reach the lower limit.
 __device__ __forceinline__ int fp8_scale_exp(float amax) {
   if (!(amax > 0.0f)) return 0;
   int E;
   const float f = frexpf(amax, &E);
-  return f <= 0.875f ? E - 9 : E - 8;
+  const int e = f <= 0.875f ? E - 9 : E - 8;
+  return e < -127 ? -127 : e;
 }
 
 }  // namespace rsvd

@@ -2,21 +2,31 @@
 // FP32 accumulation: out[split][c][r] = sum_{k in split} A(r, k) X(k, c).
 //
 //   bf16: v_mfma_f32_16x16x32_bf16, X rounded to bf16 (nearest even).
-//   fp8:  v_mfma_f32_16x16x32_fp8_fp8 (OCP E4M3 on gfx950); A carries one
-//         power-of-two scale per 128 x 128 tile, X one per 128-row segment of
-//         each column, so a 128-wide contraction block is one tile column
-//         and one segment: its partial product (four MFMAs into a fresh
-//         accumulator) is added with the product of the two scales.
+//   fp8:  v_mfma_scale_f32_16x16x128_f8f6f4 on OCP E4M3 operands with the
+//         block scales applied by the instruction: A carries one power-of-two
+//         scale per 128 x 128 tile, X one per 128-row segment of each column,
+//         so a 128-wide contraction chunk is one MFMA per 16 x 16 output tile
+//         with the tile's scale on the A operand and the segment scales on the
+//         B operand (both E8M0, exact for powers of two).
 //
-// The thin operand is converted once per product (panel_to_bf16 / _fp8) into
-// a padded copy with 128-row segments, so the product kernel only moves bytes.
-// A block of 256 threads owns 128 rows x 16 NB columns; a wave 32 rows (two
-// 16-row MFMA blocks).  Each 128-wide contraction chunk: a lane loads 32
-// contiguous values of each of its two rows (lane group g covers contraction
-// indices 32 g .. 32 g + 31, fed to MFMA t as 32 g + 8 t + e on both
-// operands), the X chunk is staged in LDS in fragment order.  The next
-// chunk's A values and X fragments are loaded while the current one is
-// multiplied (LDS double buffer, one barrier per chunk).
+// The thin operand is converted once per product into a copy laid out in MFMA
+// fragment order: for every 128-wide chunk and every 16 columns, the 1 KB
+// blocks that one wave reads with a single 16-byte-per-lane load (4 blocks of
+// 8 bf16 per lane, or 2 blocks of 16 E4M3 codes per lane).  Lane l of a block
+// holds column l % 16 and the contraction indices 32 (l / 16) + 8 t + e (bf16,
+// block t) or 32 (l / 16) + 16 h + e (fp8, block h); the A operand uses the
+// same indices (a lane loads 32 contiguous values of its row), which is all
+// the MFMA needs, whatever order it sums in.
+//
+// A block of 256 threads owns 256 rows x 16 NB columns, a wave 64 rows (four
+// 16-row MFMA blocks), so each X fragment read from LDS feeds four MFMAs.
+// Pipeline per chunk i: the loads of the X fragments and of the A values of
+// chunk i+1 are issued, chunk i is multiplied, the X fragments are stored
+// into the spare of two LDS buffers; one barrier per chunk, which leaves the
+// A loads in flight (no fence: LDS completion is all it waits for).  Every load is unconditional (padded
+// columns are zero, rows past the end are clamped and never stored, chunk
+// indices past the end are clamped), so the compiler never has to wait for a
+// load at a lane-masked join.
 //
 // Tile order: workgroups are dealt to the 8 XCDs round-robin by their linear
 // index, so index L runs on XCD L % 8.  The column groups of one row block are
@@ -29,166 +39,214 @@
 namespace rsvd {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int LKC = 128;
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+constexpr int LKC = 128;          // contraction chunk (one FP8 scale block)
+constexpr int LP_RB = 4;          // 16-row MFMA blocks per wave (a workgroup owns 64 LP_RB rows)
+constexpr int LP_PD = 1;          // chunks of A loaded ahead
+
+template <int KIND> struct LpFmt;
+template <> struct LpFmt<0> {     // bf16
+  static constexpr int EB = 2;    // bytes per element
+  static constexpr int NFI = 4;   // 1 KB fragment blocks per 16 columns per chunk
+  static constexpr int AW = 4;    // 16-byte A loads per lane per row block per chunk
+};
+template <> struct LpFmt<1> {     // E4M3
+  static constexpr int EB = 1;
+  static constexpr int NFI = 2;
+  static constexpr int AW = 2;
+};
+
+// Column tiles of 16 per workgroup.  FP8 takes an even count so that the fragment blocks of a chunk split evenly
+// over the four waves.
+static int lp_nb(int kind, int ncols) {
+  int nb = (ncols + 15) / 16;
+  if (kind == 0) return nb > 7 ? 7 : nb;
+  nb = nb > 8 ? 8 : nb;
+  return (nb + 1) & ~1;
+}
+
+// Columns of the converted panel: ncols rounded up to whole workgroups (non-decreasing in ncols).
+static int lp_padded_cols(int kind, int ncols) {
+  const int w = 16 * lp_nb(kind, ncols);
+  return (ncols + w - 1) / w * w;
+}
 
 // ------------------------------------------------------------------ thin-operand conversion
 
-// Xq[c*ldq + k] = bf16(X[c*ldx + k]) for k < K, 0 for K <= k < ldq.  One thread per 8 values.
-__global__ void panel_to_bf16_kernel(const float* __restrict__ X, int64_t ldx, int64_t K, int ncols,
-                                     uint16_t* __restrict__ Xq, int64_t ldq) {
+// One thread per (chunk c, column block j, column cli, lane group gg): the 32 values X(col, k), col = 16 j + cli,
+// k = 128 c + 32 gg + e, zero past K and past ncols.  bf16: four 16-byte pieces (e = 8 t ..) to block t.
+__global__ void panel_to_bf16_frag_kernel(const float* __restrict__ X, int64_t ldx, int64_t K, int ncols, int ncb,
+                                          int64_t nthreads, uint8_t* __restrict__ Xf) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t per = ldq / 8;
-  if (t >= per * ncols) return;
-  const int64_t c = t / per, k = 8 * (t - c * per);
-  uint16_t b[8];
+  if (t >= nthreads) return;
+  const int gg = (int)(t & 3), cli = (int)((t >> 2) & 15);
+  const int64_t rest = t >> 6, c = rest / ncb;
+  const int j = (int)(rest - c * ncb);
+  const int col = 16 * j + cli;
+  const int64_t kb = c * LKC + 32 * gg;
+  uint8_t* blk = Xf + (c * ncb + j) * (int64_t)(4 * 1024) + 16 * (cli + 16 * gg);
 #pragma unroll
-  for (int e = 0; e < 8; ++e) b[e] = (k + e < K) ? f32_to_bf16_rne(X[c * ldx + k + e]) : (uint16_t)0;
-  *reinterpret_cast<uint4*>(Xq + c * ldq + k) =
-      make_uint4(pack2(b[0], b[1]), pack2(b[2], b[3]), pack2(b[4], b[5]), pack2(b[6], b[7]));
+  for (int tt = 0; tt < 4; ++tt) {
+    uint16_t b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = kb + 8 * tt + e;
+      b[e] = (col < ncols && k < K) ? f32_to_bf16_rne(X[(int64_t)col * ldx + k]) : (uint16_t)0;
+    }
+    *reinterpret_cast<u32x4*>(blk + tt * 1024) =
+        u32x4{pack2(b[0], b[1]), pack2(b[2], b[3]), pack2(b[4], b[5]), pack2(b[6], b[7])};
+  }
 }
 
-// Xq[c*ldq + k] = E4M3(X / 2^e) with e per 128-row segment of column c (sX[c*(ldq/128) + seg] = 2^e).
-// 16 consecutive threads cover one segment (amax by shuffles).
-__global__ void panel_to_fp8_kernel(const float* __restrict__ X, int64_t ldx, int64_t K, int ncols,
-                                    uint8_t* __restrict__ Xq, int64_t ldq, float* __restrict__ sX) {
+// As above for E4M3: the four threads of a 128-row segment share its scale (amax by shuffles); two 16-byte
+// pieces (e = 16 h ..) to block h; sXf[(c * ncb + j) * 16 + cli] = 2^e.
+__global__ void panel_to_fp8_frag_kernel(const float* __restrict__ X, int64_t ldx, int64_t K, int ncols, int ncb,
+                                         int64_t nthreads, uint8_t* __restrict__ Xf, float* __restrict__ sXf) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t per = ldq / 8;
-  const bool ok = t < per * ncols;
-  const int64_t c = ok ? t / per : 0, k = ok ? 8 * (t - c * per) : 0;
-  float v[8];
+  const bool ok = t < nthreads;   // nthreads is a multiple of 64: whole waves agree
+  const int gg = (int)(t & 3), cli = (int)((t >> 2) & 15);
+  const int64_t rest = t >> 6, c = ok ? rest / ncb : 0;
+  const int j = ok ? (int)(rest - c * ncb) : 0;
+  const int col = 16 * j + cli;
+  const int64_t kb = c * LKC + 32 * gg;
+  float v[32];
   float mx = 0.f;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    v[e] = (ok && k + e < K) ? X[c * ldx + k + e] : 0.f;
+  for (int e = 0; e < 32; ++e) {
+    const int64_t k = kb + e;
+    v[e] = (ok && col < ncols && k < K) ? X[(int64_t)col * ldx + k] : 0.f;
     mx = fmaxf(mx, fabsf(v[e]));
   }
-#pragma unroll
-  for (int o = 8; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 16));
+  mx = fmaxf(mx, __shfl_xor(mx, 1, 4));
+  mx = fmaxf(mx, __shfl_xor(mx, 2, 4));
   if (!ok) return;
   const int ex = fp8_scale_exp(mx);
-  uint32_t w0 = 0, w1 = 0;
+  uint8_t* blk = Xf + (c * ncb + j) * (int64_t)(2 * 1024) + 16 * (cli + 16 * gg);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    w0 |= f32_to_e4m3(ldexpf(v[e], -ex)) << (8 * e);
-    w1 |= f32_to_e4m3(ldexpf(v[4 + e], -ex)) << (8 * e);
+  for (int h = 0; h < 2; ++h) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      w[q] = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[q] |= f32_to_e4m3(ldexpf(v[16 * h + 4 * q + e], -ex)) << (8 * e);
+    }
+    *reinterpret_cast<u32x4*>(blk + h * 1024) = u32x4{w[0], w[1], w[2], w[3]};
   }
-  *reinterpret_cast<uint2*>(Xq + c * ldq + k) = make_uint2(w0, w1);
-  if ((k & (LKC - 1)) == 0) sX[c * (ldq / LKC) + k / LKC] = ldexpf(1.0f, ex);
+  if (gg == 0) sXf[(c * ncb + j) * 16 + cli] = ldexpf(1.0f, ex);
 }
 
 // ------------------------------------------------------------------ product
 
-template <int KIND> struct LpFrag;   // 0: bf16, 1: fp8
-template <> struct LpFrag<0> {
-  typedef u32x4 X;                    // 8 bf16
-  static constexpr int EB = 2;        // bytes per element
-  static constexpr int AW = 4;        // 16-byte A loads per lane per row block per chunk
-};
-template <> struct LpFrag<1> {
-  typedef u32x2 X;                    // 8 E4M3 codes
-  static constexpr int EB = 1;
-  static constexpr int AW = 2;
-};
+// s_waitcnt with only the vector-memory count constrained (gfx9 encoding: vmcnt in bits 3:0 and 15:14).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
 
-template <int KIND, int NB>
+// Workgroup barrier for LDS hand-over only: LDS operations complete first, vector-memory loads may stay in
+// flight (the fence of __syncthreads would wait for them, which would end the prefetch at every chunk).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt((15) | (7 << 4) | (0 << 8) | (3 << 14));   // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+__device__ __forceinline__ i32x8 cat8(u32x4 a, u32x4 b) {
+  return i32x8{(int)a[0], (int)a[1], (int)a[2], (int)a[3], (int)b[0], (int)b[1], (int)b[2], (int)b[3]};
+}
+
+// E8M0 code of a power of two held as a float (its biased exponent; 2^-127 is the subnormal with field 0).
+__device__ __forceinline__ int e8m0_of(float s) { return (int)(__float_as_uint(s) >> 23); }
+
+template <int KIND, int NB, int LRB, int PD>
 __global__ __launch_bounds__(256) void lp_nn_kernel(const uint8_t* __restrict__ A, int64_t lda,
                                                     const float* __restrict__ sA, int64_t s_row, int64_t s_k,
-                                                    int64_t rows, int64_t K, const uint8_t* __restrict__ Xq,
-                                                    int64_t ldq, const float* __restrict__ sX, int ncols, int groups,
+                                                    int64_t rows, int64_t K, const uint8_t* __restrict__ Xf,
+                                                    const float* __restrict__ sXf, int ncb, int ncols, int groups,
                                                     int rblocks, float* __restrict__ out, int64_t ldo,
                                                     int64_t part_stride, int64_t kchunk) {
-  typedef LpFrag<KIND> F;
-  typedef typename F::X XF;
-  constexpr int EB = F::EB, AW = F::AW;
-  __shared__ XF xs[2][NB * 4 * 64];   // (buffer, cb, t, lane)
-  __shared__ float sxs[2][NB * 16];
+  typedef LpFmt<KIND> F;
+  constexpr int EB = F::EB, NFI = F::NFI, AW = F::AW;
+  constexpr int LROWS = 64 * LRB;                     // rows per workgroup (LRB 16-row blocks per wave)
+  constexpr int NF = NB * NFI;                        // fragment blocks per chunk
+  static_assert(NF % 4 == 0, "fragment blocks must split evenly over the waves");
+  constexpr int NXW = NF / 4;                         // fragment loads per wave per chunk
+  // Double buffer for X (and the fp8 scales of its columns).
+  __shared__ u32x4 xs0[NF][64], xs1[NF][64];
+  __shared__ float sx0[KIND == 1 ? 256 : 1], sx1[KIND == 1 ? 256 : 1];
   typedef Mma<float> M;
   const int slot = blockIdx.x >> 3, xcd = blockIdx.x & 7;
   const int rb = (slot / groups) * 8 + xcd;
   const int cgi = slot - (slot / groups) * groups;
-  if (rb >= rblocks) return;   // whole block: no barrier has been reached
+  if (rb >= rblocks) return;   // whole workgroup: no barrier has been reached
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
-  const int64_t rbase = (int64_t)rb * 128 + wave * 32;
-  const int cg0 = cgi * NB * 16;
+  const int64_t rbase = (int64_t)rb * LROWS + wave * (16 * LRB);
+  const int j0 = cgi * NB;
   const int split = blockIdx.y;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
-  const int64_t nseg = ldq / LKC;
+  const int64_t nck = (kend - kbeg + LKC - 1) / LKC;
+  auto kc = [&](int64_t i) { return kbeg + (i < nck ? i : nck - 1) * LKC; };
 
-  // staging assignment: slot u of this thread covers column cl(u), values 8 ch .. 8 ch + 7 of the chunk
-  auto load_x = [&](int64_t k0, XF (&xr)[NB], float (&sr)[NB]) {
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int it = threadIdx.x + 256 * u;
-      const int cl = it >> 4, ch = it & 15;
-      const int c = cg0 + cl;
-      if (c < ncols) {
-        xr[u] = *reinterpret_cast<const XF*>(Xq + ((int64_t)c * ldq + k0 + 8 * ch) * EB);
-        if constexpr (KIND == 1) sr[u] = sX[(int64_t)c * nseg + k0 / LKC];
-      } else {
-        xr[u] = XF{};
-        sr[u] = 0.f;
-      }
-    }
+  // X fragments (and fp8 scales) of the chunk at k0: wave w moves fragment blocks w, w + 4, ... (one linear
+  // 16-byte load per lane from the fragment-ordered copy, one linear 16-byte LDS store).
+  struct XStage {
+    u32x4 v[NXW];
+    float s;
   };
-  auto store_x = [&](int buf, const XF (&xr)[NB], const float (&sr)[NB]) {
+  // (Addresses are a workgroup-uniform base plus a 32-bit lane offset, which keeps them to one register each.)
+  const uint32_t xoff = 16u * (uint32_t)(wave * 64 + lane);
+  const uint32_t soff = 4u * (uint32_t)min(wave * 64 + lane, NB * 16 - 1);
+  auto load_x = [&](int64_t k0, XStage& xr) {
+    const int64_t c = k0 / LKC;
+    const uint8_t* base = Xf + (c * ncb + j0) * (int64_t)(NFI * 1024);
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int it = threadIdx.x + 256 * u;
-      const int cl = it >> 4, ch = it & 15;
-      const int cb = cl >> 4, cli = cl & 15, gg = ch >> 2, tt = ch & 3;
-      xs[buf][(cb * 4 + tt) * 64 + cli + 16 * gg] = xr[u];
-      if constexpr (KIND == 1)
-        if (ch == 0) sxs[buf][cl] = sr[u];
-    }
+    for (int f = 0; f < NXW; ++f) xr.v[f] = *reinterpret_cast<const u32x4*>(base + xoff + f * 4096u);
+    if constexpr (KIND == 1)
+      xr.s = *reinterpret_cast<const float*>(reinterpret_cast<const uint8_t*>(sXf + (c * ncb + j0) * 16) + soff);
+    else
+      xr.s = 0.f;
   };
-  auto load_a = [&](int64_t k0, u32x4 (&ar)[2][AW]) {
+  auto store_x = [&](const XStage& xr, u32x4 (&xd)[NF][64], float* sd) {
 #pragma unroll
-    for (int rblk = 0; rblk < 2; ++rblk) {
-      const int64_t r = rbase + 16 * rblk + li;
-      if (r < rows) {
-        const u32x4* p = reinterpret_cast<const u32x4*>(A + (r * lda + k0 + 32 * g) * EB);
+    for (int f = 0; f < NXW; ++f) xd[wave + 4 * f][lane] = xr.v[f];
+    if constexpr (KIND == 1) sd[wave * 64 + lane] = xr.s;   // entries past the group are never read
+  };
+  const int64_t row0 = (int64_t)rb * LROWS;
+  const uint8_t* Ablk = A + row0 * lda * EB;   // this workgroup's first row
+  uint32_t aoff[LRB];                         // < 256 rows x lda x EB: 32 bits suffice
 #pragma unroll
-        for (int w = 0; w < AW; ++w) ar[rblk][w] = p[w];
-      } else {
+  for (int rblk = 0; rblk < LRB; ++rblk) {
+    const int64_t r = min(rbase + 16 * rblk + li, rows - 1);   // rows past the end: a valid row, never stored
+    aoff[rblk] = (uint32_t)(((r - row0) * lda + 32 * g) * EB);
+  }
+  auto load_a = [&](int64_t k0, u32x4 (&ar)[LRB][AW]) {
+    const uint8_t* base = Ablk + k0 * EB;
 #pragma unroll
-        for (int w = 0; w < AW; ++w) ar[rblk][w] = u32x4{0u, 0u, 0u, 0u};
-      }
-    }
+    for (int rblk = 0; rblk < LRB; ++rblk)
+#pragma unroll
+      for (int w = 0; w < AW; ++w) ar[rblk][w] = *reinterpret_cast<const u32x4*>(base + aoff[rblk] + 16u * w);
   };
 
-  f32x4 acc[2][NB];
+  f32x4 acc[LRB][NB];
 #pragma unroll
-  for (int rblk = 0; rblk < 2; ++rblk)
+  for (int rblk = 0; rblk < LRB; ++rblk)
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) acc[rblk][cb] = M::zero();
 
-  XF xr[NB];
-  float sr[NB];
-  u32x4 ar[2][AW];
-  if (kbeg < kend) {
-    load_x(kbeg, xr, sr);
-    load_a(kbeg, ar);
-    store_x(0, xr, sr);
-  }
-  __syncthreads();
-  int cur = 0;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += LKC) {
-    const bool more = k0 + LKC < kend;
-    u32x4 an[2][AW];
-    if (more) {
-      load_x(k0 + LKC, xr, sr);
-      load_a(k0 + LKC, an);
-    }
+  auto compute = [&](const u32x4 (&xb)[NF][64], const float* sb_, const u32x4 (&ar)[LRB][AW], int64_t k0) {
     if constexpr (KIND == 0) {
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
         bf16x8 b[NB];
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) b[cb] = __builtin_bit_cast(bf16x8, xs[cur][(cb * 4 + tt) * 64 + lane]);
+        for (int cb = 0; cb < NB; ++cb) b[cb] = __builtin_bit_cast(bf16x8, xb[cb * 4 + tt][lane]);
 #pragma unroll
-        for (int rblk = 0; rblk < 2; ++rblk) {
+        for (int rblk = 0; rblk < LRB; ++rblk) {
           const bf16x8 av = __builtin_bit_cast(bf16x8, ar[rblk][tt]);
 #pragma unroll
           for (int cb = 0; cb < NB; ++cb)
@@ -196,53 +254,78 @@ __global__ __launch_bounds__(256) void lp_nn_kernel(const uint8_t* __restrict__ 
         }
       }
     } else {
-      f32x4 part[2][NB];
-#pragma unroll
-      for (int rblk = 0; rblk < 2; ++rblk)
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) part[rblk][cb] = M::zero();
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        long b[NB];
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) b[cb] = __builtin_bit_cast(long, xs[cur][(cb * 4 + tt) * 64 + lane]);
-#pragma unroll
-        for (int rblk = 0; rblk < 2; ++rblk) {
-          const u32x4 q = ar[rblk][tt >> 1];
-          const long av = (tt & 1) ? __builtin_bit_cast(long, u32x2{q[2], q[3]})
-                                   : __builtin_bit_cast(long, u32x2{q[0], q[1]});
-#pragma unroll
-          for (int cb = 0; cb < NB; ++cb)
-            part[rblk][cb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, b[cb], part[rblk][cb], 0, 0, 0);
-        }
-      }
-      const float sa = sA[(int64_t)rb * s_row + (k0 / LKC) * s_k];
+      // the wave's rows lie in one tile; a wave-uniform index makes this a scalar load
+      const int sidx = __builtin_amdgcn_readfirstlane((int)((rbase / 128) * s_row + (k0 / LKC) * s_k));
+      const int sa = e8m0_of(sA[sidx]);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
-        const float sc = sa * sxs[cur][cb * 16 + li];
+        const i32x8 bv = cat8(xb[2 * cb][lane], xb[2 * cb + 1][lane]);
+        const int sb = e8m0_of(sb_[cb * 16 + li]);
 #pragma unroll
-        for (int rblk = 0; rblk < 2; ++rblk)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[rblk][cb][e] += sc * part[rblk][cb][e];
+        for (int rblk = 0; rblk < LRB; ++rblk) {
+          const i32x8 av = cat8(ar[rblk][0], ar[rblk][1]);
+          acc[rblk][cb] =
+              __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc[rblk][cb], 0, 0, 0, sa, 0, sb);
+        }
       }
     }
-    if (more) store_x(cur ^ 1, xr, sr);
-    __syncthreads();
-    cur ^= 1;
-    if (more) {
-#pragma unroll
-      for (int rblk = 0; rblk < 2; ++rblk)
-#pragma unroll
-        for (int w = 0; w < AW; ++w) ar[rblk][w] = an[rblk][w];
+  };
+
+  // Step i: issue the loads of X(i+2) (into a spare register stage) and of A(i+PD) (into a spare register set),
+  // multiply chunk i (LDS buffer i mod 2), store X(i+1), loaded a step earlier, into the other buffer and pass
+  // the barrier.  The store's wait leaves this step's loads in flight, and the barrier (no fence) leaves every
+  // global load in flight.  X comes from L2 or beyond; loading it two chunks ahead hides that latency as well.
+  // The loop is unrolled so that register sets and stages are static (no copies).
+  auto step = [&](int64_t i, const u32x4 (&acur)[LRB][AW], u32x4 (&afar)[LRB][AW], XStage& xfar,
+                  const XStage& xnext) {
+    const bool odd = (i & 1) != 0;
+    load_x(kc(i + 2), xfar);
+    load_a(kc(i + PD), afar);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(odd ? xs1 : xs0, odd ? sx1 : sx0, acur, kc(i));
+    __builtin_amdgcn_sched_barrier(0);
+    store_x(xnext, odd ? xs0 : xs1, odd ? sx0 : sx1);
+    lds_barrier();
+  };
+  u32x4 a0[LRB][AW], a1[LRB][AW];
+  XStage x0, x1;
+  load_x(kc(0), x0);
+  load_x(kc(1), x1);
+  load_a(kc(0), a0);
+  store_x(x0, xs0, sx0);
+  lds_barrier();
+  if constexpr (PD == 1) {
+    int64_t i = 0;
+    for (; i + 2 <= nck; i += 2) {
+      step(i, a0, a1, x0, x1);
+      step(i + 1, a1, a0, x1, x0);
     }
+    if (i < nck) step(i, a0, a1, x0, x1);
+  } else {
+    u32x4 a2[LRB][AW];
+    load_a(kc(1), a1);
+    int64_t i = 0;
+    for (; i + 6 <= nck; i += 6) {
+      step(i, a0, a2, x0, x1);
+      step(i + 1, a1, a0, x1, x0);
+      step(i + 2, a2, a1, x0, x1);
+      step(i + 3, a0, a2, x1, x0);
+      step(i + 4, a1, a0, x0, x1);
+      step(i + 5, a2, a1, x1, x0);
+    }
+    if (i < nck) step(i, a0, a2, x0, x1);
+    if (i + 1 < nck) step(i + 1, a1, a0, x1, x0);
+    if (i + 2 < nck) step(i + 2, a2, a1, x0, x1);
+    if (i + 3 < nck) step(i + 3, a0, a2, x1, x0);
+    if (i + 4 < nck) step(i + 4, a1, a0, x0, x1);
   }
 
   float* o = out + (int64_t)split * part_stride;
 #pragma unroll
-  for (int rblk = 0; rblk < 2; ++rblk)
+  for (int rblk = 0; rblk < LRB; ++rblk)
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
-      const int c = cg0 + cb * 16 + li;
+      const int c = 16 * (j0 + cb) + li;
       if (c >= ncols) continue;
       const int64_t r = rbase + rblk * 16 + 4 * g;
       float* p = o + (int64_t)c * ldo + r;
@@ -257,11 +340,13 @@ __global__ __launch_bounds__(256) void lp_nn_kernel(const uint8_t* __restrict__ 
     }
 }
 
+// Scratch: the fragment-ordered copy (nchunk x ncb blocks of NFI KB), then (fp8) its scales.
 size_t lp_scratch_bytes(int kind, int64_t K, int ncols) {
-  const size_t ldq = (size_t)((K + LKC - 1) / LKC) * LKC;
-  const size_t codes = (size_t)ncols * ldq * (kind == 0 ? 2 : 1);
-  const size_t scales = kind == 0 ? 0 : (size_t)ncols * (ldq / LKC) * sizeof(float);
-  return (codes + 255) / 256 * 256 + scales;
+  const size_t nchunk = (size_t)((K + LKC - 1) / LKC);
+  const size_t ncb = (size_t)lp_padded_cols(kind, ncols) / 16;
+  const size_t frag = nchunk * ncb * (kind == 0 ? 4096 : 2048);
+  const size_t scales = kind == 0 ? 0 : nchunk * ncb * 16 * sizeof(float);
+  return (frag + 255) / 256 * 256 + scales;
 }
 
 int lp_splits_used(int64_t K, int splits) {
@@ -281,45 +366,51 @@ hipError_t launch_nn_lp(int kind, const void* A, int64_t lda, const float* sA, i
   if (lda % LKC != 0 || lda < K || (reinterpret_cast<uintptr_t>(A) & 15) != 0 || !scratch ||
       (reinterpret_cast<uintptr_t>(scratch) & 255) != 0 || (kind == 1 && !sA))
     return hipErrorInvalidValue;
-  const int64_t ldq = (K + LKC - 1) / LKC * LKC;
-  uint8_t* Xq = reinterpret_cast<uint8_t*>(scratch);
-  float* sX = kind == 1 ? reinterpret_cast<float*>(Xq + ((size_t)ncols * ldq + 255) / 256 * 256) : nullptr;
-  const int64_t nthr = (ldq / 8) * ncols;
+  const int64_t nchunk = (K + LKC - 1) / LKC;
+  const int nb = lp_nb(kind, ncols);
+  const int cpad = lp_padded_cols(kind, ncols);
+  const int ncb = cpad / 16;
+  uint8_t* Xf = reinterpret_cast<uint8_t*>(scratch);
+  const size_t frag = (size_t)nchunk * ncb * (kind == 0 ? 4096 : 2048);
+  float* sXf = kind == 1 ? reinterpret_cast<float*>(Xf + (frag + 255) / 256 * 256) : nullptr;
+  const int64_t nthr = nchunk * ncb * 64;
+  const unsigned cgrid = (unsigned)((nthr + 255) / 256);
   if (kind == 0)
-    hipLaunchKernelGGL(panel_to_bf16_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, X, ldx, K, ncols,
-                       reinterpret_cast<uint16_t*>(Xq), ldq);
+    hipLaunchKernelGGL(panel_to_bf16_frag_kernel, dim3(cgrid), dim3(256), 0, s, X, ldx, K, ncols, ncb, nthr, Xf);
   else
-    hipLaunchKernelGGL(panel_to_fp8_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, X, ldx, K, ncols,
-                       Xq, ldq, sX);
+    hipLaunchKernelGGL(panel_to_fp8_frag_kernel, dim3(cgrid), dim3(256), 0, s, X, ldx, K, ncols, ncb, nthr, Xf,
+                       sXf);
   if (splits < 1) splits = 1;
   int64_t kchunk = ((K + splits - 1) / splits + LKC - 1) / LKC * LKC;
   if (kchunk < LKC) kchunk = LKC;
   const int used = (int)((K + kchunk - 1) / kchunk);
-  // column tiles per block: capped where the accumulators would drop occupancy to one wave per SIMD
-  const int nbmax = kind == 0 ? 7 : 5;
-  int nb = (ncols + 15) / 16;
-  nb = nb > nbmax ? nbmax : nb;
-  const int groups = (ncols + nb * 16 - 1) / (nb * 16);
-  const int rblocks = (int)((rows + 127) / 128);
+  const int groups = cpad / (nb * 16);
+  const int lrb = LP_RB;
+  const int rblocks = (int)((rows + 64 * lrb - 1) / (64 * lrb));
   const int slots = (rblocks + 7) / 8 * groups;
   dim3 grid((unsigned)(slots * 8), (unsigned)used, 1);
   const uint8_t* Ab = reinterpret_cast<const uint8_t*>(A);
 #define RSVD_LP_CASE(KV, NBV)                                                                                    \
-  hipLaunchKernelGGL((lp_nn_kernel<KV, NBV>), grid, dim3(256), 0, s, Ab, lda, sA, s_row, s_k, rows, K, Xq, ldq, sX, \
-                     ncols, groups, rblocks, out, ldo, part_stride, kchunk)
-#define RSVD_LP_SWITCH(KV)                                                                                       \
-  switch (nb) {                                                                                                  \
-    case 1: RSVD_LP_CASE(KV, 1); break;                                                                          \
-    case 2: RSVD_LP_CASE(KV, 2); break;                                                                          \
-    case 3: RSVD_LP_CASE(KV, 3); break;                                                                          \
-    case 4: RSVD_LP_CASE(KV, 4); break;                                                                          \
-    case 5: RSVD_LP_CASE(KV, 5); break;                                                                          \
-    case 6: RSVD_LP_CASE(KV, 6); break;                                                                          \
-    case 7: RSVD_LP_CASE(KV, 7); break;                                                                          \
-    default: RSVD_LP_CASE(KV, 8); break;                                                                         \
+  hipLaunchKernelGGL((lp_nn_kernel<KV, NBV, LP_RB, LP_PD>), grid, dim3(256), 0, s, Ab, lda, sA, s_row, s_k, rows, K, Xf, sXf, \
+                     ncb, ncols, groups, rblocks, out, ldo, part_stride, kchunk)
+  if (kind == 0) {
+    switch (nb) {
+      case 1: RSVD_LP_CASE(0, 1); break;
+      case 2: RSVD_LP_CASE(0, 2); break;
+      case 3: RSVD_LP_CASE(0, 3); break;
+      case 4: RSVD_LP_CASE(0, 4); break;
+      case 5: RSVD_LP_CASE(0, 5); break;
+      case 6: RSVD_LP_CASE(0, 6); break;
+      default: RSVD_LP_CASE(0, 7); break;
+    }
+  } else {
+    switch (nb) {
+      case 2: RSVD_LP_CASE(1, 2); break;
+      case 4: RSVD_LP_CASE(1, 4); break;
+      case 6: RSVD_LP_CASE(1, 6); break;
+      default: RSVD_LP_CASE(1, 8); break;
+    }
   }
-  if (kind == 0) { RSVD_LP_SWITCH(0) } else { RSVD_LP_SWITCH(1) }
-#undef RSVD_LP_SWITCH
 #undef RSVD_LP_CASE
   return hipGetLastError();
 }

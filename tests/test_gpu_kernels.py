@@ -283,6 +283,7 @@ def test_convert_fp8_is_bit_exact():
     m, n = 300, 517
     A = (rng.standard_normal((m, n)) * np.exp(rng.uniform(-8, 8, (m, 1)))).astype(np.float32)
     A[:128, :128] *= np.float32(1e-30)           # a tile far below the others
+    A[128:256, 128:256] *= np.float32(1e-40)     # a tile (mostly subnormal) at the lower limit of the E8M0 scale
     A[200, :8] = np.array([1.0, 1.0625, 1.1875, 3.0, 2 ** -10, -2 ** -9, 0.0, -0.0], dtype=np.float32)
     A8, A8T, sc, flag, ld8, ldT = _fp8_convert(A, torch)
     codes, ex, _ = quant.fp8_blocks_matrix(A)

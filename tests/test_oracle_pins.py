@@ -420,6 +420,15 @@ def test_fp8_block_scale_rule():
     e = quant.fp8_scale_exponent(a)
     assert np.all(a <= 448.0 * 2.0 ** e) and np.all(a > 448.0 * 2.0 ** (e - 1))
     assert quant.fp8_scale_exponent(0.0) == 0
+    # E8M0 range: the least exponent is -127 (only below 448 2^-127 does the limit bite)
+    assert quant.fp8_scale_exponent(448.0 * 2.0 ** -127) == -127
+    assert quant.fp8_scale_exponent(449.0 * 2.0 ** -127) == -126
+    assert quant.fp8_scale_exponent(2.0 ** -140) == -127
+    assert quant.fp8_scale_exponent(np.float32(1e-45)) == -127    # smallest subnormal
+    # a tiny block keeps scale 2^-127: its values are rounded on that grid (here all to zero or subnormal codes)
+    blk = np.full((4, 4), 2.0 ** -140)
+    codes, ex, deq = quant.fp8_blocks_matrix(blk, tile=4)
+    assert ex[0, 0] == -127 and np.all(codes == quant.fp8_e4m3_bits(blk * 2.0 ** 127))
     codes, ex, deq = quant.fp8_blocks_matrix(rng.standard_normal((300, 200)) * 10, tile=128)
     assert ex.shape == (3, 2)
     assert np.all(np.abs(quant.fp8_e4m3_decode(codes)) <= 448)
