@@ -10,9 +10,16 @@
 // lift kernel.
 //
 // Pairs are visited in round-robin ("circle method") order: each round holds
-// floor(l/2) disjoint pairs, processed in parallel by groups of 8 lanes (128
-// pairs at once in a 1024-thread block); l-1 (or l) rounds make a sweep.  Sweeps repeat until no pair needs a
-// rotation (|x_p . x_q| <= tol * ||x_p|| ||x_q||).  Results are sorted by
+// floor(l/2) disjoint pairs, processed in parallel by groups of 16 lanes (64
+// pairs at once in a 1024-thread block); l-1 (or l) rounds make a sweep.
+// Sweeps repeat until no pair needs a rotation (|x_p . x_q| <= tol * ||x_p||
+// ||x_q||).  The round is bound by instruction issue on one CU, so it is kept
+// lean: the squared norms are computed at the start of a sweep and then
+// updated exactly as the rotation changes them (||x_p||^2 - t g, ||x_q||^2 +
+// t g), so a pair only forms its dot product; the reductions use DPP lane
+// moves; the rotation comes from one square root, one division and one
+// reciprocal square root; a lane holds pairs of consecutive rows (16-byte LDS
+// accesses) and the rows past l are zero, so no access is guarded.  Results are sorted by
 // descending sigma and each u_hat column is signed so that its entry of
 // largest magnitude (lowest index on ties) is positive.
 #include "internal.hpp"
@@ -23,28 +30,40 @@ __device__ __forceinline__ int rr_player(int pos, int round, int le) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (le - 1);
 }
 
-// Lanes per column pair.  The kernel is VALU-bound on one CU, so packing
-// several pairs into each wave (fewer waves per round) is what pays.
-constexpr int kPairLanes = 8;
+// Lanes per column pair.
+constexpr int kPairLanes = 16;
 
-// Reduction over the lanes of one pair group.
+// Value of the lane chosen by a DPP pattern (applied to both halves of the double).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each aligned group of 16 lanes: lane ^ 1, lane ^ 2 (quad permutes), then the mirror images within 8
+// and within 16 lanes, each of which pairs a lane with one of the other half.
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = kPairLanes / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kPairLanes);
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
   return v;
 }
 
 // Norms, order, signs and outputs of the converged columns (column p of X at
 // xs[p*LP + i]): sigma descending, u_hat = x / sigma signed so that its entry
-// of largest magnitude (lowest index on ties) is positive, v_hat = u_hat / sigma.
+// of largest magnitude (lowest index on ties) is positive, v_hat = u_hat / sigma.  Column p of X is at
+// xs[p*LX + i]; the outputs have leading dimension LP.
 template <typename TU>
-__device__ void jacobi_epilogue(const double* xs, int l, int LP, double* nrm, int* rnk, double* __restrict__ sigma,
+__device__ void jacobi_epilogue(const double* xs, int LX, int l, int LP, double* nrm, int* rnk, double* __restrict__ sigma,
                                 double* __restrict__ uhat_d, TU* __restrict__ uhat_p, TU* __restrict__ vhat_p) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
   for (int p = w; p < l; p += nw) {
     double s = 0.0;
-    for (int i = lane; i < l; i += 64) s += xs[p * LP + i] * xs[p * LP + i];
+    for (int i = lane; i < l; i += 64) s += xs[p * LX + i] * xs[p * LX + i];
     s = wave_sum(s);
     if (lane == 0) nrm[p] = sqrt(s);
   }
@@ -70,7 +89,7 @@ __device__ void jacobi_epilogue(const double* xs, int l, int LP, double* nrm, in
     double best = -1.0;
     int bi = 0;
     for (int i = lane; i < l; i += 64) {
-      double a = fabs(xs[p * LP + i]);
+      double a = fabs(xs[p * LX + i]);
       if (a > best) { best = a; bi = i; }
     }
 #pragma unroll
@@ -79,13 +98,13 @@ __device__ void jacobi_epilogue(const double* xs, int l, int LP, double* nrm, in
       int oi = __shfl_xor(bi, o, 64);
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    double sg = xs[p * LP + bi] < 0.0 ? -1.0 : 1.0;
+    double sg = xs[p * LX + bi] < 0.0 ? -1.0 : 1.0;
     double sv = nrm[p];
     int j = rnk[p];
     double inv = sv > 0.0 ? sg / sv : 0.0;
     double inv2 = sv > 0.0 ? inv / sv : 0.0;
     for (int i = lane; i < LP; i += 64) {
-      double x = (i < l) ? xs[p * LP + i] : 0.0;
+      double x = (i < l) ? xs[p * LX + i] : 0.0;
       uhat_d[(int64_t)j * LP + i] = x * inv;
       if (uhat_p) uhat_p[(int64_t)j * LP + i] = static_cast<TU>(x * inv);
       if (vhat_p) vhat_p[(int64_t)j * LP + i] = static_cast<TU>(x * inv2);
@@ -94,67 +113,83 @@ __device__ void jacobi_epilogue(const double* xs, int l, int LP, double* nrm, in
   }
 }
 
-template <typename TU>
+template <typename TU, int NH>
 __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__ R, int l, int LP, double tol,
                                                        int max_sweeps, double* __restrict__ sigma,
                                                        double* __restrict__ uhat_d, TU* __restrict__ uhat_p,
                                                        TU* __restrict__ vhat_p, int* __restrict__ flags) {
-  extern __shared__ double smem[];
-  double* xs = smem;   // column p of X = row p of R, at xs[p*LP + i]
+  // A lane of a pair group holds rows 2 sub + 32 h and the next one, h < NH; LX = 32 NH >= LP.
+  constexpr int LX = 32 * NH;
+  extern __shared__ double2 smem2[];   // 16-byte aligned: accessed as double2
+  double* xs = reinterpret_cast<double*>(smem2);   // column p of X = row p of R, at xs[p*LX + i]; rows l .. LX-1 zero
   __shared__ double nrm[1024];
+  __shared__ double nrm2[1024];   // squared column norms, kept current through the sweep
   __shared__ int rnk[1024];
   __shared__ int rotated;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
   const int slot = tid / kPairLanes, sub = tid % kPairLanes, nslots = nt / kPairLanes;
 
-  for (int idx = tid; idx < l * l; idx += nt) {
-    int p = idx / l, i = idx - (idx / l) * l;
-    xs[p * LP + i] = R[(int64_t)p * LP + i];
+  for (int idx = tid; idx < l * LX; idx += nt) {
+    int p = idx / LX, i = idx - (idx / LX) * LX;
+    xs[p * LX + i] = (i < l) ? R[(int64_t)p * LP + i] : 0.0;
   }
   const int le = l + (l & 1);
+  const int m1 = le - 1;
   const int npairs = le / 2;
+  const double tol2 = tol * tol;
   int sweep = 0;
   bool converged = (l < 2);
   for (; sweep < max_sweeps && !converged; ++sweep) {
     __syncthreads();
     if (tid == 0) rotated = 0;
+    for (int p = w; p < l; p += nw) {
+      double ss = 0.0;
+      for (int i = lane; i < l; i += 64) ss += xs[p * LX + i] * xs[p * LX + i];
+      ss = wave_sum(ss);
+      if (lane == 0) nrm2[p] = ss;
+    }
     __syncthreads();
-    for (int round = 0; round < le - 1; ++round) {
+    for (int round = 0; round < m1; ++round) {
       for (int pi = slot; pi < npairs; pi += nslots) {
-        int p = rr_player(pi, round, le), q = rr_player(le - 1 - pi, round, le);
-        if (p >= l || q >= l) continue;   // uniform within the pair group
-        double* xp = xs + p * LP;
-        double* xq = xs + q * LP;
-        // the lane's slice of both columns, loaded at once (unrolled, predicated) and kept for the rotation
-        constexpr int NI = 128 / kPairLanes;
-        double av[NI], bv[NI];
-        double al = 0.0, be = 0.0, ga = 0.0;
+        // circle method: position 0 stays, the others advance by one each round
+        int a = pi - 1 + round;
+        a = a >= m1 ? a - m1 : a;
+        const int p = pi == 0 ? 0 : 1 + a;
+        int b = le - 2 - pi + round;
+        b = b >= m1 ? b - m1 : b;
+        const int q = 1 + b;
+        if (p >= l || q >= l) continue;   // the bye of an odd l (uniform within the pair group)
+        double2* xp = reinterpret_cast<double2*>(xs + p * LX) + sub;
+        double2* xq = reinterpret_cast<double2*>(xs + q * LX) + sub;
+        double2 av[NH], bv[NH];
+        double ga = 0.0;
 #pragma unroll
-        for (int u = 0; u < NI; ++u) {
-          const int i = sub + u * kPairLanes;
-          av[u] = (i < l) ? xp[i] : 0.0;
-          bv[u] = (i < l) ? xq[i] : 0.0;
+        for (int h = 0; h < NH; ++h) {
+          av[h] = xp[h * kPairLanes];
+          bv[h] = xq[h * kPairLanes];
         }
 #pragma unroll
-        for (int u = 0; u < NI; ++u) {
-          al += av[u] * av[u]; be += bv[u] * bv[u]; ga += av[u] * bv[u];
-        }
-        al = group_sum(al); be = group_sum(be); ga = group_sum(ga);
-        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-          double zeta = (be - al) / (2.0 * ga);
-          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double c = 1.0 / sqrt(1.0 + t * t);
-          double s = c * t;
+        for (int h = 0; h < NH; ++h) ga += av[h].x * bv[h].x + av[h].y * bv[h].y;
+        ga = group_sum(ga);
+        const double al = nrm2[p], be = nrm2[q];
+        if (al > 0.0 && be > 0.0 && ga * ga > tol2 * (al * be)) {
+          // t = tan of the angle zeroing the off-diagonal of [[al, ga], [ga, be]] (the smaller root)
+          const double d = be - al;
+          const double hyp = sqrt(d * d + 4.0 * ga * ga);
+          const double t = (2.0 * ga) / (d >= 0.0 ? d + hyp : d - hyp);
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double s = c * t;
 #pragma unroll
-          for (int u = 0; u < NI; ++u) {
-            const int i = sub + u * kPairLanes;
-            if (i < l) {
-              xp[i] = c * av[u] - s * bv[u];
-              xq[i] = s * av[u] + c * bv[u];
-            }
+          for (int h = 0; h < NH; ++h) {
+            xp[h * kPairLanes] = make_double2(c * av[h].x - s * bv[h].x, c * av[h].y - s * bv[h].y);
+            xq[h * kPairLanes] = make_double2(s * av[h].x + c * bv[h].x, s * av[h].y + c * bv[h].y);
           }
-          if (sub == 0) rotated = 1;
+          if (sub == 0) {
+            rotated = 1;
+            nrm2[p] = al - t * ga;
+            nrm2[q] = be + t * ga;
+          }
         }
       }
       __syncthreads();
@@ -167,7 +202,7 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
   }
   __syncthreads();
 
-  jacobi_epilogue<TU>(xs, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
+  jacobi_epilogue<TU>(xs, LX, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
 }
 
 template <typename TU>
@@ -176,7 +211,7 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* __res
                                                               TU* __restrict__ uhat_p, TU* __restrict__ vhat_p) {
   __shared__ double nrm[1024];
   __shared__ int rnk[1024];
-  jacobi_epilogue<TU>(xs, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
+  jacobi_epilogue<TU>(xs, LP, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
 }
 
 template <typename TU>
@@ -197,16 +232,27 @@ hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_swe
                          TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s) {
   if (l < 1 || l > 1024) return hipErrorInvalidValue;
   if (LP <= 128) {
+    // rows held in LDS padded to a multiple of 32 (two per lane, 16 lanes per pair)
+    const int nh = (LP + 31) / 32;
     static bool attr_set = false;
     if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<TU>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
-      if (e != hipSuccess) return e;
+      const void* fns[4] = {reinterpret_cast<const void*>(&jacobi_kernel<TU, 1>),
+                            reinterpret_cast<const void*>(&jacobi_kernel<TU, 2>),
+                            reinterpret_cast<const void*>(&jacobi_kernel<TU, 3>),
+                            reinterpret_cast<const void*>(&jacobi_kernel<TU, 4>)};
+      for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
+        if (e != hipSuccess) return e;
+      }
       attr_set = true;
     }
-    size_t sh = (size_t)LP * LP * sizeof(double);
-    hipLaunchKernelGGL((jacobi_kernel<TU>), dim3(1), dim3(1024), sh, s, R, l, LP, tol, max_sweeps, sigma,
-                       uhat_d, uhat_p, vhat_p, flags);
+    size_t sh = (size_t)LP * (32 * nh) * sizeof(double);
+    switch (nh) {
+      case 1: hipLaunchKernelGGL((jacobi_kernel<TU, 1>), dim3(1), dim3(1024), sh, s, R, l, LP, tol, max_sweeps, sigma, uhat_d, uhat_p, vhat_p, flags); break;
+      case 2: hipLaunchKernelGGL((jacobi_kernel<TU, 2>), dim3(1), dim3(1024), sh, s, R, l, LP, tol, max_sweeps, sigma, uhat_d, uhat_p, vhat_p, flags); break;
+      case 3: hipLaunchKernelGGL((jacobi_kernel<TU, 3>), dim3(1), dim3(1024), sh, s, R, l, LP, tol, max_sweeps, sigma, uhat_d, uhat_p, vhat_p, flags); break;
+      default: hipLaunchKernelGGL((jacobi_kernel<TU, 4>), dim3(1), dim3(1024), sh, s, R, l, LP, tol, max_sweeps, sigma, uhat_d, uhat_p, vhat_p, flags); break;
+    }
   } else {
     return launch_jacobi_blocked<TU>(R, l, LP, tol, max_sweeps, sigma, uhat_d, uhat_p, vhat_p, scratch, flags, s);
   }
