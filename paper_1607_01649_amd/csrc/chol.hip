@@ -28,13 +28,17 @@ namespace rsvd {
 constexpr int kCholThreads = 1024;
 
 // l <= 128: thread t owns the 4 x 4 register blocks U[4][4] and T[4][4] of
-// rows 4*(t/32)..+3 and columns 4*(t%32)..+3.  U starts as G's upper
-// triangle, T as the identity.  Step j, branch-free on the block:
+// rows a0..a0+3 and columns b0..b0+3.  A wave covers a 32 x 32 tile (wave w:
+// row band w / 4, column band w % 4), so that at step j whole waves can skip:
+// a wave whose rows are all <= j has nothing to do, a wave whose columns are
+// all > j only updates U and one whose columns are all <= j only T.  U starts
+// as G's upper triangle, T as the identity.  Step j:
 //     U(a, b) -= f_a U(j, b)   for a > j, b > j      (f_a = U(j, a) / d_j)
 //     T(a, b) -= f_a T(j, b)   for a > j (T(j, b) = 0 for b > j)
-// using the masked vectors f (zero for a <= j) and U(j, b) (zero for b <= j).
-// The owners of row j+1 publish U(j+1, :) and T(j+1, :) to LDS before the
-// step's barrier (double-buffered); threads whose rows are all <= j skip.
+// with masked vectors (f zero for a <= j, U(j, b) zero for b <= j).  The
+// owners of row j+1 publish U(j+1, :) and T(j+1, :) to LDS before the step's
+// barrier (double-buffered), and the owner of the diagonal entry decides the
+// pivot (drop test, 1/d, 1/sqrt(d)) once for everyone.
 template <typename TQ>
 __global__ __launch_bounds__(kCholThreads) void chol_reg_kernel(const double* __restrict__ g, int64_t ldg, int l,
                                                                  int LP, double tau_rel, TQ* __restrict__ rinv_p,
@@ -43,11 +47,14 @@ __global__ __launch_bounds__(kCholThreads) void chol_reg_kernel(const double* __
                                                                  int* __restrict__ flags) {
   __shared__ double urow[2][128];
   __shared__ double trow[2][128];
+  __shared__ double pinv[2];      // 1/d_j of the published row, 0 for a dropped pivot
   __shared__ double gdiag[128];
   __shared__ double rsd[128];     // 1/sqrt(d_j), 0 for a dropped column
   extern __shared__ double Ufull[];   // LP x LP, filled at the end when r_out is wanted
   const int tid = threadIdx.x;
-  const int a0 = 4 * (tid >> 5), b0 = 4 * (tid & 31);
+  const int wv = tid >> 6, ln = tid & 63;
+  const int a0 = 32 * (wv >> 2) + 4 * (ln >> 3), b0 = 32 * (wv & 3) + 4 * (ln & 7);
+  const int rlast = 32 * (wv >> 2) + 31, cfirst = 32 * (wv & 3), clast = cfirst + 31;
   double U[4][4], T[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -58,57 +65,68 @@ __global__ __launch_bounds__(kCholThreads) void chol_reg_kernel(const double* __
       T[i][k] = (a == b) ? 1.0 : 0.0;
       if (a == b && a < l) gdiag[a] = U[i][k];
     }
-  if (a0 == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { urow[0][b0 + k] = U[0][k]; trow[0][b0 + k] = T[0][k]; }
-  }
-  __syncthreads();
-
   int bad = 0, dropped = 0;
-  for (int j = 0; j < l; ++j) {
-    const double* uj = urow[j & 1];
-    const double* tj = trow[j & 1];
-    const double d = uj[j];
-    const double gd = gdiag[j];
+  // pivot decision for row r (r < l) from its current diagonal d, by the diagonal's owner
+  auto decide = [&](int r, double d, int buf) {
+    const double gd = gdiag[r];
     const bool nonfinite = !isfinite(d) || !isfinite(gd);
     const bool drop = nonfinite || !(d > tau_rel * gd) || !(d > 0.0);
     bad += nonfinite;
     dropped += (drop && !nonfinite);
-    if (!drop && a0 + 3 > j) {
-      const double invd = 1.0 / d;
-      double f[4], ub[4], tb[4];
+    pinv[buf] = drop ? 0.0 : 1.0 / d;
+    rsd[r] = drop ? 0.0 : 1.0 / sqrt(d);
+  };
+  __syncthreads();   // gdiag
+  if (a0 == 0) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) f[i] = (a0 + i > j) ? uj[a0 + i] * invd : 0.0;
+    for (int k = 0; k < 4; ++k) { urow[0][b0 + k] = U[0][k]; trow[0][b0 + k] = T[0][k]; }
+    if (b0 == 0) decide(0, U[0][0], 0);
+  }
+  __syncthreads();
+
+  for (int j = 0; j < l; ++j) {
+    const int buf = j & 1;
+    const double dinv = pinv[buf];
+    if (rlast > j && dinv != 0.0) {   // uniform over the wave
+      const double* uj = urow[buf];
+      const double* tj = trow[buf];
+      double f[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        ub[k] = (b0 + k > j) ? uj[b0 + k] : 0.0;
-        tb[k] = tj[b0 + k];
+      for (int i = 0; i < 4; ++i) f[i] = (a0 + i > j) ? uj[a0 + i] * dinv : 0.0;
+      if (clast > j) {
+        double ub[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ub[k] = (b0 + k > j) ? uj[b0 + k] : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) U[i][k] -= f[i] * ub[k];
       }
+      if (cfirst <= j) {
+        double tb[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int k = 0; k < 4; ++k) tb[k] = tj[b0 + k];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          U[i][k] -= f[i] * ub[k];
-          T[i][k] -= f[i] * tb[k];
-        }
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) T[i][k] -= f[i] * tb[k];
+      }
     }
-    if (tid == 0) rsd[j] = drop ? 0.0 : 1.0 / sqrt(d);
     // (static row index: a runtime index into U/T would move them to scratch)
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (a0 + i == j + 1 && j + 1 < l) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          urow[(j + 1) & 1][b0 + k] = U[i][k];
-          trow[(j + 1) & 1][b0 + k] = T[i][k];
+          urow[buf ^ 1][b0 + k] = U[i][k];
+          trow[buf ^ 1][b0 + k] = T[i][k];
+          if (b0 + k == j + 1) decide(j + 1, U[i][k], buf ^ 1);
         }
       }
     __syncthreads();
   }
-  if (tid == 0) {
-    if (bad) atomicAdd(&flags[0], bad);
-    if (dropped) atomicAdd(&flags[1], dropped);
-  }
+  if (bad) atomicAdd(&flags[0], bad);
+  if (dropped) atomicAdd(&flags[1], dropped);
   // R^-1 in panel layout: rinv_p[c*LP + k] = R^-T(c, k) = T(c, k) / sqrt(d_c); identity on padding.
   if (a0 < LP && b0 < LP) {
 #pragma unroll
