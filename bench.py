@@ -26,8 +26,83 @@ METRIC = "time-to-ε and TFLOP/s for rank-k RSVD; BF16/FP8+learned vs plain FP32
 MI355X_PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "fp8": 5000.0}   # dense MFMA TFLOP/s
 HBM_PEAK_GBS = 8000.0
 ELT_BYTES = {"f32": 4, "f64": 8, "bf16": 2, "fp8": 1}
+# HBM traffic of the dominant product kernel, per launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
+# plain copy kernel (see traffic_summary); used only while the kernel source is the one the counters were taken on
+TRAFFIC_FILES = {("bf16", "slowdecay_50000x20000"): "profiles/traffic_lp_nn_bf16_slowdecay_50000x20000.md"}
+TRAFFIC_SOURCE = "paper_1607_01649_amd/csrc/lpgemm.hip"
 # time-to-eps target per workload: eps = factor * sigma_{k+1} (spectral norm of the residual)
 EPS_FACTOR = {"slowdecay_50000x20000": 1.15, "expdecay_65536": 1.10, "plain_f64_2000": 1.15}
+
+
+def _sha256(path):
+    import hashlib
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_per_launch(sketch, workload):
+    """HBM bytes per launch of the product kernel from the committed counter summary, or None when there is none
+    or the kernel source changed since it was taken."""
+    rel = TRAFFIC_FILES.get((sketch, workload))
+    if not rel or not os.path.exists(os.path.join(ROOT, rel)):
+        return None
+    with open(os.path.join(ROOT, rel)) as f:
+        for line in f:
+            if line.startswith("traffic-json: "):
+                d = json.loads(line[len("traffic-json: "):])
+                if d.get("source_sha256") == _sha256(TRAFFIC_SOURCE):
+                    return d["bytes_per_launch"]
+    return None
+
+
+def traffic_summary(fetch_dir, write_dir, out_path, calib_bytes, kernel_prefix="rsvd::lp_nn_kernel"):
+    """Summarise two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) into out_path.  Each
+    counter is scaled by calib_bytes / counter of the first dispatch that moves a sizeable share of them:
+    --copy-calibration issues, before anything else, a fill (writes calib_bytes) and an elementwise copy (reads and
+    writes them)."""
+    import csv
+
+    def load(d, counter):
+        path = os.path.join(d, "run_counter_collection.csv")
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"]) * 1024.0
+        return vals
+
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        vals = load(d, counter)
+        first = sorted((disp, v) for (name, disp), v in vals.items() if v > calib_bytes / 16)
+        if not first:
+            raise SystemExit(f"no calibration dispatch among the {counter} dispatches")
+        scale = calib_bytes / first[0][1]
+        mine = [v for (name, _), v in vals.items() if name.startswith("void " + kernel_prefix) or
+                name.startswith(kernel_prefix)]
+        out[counter] = {"scale": scale, "launches": len(mine), "raw_bytes_per_launch": sum(mine) / len(mine),
+                        "bytes_per_launch": scale * sum(mine) / len(mine)}
+    tot = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
+    rec = {"kernel": kernel_prefix, "source_sha256": _sha256(TRAFFIC_SOURCE), "bytes_per_launch": tot,
+           "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"], "calibration_copy_bytes": calib_bytes}
+    lines = [f"# HBM traffic of `{kernel_prefix}` (bf16 products), 50000 x 20000 workload", "",
+             "Two rocprofv3 counter passes over the same bench command (repository root, MI355X), each counter",
+             "scaled by what it reads for a plain copy of a known size (an elementwise torch kernel, `--copy-calibration`):",
+             "", "    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'lp_nn|Functor' -d gpurun_out/pmc_fetch -o run "
+             f"--output-format csv -- python -u bench.py --paths bf16 --steps 1 --warmup 0 --no-cpu --copy-calibration {calib_bytes}",
+             "    rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'lp_nn|Functor' -d gpurun_out/pmc_write -o run "
+             f"--output-format csv -- python -u bench.py --paths bf16 --steps 1 --warmup 0 --no-cpu --copy-calibration {calib_bytes}",
+             f"    python bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write {calib_bytes}", "",
+             "| counter | copy scale | launches | bytes per launch (scaled) |", "|---|---|---|---|"]
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        lines.append(f"| {c} | {out[c]['scale']:.4f} | {out[c]['launches']} | {out[c]['bytes_per_launch'] / 1e9:.3f} GB |")
+    lines += ["", f"Total per launch: {tot / 1e9:.3f} GB (algorithmic: 2.031 GB; A in bf16 once, X and the result).",
+              "bench.py reports it as `roofline.traffic` while the kernel source hash matches.", "",
+              "traffic-json: " + json.dumps(rec)]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines[-6:]))
 
 
 def spectral_residual(A, U, S, V, iters=40, seed=0):
@@ -130,7 +205,8 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed):
                 "frac": achieved / HBM_PEAK_GBS, "achieved_tflops": flops_pass / avg / 1e12}
     roof.update({"algorithmic_bytes_per_launch": bytes_launch, "flops_per_launch": flops_pass,
                  "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge})
-    roof.update({"traffic": None, "kernel": names[0] if dom_nn else names[1], "avg_launch_ms": avg * 1e3,
+    roof.update({"traffic": traffic_per_launch(sketch, cfg.name), "kernel": names[0] if dom_nn else names[1],
+                 "avg_launch_ms": avg * 1e3,
                  "launches_per_step": (nn_n + tn_n) / steps,
                  "other_kernel": {"name": names[1] if dom_nn else names[0],
                                   "avg_launch_ms": (avg_tn if dom_nn else avg_nn) * 1e3,
@@ -219,7 +295,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--batched-wg", type=int, default=0, help="workgroups of the batched launch (0 = library default)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="bytes of one plain device copy issued first (scale of the traffic counters)")
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "CALIB_BYTES"),
+                    help="write the traffic summary of two rocprofv3 --pmc passes to profiles/ and exit")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        fd, wd, cb = args.summarize_traffic
+        traffic_summary(fd, wd, os.path.join(ROOT, TRAFFIC_FILES[("bf16", "slowdecay_50000x20000")]), int(cb))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -231,6 +315,13 @@ def main():
     from workloads import gen
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)   # an elementwise kernel that reads and writes calibration bytes once
+        torch.cuda.synchronize()
+        del src, dst
     cfg = gen.config(args.workload)
     A = cfg.matrix(seed=args.seed, device=str(dev))
     A = A.to(torch.float32) if cfg.dtype == "f32" else A
