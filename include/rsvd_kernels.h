@@ -36,6 +36,19 @@ rsvd_status rsvd_k_product_nn(int32_t precision, int64_t rows, int64_t K, const 
                               void* stream);
 
 /*
+ * d_G (nc x nc FP64, column-major, ldg >= nc) = Y^T Y for Y a K x nc panel
+ * (d_Y[c*ldy + i], precision RSVD_F32 or RSVD_F64, ldy >= K a multiple of 64,
+ * 16-byte aligned): the Gram matrix of CholeskyQR (Section 2.3 allows any
+ * unpivoted orthonormalisation; the library runs Cholesky on this FP64
+ * Gram).  FP32 entries and their products are exact in FP64; the sum is
+ * accumulated in FP64 on the FP64 MFMA.  Both triangles are written.
+ * 1 <= nc <= 1024.  Caller owns all buffers; no allocation.
+ * Errors: RSVD_E_ARG (sizes, alignment, precision), RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_gram(int32_t precision, int64_t K, int32_t nc, const void* d_Y, int64_t ldy, double* d_G,
+                        int64_t ldg, void* stream);
+
+/*
  * d_out = A^T P for A K x N row-major (lda >= N) and P a K x ncols panel
  * (ldp >= K): the power step Z = A^T Q and the projection B^T = A^T Q
  * (Figure 5).  out_rowmajor = 0: d_out is an N x ncols panel (ldo >= N);

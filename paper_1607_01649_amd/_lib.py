@@ -98,6 +98,8 @@ SIGNATURES = [
                                          ctypes.c_int32, _c_void_p, _i64, _c_void_p]),
     ("rsvd_k_product_tn", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, _c_void_p, _i64,
                                          ctypes.c_int32, _c_void_p, _i64, ctypes.c_int32, _c_void_p]),
+    ("rsvd_k_gram", ctypes.c_int, [ctypes.c_int32, _i64, ctypes.c_int32, _c_void_p, _i64, _c_void_p, _i64,
+                                   _c_void_p]),
     ("rsvd_k_cholesky", ctypes.c_int, [ctypes.c_int32, _c_void_p, _i64, ctypes.c_double, _c_void_p, _c_void_p,
                                        _c_void_p, _c_void_p, _c_void_p]),
     ("rsvd_k_small_svd", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,

@@ -55,6 +55,12 @@ hipError_t launch_to_fp8(const float* A, int64_t lda, int64_t m, int64_t n, uint
                          int64_t ldT, float* scale, int* flag, hipStream_t s);
 // lpgemm.hip -- products of a low-precision copy of A (kind 0: bf16, 1: E4M3 with tile scales, scale of row
 // block rb and contraction block kb at sA[rb * s_row + kb * s_k]) with an FP32 panel converted once into
+// FP64-accumulated Gram Y^T Y of an nc-column panel (FP32 or FP64), split-K partials as launch_nn (gram.hip);
+// gram_tile_pairs(nc) workgroups per contraction range.
+int gram_tile_pairs(int nc);
+template <typename TI>
+hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, int64_t ldo, int64_t part_stride,
+                       int splits, hipStream_t s);
 // `scratch` (lp_scratch_bytes); output as launch_nn (split-K partials).
 size_t lp_scratch_bytes(int kind, int64_t K, int ncols);
 int lp_splits_used(int64_t K, int splits);

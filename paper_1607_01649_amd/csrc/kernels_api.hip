@@ -33,6 +33,20 @@ rsvd_status rsvd_k_product_nn(int32_t prec, int64_t rows, int64_t K, const void*
   return RSVD_OK;
 }
 
+rsvd_status rsvd_k_gram(int32_t prec, int64_t K, int32_t nc, const void* Y, int64_t ldy, double* G, int64_t ldg,
+                        void* stream) {
+  if (!Y || !G || K < 1 || nc < 1 || nc > 1024 || ldy < K || (ldy % 64) != 0 || ldg < nc) return RSVD_E_ARG;
+  if ((reinterpret_cast<uintptr_t>(Y) & 15) != 0) return RSVD_E_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (prec == RSVD_F32)
+    K_TRY(launch_gram<float>((const float*)Y, ldy, K, nc, G, ldg, 0, 1, s));
+  else if (prec == RSVD_F64)
+    K_TRY(launch_gram<double>((const double*)Y, ldy, K, nc, G, ldg, 0, 1, s));
+  else
+    return RSVD_E_ARG;
+  return RSVD_OK;
+}
+
 rsvd_status rsvd_k_product_tn(int32_t prec, int64_t K, int64_t N, const void* A, int64_t lda, const void* P,
                               int64_t ldp, int32_t ncols, void* out, int64_t ldo, int32_t out_rowmajor,
                               void* stream) {

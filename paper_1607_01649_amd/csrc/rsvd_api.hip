@@ -65,6 +65,14 @@ int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
   return (int)std::min<int64_t>(s, 1024);
 }
 
+// Contraction ranges of the Gram (multiples of 64 rows) so that pairs x ranges <= 256 workgroups, as many as fit.
+int gram_splits(int pairs, int64_t K) {
+  const int64_t nchunk = (K + 63) / 64;
+  const int64_t target = std::max<int64_t>(1, 256 / std::max(pairs, 1));
+  const int64_t per = (nchunk + target - 1) / target;   // chunks per range
+  return (int)std::max<int64_t>(1, (nchunk + per - 1) / per);
+}
+
 bool validate(const rsvd_desc* d) {
   if (!d) return false;
   if (d->m < 1 || d->n < 1 || d->k < 1) return false;
@@ -112,9 +120,10 @@ Layout make_layout(const rsvd_desc* d) {
   const int64_t cg = (L.l + 127) / 128;
   L.s_nn = pick_splits(((d->m + 127) / 128) * cg, d->n, 2048, 512);
   L.s_tn = pick_splits(((d->n + 255) / 256) * cg, d->m, 2048, 512);
-  const int64_t gt = ((L.l + 127) / 128) * cg;
-  L.s_gm = pick_splits(gt, d->m, 512, 128);
-  L.s_gn = pick_splits(gt, d->n, 512, 128);
+  // Gram: one workgroup per CU (it needs the whole register file), so aim for at most 256 workgroups
+  const int gp = gram_tile_pairs(L.l);
+  L.s_gm = gram_splits(gp, d->m);
+  L.s_gn = gram_splits(gp, d->n);
   L.s_nn = nn_splits_used(d->n, L.s_nn);
   L.s_tn = nn_splits_used(d->m, L.s_tn);
   L.s_gm = nn_splits_used(d->m, L.s_gm);
@@ -270,7 +279,7 @@ template <typename T> struct Path {
   rsvd_status gram(const T* X, int64_t ldx, int64_t rows, int nc, int splits, double* G) {
     const int LPc = lp16(nc);
     double* gp = P.at<double>(L.gpart);
-    HIP_TRY((launch_nn<T, T, double, double>(X, ldx, nc, rows, X, ldx, nc, gp, LPc, (int64_t)LPc * LPc, splits, st)));
+    HIP_TRY(launch_gram<T>(X, ldx, rows, nc, gp, LPc, (int64_t)LPc * LPc, splits, st));
     HIP_TRY(launch_reduce2<double>(gp, splits, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, P.at<double>(L.gpart2), G,
                                    LPc, st));
     return RSVD_OK;
@@ -379,12 +388,11 @@ template <typename T> struct Path {
     double* gp2 = P.at<double>(L.gpart2);
     double* scr = P.at<double>(L.scr_chol);
     int* flags = P.at<int>(L.flags);
-    HIP_TRY((launch_nn<T, T, double, double>(Bt, L.ldn, nc, n, Bt, L.ldn, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st)));
+    HIP_TRY(launch_gram<T>(Bt, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
     HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R1, nullptr, scr, flags, st));
     HIP_TRY((launch_tn<T, double, double, double>(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, 0, 1, false, st)));
-    HIP_TRY((launch_nn<double, double, double, double>(Q1d, L.ldn, nc, n, Q1d, L.ldn, nc, gp, LPc, (int64_t)LPc * LPc,
-                                                       L.s_gn, st)));
+    HIP_TRY(launch_gram<double>(Q1d, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
     HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R, R1, scr, flags, st));
     const double tol = (double)nc * 2.220446049250313e-16;

@@ -57,6 +57,39 @@ def test_product_nn_is_exact_on_integers(prec, rows, K, ncols, lda_pad):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("K,nc", [(64, 16), (777, 110), (1000, 128), (300, 129), (2049, 300), (5000, 520),
+                                  (100, 1), (130, 17), (64, 1024)])
+def test_gram_is_exact_on_integers(prec, K, nc):
+    """G = Y^T Y through rsvd_k_gram (FP64 accumulation on the FP64 MFMA, upper tile pairs mirrored): exact on
+    small integers, both triangles, rows of the panel past K ignored (filled with garbage), nothing written past
+    nc rows of G."""
+    import torch
+    rng = np.random.default_rng(K * 7 + nc)
+    Y = rng.integers(-3, 4, size=(K, nc)).astype(np.float64)
+    ref = Y.T @ Y
+    ldy = (K + 63) // 64 * 64 + 64
+    Yp = np.full((nc, ldy), 5.0)          # rows K .. ldy-1 of every column: garbage the kernel must not read in
+    Yp[:, :K] = Y.T
+    dY = _t(Yp, torch.float64 if prec == "f64" else torch.float32)
+    ldg = nc + 3
+    G = torch.full((nc, ldg), -7.0, dtype=torch.float64, device=device())
+    assert _lib().rsvd_k_gram(PREC[prec], K, nc, _p(dY), ldy, _p(G), ldg, None) == 0
+    got = G.cpu().numpy()
+    assert np.array_equal(got[:, :nc], ref)
+    assert np.all(got[:, nc:] == -7.0)
+
+
+def test_gram_rejects_bad_arguments():
+    import torch
+    dY = torch.zeros(64 * 10, dtype=torch.float32, device=device())
+    G = torch.zeros(100, dtype=torch.float64, device=device())
+    assert _lib().rsvd_k_gram(PREC["f32"], 64, 10, _p(dY), 60, _p(G), 10, None) != 0     # ldy not a multiple of 64
+    assert _lib().rsvd_k_gram(PREC["f32"], 65, 1, _p(dY), 64, _p(G), 10, None) != 0     # ldy < K
+    assert _lib().rsvd_k_gram(PREC["f32acc64"], 64, 10, _p(dY), 64, _p(G), 10, None) != 0
+    assert _lib().rsvd_k_gram(PREC["f32"], 64, 10, _p(dY), 64, _p(G), 9, None) != 0     # ldg < nc
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("K,N,ncols,rowmajor", [(64, 256, 16, 0), (517, 300, 30, 0), (1000, 77, 110, 1),
                                                 (30, 1000, 30, 0), (129, 513, 200, 1), (2048, 260, 9, 0)])
 def test_product_tn_is_exact_on_integers(prec, K, N, ncols, rowmajor):
