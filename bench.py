@@ -238,6 +238,10 @@ def run_batched(args):
     torch.cuda.synchronize()
     bat = Batched(blocks, eps=eps, rank_cap=64, seed=args.seed, n_workgroups=args.batched_wg)
     s = torch.cuda.Stream(device=dev)
+    bat.stream = s
+    tiles, tune_ms = bat.autotune()      # untimed: per size class, the fastest MFMA tile shape
+    print(f"autotuned tiles {tiles}: ms per class/variant {[[round(x, 3) for x in r] for r in tune_ms]}",
+          file=sys.stderr, flush=True)
     bat.capture(s)
     for _ in range(args.warmup):
         bat.replay(s)
@@ -274,7 +278,8 @@ def run_batched(args):
            "wall_ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32 data, f64 arithmetic", "data": "synthetic",
            "config": {"workload": "kernel_blocks_4096", "nblk": nblk, "rows_cols": "uniform [64, 512]", "eps": eps,
-                      "elements": elems, "n_workgroups": args.batched_wg or "default (2 per CU)"},
+                      "elements": elems, "n_workgroups": args.batched_wg or "default (resident slots)",
+                      "tiles": tiles},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": MI355X_PEAK["f64"], "unit": "TFLOP/s",
                         "frac": achieved / MI355X_PEAK["f64"], "traffic": None, "kernel": "batched_kernel",
                         "hbm_gbs_algorithmic": bytes_alg / (ms_rep * 1e-3) / 1e9},

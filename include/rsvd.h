@@ -299,20 +299,50 @@ rsvd_status rsvd_mlp_adam(float* d_theta, const float* d_grad, float* d_m, float
  * d_rank[b] = columns kept; d_status[b] = 0 certified, 1 not certified at the
  * rank cap, -1 invalid block shape, -4 non-finite entries.
  * eps in (0, 1); 16 <= rank_cap <= 64.  n_workgroups = persistent workgroups
- * (0 = two per compute unit).  Blocks are taken largest first from an atomic
- * queue.  Fully asynchronous; no host synchronisation; capturable.
+ * (0 = as many as are resident at once on the device).  Blocks are taken
+ * largest first from an atomic queue.  The products with the block run on the
+ * FP64 MFMA in wave tiles whose shape is chosen per size class: h_tiles (host,
+ * RSVD_BATCHED_CLASSES entries, or NULL for the default) gives the variant
+ * (0 .. RSVD_BATCHED_TILE_VARIANTS-1) for blocks with max(m_b, n_b) in
+ * (0,128], (128,256], (256,384], (384,512]; variant v takes 1 + (v & 1)
+ * 16-row tiles and 1 + ((v >> 1) & 1) 16-column tiles per wave task with
+ * 2 << ((v >> 2) & 1) k-slices in flight.  All variants give bit-identical
+ * outputs; rsvd_batched_autotune picks the fastest.  Fully asynchronous; no
+ * host synchronisation; capturable.
  * Workspace: rsvd_batched_workspace_size(nblk, n_workgroups).
- * Errors: RSVD_E_ARG, RSVD_E_WORKSPACE, RSVD_E_HIP.
+ * Errors: RSVD_E_ARG (also a variant out of range), RSVD_E_WORKSPACE,
+ * RSVD_E_HIP.
  */
+#define RSVD_BATCHED_CLASSES 4
+#define RSVD_BATCHED_TILE_VARIANTS 8
 rsvd_status rsvd_batched_workspace_size(int32_t nblk, int32_t n_workgroups, size_t* h_bytes);
 rsvd_status rsvd_batched(int32_t nblk, const int32_t* d_m, const int32_t* d_n, const float* const* d_A,
                          const int32_t* d_lda, double eps, int32_t rank_cap, uint64_t seed, float* d_U, double* d_S,
                          float* d_V, const int64_t* d_offU, const int64_t* d_offV, int32_t* d_rank,
-                         int32_t* d_status, int32_t n_workgroups, void* d_ws, size_t ws_bytes, void* stream);
+                         int32_t* d_status, int32_t n_workgroups, const int32_t* h_tiles, void* d_ws,
+                         size_t ws_bytes, void* stream);
 
 /*
- * Capture one rsvd_batched call (same arguments) on `stream` (not the NULL
- * stream) into a HIP graph and instantiate it; rsvd_graph_launch replays it
+ * Tile autotuner of rsvd_batched (same arguments, minus h_tiles).  For every
+ * size class that holds blocks it times each tile variant with HIP events
+ * (one warm-up and two timed launches in which only that class's blocks are
+ * compressed) and writes the fastest variant per class to h_tiles_out
+ * (RSVD_BATCHED_CLASSES entries; the default for empty classes).  h_ms_out
+ * (optional, RSVD_BATCHED_CLASSES x RSVD_BATCHED_TILE_VARIANTS, row-major)
+ * receives the mean milliseconds per launch (0 for empty classes).
+ * Synchronises `stream`; not capturable.  The outputs hold partial results
+ * afterwards: run rsvd_batched (or a graph) with the chosen tiles.
+ * Errors: as rsvd_batched.
+ */
+rsvd_status rsvd_batched_autotune(int32_t nblk, const int32_t* d_m, const int32_t* d_n, const float* const* d_A,
+                                  const int32_t* d_lda, double eps, int32_t rank_cap, uint64_t seed, float* d_U,
+                                  double* d_S, float* d_V, const int64_t* d_offU, const int64_t* d_offV,
+                                  int32_t* d_rank, int32_t* d_status, int32_t n_workgroups, void* d_ws,
+                                  size_t ws_bytes, void* stream, int32_t* h_tiles_out, float* h_ms_out);
+
+/*
+ * Capture one rsvd_batched call (same arguments, the tile table included) on
+ * `stream` (not the NULL stream) into a HIP graph and instantiate it; rsvd_graph_launch replays it
  * on any stream (the buffers named at capture are reused).  The sequence
  * contains kernels only (no memset nodes).
  * Errors: RSVD_E_ARG, RSVD_E_WORKSPACE, RSVD_E_HIP.
@@ -322,8 +352,8 @@ rsvd_status rsvd_batched_graph_create(int32_t nblk, const int32_t* d_m, const in
                                       const float* const* d_A, const int32_t* d_lda, double eps, int32_t rank_cap,
                                       uint64_t seed, float* d_U, double* d_S, float* d_V, const int64_t* d_offU,
                                       const int64_t* d_offV, int32_t* d_rank, int32_t* d_status,
-                                      int32_t n_workgroups, void* d_ws, size_t ws_bytes, void* stream,
-                                      rsvd_graph_t* h_out);
+                                      int32_t n_workgroups, const int32_t* h_tiles, void* d_ws, size_t ws_bytes,
+                                      void* stream, rsvd_graph_t* h_out);
 rsvd_status rsvd_graph_launch(rsvd_graph_t graph, void* stream);
 void rsvd_graph_destroy(rsvd_graph_t graph);
 

@@ -15,7 +15,7 @@ import torch
 
 from . import _lib
 from ._lib import (  # noqa: F401
-    RSVD_BF16, RSVD_E_ARG, RSVD_E_BREAKDOWN, RSVD_E_HIP, RSVD_E_NONFINITE, RSVD_E_UNSUPPORTED, RSVD_E_WORKSPACE,
+    RSVD_BATCHED_CLASSES, RSVD_BATCHED_TILE_VARIANTS, RSVD_BF16, RSVD_E_ARG, RSVD_E_BREAKDOWN, RSVD_E_HIP, RSVD_E_NONFINITE, RSVD_E_UNSUPPORTED, RSVD_E_WORKSPACE,
     RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RSVD_MLP_NPARAM, RSVD_NOT_CERTIFIED, RSVD_OK, RSVD_RETURN_RANK_L,
     RSVD_SEL_NQ, RSVD_SEL_P, RSVD_TIMING, RSVDError, STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info,
     status_str,
@@ -223,9 +223,11 @@ class Batched:
     pointers, output offsets and the workspace are built once; `run()`
     launches rsvd_batched, `capture()` records it into a HIP graph and
     `replay()` launches the graph.  Outputs: U (sum m_b x rank_cap),
-    V (sum n_b x rank_cap), S (nblk x rank_cap), rank, status."""
+    V (sum n_b x rank_cap), S (nblk x rank_cap), rank, status.  `tiles`
+    (one MFMA tile variant per size class, None = library default) is set
+    by hand or by `autotune()` and applies to later run() / capture()."""
 
-    def __init__(self, blocks, eps=1e-6, rank_cap=64, seed=0, n_workgroups=0, stream=None):
+    def __init__(self, blocks, eps=1e-6, rank_cap=64, seed=0, n_workgroups=0, stream=None, tiles=None):
         self.blocks = list(blocks)
         dev = self.blocks[0].device
         self.device = dev
@@ -258,17 +260,41 @@ class Batched:
         self.ws = ws[off:off + nbytes.value]
         self.stream = stream
         self.graph = None
+        self.tiles = None if tiles is None else [int(t) for t in tiles]
 
-    def _args(self):
+    def _head(self):
         return (len(self.blocks), _ptr(self.m), _ptr(self.n), _ptr(self.ptrs), _ptr(self.lda), self.eps,
                 self.rank_cap, self.seed, _ptr(self.U), _ptr(self.S), _ptr(self.V), _ptr(self.offU),
-                _ptr(self.offV), _ptr(self.rank), _ptr(self.status), self.nwg, _ptr(self.ws),
-                self.ws.numel())
+                _ptr(self.offV), _ptr(self.rank), _ptr(self.status), self.nwg)
+
+    def _tiles_arg(self):
+        if self.tiles is None:
+            return None
+        if len(self.tiles) != _lib.RSVD_BATCHED_CLASSES:
+            raise ValueError(f"tiles needs {_lib.RSVD_BATCHED_CLASSES} entries")
+        return ctypes.cast((ctypes.c_int32 * len(self.tiles))(*self.tiles), ctypes.c_void_p)
+
+    def _args(self):
+        return self._head() + (self._tiles_arg(), _ptr(self.ws), self.ws.numel())
 
     def run(self):
         st = _lib.lib().rsvd_batched(*self._args(), _stream_handle(self.device, self.stream))
         if st != RSVD_OK:
             raise RSVDError(st, "rsvd_batched")
+
+    def autotune(self):
+        """Time every tile variant per size class (rsvd_batched_autotune), keep
+        the fastest in `tiles`; returns (tiles, ms) with ms[class][variant]."""
+        nc, nv = _lib.RSVD_BATCHED_CLASSES, _lib.RSVD_BATCHED_TILE_VARIANTS
+        out = (ctypes.c_int32 * nc)()
+        ms = (ctypes.c_float * (nc * nv))()
+        st = _lib.lib().rsvd_batched_autotune(*self._head(), _ptr(self.ws), self.ws.numel(),
+                                              _stream_handle(self.device, self.stream),
+                                              ctypes.cast(out, ctypes.c_void_p), ctypes.cast(ms, ctypes.c_void_p))
+        if st != RSVD_OK:
+            raise RSVDError(st, "rsvd_batched_autotune")
+        self.tiles = list(out)
+        return self.tiles, [list(ms[c * nv:(c + 1) * nv]) for c in range(nc)]
 
     def capture(self, stream):
         h = ctypes.c_void_p()

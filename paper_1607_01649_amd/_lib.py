@@ -74,12 +74,17 @@ SIGNATURES = [
     ("rsvd_batched_workspace_size", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     ("rsvd_batched", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p, ctypes.c_double,
                                     ctypes.c_int32, ctypes.c_uint64, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
-                                    _c_void_p, _c_void_p, _c_void_p, ctypes.c_int32, _c_void_p, ctypes.c_size_t,
-                                    _c_void_p]),
+                                    _c_void_p, _c_void_p, _c_void_p, ctypes.c_int32, _c_void_p, _c_void_p,
+                                    ctypes.c_size_t, _c_void_p]),
+    ("rsvd_batched_autotune", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                             ctypes.c_double, ctypes.c_int32, ctypes.c_uint64, _c_void_p,
+                                             _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
+                                             ctypes.c_int32, _c_void_p, ctypes.c_size_t, _c_void_p, _c_void_p,
+                                             _c_void_p]),
     ("rsvd_batched_graph_create", ctypes.c_int, [ctypes.c_int32, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
                                                  ctypes.c_double, ctypes.c_int32, ctypes.c_uint64, _c_void_p,
                                                  _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p,
-                                                 ctypes.c_int32, _c_void_p, ctypes.c_size_t, _c_void_p,
+                                                 ctypes.c_int32, _c_void_p, _c_void_p, ctypes.c_size_t, _c_void_p,
                                                  ctypes.POINTER(_c_void_p)]),
     ("rsvd_graph_launch", ctypes.c_int, [_c_void_p, _c_void_p]),
     ("rsvd_graph_destroy", None, [_c_void_p]),
@@ -122,6 +127,9 @@ RSVD_F32_ACC64 = 10
 RSVD_MLP_IN, RSVD_MLP_HIDDEN, RSVD_MLP_OUT, RSVD_MLP_NPARAM = 16, 64, 40, 7848
 RSVD_SEL_P = (0, 5, 10, 20, 40, 80, 160, 320)
 RSVD_SEL_NQ = 5
+
+# batched compression tile table (include/rsvd.h)
+RSVD_BATCHED_CLASSES, RSVD_BATCHED_TILE_VARIANTS = 4, 8
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:

@@ -15,9 +15,19 @@
 //   SVD of B via the eigen-decomposition of B B^T (cyclic Jacobi, FP64), kept
 //   singular values > eps sigma_hat_1 / 2, U = Q U_hat, V = B^T U_hat S^-1.
 // All accumulation is FP64 (the probe threshold sits near FP32's noise floor
-// at eps = 1e-6).  Thread t owns row t of the row-indexed quantities (Y, Q,
-// E) and column t of the column-indexed ones (B^T); cross-thread sums go
-// through 64-row chunks staged in LDS.
+// at eps = 1e-6).
+//
+// The products with the block -- Y = K [Omega | G_c], B^T = K^T Q, the growth
+// sketch K Omega_b -- and the final U = Q U_hat, V = B^T U_hat run on the FP64
+// MFMA (mfma_panel below): each wave takes tiles of 16-row groups x 16-column
+// groups, streams K straight from memory and the thin panel from the
+// workgroup's scratch (L2), with a register ring of prefetched k-slices.  The
+// tile shape (row tiles and column tiles per wave task, prefetch depth) is a
+// per-size-class parameter picked by the autotuner in batched_api.hip; every
+// shape gives bit-identical results.  The small dense steps (16-column Gram
+// matrices, Cholesky, the Jacobi eigen-decomposition) stay row-owned: thread t
+// owns row t of Y, Q and the probe residual E and column t of B^T, with
+// cross-thread sums through 64-row chunks staged in LDS.
 //
 // Per-block random streams: 16*blk + 4 (Omega and its continuation),
 // 16*blk + 6 (probes), same Philox4x32-10 / Box-Muller mapping as the
@@ -33,8 +43,12 @@ constexpr int L0 = 16;        // initial sketch width
 constexpr int BG = 8;         // growth block
 constexpr int NP = 10;        // certificate probes
 constexpr int CH = 64;        // rows per LDS chunk of the cross-thread sums
-constexpr int KC = 16;        // columns of K per staged tile in the row-owned products
-constexpr int KLD = KC + 1;   // LDS pitch of a staged K row
+constexpr int NWAVE = BT / 64;
+constexpr int OW = 32;        // columns of the sketch panel [Omega | G_c | 0] and of Y
+constexpr int GW = 16;        // columns of the growth panel [Omega_b | 0]
+constexpr int NCLASS = 4;     // size classes by max(m, n): (0,128], (128,256], (256,384], (384,512]
+constexpr int NVARIANT = 8;   // MFMA tile shapes, see TileShape
+constexpr int DEFAULT_VARIANT = 2;
 
 struct BatchedArgs {
   int nblk;
@@ -56,6 +70,8 @@ struct BatchedArgs {
   int* queue;         // work counter, zero before launch
   double* scratch;    // per-workgroup scratch
   int64_t scratch_per_wg;
+  int tile[NCLASS];   // MFMA tile variant per size class
+  int class_mask;     // blocks of classes outside the mask are skipped (autotuner timing)
 };
 
 // Philox4x32-10, same as rng.hip (kept local so this file stands alone).
@@ -85,38 +101,153 @@ __device__ __forceinline__ void bgauss_pair(uint64_t seed, uint32_t stream, uint
   z1 = rad * sin(th);
 }
 
-// Stage rows [j0, j0+KC) of `nc` Gaussian columns into lds[jj*ldl + c] (zero past n):
-// columns [0, nc0) from stream s0 starting at column col0, columns [nc0, nc) from stream s1.
-__device__ void stage_gauss(double* lds, int ldl, int j0, int n, int nc, int nc0, uint64_t seed, uint32_t s0,
-                            int col0, uint32_t s1) {
-  const int pairs = KC / 2;
-  for (int t = threadIdx.x; t < pairs * nc; t += BT) {
-    int c = t / pairs, i2 = t - (t / pairs) * pairs;
-    int j = j0 + 2 * i2;
-    double z0 = 0.0, z1 = 0.0;
-    if (j < n) {
-      if (c < nc0) bgauss_pair(seed, s0, (uint32_t)(j >> 1), (uint32_t)(col0 + c), z0, z1);
-      else bgauss_pair(seed, s1, (uint32_t)(j >> 1), (uint32_t)(c - nc0), z0, z1);
-    }
-    lds[(2 * i2) * ldl + c] = z0;
-    lds[(2 * i2 + 1) * ldl + c] = (j + 1 < n) ? z1 : 0.0;
+// threadIdx.x behind an empty asm: values derived from it cannot be hoisted out
+// of the per-block loop.  Without this the compiler precomputes the per-lane
+// operand addresses of every inlined product and helper at kernel entry and
+// keeps them live (spilled) across the whole persistent loop.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Tile shape of the MFMA products: RT 16-row tiles and NCT 16-column tiles per
+// wave task, DEPTH k-slices of 16 in flight.  Variant v: RT = 1 + bit 0,
+// NCT = 1 + bit 1, DEPTH = 2 << bit 2.
+template <int RT_, int NCT_, int DEPTH_> struct TileShape {
+  static constexpr int RT = RT_, NCT = NCT_, DEPTH = DEPTH_;
+};
+
+template <typename F> __device__ __forceinline__ void with_tile(int v, F&& f) {
+  switch (v) {
+    case 0: f(TileShape<1, 1, 2>{}); break;
+    case 1: f(TileShape<2, 1, 2>{}); break;
+    case 3: f(TileShape<2, 2, 2>{}); break;
+    case 4: f(TileShape<1, 1, 4>{}); break;
+    case 5: f(TileShape<2, 1, 4>{}); break;
+    case 6: f(TileShape<1, 2, 4>{}); break;
+    case 7: f(TileShape<2, 2, 4>{}); break;
+    default: f(TileShape<1, 2, 2>{}); break;   // variant 2
   }
 }
 
-// Stage columns [j0, j0+KC) of rows [0, m) of K into tile[r*KLD + c] (zero past n).  Each
-// group of KC threads reads KC consecutive floats of one row, so the global reads are
-// contiguous; the odd LDS row pitch keeps the row-per-thread reads conflict-free.
-__device__ void stage_k(const float* __restrict__ A, int lda, int m, int n, int j0, float* tile) {
-  for (int t = threadIdx.x; t < m * KC; t += BT) {
-    const int r = t / KC, c = t - (t / KC) * KC;
-    tile[r * KLD + c] = (j0 + c < n) ? A[(int64_t)r * lda + j0 + c] : 0.0f;
+// out = X W on the FP64 MFMA (v_mfma_f64_16x16x4f64).  X is rows x kdim with
+// entry (r, k) at X[r*xr + k*xk] (TX = float for the block, double for the
+// scratch panels; xr = 1 reads the block transposed); W is kdim x ncols with
+// entry (k, c) at W[k*ldw + c].  Entries past rows, kdim or ncols read as zero
+// (addresses are clamped, so nothing outside the operands is touched).
+// Wave w takes the tasks w, w+8, ... of (RT row tiles) x (NCT column tiles).
+// Over each 16-wide k-slice, lane l (g = l/16) feeds data columns k0+4g+s in
+// MFMA step s = 0..3, so lane l loads four consecutive k of its row; the
+// k-slices are consumed in increasing order by every shape, which makes the
+// result of every entry independent of the shape.  epi(r, c, v) receives each
+// entry r < rows, c < ncols.
+template <typename TX, int RT, int NCT, int DEPTH, typename Epi>
+__device__ __forceinline__ void mfma_panel(const TX* __restrict__ X, int64_t xr, int64_t xk, int rows, int kdim,
+                                           const double* W, int ldw, int ncols, Epi&& epi) {
+  typedef Mma<double> M;
+  const int tid = opaque_tid();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int rgroups = (rows + 16 * RT - 1) / (16 * RT);
+  const int cgroups = (ncols + 16 * NCT - 1) / (16 * NCT);
+  const int ntask = rgroups * cgroups;
+  const int nk = (kdim + 15) >> 4;
+  for (int task = wave; task < ntask; task += NWAVE) {
+    const int rg = task / cgroups, cg = task - rg * cgroups;
+    const TX* xp[RT];
+    bool rok[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int r = 16 * (RT * rg + rt) + M::arow(li);
+      rok[rt] = r < rows;
+      xp[rt] = X + (int64_t)(rok[rt] ? r : 0) * xr;
+    }
+    int wcol[NCT];
+    bool cok[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int c = 16 * (NCT * cg + ct) + li;
+      cok[ct] = c < ncols;
+      wcol[ct] = cok[ct] ? c : 0;
+    }
+    typename M::acc acc[RT][NCT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) acc[rt][ct] = M::zero();
+    TX xa[DEPTH][RT][4];
+    double wb[DEPTH][NCT][4];
+    auto load = [&](int kc, TX(&xs)[RT][4], double(&ws)[NCT][4]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 16 * kc + 4 * g + s;
+        const bool kok = k < kdim;
+        const int64_t kk = kok ? k : 0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          const TX v = xp[rt][kk * xk];
+          xs[rt][s] = (kok && rok[rt]) ? v : TX(0);
+        }
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const double v = W[kk * ldw + wcol[ct]];
+          ws[ct][s] = (kok && cok[ct]) ? v : 0.0;
+        }
+      }
+    };
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) load(d, xa[d], wb[d]);
+    for (int kc0 = 0; kc0 < nk; kc0 += DEPTH) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; ++d) {
+        if (kc0 + d < nk) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+              for (int ct = 0; ct < NCT; ++ct)
+                acc[rt][ct] = M::op((double)xa[d][rt][s], wb[d][ct][s], acc[rt][ct]);
+        }
+        load(kc0 + d + DEPTH, xa[d], wb[d]);
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int c = 16 * (NCT * cg + ct) + li;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = 16 * (RT * rg + rt) + 4 * g + e;
+          if (r < rows && c < ncols) epi(r, c, acc[rt][ct][e]);
+        }
+      }
+  }
+}
+
+// Gaussian panel P (ld ldp) for rows [0, n): columns [0, nc0) from stream s0
+// starting at column col0, columns [nc0, nc) from stream s1 starting at 0.
+// Consecutive threads fill consecutive columns of a row pair.
+__device__ void fill_gauss(double* P, int ldp, int n, int nc, int nc0, uint64_t seed, uint32_t s0, int col0,
+                           uint32_t s1) {
+  const int hp = (n + 1) >> 1;
+  for (int t = opaque_tid(); t < hp * nc; t += BT) {
+    const int i2 = t / nc, c = t - (t / nc) * nc;
+    double z0, z1;
+    const bool first = c < nc0;   // one inlined copy of the transform
+    bgauss_pair(seed, first ? s0 : s1, (uint32_t)i2, (uint32_t)(first ? col0 + c : c - nc0), z0, z1);
+    P[(int64_t)(2 * i2) * ldp + c] = z0;
+    if (2 * i2 + 1 < n) P[(int64_t)(2 * i2 + 1) * ldp + c] = z1;
   }
 }
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  const int tid = opaque_tid();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
   double t = 0.0;
 #pragma unroll
@@ -131,13 +262,13 @@ __device__ void rows_inner(const double (&xr)[NX], int na, const double (&zr)[NZ
                            double* C, int ldc) {
   double acc = 0.0;
   const int nout = na * nbz;
-  const int o = threadIdx.x;
+  const int o = opaque_tid();
   const int a = o / max(nbz, 1), b = o - a * max(nbz, 1);
   for (int r0 = 0; r0 < rows; r0 += CH) {
     __syncthreads();
-    if (threadIdx.x >= r0 && threadIdx.x < r0 + CH) {
-      const int rr = threadIdx.x - r0;
-      const bool ok = threadIdx.x < rows;
+    if (o >= r0 && o < r0 + CH) {
+      const int rr = o - r0;
+      const bool ok = o < rows;
 #pragma unroll
       for (int q = 0; q < NX; ++q) stage[rr * (NX + NZ) + q] = ok ? xr[q] : 0.0;
 #pragma unroll
@@ -163,7 +294,7 @@ __device__ void rows_inner(const double (&xr)[NX], int na, const double (&zr)[NZ
 template <int NC>
 __device__ void small_chol_inv(double* G, double* Tm, double* Ri, double tau) {
   __shared__ double gd[16], rs[16];
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int a = tid / NC, b = tid - (tid / NC) * NC;
   const bool own = tid < NC * NC;
   if (own) Tm[tid] = (a == b) ? 1.0 : 0.0;
@@ -204,7 +335,7 @@ __device__ void small_eig(double* M, double* Vm, int nc) {
   __shared__ int any_rot;
   __shared__ double dmax_s;
   constexpr int PER = RMAX * RMAX / BT;
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   const int N = (nc + 1) & ~1;
   for (int t = tid; t < N * N; t += BT) {
     const int a = t / N, b = t - (t / N) * N;
@@ -283,19 +414,21 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
   __shared__ double lds[2 * RMAX * RMAX];   // phase-dependent union (64 KB)
   __shared__ double H[RMAX * NP];
   __shared__ double Ri[16 * 16];
-  __shared__ double red[BT / 64];
+  __shared__ double red[NWAVE * NP];
   __shared__ double sig[RMAX];
   __shared__ double sgn[RMAX];
   __shared__ int perm[RMAX];
   __shared__ int sh_blk;
-  const int tid = threadIdx.x;
   double* scr = g.scratch + (int64_t)blockIdx.x * g.scratch_per_wg;
   double* Qs = scr;                          // BROWS x RMAX, row i at Qs[i*RMAX]
   double* Bs = Qs + BROWS * RMAX;            // B^T: BROWS x RMAX, row j at Bs[j*RMAX]
-  double* Gcs = Bs + BROWS * RMAX;           // probes: BROWS x NP
+  double* OmG = Bs + BROWS * RMAX;           // [Omega | G_c]: BROWS x OW
+  double* Ys = OmG + BROWS * OW;             // sketch outputs: BROWS x OW
+  double* Wb = Ys + BROWS * OW;              // growth panel: BROWS x GW
   const double c_alpha = 10.0 * sqrt(2.0 / 3.14159265358979323846);
 
   for (;;) {
+    const int tid = opaque_tid();
     if (tid == 0) {
       int idx = atomicAdd(g.queue, 1);
       sh_blk = idx < g.nblk ? g.order[idx] : -1;
@@ -311,42 +444,33 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
       __syncthreads();
       continue;
     }
+    const int cls = (max(m, n) - 1) >> 7;
+    if (!((g.class_mask >> cls) & 1)) continue;   // uniform: no barrier crossed
+    const int tv = g.tile[cls];
     const uint32_t s_om = 16u * (uint32_t)blk + 4u, s_pr = 16u * (uint32_t)blk + 6u;
     const double tau = 16.0 * 1.2e-32;
     const bool row_ok = tid < m, col_ok = tid < n;
     bool nonfinite = false;
 
-    // ---- Y = K [Omega_0 | Gc] (row tid), FP64; the probe part stays as e
+    // ---- Y = K [Omega_0 | G_c] on the MFMA; row tid: first 16 columns to qv, probes to e
+    fill_gauss(OmG, OW, n, L0 + NP, L0, g.seed, s_om, 0, s_pr);
+    __syncthreads();
+    with_tile(tv, [&](auto sh) {
+      typedef decltype(sh) T;
+      mfma_panel<float, T::RT, T::NCT, T::DEPTH>(A, lda, 1, m, n, OmG, OW, L0 + NP,
+                                                 [&](int r, int c, double v) { Ys[r * OW + c] = v; });
+    });
+    __syncthreads();
     double qv[L0], e[NP];
-    {
-      double y[L0 + NP];
 #pragma unroll
-      for (int c = 0; c < L0 + NP; ++c) y[c] = 0.0;
-      float* tile = reinterpret_cast<float*>(lds + KC * (L0 + NP));
-      for (int j0 = 0; j0 < n; j0 += KC) {
-        __syncthreads();
-        stage_gauss(lds, L0 + NP, j0, n, L0 + NP, L0, g.seed, s_om, 0, s_pr);
-        stage_k(A, lda, m, n, j0, tile);
-        __syncthreads();
-        for (int t = tid; t < KC * NP; t += BT) {   // keep the probes for B Gc
-          int jj = t / NP, c = t - (t / NP) * NP;
-          if (j0 + jj < n) Gcs[(j0 + jj) * NP + c] = lds[jj * (L0 + NP) + L0 + c];
-        }
-        if (row_ok) {
-#pragma unroll 2
-          for (int jj = 0; jj < KC; ++jj) {
-            double a = (double)tile[tid * KLD + jj];
-            nonfinite |= !isfinite(a);
+    for (int c = 0; c < L0; ++c) qv[c] = row_ok ? Ys[tid * OW + c] : 0.0;
 #pragma unroll
-            for (int c = 0; c < L0 + NP; ++c) y[c] += a * lds[jj * (L0 + NP) + c];
-          }
-        }
-      }
+    for (int c = 0; c < NP; ++c) e[c] = row_ok ? Ys[tid * OW + L0 + c] : 0.0;
+    // every Gaussian entry is nonzero, so a non-finite entry of row tid reaches Y(tid, :)
 #pragma unroll
-      for (int c = 0; c < L0; ++c) qv[c] = row_ok ? y[c] : 0.0;
+    for (int c = 0; c < L0; ++c) nonfinite |= !isfinite(qv[c]);
 #pragma unroll
-      for (int c = 0; c < NP; ++c) e[c] = row_ok ? y[L0 + c] : 0.0;
-    }
+    for (int c = 0; c < NP; ++c) nonfinite |= !isfinite(e[c]);
 
     // ---- Q = CholeskyQR2 of Y[:, 0:16]
     for (int pass = 0; pass < 2; ++pass) {
@@ -373,35 +497,23 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
     int steps = 0;
     for (;;) {
       const int nw = (rc == 0) ? L0 : BG;   // columns added in this round
-      // ---- B_new^T = K^T Q_new (column tid), Q_new rows staged through LDS
+      // ---- B_new^T = K^T Q_new on the MFMA (rows of B^T are the block's columns)
+      __syncthreads();
+      with_tile(tv, [&](auto sh) {
+        typedef decltype(sh) T;
+        mfma_panel<float, T::RT, 1, T::DEPTH>(A, 1, lda, n, m, Qs + rc, RMAX, nw, [&](int j, int c, double v) {
+          Bs[j * RMAX + rc + c] = v;
+        });
+      });
+      __syncthreads();
       double bt[L0];
 #pragma unroll
-      for (int c = 0; c < L0; ++c) bt[c] = 0.0;
-      for (int i0 = 0; i0 < m; i0 += CH) {
-        __syncthreads();
-        for (int t = tid; t < CH * L0; t += BT) {
-          int ii = t / L0, c = t - (t / L0) * L0;
-          lds[ii * L0 + c] = (i0 + ii < m && c < nw) ? Qs[(i0 + ii) * RMAX + rc + c] : 0.0;
-        }
-        __syncthreads();
-        if (col_ok) {
-          const int in_ = min(CH, m - i0);
-          for (int ii = 0; ii < in_; ++ii) {
-            double a = (double)A[(int64_t)(i0 + ii) * lda + tid];
-#pragma unroll
-            for (int c = 0; c < L0; ++c) bt[c] += a * lds[ii * L0 + c];
-          }
-        }
-      }
-      if (col_ok)
-#pragma unroll
-        for (int c = 0; c < L0; ++c)
-          if (c < nw) Bs[tid * RMAX + rc + c] = bt[c];
+      for (int c = 0; c < L0; ++c) bt[c] = (col_ok && c < nw) ? Bs[tid * RMAX + rc + c] : 0.0;
       // ---- H = B_new Gc (nw x NP); e -= Q_new H
       {
         double gcv[NP];
 #pragma unroll
-        for (int c = 0; c < NP; ++c) gcv[c] = col_ok ? Gcs[tid * NP + c] : 0.0;
+        for (int c = 0; c < NP; ++c) gcv[c] = col_ok ? OmG[tid * OW + L0 + c] : 0.0;
         rows_inner<L0, NP>(bt, nw, gcv, NP, n, lds, H, NP);
       }
       if (row_ok) {
@@ -418,10 +530,24 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
         }
       }
       rc += nw;
-      // ---- bound = 10 sqrt(2/pi) max_b ||e(:, b)||
-      double mx = 0.0;
-      for (int b = 0; b < NP; ++b) mx = fmax(mx, block_sum(row_ok ? e[b] * e[b] : 0.0, red));
-      bound = c_alpha * sqrt(mx);
+      // ---- bound = 10 sqrt(2/pi) max_b ||e(:, b)||: the NP column sums in one reduction
+      {
+        double ss[NP];
+#pragma unroll
+        for (int b = 0; b < NP; ++b) ss[b] = wave_sum(row_ok ? e[b] * e[b] : 0.0);
+        if ((tid & 63) == 0)
+#pragma unroll
+          for (int b = 0; b < NP; ++b) red[(tid >> 6) * NP + b] = ss[b];
+        __syncthreads();
+        double mx = 0.0;
+        for (int b = 0; b < NP; ++b) {
+          double t = 0.0;
+#pragma unroll
+          for (int w = 0; w < NWAVE; ++w) t += red[w * NP + b];
+          mx = fmax(mx, t);
+        }
+        bound = c_alpha * sqrt(mx);
+      }
       if (rc == L0) {
         // sigma_hat_1: largest eigenvalue of B B^T for the first basis
         double* M = lds;
@@ -437,29 +563,22 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
         double mxl = 0.0;
         for (int a = 0; a < L0; ++a) mxl = fmax(mxl, M[a * RMAX + a]);
         sigma1 = sqrt(fmax(mxl, 0.0));
-        __syncthreads();
       }
+      __syncthreads();
       if (bound <= 0.5 * g.eps * sigma1 || rc + BG > min(min(g.rank_cap, RMAX), min(m, n))) break;
 
-      // ---- grow: Y_b = K G_b, projected twice against Q, orthonormalised, appended to Q
+      // ---- grow: Y_b = K Omega_b on the MFMA, projected twice against Q, orthonormalised, appended
+      fill_gauss(Wb, GW, n, BG, BG, g.seed, s_om, L0 + steps * BG, s_pr);
+      __syncthreads();
+      with_tile(tv, [&](auto sh) {
+        typedef decltype(sh) T;
+        mfma_panel<float, T::RT, 1, T::DEPTH>(A, lda, 1, m, n, Wb, GW, BG,
+                                              [&](int r, int c, double v) { Ys[r * OW + c] = v; });
+      });
+      __syncthreads();
       double yb[BG];
 #pragma unroll
-      for (int c = 0; c < BG; ++c) yb[c] = 0.0;
-      float* tile = reinterpret_cast<float*>(lds + KC * BG);
-      for (int j0 = 0; j0 < n; j0 += KC) {
-        __syncthreads();
-        stage_gauss(lds, BG, j0, n, BG, BG, g.seed, s_om, L0 + steps * BG, s_pr);
-        stage_k(A, lda, m, n, j0, tile);
-        __syncthreads();
-        if (row_ok) {
-#pragma unroll 2
-          for (int jj = 0; jj < KC; ++jj) {
-            double a = (double)tile[tid * KLD + jj];
-#pragma unroll
-            for (int c = 0; c < BG; ++c) yb[c] += a * lds[jj * BG + c];
-          }
-        }
-      }
+      for (int c = 0; c < BG; ++c) yb[c] = row_ok ? Ys[tid * OW + c] : 0.0;
       for (int pass = 0; pass < 2; ++pass) {
         for (int c0 = 0; c0 < rc; c0 += L0) {   // C = Q^T Y_b in blocks of 16 basis vectors
           double qb[L0];
@@ -503,25 +622,25 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
     double* Vm = lds + RMAX * RMAX;
     __syncthreads();
     if (rc != L0) {
-    for (int t = tid; t < RMAX * RMAX; t += BT) M[t] = 0.0;
-    __syncthreads();
-    for (int a0 = 0; a0 < rc; a0 += L0)
-      for (int b0 = 0; b0 < rc; b0 += L0) {
-        double ba[L0], bb[L0];
+      for (int t = tid; t < RMAX * RMAX; t += BT) M[t] = 0.0;
+      __syncthreads();
+      for (int a0 = 0; a0 < rc; a0 += L0)
+        for (int b0 = 0; b0 < rc; b0 += L0) {
+          double ba[L0], bb[L0];
 #pragma unroll
-        for (int c = 0; c < L0; ++c) {
-          ba[c] = (col_ok && a0 + c < rc) ? Bs[tid * RMAX + a0 + c] : 0.0;
-          bb[c] = (col_ok && b0 + c < rc) ? Bs[tid * RMAX + b0 + c] : 0.0;
+          for (int c = 0; c < L0; ++c) {
+            ba[c] = (col_ok && a0 + c < rc) ? Bs[tid * RMAX + a0 + c] : 0.0;
+            bb[c] = (col_ok && b0 + c < rc) ? Bs[tid * RMAX + b0 + c] : 0.0;
+          }
+          rows_inner<L0, L0>(ba, L0, bb, L0, n, Vm, H, L0);   // stage in Vm (free until small_eig)
+          for (int t = tid; t < L0 * L0; t += BT) {
+            int a = t / L0, b = t % L0;
+            if (a0 + a < rc && b0 + b < rc) M[(a0 + a) * RMAX + b0 + b] = H[t];
+          }
+          __syncthreads();
         }
-        rows_inner<L0, L0>(ba, L0, bb, L0, n, Vm, H, L0);   // stage in Vm (free until small_eig)
-        for (int t = tid; t < L0 * L0; t += BT) {
-          int a = t / L0, b = t % L0;
-          if (a0 + a < rc && b0 + b < rc) M[(a0 + a) * RMAX + b0 + b] = H[t];
-        }
-        __syncthreads();
-      }
-    small_eig(M, Vm, rc);
-    __syncthreads();
+      small_eig(M, Vm, rc);
+      __syncthreads();
     }
     if (tid < rc) {
       double v = M[tid * RMAX + tid];
@@ -548,23 +667,23 @@ __global__ __launch_bounds__(BT) void batched_kernel(BatchedArgs g) {
       sgn[tid] = sg;
     }
     __syncthreads();
-    // U = Q U_hat(:, :keep), V = B^T U_hat S^-1, S
+    // W = U_hat(:, perm[:keep]) with the signs applied, over M (free now)
+    double* Wu = M;
+    for (int t = tid; t < RMAX * RMAX; t += BT) {
+      const int a = t / RMAX, c = t - (t / RMAX) * RMAX;
+      Wu[t] = (a < rc && c < keep) ? sgn[c] * Vm[a * RMAX + perm[c]] : 0.0;
+    }
+    __syncthreads();
+    // U = Q W, V = B^T W S^-1, S
     float* Uo = g.U + g.offU[blk];
     float* Vo = g.V + g.offV[blk];
-    if (row_ok)
-      for (int c = 0; c < keep; ++c) {
-        const int col = perm[c];
-        double acc = 0.0;
-        for (int a = 0; a < rc; ++a) acc += Qs[tid * RMAX + a] * Vm[a * RMAX + col];
-        Uo[(int64_t)tid * g.rank_cap + c] = (float)(sgn[c] * acc);
-      }
-    if (col_ok)
-      for (int c = 0; c < keep; ++c) {
-        const int col = perm[c];
-        double acc = 0.0;
-        for (int a = 0; a < rc; ++a) acc += Bs[tid * RMAX + a] * Vm[a * RMAX + col];
-        Vo[(int64_t)tid * g.rank_cap + c] = (float)(sig[c] > 0.0 ? sgn[c] * acc / sig[c] : 0.0);
-      }
+    const int rcap = g.rank_cap;
+    mfma_panel<double, 1, 1, 2>(Qs, RMAX, 1, m, rc, Wu, RMAX, keep, [&](int r, int c, double v) {
+      Uo[(int64_t)r * rcap + c] = (float)v;
+    });
+    mfma_panel<double, 1, 1, 2>(Bs, RMAX, 1, n, rc, Wu, RMAX, keep, [&](int j, int c, double v) {
+      Vo[(int64_t)j * rcap + c] = (float)(sig[c] > 0.0 ? v / sig[c] : 0.0);
+    });
     if (tid < keep) g.S[(int64_t)blk * g.rank_cap + tid] = sig[tid];
     const double nf = block_sum(nonfinite ? 1.0 : 0.0, red);
     if (tid == 0) {
@@ -580,7 +699,7 @@ __global__ __launch_bounds__(1024) void order_kernel(int nblk, const int* __rest
                                                      int* __restrict__ order, int* __restrict__ queue) {
   __shared__ int hist[65];
   __shared__ int start[65];
-  const int tid = threadIdx.x;
+  const int tid = opaque_tid();
   if (tid < 65) hist[tid] = 0;
   if (tid == 0) *queue = 0;
   __syncthreads();
@@ -603,19 +722,33 @@ __global__ __launch_bounds__(1024) void order_kernel(int nblk, const int* __rest
   }
 }
 
-int batched_scratch_doubles_per_wg() { return BROWS * RMAX * 2 + BROWS * NP; }
+int batched_scratch_doubles_per_wg() { return BROWS * (2 * RMAX + 2 * OW + GW); }
+int batched_num_classes() { return NCLASS; }
+int batched_num_variants() { return NVARIANT; }
+int batched_default_variant() { return DEFAULT_VARIANT; }
 int batched_max_rank() { return RMAX; }
 int batched_max_dim() { return BROWS; }
+
+int batched_resident_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batched_kernel, BT, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
 
 hipError_t launch_batched(int nblk, const int* m, const int* n, const float* const* A, const int* lda, double eps,
                           int rank_cap, uint64_t seed, float* U, double* S, float* V, const int64_t* offU,
                           const int64_t* offV, int* rank, int* status, int* order, int* queue, double* scratch,
-                          int nwg, hipStream_t s) {
+                          int nwg, const int* tiles, int class_mask, hipStream_t s) {
   hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, s, nblk, m, n, order, queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   BatchedArgs g{nblk, m, n, A, lda, eps, rank_cap, seed, U, S, V, offU, offV, rank, status, order, queue, scratch,
-                (int64_t)batched_scratch_doubles_per_wg()};
+                (int64_t)batched_scratch_doubles_per_wg(), {}, class_mask};
+  for (int c = 0; c < NCLASS; ++c) {
+    const int v = tiles ? tiles[c] : DEFAULT_VARIANT;
+    if (v < 0 || v >= NVARIANT) return hipErrorInvalidValue;
+    g.tile[c] = v;
+  }
   hipLaunchKernelGGL(batched_kernel, dim3((unsigned)nwg), dim3(BT), 0, s, g);
   return hipGetLastError();
 }

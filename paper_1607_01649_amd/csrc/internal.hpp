@@ -94,10 +94,16 @@ hipError_t launch_to_bf16(const float* A, int64_t lda, int64_t m, int64_t n, uin
 int batched_scratch_doubles_per_wg();
 int batched_max_rank();
 int batched_max_dim();
+int batched_num_classes();
+int batched_num_variants();
+int batched_default_variant();
+int batched_resident_per_cu();
+// tiles: host array of batched_num_classes() variants (nullptr = default); blocks
+// whose size class is outside class_mask are skipped.
 hipError_t launch_batched(int nblk, const int* m, const int* n, const float* const* A, const int* lda, double eps,
                           int rank_cap, uint64_t seed, float* U, double* S, float* V, const int64_t* offU,
                           const int64_t* offV, int* rank, int* status, int* order, int* queue, double* scratch,
-                          int nwg, hipStream_t s);
+                          int nwg, const int* tiles, int class_mask, hipStream_t s);
 
 // misc.hip
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);

@@ -371,3 +371,64 @@ def test_batched_graph_replay_and_invalid_blocks():
         assert torch.equal(bt.S, S0) and torch.equal(bt.U, U0)
         bt.U.zero_()
         torch.cuda.synchronize()
+
+
+def _batched_outputs(bt):
+    return [t.clone() for t in (bt.U, bt.V, bt.S, bt.rank, bt.status)]
+
+
+def test_batched_tile_variants_are_bit_identical():
+    """Every MFMA tile shape consumes the k-slices in the same order, so all
+    variants reproduce the default's outputs bit for bit (blocks from 16 to
+    512 rows and columns: all four size classes, ragged tiles)."""
+    import torch
+    from paper_1607_01649_amd import Batched, RSVD_BATCHED_TILE_VARIANTS
+    host, dev = _batched_case(24, seed=5, lo=16, hi=512)
+    bt = Batched(dev, eps=1e-6, rank_cap=64, seed=11)
+    for t in (bt.U, bt.V, bt.S):       # columns past rank_b are never written
+        t.fill_(7.0)
+    bt.run()
+    torch.cuda.synchronize()
+    ref = _batched_outputs(bt)
+    assert all(int(s) in (0, 1) for s in ref[4].cpu())
+    for v in range(RSVD_BATCHED_TILE_VARIANTS):
+        for t in (bt.U, bt.V, bt.S):
+            t.fill_(7.0)
+        bt.tiles = [v, (v + 1) % RSVD_BATCHED_TILE_VARIANTS, (v + 3) % RSVD_BATCHED_TILE_VARIANTS, v]
+        bt.run()
+        torch.cuda.synchronize()
+        got = _batched_outputs(bt)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), f"tiles {bt.tiles}"
+
+
+def test_batched_autotune_picks_valid_tiles_and_keeps_results():
+    import torch
+    from paper_1607_01649_amd import Batched, RSVDError, RSVD_BATCHED_TILE_VARIANTS
+    host, dev = _batched_case(40, seed=6, lo=16, hi=400)      # classes 0..3 (400 > 384)
+    bt = Batched(dev, eps=1e-6, rank_cap=64, seed=3)
+    bt.run()
+    torch.cuda.synchronize()
+    ref = _batched_outputs(bt)
+    tiles, ms = bt.autotune()
+    assert len(tiles) == 4 and all(0 <= t < RSVD_BATCHED_TILE_VARIANTS for t in tiles)
+    mx = [max(int(m), int(n)) for m, n in zip(bt.m.cpu(), bt.n.cpu())]
+    for c in range(4):
+        present = any((x - 1) // 128 == c for x in mx)
+        assert all((t > 0) == present for t in ms[c]), (c, ms[c])
+        if present:
+            assert ms[c][tiles[c]] == min(ms[c])
+    bt.run()
+    torch.cuda.synchronize()
+    for a, b in zip(_batched_outputs(bt), ref):
+        assert torch.equal(a, b)
+    s = torch.cuda.Stream(device=device())
+    bt.U.zero_()
+    torch.cuda.synchronize()
+    bt.capture(s)
+    bt.replay(s)
+    s.synchronize()
+    assert torch.equal(bt.U, ref[0]) and torch.equal(bt.S, ref[2])
+    bt.tiles = [0, 0, 0, RSVD_BATCHED_TILE_VARIANTS]
+    with pytest.raises(RSVDError):
+        bt.run()
