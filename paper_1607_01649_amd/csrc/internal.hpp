@@ -64,6 +64,8 @@ hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, 
 // `scratch` (lp_scratch_bytes); output as launch_nn (split-K partials).
 size_t lp_scratch_bytes(int kind, int64_t K, int ncols);
 int lp_splits_used(int64_t K, int splits);
+int64_t lp_row_workgroups(int kind, int64_t rows, int ncols);
+int lp_resident_workgroups();
 hipError_t launch_nn_lp(int kind, const void* A, int64_t lda, const float* sA, int64_t s_row, int64_t s_k,
                         int64_t rows, int64_t K, const float* X, int64_t ldx, int ncols, void* scratch, float* out,
                         int64_t ldo, int64_t part_stride, int splits, hipStream_t s);

@@ -349,6 +349,30 @@ size_t lp_scratch_bytes(int kind, int64_t K, int ncols) {
   return (frag + 255) / 256 * 256 + scales;
 }
 
+// Workgroups of a low-precision product along the row axis: row blocks of 64 * LP_RB rows,
+// rounded up to whole XCD groups of 8, times the column groups.
+int64_t lp_row_workgroups(int kind, int64_t rows, int ncols) {
+  const int nb = lp_nb(kind, ncols);
+  const int groups = lp_padded_cols(kind, ncols) / (nb * 16);
+  const int64_t rblocks = (rows + 64 * LP_RB - 1) / (64 * LP_RB);
+  return (rblocks + 7) / 8 * 8 * groups;
+}
+
+// Product workgroups resident at once on the current device: compute units x workgroups per
+// unit (occupancy of the bf16 instantiation used at l <= 112); 256 if a query fails.
+int lp_resident_workgroups() {
+  static int cached = 0;
+  if (cached) return cached;
+  int dev = 0, cu = 0, per = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    cu = prop.multiProcessorCount;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, lp_nn_kernel<0, 7, LP_RB, LP_PD>, 256, 0) != hipSuccess)
+    per = 0;
+  cached = (cu > 0 && per > 0) ? cu * per : 256;
+  return cached;
+}
+
 int lp_splits_used(int64_t K, int splits) {
   if (splits < 1) splits = 1;
   int64_t kchunk = ((K + splits - 1) / splits + LKC - 1) / LKC * LKC;

@@ -65,6 +65,25 @@ int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
   return (int)std::min<int64_t>(s, 1024);
 }
 
+// Split count of a low-precision product: the fewest contraction ranges whose workgroups
+// (row_wgs per range) fill whole waves of the resident workgroups to at least 90 %.  Each
+// extra range writes one more partial panel and the reduction reads it back (at l = 110
+// on 50000 x 20000 the former choice of ~2048 workgroups wrote 0.24 GB of partials per
+// A^T product).
+int lp_pick_splits(int64_t row_wgs, int64_t K, int resident) {
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(64, K / 512));
+  int best = 1;
+  double best_eff = 0.0;
+  for (int64_t s = 1; s <= cap; ++s) {
+    const int64_t wg = row_wgs * s;
+    const int64_t waves = (wg + resident - 1) / resident;
+    const double eff = (double)wg / (double)(waves * resident);
+    if (eff >= 0.9) return (int)s;
+    if (eff > best_eff + 1e-9) { best_eff = eff; best = (int)s; }
+  }
+  return best;
+}
+
 // Contraction ranges of the Gram (multiples of 64 rows) so that pairs x ranges <= 256 workgroups, as many as fit.
 int gram_splits(int pairs, int64_t K) {
   const int64_t nchunk = (K + 63) / 64;
@@ -128,8 +147,13 @@ Layout make_layout(const rsvd_desc* d) {
   L.s_tn = nn_splits_used(d->m, L.s_tn);
   L.s_gm = nn_splits_used(d->m, L.s_gm);
   L.s_gn = nn_splits_used(d->n, L.s_gn);
-  L.s_nn16 = lp_splits_used(d->n, L.s_nn);
-  L.s_tn16 = lp_splits_used(d->m, L.s_tn);
+  {
+    const int kind_nn = d->sketch_dtype == RSVD_FP8_E4M3 ? 1 : 0;   // Y = A X products
+    const int kind_tn = d->proj_dtype == RSVD_FP8_E4M3 ? 1 : 0;     // A^T Q products
+    const int res = lp_resident_workgroups();
+    L.s_nn16 = lp_splits_used(d->n, lp_pick_splits(lp_row_workgroups(kind_nn, d->m, L.l), d->n, res));
+    L.s_tn16 = lp_splits_used(d->m, lp_pick_splits(lp_row_workgroups(kind_tn, d->n, L.l), d->m, res));
+  }
   L.ld16 = round_up(d->n, 128);
   L.ldT = round_up(d->m, 128);
   const size_t LP = (size_t)L.LP, LPM = (size_t)L.LPmax, Wd = (size_t)L.W;
