@@ -65,23 +65,14 @@ int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
   return (int)std::min<int64_t>(s, 1024);
 }
 
-// Split count of a low-precision product: the fewest contraction ranges whose workgroups
-// (row_wgs per range) fill whole waves of the resident workgroups to at least 90 %.  Each
-// extra range writes one more partial panel and the reduction reads it back (at l = 110
-// on 50000 x 20000 the former choice of ~2048 workgroups wrote 0.24 GB of partials per
-// A^T product).
+// Split count of a low-precision product: as many contraction ranges as fit in one wave of
+// the resident workgroups (at least one).  The products stream A once; one wave of long
+// workgroups beats several waves of short ones, and each extra range writes one more
+// partial panel that the reduction reads back (at l = 110 on 50000 x 20000 the former
+// choice of ~2048 workgroups wrote 0.24 GB of partials per A^T product).
 int lp_pick_splits(int64_t row_wgs, int64_t K, int resident) {
   const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(64, K / 512));
-  int best = 1;
-  double best_eff = 0.0;
-  for (int64_t s = 1; s <= cap; ++s) {
-    const int64_t wg = row_wgs * s;
-    const int64_t waves = (wg + resident - 1) / resident;
-    const double eff = (double)wg / (double)(waves * resident);
-    if (eff >= 0.9) return (int)s;
-    if (eff > best_eff + 1e-9) { best_eff = eff; best = (int)s; }
-  }
-  return best;
+  return (int)std::min<int64_t>(cap, std::max<int64_t>(1, resident / std::max<int64_t>(row_wgs, 1)));
 }
 
 // Contraction ranges of the Gram (multiples of 64 rows) so that pairs x ranges <= 256 workgroups, as many as fit.
@@ -337,19 +328,20 @@ template <typename T> struct Path {
       if constexpr (sizeof(T) == 4) {
         S = L.s_nn16;
         HIP_TRY(launch_nn_lp(0, P.at<uint16_t>(L.a16), L.ld16, nullptr, 0, 0, m, n, X, L.ldn, nc, P.at<char>(L.xq),
-                             part, L.ldm, (int64_t)LPc * L.ldm, S, st));
+                             S == 1 ? Y : part, L.ldm, (int64_t)LPc * L.ldm, S, st));
       }
     } else if (dt == RSVD_FP8_E4M3) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_nn16;
         HIP_TRY(launch_nn_lp(1, P.at<uint8_t>(L.a8), L.ld16, P.at<float>(L.s8), L.ld16 / 128, 1, m, n, X, L.ldn, nc,
-                             P.at<char>(L.xq), part, L.ldm, (int64_t)LPc * L.ldm, S, st));
+                             P.at<char>(L.xq), S == 1 ? Y : part, L.ldm, (int64_t)LPc * L.ldm, S, st));
       }
     } else {
       HIP_TRY((launch_nn<T, T, T, T>(A, lda, m, n, X, L.ldn, nc, part, L.ldm, (int64_t)LPc * L.ldm, S, st)));
     }
     gemm_end(ev);
-    HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LPc * L.ldm, L.ldm, m, nc, Y, L.ldm, st)));
+    const bool direct = S == 1 && (dt == RSVD_BF16 || dt == RSVD_FP8_E4M3) && sizeof(T) == 4;   // written in place
+    if (!direct) HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LPc * L.ldm, L.ldm, m, nc, Y, L.ldm, st)));
     return RSVD_OK;
   }
 
@@ -364,20 +356,21 @@ template <typename T> struct Path {
       if constexpr (sizeof(T) == 4) {
         S = L.s_tn16;
         HIP_TRY(launch_nn_lp(0, P.at<uint16_t>(L.a16t), L.ldT, nullptr, 0, 0, n, m, Qp, L.ldm, nc, P.at<char>(L.xq),
-                             part, L.ldn, (int64_t)LPc * L.ldn, S, st));
+                             S == 1 ? Z : part, L.ldn, (int64_t)LPc * L.ldn, S, st));
       }
     } else if (dt == RSVD_FP8_E4M3) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_tn16;
         HIP_TRY(launch_nn_lp(1, P.at<uint8_t>(L.a8t), L.ldT, P.at<float>(L.s8), 1, L.ld16 / 128, n, m, Qp, L.ldm, nc,
-                             P.at<char>(L.xq), part, L.ldn, (int64_t)LPc * L.ldn, S, st));
+                             P.at<char>(L.xq), S == 1 ? Z : part, L.ldn, (int64_t)LPc * L.ldn, S, st));
       }
     } else {
       HIP_TRY(
           (launch_tn<T, T, T, T>(A, lda, m, n, Qp, L.ldm, nc, part, L.ldn, (int64_t)LPc * L.ldn, S, false, st)));
     }
     gemm_end(ev);
-    HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LPc * L.ldn, L.ldn, n, nc, Z, L.ldn, st)));
+    const bool direct = S == 1 && (dt == RSVD_BF16 || dt == RSVD_FP8_E4M3) && sizeof(T) == 4;   // written in place
+    if (!direct) HIP_TRY((launch_reduce<T, T>(part, S, (int64_t)LPc * L.ldn, L.ldn, n, nc, Z, L.ldn, st)));
     return RSVD_OK;
   }
 
