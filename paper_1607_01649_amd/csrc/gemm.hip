@@ -24,6 +24,9 @@
 //     read once per group; the K range is split over grid.y and partial
 //     results are summed afterwards in a fixed order (deterministic, no
 //     atomics).
+#include <algorithm>
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace rsvd {
@@ -274,11 +277,134 @@ int nn_splits_used(int64_t K, int splits) {
   return used < 1 ? 1 : used;
 }
 
+// Short contractions (K <= 128, ncols <= 128, FP32): out[c*ldo + j] = sum_{i < K} A[i*lda + j] * P(i, c),
+// as tn_kernel with one range, for the apply X <- X R^-1 of CholeskyQR (K = l).  The whole of P
+// goes to LDS once per workgroup as 128 rows (rows K .. 127 zero, so every task runs the same 32
+// MFMA steps with no branches; pitch 144 floats so that the four k-rows a B fragment reads fall on
+// different banks); a wave takes 16-row tasks (all columns at once) and loads the task's A slice
+// in full before its MFMAs, prefetching the next task's slice meanwhile.  One workgroup per
+// compute unit: more workgroups only repeat the staging of P (measured: 512 or 1024 workgroups
+// of 256 threads, or 256 of 512 threads, are all slower at l = 110).
+// Every A load is unconditional: rows past N are clamped (their outputs are not stored) and k past
+// K is clamped (it meets a zero row of P).
+constexpr int kApplyPitch = 144;
+constexpr int kApplyKMax = 128;
+constexpr int kApplyThreads = 256;   // 4 waves; one workgroup per compute unit stages P once
+
+template <int NCT>
+__global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float* __restrict__ A, int64_t lda, int K, int64_t N,
+                                                          const float* __restrict__ P, int64_t ldp, int ncols,
+                                                          float* __restrict__ out, int64_t ldo, bool vec_out) {
+  constexpr int KS = kApplyKMax / 4;   // MFMA k-steps of a task at most
+  __shared__ float ps[kApplyKMax * kApplyPitch];
+  typedef Mma<float> M;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  {
+    // all loads first (unconditional, clamped indices), then the LDS stores: a guarded load per
+    // iteration would wait for each load in turn.  Rows K .. 127 are zeroed by a 0/1 factor
+    // (P is finite), columns past ncols are never read by a stored output.
+    constexpr int PER = kApplyKMax * kApplyKMax / kApplyThreads;
+    constexpr int total = kApplyKMax * NCT * 16;   // all 128 rows: those past K are zero
+    float v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = min(tid + kApplyThreads * u, total - 1);   // consecutive threads: consecutive k of a column
+      const int c = t / kApplyKMax, i = t - c * kApplyKMax;
+      v[u] = P[(uint32_t)(min(c, ncols - 1) * (uint32_t)ldp + min(i, K - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = tid + kApplyThreads * u;
+      const int c = t / kApplyKMax, i = t - c * kApplyKMax;
+      if (t < total) ps[i * kApplyPitch + c] = v[u] * (i < K ? 1.0f : 0.0f);
+    }
+  }
+  __syncthreads();
+  const int64_t ntask = (N + 15) / 16;
+  const int64_t stride = (int64_t)gridDim.x * (kApplyThreads / 64);
+  int64_t task = (int64_t)blockIdx.x * (kApplyThreads / 64) + wave;
+  float a[KS];
+  // 32-bit offsets from the scalar base (K * lda < 2^32 is checked at launch): one VGPR per address
+  auto load = [&](int64_t tk, float(&av)[KS]) {
+    const uint32_t j = (uint32_t)min(tk * 16 + li, N - 1);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const uint32_t i = (uint32_t)min(4 * s + g, K - 1);
+      av[s] = A[i * (uint32_t)lda + j];
+    }
+  };
+  auto compute = [&](int64_t tk, const float(&av)[KS]) {
+    typename M::acc acc[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[ct] = M::zero();
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {   // every step: rows past K of P are zero in LDS (no branches)
+      const float* pr = ps + (4 * s + g) * kApplyPitch + li;
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) acc[ct] = M::op(av[s], pr[16 * ct], acc[ct]);
+    }
+    const int64_t j = tk * 16 + 4 * g;   // rows j .. j+3 <-> accumulator elements 0..3
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int c = 16 * ct + li;
+      if (c >= ncols) continue;
+      float* p = out + (int64_t)c * ldo + j;
+      if (vec_out && j + 4 <= N) {
+        *reinterpret_cast<float4*>(p) = make_float4(acc[ct][0], acc[ct][1], acc[ct][2], acc[ct][3]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (j + r < N) p[r] = acc[ct][r];
+      }
+    }
+  };
+  // two tasks per iteration with fixed buffers: the next task's slice loads during the products
+  float a2[KS];
+  if (task < ntask) load(task, a);
+  for (; task < ntask; task += 2 * stride) {
+    const int64_t t1 = task + stride;
+    if (t1 < ntask) load(t1, a2);
+    compute(task, a);
+    if (t1 >= ntask) break;
+    if (t1 + stride < ntask) load(t1 + stride, a);
+    compute(t1, a2);
+  }
+}
+
+hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, const float* P, int64_t ldp, int ncols,
+                              float* out, int64_t ldo, hipStream_t s) {
+  const int nct = (ncols + 15) / 16;
+  const int64_t ntask = (N + 15) / 16;
+  const int wpg = kApplyThreads / 64;
+  const unsigned grid = (unsigned)std::min<int64_t>((ntask + wpg - 1) / wpg, 256);   // each workgroup stages P once
+  const bool vec = (ldo % 4 == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
+  switch (nct) {
+#define RSVD_APPLY_CASE(N_)                                                                                       \
+  case N_:                                                                                                        \
+    hipLaunchKernelGGL((apply_small_kernel<N_>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, P, ldp, ncols, out, \
+                       ldo, vec);                                                                                 \
+    break;
+    RSVD_APPLY_CASE(1) RSVD_APPLY_CASE(2) RSVD_APPLY_CASE(3) RSVD_APPLY_CASE(4)
+    RSVD_APPLY_CASE(5) RSVD_APPLY_CASE(6) RSVD_APPLY_CASE(7) RSVD_APPLY_CASE(8)
+#undef RSVD_APPLY_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename TA, typename TP, typename TC, typename TO>
 hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols, TO* out,
                      int64_t ldo, int64_t part_stride, int splits, bool out_rowmajor, hipStream_t s) {
   if (N <= 0 || ncols <= 0) return hipSuccess;
   if (splits < 1 || out_rowmajor) splits = 1;
+  if constexpr (std::is_same<TA, float>::value && std::is_same<TP, float>::value && std::is_same<TO, float>::value &&
+                std::is_same<TC, float>::value) {
+    if (!out_rowmajor && splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
+        (int64_t)ncols * ldp < (int64_t(1) << 32))
+      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, s);
+  }
   int64_t kchunk = ((K + splits - 1) / splits + KC - 1) / KC * KC;
   if (kchunk < KC) kchunk = KC;
   int used = (int)((K + kchunk - 1) / kchunk);
