@@ -244,18 +244,42 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(const double* 
         for (int k = 0; k < 4; ++k) Ufull[(a0 + i) * LP + b0 + k] = U[i][k];
     }
     __syncthreads();
-    for (int idx = tid; idx < LP * LP; idx += kCholThreads) {
-      int a = idx / LP, b = idx - (idx / LP) * LP;
-      double v;
-      if (a >= l || b >= l) v = (a == b) ? 1.0 : 0.0;
-      else if (b < a || rsd[a] == 0.0) v = 0.0;
-      else if (!r_prev) v = Ufull[a * LP + b] * rsd[a];
-      else {
-        v = 0.0;
-        for (int k = a; k <= b; ++k) v += Ufull[a * LP + k] * r_prev[k * LP + b];
-        v *= rsd[a];
+    // R = D^-1/2 U, or D^-1/2 U R_prev when the previous pass's factor is given (the product
+    // of the two passes of CholeskyQR2): each thread its own 4 x 4 block; k runs over
+    // [a0, b0+3], the terms outside [a, b] being exact zeros (U masked left of its diagonal,
+    // R_prev upper triangular with identity padding).
+    if (a0 < LP && b0 < LP) {
+      double acc[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[i][k] = 0.0;
+      if (r_prev) {
+        const int kend = min(b0 + 3, l - 1);
+#pragma unroll 4
+        for (int k = a0; k <= kend; ++k) {
+          const double2 p01 = *reinterpret_cast<const double2*>(r_prev + (int64_t)k * LP + b0);
+          const double2 p23 = *reinterpret_cast<const double2*>(r_prev + (int64_t)k * LP + b0 + 2);
+          const double p[4] = {p01.x, p01.y, p23.x, p23.y};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double u = (k >= a0 + i) ? Ufull[(a0 + i) * LP + k] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] += u * p[j];
+          }
+        }
       }
-      r_out[idx] = v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int a = a0 + i, b = b0 + j;
+          double v;
+          if (a >= l || b >= l) v = (a == b) ? 1.0 : 0.0;
+          else if (b < a || rsd[a] == 0.0) v = 0.0;
+          else v = (r_prev ? acc[i][j] : Ufull[a * LP + b]) * rsd[a];
+          r_out[a * LP + b] = v;
+        }
     }
   }
 }
