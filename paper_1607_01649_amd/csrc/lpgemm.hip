@@ -73,8 +73,39 @@ static int lp_padded_cols(int kind, int ncols) {
 
 // ------------------------------------------------------------------ thin-operand conversion
 
+// The 32 values X(col, kb .. kb+31) of one thread, zero past K and past ncols.  VEC (ldx and K multiples
+// of 4, X 16-byte aligned): eight 16-byte loads at clamped addresses, each inside the first K entries of an
+// existing column, then the out-of-range entries masked; otherwise guarded scalar loads (which the compiler
+// waits for one at a time).
+template <bool VEC>
+__device__ __forceinline__ void load_seg32(const float* __restrict__ X, int64_t ldx, int64_t K, int ncols, int col,
+                                           int64_t kb, float (&v)[32]) {
+  if constexpr (VEC) {
+    const float* base = X + (int64_t)min(col, ncols - 1) * ldx;
+    float4 q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = *reinterpret_cast<const float4*>(base + min(kb + 4 * u, K - 4));
+    const bool cok = col < ncols;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t k = kb + 4 * u;
+      v[4 * u + 0] = (cok && k + 0 < K) ? q[u].x : 0.f;
+      v[4 * u + 1] = (cok && k + 1 < K) ? q[u].y : 0.f;
+      v[4 * u + 2] = (cok && k + 2 < K) ? q[u].z : 0.f;
+      v[4 * u + 3] = (cok && k + 3 < K) ? q[u].w : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 32; ++e) {
+      const int64_t k = kb + e;
+      v[e] = (col < ncols && k < K) ? X[(int64_t)col * ldx + k] : 0.f;
+    }
+  }
+}
+
 // One thread per (chunk c, column block j, column cli, lane group gg): the 32 values X(col, k), col = 16 j + cli,
 // k = 128 c + 32 gg + e, zero past K and past ncols.  bf16: four 16-byte pieces (e = 8 t ..) to block t.
+template <bool VEC>
 __global__ void panel_to_bf16_frag_kernel(const float* __restrict__ X, int64_t ldx, int64_t K, int ncols, int ncb,
                                           int64_t nthreads, uint8_t* __restrict__ Xf) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -85,14 +116,13 @@ __global__ void panel_to_bf16_frag_kernel(const float* __restrict__ X, int64_t l
   const int col = 16 * j + cli;
   const int64_t kb = c * LKC + 32 * gg;
   uint8_t* blk = Xf + (c * ncb + j) * (int64_t)(4 * 1024) + 16 * (cli + 16 * gg);
+  float v[32];
+  load_seg32<VEC>(X, ldx, K, ncols, col, kb, v);
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
     uint16_t b[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t k = kb + 8 * tt + e;
-      b[e] = (col < ncols && k < K) ? f32_to_bf16_rne(X[(int64_t)col * ldx + k]) : (uint16_t)0;
-    }
+    for (int e = 0; e < 8; ++e) b[e] = f32_to_bf16_rne(v[8 * tt + e]);
     *reinterpret_cast<u32x4*>(blk + tt * 1024) =
         u32x4{pack2(b[0], b[1]), pack2(b[2], b[3]), pack2(b[4], b[5]), pack2(b[6], b[7])};
   }
@@ -100,6 +130,7 @@ __global__ void panel_to_bf16_frag_kernel(const float* __restrict__ X, int64_t l
 
 // As above for E4M3: the four threads of a 128-row segment share its scale (amax by shuffles); two 16-byte
 // pieces (e = 16 h ..) to block h; sXf[(c * ncb + j) * 16 + cli] = 2^e.
+template <bool VEC>
 __global__ void panel_to_fp8_frag_kernel(const float* __restrict__ X, int64_t ldx, int64_t K, int ncols, int ncb,
                                          int64_t nthreads, uint8_t* __restrict__ Xf, float* __restrict__ sXf) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -110,13 +141,10 @@ __global__ void panel_to_fp8_frag_kernel(const float* __restrict__ X, int64_t ld
   const int col = 16 * j + cli;
   const int64_t kb = c * LKC + 32 * gg;
   float v[32];
+  load_seg32<VEC>(X, ldx, K, ncols, ok ? col : ncols, kb, v);   // a thread past the end loads zeros
   float mx = 0.f;
 #pragma unroll
-  for (int e = 0; e < 32; ++e) {
-    const int64_t k = kb + e;
-    v[e] = (ok && col < ncols && k < K) ? X[(int64_t)col * ldx + k] : 0.f;
-    mx = fmaxf(mx, fabsf(v[e]));
-  }
+  for (int e = 0; e < 32; ++e) mx = fmaxf(mx, fabsf(v[e]));
   mx = fmaxf(mx, __shfl_xor(mx, 1, 4));
   mx = fmaxf(mx, __shfl_xor(mx, 2, 4));
   if (!ok) return;
@@ -399,11 +427,22 @@ hipError_t launch_nn_lp(int kind, const void* A, int64_t lda, const float* sA, i
   float* sXf = kind == 1 ? reinterpret_cast<float*>(Xf + (frag + 255) / 256 * 256) : nullptr;
   const int64_t nthr = nchunk * ncb * 64;
   const unsigned cgrid = (unsigned)((nthr + 255) / 256);
-  if (kind == 0)
-    hipLaunchKernelGGL(panel_to_bf16_frag_kernel, dim3(cgrid), dim3(256), 0, s, X, ldx, K, ncols, ncb, nthr, Xf);
-  else
-    hipLaunchKernelGGL(panel_to_fp8_frag_kernel, dim3(cgrid), dim3(256), 0, s, X, ldx, K, ncols, ncb, nthr, Xf,
-                       sXf);
+  const bool xvec = ldx % 4 == 0 && K % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+  if (kind == 0) {
+    if (xvec)
+      hipLaunchKernelGGL(panel_to_bf16_frag_kernel<true>, dim3(cgrid), dim3(256), 0, s, X, ldx, K, ncols, ncb, nthr,
+                         Xf);
+    else
+      hipLaunchKernelGGL(panel_to_bf16_frag_kernel<false>, dim3(cgrid), dim3(256), 0, s, X, ldx, K, ncols, ncb, nthr,
+                         Xf);
+  } else {
+    if (xvec)
+      hipLaunchKernelGGL(panel_to_fp8_frag_kernel<true>, dim3(cgrid), dim3(256), 0, s, X, ldx, K, ncols, ncb, nthr,
+                         Xf, sXf);
+    else
+      hipLaunchKernelGGL(panel_to_fp8_frag_kernel<false>, dim3(cgrid), dim3(256), 0, s, X, ldx, K, ncols, ncb, nthr,
+                         Xf, sXf);
+  }
   if (splits < 1) splits = 1;
   int64_t kchunk = ((K + splits - 1) / splits + LKC - 1) / LKC * LKC;
   if (kchunk < LKC) kchunk = LKC;
