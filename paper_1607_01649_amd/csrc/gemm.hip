@@ -213,11 +213,17 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TP* __restrict__ part
   const TP* p = part + (int64_t)s0 * pstride + c * ldp + r;
   TO* o = out + blockIdx.y * ostride + c * ldo + r;
   if (r + 4 <= rows) {
+    // eight partials loaded ahead of their (in-order) additions, so the loads overlap; past the last
+    // partial a batch re-reads it (clamped index) and adds zero
     V4<TP> s = v4_load(p);
-    for (int k = 1; k < cnt; ++k) {
-      V4<TP> v = v4_load(p + k * pstride);
+    for (int k = 1; k < cnt; k += 8) {
+      V4<TP> v[8];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) s.x[e] += v.x[e];
+      for (int u = 0; u < 8; ++u) v[u] = v4_load(p + (int64_t)min(k + u, cnt - 1) * pstride);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s.x[e] += (k + u < cnt) ? v[u].x[e] : TP(0);
     }
     v4_store(o, v4_cast<TO>(s));
   } else {

@@ -210,6 +210,130 @@ __global__ __launch_bounds__(256) void gram_kernel(const TI* __restrict__ Y, int
     }
 }
 
+// Single tile (nc <= 128): only the blocks on and above the diagonal, 28 of 49 for seven column blocks,
+// dealt evenly to the waves (block b of the row-major upper triangle to wave b / PER).  The chunk's column
+// blocks are all staged in LDS, one fragment per (column block, 16-row group) in the layout of the B
+// operand, and the same fragment serves as the A operand: the FP64 MFMA then places column
+// 16 rb + 4 e + g (not 16 rb + 4 g + e) in element e of lane group g, which the stores follow.
+template <typename TI, int NCB>
+__global__ __launch_bounds__(256) void gram_sym_kernel(const TI* __restrict__ Y, int64_t ld, int64_t K, int nc,
+                                                       double* __restrict__ out, int64_t ldo, int64_t part_stride,
+                                                       int64_t kchunk) {
+  typedef GramFmt<TI> F;
+  typedef typename F::V V;
+  constexpr int KC = F::KC;
+  constexpr int NKQ = KC / 16;
+  constexpr int NF = NCB * NKQ;
+  constexpr int NFW = (NF + 3) / 4;
+  constexpr int NBLK = NCB * (NCB + 1) / 2;
+  constexpr int PER = (NBLK + 3) / 4;
+  __shared__ V xs0[NF][64], xs1[NF][64];
+  typedef Mma<double> M;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, li = lane & 15;
+  const int split = blockIdx.y;
+  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kend = min(K, kbeg + kchunk);
+  const int64_t nck = (kend - kbeg + KC - 1) / KC;
+
+  // staged fragment blocks (column block cb, row group kq): wave w moves blocks w, w + 4, ...
+  const TI* pb[NFW];
+  int fbw[NFW];
+#pragma unroll
+  for (int u = 0; u < NFW; ++u) {
+    const int fb = min(wave + 4 * u, NF - 1);   // waves past the last block repeat it (same data, same slot)
+    fbw[u] = fb;
+    const int cb = fb / NKQ, kq = fb - (fb / NKQ) * NKQ;
+    pb[u] = Y + (int64_t)min(16 * cb + li, nc - 1) * ld + 16 * kq + 4 * g;
+  }
+  // this wave's blocks (rb <= cb); a wave short of PER blocks repeats its last one and does not store it
+  int rbj[PER], cbj[PER];
+  bool okj[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    int b = wave * PER + j;
+    okj[j] = b < NBLK;
+    b = min(b, NBLK - 1);
+    int rb = 0;
+    while (b >= NCB - rb) { b -= NCB - rb; ++rb; }
+    rbj[j] = rb;
+    cbj[j] = rb + b;
+  }
+
+  auto kc = [&](int64_t i) { return kbeg + (i < nck ? i : nck - 1) * KC; };
+  auto load = [&](int64_t k0, V (&b)[NFW]) {
+    const bool tail = k0 + KC > K;
+#pragma unroll
+    for (int u = 0; u < NFW; ++u) {
+      const int kq = fbw[u] % NKQ;
+      const int64_t k = k0 + 16 * kq + 4 * g;
+      V v = gload4<TI>(pb[u] + min(k0, ld - KC));
+      b[u] = tail ? mask_rows(v, k, K) : v;
+    }
+  };
+  auto store_b = [&](const V (&b)[NFW], V (&xd)[NF][64]) {
+#pragma unroll
+    for (int u = 0; u < NFW; ++u) xd[fbw[u]][lane] = b[u];
+  };
+
+  typename M::acc acc[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) acc[j] = M::zero();
+
+  auto compute = [&](const V (&xb)[NF][64]) {
+#pragma unroll
+    for (int kq = 0; kq < NKQ; ++kq) {
+      V a[PER], bb[PER];
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        a[j] = xb[rbj[j] * NKQ + kq][lane];
+        bb[j] = xb[cbj[j] * NKQ + kq][lane];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int j = 0; j < PER; ++j) acc[j] = M::op(F::get(a[j], t), F::get(bb[j], t), acc[j]);
+    }
+  };
+
+  V b0[NFW], b1[NFW];
+  auto step = [&](int64_t i, V (&bnext)[NFW], const V (&xc)[NF][64], V (&xn)[NF][64]) {
+    load(kc(i + 1), bnext);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(xc);
+    __builtin_amdgcn_sched_barrier(0);
+    store_b(bnext, xn);
+    lds_barrier_g();
+  };
+  load(kc(0), b0);
+  store_b(b0, xs0);
+  lds_barrier_g();
+  int64_t i = 0;
+  for (; i + 2 <= nck; i += 2) {
+    step(i, b1, xs0, xs1);
+    step(i + 1, b0, xs1, xs0);
+  }
+  if (i < nck) step(i, b1, xs0, xs1);
+
+  double* o = out + (int64_t)split * part_stride;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    if (!okj[j]) continue;
+    const int rb = rbj[j], cb = cbj[j];
+    const int c = 16 * cb + li;
+    if (c >= nc) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * rb + 4 * e + g;
+      if (r < nc) {
+        o[(int64_t)c * ldo + r] = acc[j][e];
+        if (rb != cb) o[(int64_t)r * ldo + c] = acc[j][e];   // the mirror block
+      }
+    }
+  }
+}
+
 // Partials of G = Y^T Y (nc x nc, FP64) for `splits` contraction ranges of K rows; Y[c*ld + i] with ld >= K a
 // multiple of 64 (so every chunk of rows lies inside the allocation), 16-byte aligned.  out[s*part_stride + c*ldo + r] for r, c < nc.  `splits` is
 // a count normalised by nn_splits_used (ranges in multiples of 64 rows), so exactly `splits` partials are written.
@@ -232,6 +356,24 @@ hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, 
     hipLaunchKernelGGL((gram_kernel<TI, N>), grid, dim3(256), 0, s, Y, ld, K, nc, ntile, out, ldo, part_stride, \
                        kchunk);                                                                            \
     break;
+  if (ntile == 1) {
+#define RSVD_GRAM_SYM_CASE(N)                                                                                    \
+  case N:                                                                                                      \
+    hipLaunchKernelGGL((gram_sym_kernel<TI, N>), grid, dim3(256), 0, s, Y, ld, K, nc, out, ldo, part_stride, kchunk); \
+    break;
+    switch (ncb) {
+      RSVD_GRAM_SYM_CASE(1)
+      RSVD_GRAM_SYM_CASE(2)
+      RSVD_GRAM_SYM_CASE(3)
+      RSVD_GRAM_SYM_CASE(4)
+      RSVD_GRAM_SYM_CASE(5)
+      RSVD_GRAM_SYM_CASE(6)
+      RSVD_GRAM_SYM_CASE(7)
+      default: RSVD_GRAM_SYM_CASE(8)
+    }
+#undef RSVD_GRAM_SYM_CASE
+    return hipGetLastError();
+  }
   switch (ncb) {
     RSVD_GRAM_CASE(1)
     RSVD_GRAM_CASE(2)

@@ -180,6 +180,8 @@ BF16_CASES = [
     (3000, 1500, 300, 0.5, 20, 10, 2, "bf16", "bf16"),
     (1237, 901, 200, 1.0, 12, 8, 1, "bf16", "f32"),
     (2048, 1024, 256, 0.5, 50, 14, 2, "bf16", "bf16"),
+    # fewer row blocks than resident workgroups: both products split the contraction
+    (20000, 2048, 256, 0.5, 96, 14, 1, "bf16", "bf16"),
 ]
 
 
