@@ -297,7 +297,9 @@ constexpr int kApplyPitch = 144;
 constexpr int kApplyKMax = 128;
 constexpr int kApplyThreads = 256;   // 4 waves; one workgroup per compute unit stages P once
 
-template <int NCT>
+// TRI: P is upper triangular (P(i, c) = 0 for i > c, as R^-1 is), so column tile ct takes only the
+// k-steps s < 4 (ct + 1); the loops are unrolled, so the skip costs no branch.
+template <int NCT, bool TRI>
 __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float* __restrict__ A, int64_t lda, int K, int64_t N,
                                                           const float* __restrict__ P, int64_t ldp, int ncols,
                                                           float* __restrict__ out, int64_t ldo, bool vec_out) {
@@ -349,7 +351,8 @@ __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float*
     for (int s = 0; s < KS; ++s) {   // every step: rows past K of P are zero in LDS (no branches)
       const float* pr = ps + (4 * s + g) * kApplyPitch + li;
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) acc[ct] = M::op(av[s], pr[16 * ct], acc[ct]);
+      for (int ct = 0; ct < NCT; ++ct)
+        if (!TRI || s < 4 * (ct + 1)) acc[ct] = M::op(av[s], pr[16 * ct], acc[ct]);
     }
     const int64_t j = tk * 16 + 4 * g;   // rows j .. j+3 <-> accumulator elements 0..3
 #pragma unroll
@@ -380,7 +383,7 @@ __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float*
 }
 
 hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, const float* P, int64_t ldp, int ncols,
-                              float* out, int64_t ldo, hipStream_t s) {
+                              float* out, int64_t ldo, bool tri, hipStream_t s) {
   const int nct = (ncols + 15) / 16;
   const int64_t ntask = (N + 15) / 16;
   const int wpg = kApplyThreads / 64;
@@ -389,8 +392,12 @@ hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, con
   switch (nct) {
 #define RSVD_APPLY_CASE(N_)                                                                                       \
   case N_:                                                                                                        \
-    hipLaunchKernelGGL((apply_small_kernel<N_>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, P, ldp, ncols, out, \
-                       ldo, vec);                                                                                 \
+    if (tri)                                                                                                      \
+      hipLaunchKernelGGL((apply_small_kernel<N_, true>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, P, ldp, \
+                         ncols, out, ldo, vec);                                                                   \
+    else                                                                                                          \
+      hipLaunchKernelGGL((apply_small_kernel<N_, false>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, P, ldp, \
+                         ncols, out, ldo, vec);                                                                   \
     break;
     RSVD_APPLY_CASE(1) RSVD_APPLY_CASE(2) RSVD_APPLY_CASE(3) RSVD_APPLY_CASE(4)
     RSVD_APPLY_CASE(5) RSVD_APPLY_CASE(6) RSVD_APPLY_CASE(7) RSVD_APPLY_CASE(8)
@@ -409,7 +416,7 @@ hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P
                 std::is_same<TC, float>::value) {
     if (!out_rowmajor && splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
         (int64_t)ncols * ldp < (int64_t(1) << 32))
-      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, s);
+      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, false, s);
   }
   int64_t kchunk = ((K + splits - 1) / splits + KC - 1) / KC * KC;
   if (kchunk < KC) kchunk = KC;
@@ -463,6 +470,17 @@ hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce<TP, TP>(tmp, ng, pstride, ldp, rows, ncols, out, ldo, s);
+}
+
+// out = A P for an upper-triangular P (the apply X <- X R^-1 of CholeskyQR): the triangular short-contraction
+// kernel where it applies, otherwise the general product.
+hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const float* P, int64_t ldp,
+                              int ncols, float* out, int64_t ldo, hipStream_t s) {
+  if (N <= 0 || ncols <= 0) return hipSuccess;
+  if (K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
+      (int64_t)ncols * ldp < (int64_t(1) << 32))
+    return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, true, s);
+  return launch_tn<float, float, float, float>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, s);
 }
 
 // Explicit instantiations used by the host orchestration.

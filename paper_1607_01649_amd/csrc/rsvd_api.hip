@@ -300,6 +300,14 @@ template <typename T> struct Path {
     return RSVD_OK;
   }
 
+  // out = X R^-1 (R^-1 upper triangular, nc x nc at leading dimension LPc).
+  hipError_t apply_rinv(const T* X, int64_t ld, int64_t rows, int nc, const T* rinv, int LPc, T* out) {
+    if constexpr (sizeof(T) == 4)
+      return launch_apply_upper(X, ld, nc, rows, rinv, LPc, nc, out, ld, st);
+    else
+      return launch_tn<T, T, T, T>(X, ld, nc, rows, rinv, LPc, nc, out, ld, 0, 1, false, st);
+  }
+
   // out = orth(X) for an nc-column panel: CholeskyQR2 (two passes of G = X^T X = R^T R, X <- X R^-1).
   rsvd_status orth(const T* X, int64_t ld, int64_t rows, int nc, int splits, T* out) {
     const int LPc = lp16(nc);
@@ -310,10 +318,10 @@ template <typename T> struct Path {
     double* scr = P.at<double>(L.scr_chol);
     RS_TRY(gram(X, ld, rows, nc, splits, G));
     HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st));
-    HIP_TRY((launch_tn<T, T, T, T>(X, ld, nc, rows, rinv, LPc, nc, tmp, ld, 0, 1, false, st)));
+    HIP_TRY(apply_rinv(X, ld, rows, nc, rinv, LPc, tmp));
     RS_TRY(gram(tmp, ld, rows, nc, splits, G));
     HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st));
-    HIP_TRY((launch_tn<T, T, T, T>(tmp, ld, nc, rows, rinv, LPc, nc, out, ld, 0, 1, false, st)));
+    HIP_TRY(apply_rinv(tmp, ld, rows, nc, rinv, LPc, out));
     return RSVD_OK;
   }
 
