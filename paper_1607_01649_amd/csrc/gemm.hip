@@ -283,8 +283,9 @@ int nn_splits_used(int64_t K, int splits) {
   return used < 1 ? 1 : used;
 }
 
-// Short contractions (K <= 128, ncols <= 128, FP32): out[c*ldo + j] = sum_{i < K} A[i*lda + j] * P(i, c),
-// as tn_kernel with one range, for the apply X <- X R^-1 of CholeskyQR (K = l).  The whole of P
+// Short contractions (K <= 128, ncols <= 128, FP32): out[c*ldo + j] (or out[j*ldo + c], row-major) =
+// sum_{i < K} A[i*lda + j] * P(i, c), as tn_kernel with one range, for the apply X <- X R^-1 of
+// CholeskyQR and the lifts U = Q U_hat, V = B^T V_hat (K = l).  The whole of P
 // goes to LDS once per workgroup as 128 rows (rows K .. 127 zero, so every task runs the same 32
 // MFMA steps with no branches; pitch 144 floats so that the four k-rows a B fragment reads fall on
 // different banks); a wave takes 16-row tasks (all columns at once) and loads the task's A slice
@@ -299,13 +300,16 @@ constexpr int kApplyThreads = 256;   // 4 waves; one workgroup per compute unit 
 
 // TRI: P is upper triangular (P(i, c) = 0 for i > c, as R^-1 is), so column tile ct takes only the
 // k-steps s < 4 (ct + 1); the loops are unrolled, so the skip costs no branch.
-template <int NCT, bool TRI>
+// TP = double: P, the accumulation and the output in FP64 (A converted exactly); the FP64 MFMA puts
+// A lane arow(m) at accumulator row m, so a lane loads row arow(li) and the stores are as for FP32.
+template <typename TP, int NCT, bool TRI>
 __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float* __restrict__ A, int64_t lda, int K, int64_t N,
-                                                          const float* __restrict__ P, int64_t ldp, int ncols,
-                                                          float* __restrict__ out, int64_t ldo, bool vec_out) {
+                                                          const TP* __restrict__ P, int64_t ldp, int ncols,
+                                                          TP* __restrict__ out, int64_t ldo, bool vec_out,
+                                                          bool rowmajor) {
   constexpr int KS = kApplyKMax / 4;   // MFMA k-steps of a task at most
-  __shared__ float ps[kApplyKMax * kApplyPitch];
-  typedef Mma<float> M;
+  __shared__ TP ps[kApplyKMax * kApplyPitch];
+  typedef Mma<TP> M;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
@@ -315,7 +319,7 @@ __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float*
     // (P is finite), columns past ncols are never read by a stored output.
     constexpr int PER = kApplyKMax * kApplyKMax / kApplyThreads;
     constexpr int total = kApplyKMax * NCT * 16;   // all 128 rows: those past K are zero
-    float v[PER];
+    TP v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int t = min(tid + kApplyThreads * u, total - 1);   // consecutive threads: consecutive k of a column
@@ -326,30 +330,31 @@ __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float*
     for (int u = 0; u < PER; ++u) {
       const int t = tid + kApplyThreads * u;
       const int c = t / kApplyKMax, i = t - c * kApplyKMax;
-      if (t < total) ps[i * kApplyPitch + c] = v[u] * (i < K ? 1.0f : 0.0f);
+      if (t < total) ps[i * kApplyPitch + c] = v[u] * (i < K ? TP(1) : TP(0));
     }
   }
   __syncthreads();
   const int64_t ntask = (N + 15) / 16;
   const int64_t stride = (int64_t)gridDim.x * (kApplyThreads / 64);
   int64_t task = (int64_t)blockIdx.x * (kApplyThreads / 64) + wave;
-  float a[KS];
+  TP a[KS];
   // 32-bit offsets from the scalar base (K * lda < 2^32 is checked at launch): one VGPR per address
-  auto load = [&](int64_t tk, float(&av)[KS]) {
-    const uint32_t j = (uint32_t)min(tk * 16 + li, N - 1);
+  const int lrow = sizeof(TP) == 8 ? Mma<double>::arow(li) : li;
+  auto load = [&](int64_t tk, TP(&av)[KS]) {
+    const uint32_t j = (uint32_t)min(tk * 16 + lrow, N - 1);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const uint32_t i = (uint32_t)min(4 * s + g, K - 1);
-      av[s] = A[i * (uint32_t)lda + j];
+      av[s] = static_cast<TP>(A[i * (uint32_t)lda + j]);
     }
   };
-  auto compute = [&](int64_t tk, const float(&av)[KS]) {
+  auto compute = [&](int64_t tk, const TP(&av)[KS]) {
     typename M::acc acc[NCT];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) acc[ct] = M::zero();
 #pragma unroll
     for (int s = 0; s < KS; ++s) {   // every step: rows past K of P are zero in LDS (no branches)
-      const float* pr = ps + (4 * s + g) * kApplyPitch + li;
+      const TP* pr = ps + (4 * s + g) * kApplyPitch + li;
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct)
         if (!TRI || s < 4 * (ct + 1)) acc[ct] = M::op(av[s], pr[16 * ct], acc[ct]);
@@ -359,9 +364,18 @@ __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float*
     for (int ct = 0; ct < NCT; ++ct) {
       const int c = 16 * ct + li;
       if (c >= ncols) continue;
-      float* p = out + (int64_t)c * ldo + j;
+      if (rowmajor) {   // out[j * ldo + c]: 16 consecutive columns per row and instruction
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (j + r < N) out[(j + r) * ldo + c] = acc[ct][r];
+        continue;
+      }
+      TP* p = out + (int64_t)c * ldo + j;
       if (vec_out && j + 4 <= N) {
-        *reinterpret_cast<float4*>(p) = make_float4(acc[ct][0], acc[ct][1], acc[ct][2], acc[ct][3]);
+        V4<TP> v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v.x[r] = acc[ct][r];
+        v4_store(p, v);
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -370,7 +384,7 @@ __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float*
     }
   };
   // two tasks per iteration with fixed buffers: the next task's slice loads during the products
-  float a2[KS];
+  TP a2[KS];
   if (task < ntask) load(task, a);
   for (; task < ntask; task += 2 * stride) {
     const int64_t t1 = task + stride;
@@ -382,8 +396,9 @@ __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float*
   }
 }
 
-hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, const float* P, int64_t ldp, int ncols,
-                              float* out, int64_t ldo, bool tri, hipStream_t s) {
+template <typename TP>
+hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, const TP* P, int64_t ldp, int ncols,
+                              TP* out, int64_t ldo, bool tri, bool rowmajor, hipStream_t s) {
   const int nct = (ncols + 15) / 16;
   const int64_t ntask = (N + 15) / 16;
   const int wpg = kApplyThreads / 64;
@@ -393,11 +408,11 @@ hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, con
 #define RSVD_APPLY_CASE(N_)                                                                                       \
   case N_:                                                                                                        \
     if (tri)                                                                                                      \
-      hipLaunchKernelGGL((apply_small_kernel<N_, true>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, P, ldp, \
-                         ncols, out, ldo, vec);                                                                   \
+      hipLaunchKernelGGL((apply_small_kernel<TP, N_, true>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, P, \
+                         ldp, ncols, out, ldo, vec, rowmajor);                                                    \
     else                                                                                                          \
-      hipLaunchKernelGGL((apply_small_kernel<N_, false>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, P, ldp, \
-                         ncols, out, ldo, vec);                                                                   \
+      hipLaunchKernelGGL((apply_small_kernel<TP, N_, false>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, \
+                         P, ldp, ncols, out, ldo, vec, rowmajor);                                                 \
     break;
     RSVD_APPLY_CASE(1) RSVD_APPLY_CASE(2) RSVD_APPLY_CASE(3) RSVD_APPLY_CASE(4)
     RSVD_APPLY_CASE(5) RSVD_APPLY_CASE(6) RSVD_APPLY_CASE(7) RSVD_APPLY_CASE(8)
@@ -414,9 +429,9 @@ hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P
   if (splits < 1 || out_rowmajor) splits = 1;
   if constexpr (std::is_same<TA, float>::value && std::is_same<TP, float>::value && std::is_same<TO, float>::value &&
                 std::is_same<TC, float>::value) {
-    if (!out_rowmajor && splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
+    if (splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
         (int64_t)ncols * ldp < (int64_t(1) << 32))
-      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, false, s);
+      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, false, out_rowmajor, s);
   }
   int64_t kchunk = ((K + splits - 1) / splits + KC - 1) / KC * KC;
   if (kchunk < KC) kchunk = KC;
@@ -479,8 +494,17 @@ hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N,
   if (N <= 0 || ncols <= 0) return hipSuccess;
   if (K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
       (int64_t)ncols * ldp < (int64_t(1) << 32))
-    return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, true, s);
+    return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, true, false, s);
   return launch_tn<float, float, float, float>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, s);
+}
+
+hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
+                              int ncols, double* out, int64_t ldo, hipStream_t s) {
+  if (N <= 0 || ncols <= 0) return hipSuccess;
+  if (K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
+      (int64_t)ncols * ldp < (int64_t(1) << 32))
+    return launch_apply_small<double>(A, lda, (int)K, N, P, ldp, ncols, out, ldo, true, false, s);
+  return launch_tn<float, double, double, double>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, s);
 }
 
 // Explicit instantiations used by the host orchestration.

@@ -416,7 +416,10 @@ template <typename T> struct Path {
     HIP_TRY(launch_gram<T>(Bt, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
     HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R1, nullptr, scr, flags, st));
-    HIP_TRY((launch_tn<T, double, double, double>(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, 0, 1, false, st)));
+    if constexpr (sizeof(T) == 4)   // R1^-1 is upper triangular
+      HIP_TRY(launch_apply_upper(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, st));
+    else
+      HIP_TRY((launch_tn<T, double, double, double>(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, 0, 1, false, st)));
     HIP_TRY(launch_gram<double>(Q1d, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
     HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R, R1, scr, flags, st));

@@ -92,7 +92,8 @@ def test_gram_rejects_bad_arguments():
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("K,N,ncols,rowmajor", [(64, 256, 16, 0), (110, 3001, 110, 0), (128, 700, 128, 0),
                                                 (517, 300, 30, 0), (1000, 77, 110, 1),
-                                                (30, 1000, 30, 0), (129, 513, 200, 1), (2048, 260, 9, 0)])
+                                                (30, 1000, 30, 0), (129, 513, 200, 1), (2048, 260, 9, 0),
+                                                (110, 3001, 100, 1), (128, 700, 128, 1), (7, 50, 5, 1)])
 def test_product_tn_is_exact_on_integers(prec, K, N, ncols, rowmajor):
     import torch
     rng = np.random.default_rng(K * 3 + N)
