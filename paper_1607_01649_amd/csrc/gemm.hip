@@ -123,11 +123,12 @@ __global__ __launch_bounds__(256) void nn_kernel(const TA* __restrict__ A, int64
 
 // out[split][c][j] = sum_{i in split} A[i][j] * P(i, c)      (P in panel layout: P[c*ldp + i])
 // OUT_RM: write out[j*ldo + c] instead (row-major result, no split).
+// upper: P is upper triangular (P(i, c) = 0 for i > c), so a column group stops at its last column.
 template <typename TA, typename TP, typename TC, typename TO, int NB, bool VEC, bool OUT_RM>
 __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64_t lda, int64_t K, int64_t N,
                                                  const TP* __restrict__ P, int64_t ldp, int ncols,
                                                  TO* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                 int64_t kchunk) {
+                                                 int64_t kchunk, bool upper) {
   __shared__ V4<TC> ps[NB * 4 * 64];
   typedef Mma<TC> M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64
   const int split = blockIdx.y;
   const int cg0 = blockIdx.z * NB * 16;
   const int64_t kbeg = (int64_t)split * kchunk;
-  const int64_t kend = min(K, kbeg + kchunk);
+  const int64_t kend = upper ? min(min(K, kbeg + kchunk), (int64_t)cg0 + NB * 16) : min(K, kbeg + kchunk);
 
   // acc[bb][cb]: MFMA tile row m <-> output row jw + 4*arow(m) + bb
   typename M::acc acc[4][NB];
@@ -423,15 +424,16 @@ hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, con
 }
 
 template <typename TA, typename TP, typename TC, typename TO>
-hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols, TO* out,
-                     int64_t ldo, int64_t part_stride, int splits, bool out_rowmajor, hipStream_t s) {
+static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols,
+                              TO* out, int64_t ldo, int64_t part_stride, int splits, bool out_rowmajor, bool upper,
+                              hipStream_t s) {
   if (N <= 0 || ncols <= 0) return hipSuccess;
   if (splits < 1 || out_rowmajor) splits = 1;
   if constexpr (std::is_same<TA, float>::value && std::is_same<TP, float>::value && std::is_same<TO, float>::value &&
                 std::is_same<TC, float>::value) {
     if (splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
         (int64_t)ncols * ldp < (int64_t(1) << 32))
-      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, false, out_rowmajor, s);
+      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, upper, out_rowmajor, s);
   }
   int64_t kchunk = ((K + splits - 1) / splits + KC - 1) / KC * KC;
   if (kchunk < KC) kchunk = KC;
@@ -445,20 +447,27 @@ hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P
     if (out_rowmajor) {
       if (vec)
         hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                           ldp, ncols, out, ldo, part_stride, kchunk);
+                           ldp, ncols, out, ldo, part_stride, kchunk, upper);
       else
         hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                           ldp, ncols, out, ldo, part_stride, kchunk);
+                           ldp, ncols, out, ldo, part_stride, kchunk, upper);
     } else {
       if (vec)
         hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                           ldp, ncols, out, ldo, part_stride, kchunk);
+                           ldp, ncols, out, ldo, part_stride, kchunk, upper);
       else
         hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                           ldp, ncols, out, ldo, part_stride, kchunk);
+                           ldp, ncols, out, ldo, part_stride, kchunk, upper);
     }
   });
   return hipGetLastError();
+}
+
+template <typename TA, typename TP, typename TC, typename TO>
+hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols, TO* out,
+                     int64_t ldo, int64_t part_stride, int splits, bool out_rowmajor, hipStream_t s) {
+  return launch_tn_k<TA, TP, TC, TO>(A, lda, K, N, P, ldp, ncols, out, ldo, part_stride, splits, out_rowmajor, false,
+                                     s);
 }
 
 template <typename TP, typename TO>
@@ -488,14 +497,11 @@ hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int
 }
 
 // out = A P for an upper-triangular P (the apply X <- X R^-1 of CholeskyQR): the triangular short-contraction
-// kernel where it applies, otherwise the general product.
+// kernel where it applies, otherwise the general product with each column group's contraction cut at its
+// last column.
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const float* P, int64_t ldp,
                               int ncols, float* out, int64_t ldo, hipStream_t s) {
-  if (N <= 0 || ncols <= 0) return hipSuccess;
-  if (K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
-      (int64_t)ncols * ldp < (int64_t(1) << 32))
-    return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, true, false, s);
-  return launch_tn<float, float, float, float>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, s);
+  return launch_tn_k<float, float, float, float>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s);
 }
 
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
@@ -504,7 +510,12 @@ hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N,
   if (K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
       (int64_t)ncols * ldp < (int64_t(1) << 32))
     return launch_apply_small<double>(A, lda, (int)K, N, P, ldp, ncols, out, ldo, true, false, s);
-  return launch_tn<float, double, double, double>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, s);
+  return launch_tn_k<float, double, double, double>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s);
+}
+
+hipError_t launch_apply_upper(const double* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
+                              int ncols, double* out, int64_t ldo, hipStream_t s) {
+  return launch_tn_k<double, double, double, double>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s);
 }
 
 // Explicit instantiations used by the host orchestration.

@@ -19,11 +19,12 @@ hipError_t launch_gaussian(uint64_t seed, uint32_t stream, int64_t rows, int64_t
 template <typename TA, typename TX, typename TC, typename TO>
 hipError_t launch_nn(const TA* A, int64_t lda, int64_t rows, int64_t K, const TX* X, int64_t ldx, int ncols, TO* out,
                      int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
-// out = A P with P upper triangular (P(i, c) = 0 for i > c), A FP32, P and out FP32 or FP64; layouts as
-// launch_tn with one range.
+// out = A P with P upper triangular (P(i, c) = 0 for i > c); layouts as launch_tn with one range.
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const float* P, int64_t ldp,
                               int ncols, float* out, int64_t ldo, hipStream_t s);
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
+                              int ncols, double* out, int64_t ldo, hipStream_t s);
+hipError_t launch_apply_upper(const double* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
                               int ncols, double* out, int64_t ldo, hipStream_t s);
 // tn: out[s][c][j] = sum_{i in split s} A[i][j] P(i, c); A K x N row-major, P panel (P[c*ldp + i]).
 template <typename TA, typename TP, typename TC, typename TO>

@@ -302,10 +302,7 @@ template <typename T> struct Path {
 
   // out = X R^-1 (R^-1 upper triangular, nc x nc at leading dimension LPc).
   hipError_t apply_rinv(const T* X, int64_t ld, int64_t rows, int nc, const T* rinv, int LPc, T* out) {
-    if constexpr (sizeof(T) == 4)
-      return launch_apply_upper(X, ld, nc, rows, rinv, LPc, nc, out, ld, st);
-    else
-      return launch_tn<T, T, T, T>(X, ld, nc, rows, rinv, LPc, nc, out, ld, 0, 1, false, st);
+    return launch_apply_upper(X, ld, nc, rows, rinv, LPc, nc, out, ld, st);
   }
 
   // out = orth(X) for an nc-column panel: CholeskyQR2 (two passes of G = X^T X = R^T R, X <- X R^-1).
@@ -416,10 +413,7 @@ template <typename T> struct Path {
     HIP_TRY(launch_gram<T>(Bt, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
     HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R1, nullptr, scr, flags, st));
-    if constexpr (sizeof(T) == 4)   // R1^-1 is upper triangular
-      HIP_TRY(launch_apply_upper(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, st));
-    else
-      HIP_TRY((launch_tn<T, double, double, double>(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, 0, 1, false, st)));
+    HIP_TRY(launch_apply_upper(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, st));   // R1^-1 upper triangular
     HIP_TRY(launch_gram<double>(Q1d, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
     HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R, R1, scr, flags, st));

@@ -118,6 +118,7 @@ F32_CASES = [
     (1237, 901, 200, 1.0, 12, 8, 1, 0),    # n % 4 != 0: unaligned rows, scalar loads
     (2048, 1024, 256, 0.5, 50, 14, 2, 3),  # lda = n + 3
     (777, 2500, 150, 0.8, 30, 10, 1, 0),
+    (2000, 1500, 400, 0.5, 180, 20, 1, 0),  # l = 200: blocked Cholesky, triangular apply over two column groups
 ]
 
 
