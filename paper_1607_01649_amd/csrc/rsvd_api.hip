@@ -417,7 +417,10 @@ template <typename T> struct Path {
     HIP_TRY(launch_gram<double>(Q1d, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
     HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R, R1, scr, flags, st));
-    const double tol = (double)nc * 2.220446049250313e-16;
+    // Jacobi stops when every pair's cosine is below tol: l u for FP64 data; for FP32 data (whose own
+    // rounding is 6e-8) 1e-10 already leaves U_hat orthogonal and sigma exact far below that, and saves
+    // about one sweep.
+    const double tol = std::max((double)nc * 2.220446049250313e-16, sizeof(T) == 4 ? 1e-10 : 0.0);
     HIP_TRY(launch_jacobi<T>(R, nc, LPc, tol, 60, P.at<double>(L.sigma), P.at<double>(L.uhat_d), P.at<T>(L.uhat_p),
                              P.at<T>(L.vhat_p), P.at<double>(L.scr_jac), flags, st));
     return RSVD_OK;
