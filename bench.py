@@ -185,10 +185,12 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed):
     passes = 2 * q + 2
     avg_nn = nn_ms / max(nn_n, 1) * 1e-3
     avg_tn = tn_ms / max(tn_n, 1) * 1e-3
+    # column tiles of 16 per workgroup of the low-precision product (bf16 at most 7, FP8 an even count <= 8)
+    lp_nb = min(7, (l + 15) // 16) if sketch == "bf16" else (min(8, (l + 15) // 16) + 1) // 2 * 2
     names = {"f32": ("nn_kernel (Y = A X, FP32 MFMA)", "tn_kernel (Z = A^T Q, FP32 MFMA)"),
              "f64": ("nn_kernel (Y = A X, FP64 MFMA)", "tn_kernel (Z = A^T Q, FP64 MFMA)"),
-             "bf16": ("nn_bf16_kernel (Y = bf16(A) X)", "nn_bf16_kernel (Z = bf16(A)^T Q)"),
-             "fp8": ("nn_fp8_kernel (Y = fp8(A) X)", "nn_fp8_kernel (Z = fp8(A)^T Q)")}[sketch]
+             "bf16": ("lp_nn_kernel<0,%d,4,1> (Y = bf16(A) X)" % lp_nb, "lp_nn_kernel<0,%d,4,1> (Z = bf16(A)^T Q)" % lp_nb),
+             "fp8": ("lp_nn_kernel<1,%d,4,1> (Y = fp8(A) X)" % lp_nb, "lp_nn_kernel<1,%d,4,1> (Z = fp8(A)^T Q)" % lp_nb)}[sketch]
     dom_nn = nn_ms >= tn_ms
     avg = avg_nn if dom_nn else avg_tn
     # algorithmic bytes of one product: A once in its operand format, the thin FP32 operand and result
