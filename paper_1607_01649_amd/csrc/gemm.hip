@@ -284,11 +284,12 @@ int nn_splits_used(int64_t K, int splits) {
   return used < 1 ? 1 : used;
 }
 
-// Short contractions (K <= 128, ncols <= 128, FP32): out[c*ldo + j] (or out[j*ldo + c], row-major) =
+// Short contractions (K <= 128, ncols <= 128; A FP32, P and out FP32 or FP64): out[c*ldo + j] (or
+// out[j*ldo + c], row-major) =
 // sum_{i < K} A[i*lda + j] * P(i, c), as tn_kernel with one range, for the apply X <- X R^-1 of
 // CholeskyQR and the lifts U = Q U_hat, V = B^T V_hat (K = l).  The whole of P
 // goes to LDS once per workgroup as 128 rows (rows K .. 127 zero, so every task runs the same 32
-// MFMA steps with no branches; pitch 144 floats so that the four k-rows a B fragment reads fall on
+// MFMA steps with no branches; pitch 144 elements so that the four k-rows a B fragment reads fall on
 // different banks); a wave takes 16-row tasks (all columns at once) and loads the task's A slice
 // in full before its MFMAs, prefetching the next task's slice meanwhile.  One workgroup per
 // compute unit: more workgroups only repeat the staging of P (measured: 512 or 1024 workgroups

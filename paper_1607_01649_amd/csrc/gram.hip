@@ -9,8 +9,10 @@
 //
 // G is symmetric: only the tile pairs (I, J), I <= J, of 128 x 128 tiles are
 // computed, and each off-diagonal tile is written twice, as itself and
-// transposed.  (Diagonal tiles are computed whole: skipping their lower
-// blocks costs a branch between MFMAs and leaves the waves unbalanced.)  FP32 values are exact in FP64 and so are their products; the
+// transposed.  (Diagonal tiles of several-tile panels are computed whole:
+// there every workgroup of the launch is resident at once, so a lighter diagonal workgroup would not
+// shorten it.  A single tile, nc <= 128, has its own kernel below that computes only the 16 x 16
+// blocks on and above the diagonal, dealt evenly to the waves.)  FP32 values are exact in FP64 and so are their products; the
 // only rounding is the FP64 accumulation.
 //
 // Workgroup = 256 threads = 4 waves; tile pair from blockIdx.x, contraction
