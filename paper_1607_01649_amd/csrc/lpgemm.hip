@@ -57,11 +57,13 @@ template <> struct LpFmt<1> {     // E4M3
 };
 
 // Column tiles of 16 per workgroup.  FP8 takes an even count so that the fragment blocks of a chunk split evenly
-// over the four waves.
+// over the four waves, at most 12: the fewest column groups (each re-reads A), then the fewest tiles per group
+// (ncols = 520: three groups of 12 tiles, 576 columns, instead of five of 8, 640).
 static int lp_nb(int kind, int ncols) {
   int nb = (ncols + 15) / 16;
   if (kind == 0) return nb > 7 ? 7 : nb;
-  nb = nb > 8 ? 8 : nb;
+  const int groups = (nb + 11) / 12;
+  nb = (nb + groups - 1) / groups;
   return (nb + 1) & ~1;
 }
 
@@ -471,7 +473,9 @@ hipError_t launch_nn_lp(int kind, const void* A, int64_t lda, const float* sA, i
       case 2: RSVD_LP_CASE(1, 2); break;
       case 4: RSVD_LP_CASE(1, 4); break;
       case 6: RSVD_LP_CASE(1, 6); break;
-      default: RSVD_LP_CASE(1, 8); break;
+      case 8: RSVD_LP_CASE(1, 8); break;
+      case 10: RSVD_LP_CASE(1, 10); break;
+      default: RSVD_LP_CASE(1, 12); break;
     }
   }
 #undef RSVD_LP_CASE

@@ -339,7 +339,7 @@ def test_convert_fp8_is_bit_exact():
 
 
 @pytest.mark.parametrize("rows,K,ncols", [(128, 128, 16), (300, 517, 30), (77, 1000, 110), (1000, 129, 128),
-                                          (33, 70, 7), (513, 2048, 200)])
+                                          (33, 70, 7), (513, 2048, 200), (300, 700, 520)])
 def test_product_fp8_is_exact_on_integers(rows, K, ncols):
     """Integers of magnitude <= 16 stay exact under the block scales and the
     FP32 sums stay below 2^24: A X and (through the transposed copy) A^T P are
