@@ -236,6 +236,39 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TP* __restrict__ part
   }
 }
 
+// out[c*ldo + r] = sum_{s < S} part[s*ps + c*ldp + r] in one launch, for many partials of a small
+// result: a workgroup takes 64 consecutive entries and 16 partial groups; thread (entry e, group q) adds
+// partials q, q + 16, q + 32, ... of its entry in that order (eight loads ahead of the additions), then the
+// 16 group sums are added in order q = 0 .. 15 (a fixed order: deterministic).
+template <typename TP>
+__global__ __launch_bounds__(1024) void reduce_tree_kernel(const TP* __restrict__ part, int S, int64_t pstride,
+                                                           int64_t ldp, int64_t rows, int ncols,
+                                                           TP* __restrict__ out, int64_t ldo) {
+  __shared__ TP red[16][64];
+  const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t n = rows * ncols;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + e;
+  const int64_t ii = idx < n ? idx : n - 1;   // past the end: a valid entry, never stored
+  const int64_t c = ii / rows, r = ii - (ii / rows) * rows;
+  const TP* p = part + c * ldp + r;
+  TP acc = TP(0);
+  for (int k = q; k < S; k += 16 * 8) {
+    TP v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)min(k + 16 * u, S - 1) * pstride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (k + 16 * u < S) ? v[u] : TP(0);
+  }
+  red[q][e] = acc;
+  __syncthreads();
+  if (q == 0 && idx < n) {
+    TP t = red[0][e];
+#pragma unroll
+    for (int j = 1; j < 16; ++j) t += red[j][e];
+    out[c * ldo + r] = t;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline int nb_for(int ncols) { int nb = (ncols + 15) / 16; return nb > 8 ? 8 : (nb < 1 ? 1 : nb); }
@@ -487,6 +520,14 @@ template <typename TP>
 hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int64_t ldp, int64_t rows, int ncols,
                           TP* tmp, TP* out, int64_t ldo, hipStream_t s) {
   if (S <= 2 * group) return launch_reduce<TP, TP>(part, S, pstride, ldp, rows, ncols, out, ldo, s);
+  // more than 128 partials (a long panel's Gram, l <= 128): one launch, 16 groups per entry (196 partials of a
+  // 110 x 110 Gram: 5.7 us against two launches of 6.6 us)
+  if (S > 128) {
+    const int64_t n = rows * ncols;
+    hipLaunchKernelGGL((reduce_tree_kernel<TP>), dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, s, part, S,
+                       pstride, ldp, rows, ncols, out, ldo);
+    return hipGetLastError();
+  }
   int64_t work = ((rows + 3) / 4) * ncols;
   if (work <= 0) return hipSuccess;
   int ng = (S + group - 1) / group;
