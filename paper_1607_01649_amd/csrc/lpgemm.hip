@@ -20,10 +20,11 @@
 //
 // A block of 256 threads owns 256 rows x 16 NB columns, a wave 64 rows (four
 // 16-row MFMA blocks), so each X fragment read from LDS feeds four MFMAs.
-// Pipeline per chunk i: the loads of the X fragments and of the A values of
-// chunk i+1 are issued, chunk i is multiplied, the X fragments are stored
-// into the spare of two LDS buffers; one barrier per chunk, which leaves the
-// A loads in flight (no fence: LDS completion is all it waits for).  Every load is unconditional (padded
+// Pipeline over pairs of chunks: the X fragments of the next pair and the A
+// values one chunk ahead are loaded while the pair is multiplied, then the X
+// fragments go to the spare of two LDS buffers (two chunks each); one barrier
+// per pair, which leaves the A loads in flight (no fence: LDS completion is
+// all it waits for).  Every load is unconditional (padded
 // columns are zero, rows past the end are clamped and never stored, chunk
 // indices past the end are clamped), so the compiler never has to wait for a
 // load at a lane-masked join.
@@ -205,8 +206,9 @@ __global__ __launch_bounds__(256) void lp_nn_kernel(const uint8_t* __restrict__ 
   static_assert(NF % 4 == 0, "fragment blocks must split evenly over the waves");
   constexpr int NXW = NF / 4;                         // fragment loads per wave per chunk
   // Double buffer for X (and the fp8 scales of its columns).
-  __shared__ u32x4 xs0[NF][64], xs1[NF][64];
-  __shared__ float sx0[KIND == 1 ? 256 : 1], sx1[KIND == 1 ? 256 : 1];
+  // X fragments (and fp8 column scales) staged two chunks at a time: buffer b, chunk h of the pair
+  __shared__ u32x4 xs[2][2][NF][64];
+  __shared__ float sx[2][2][KIND == 1 ? 256 : 1];
   typedef Mma<float> M;
   const int slot = blockIdx.x >> 3, xcd = blockIdx.x & 7;
   const int rb = (slot / groups) * 8 + xcd;
@@ -301,54 +303,40 @@ __global__ __launch_bounds__(256) void lp_nn_kernel(const uint8_t* __restrict__ 
     }
   };
 
-  // Step i: issue the loads of X(i+2) (into a spare register stage) and of A(i+PD) (into a spare register set),
-  // multiply chunk i (LDS buffer i mod 2), store X(i+1), loaded a step earlier, into the other buffer and pass
-  // the barrier.  The store's wait leaves this step's loads in flight, and the barrier (no fence) leaves every
-  // global load in flight.  X comes from L2 or beyond; loading it two chunks ahead hides that latency as well.
-  // The loop is unrolled so that register sets and stages are static (no copies).
-  auto step = [&](int64_t i, const u32x4 (&acur)[LRB][AW], u32x4 (&afar)[LRB][AW], XStage& xfar,
-                  const XStage& xnext) {
-    const bool odd = (i & 1) != 0;
-    load_x(kc(i + 2), xfar);
-    load_a(kc(i + PD), afar);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(odd ? xs1 : xs0, odd ? sx1 : sx0, acur, kc(i));
-    __builtin_amdgcn_sched_barrier(0);
-    store_x(xnext, odd ? xs0 : xs1, odd ? sx0 : sx1);
-    lds_barrier();
-  };
+  // Chunks are taken in pairs (i, i+1) from LDS buffer b: the loads of X for the next pair (i+2, i+3) and of
+  // A(i+1) are issued, chunk i is multiplied, A(i+2) is issued, chunk i+1 is multiplied, then the next pair's
+  // X goes to the other buffer and the workgroup passes one barrier (no fence: every global load stays in
+  // flight) -- one barrier per two chunks.  A is one chunk ahead in registers, X two.  Register sets are
+  // static (no copies); chunk indices past the end are clamped, so the last pair may repeat a chunk that is
+  // never multiplied.
+  static_assert(PD == 1, "one chunk of A ahead");
+  XStage xp0, xp1;   // the next pair's X
   u32x4 a0[LRB][AW], a1[LRB][AW];
-  XStage x0, x1;
-  load_x(kc(0), x0);
-  load_x(kc(1), x1);
+  load_x(kc(0), xp0);
+  load_x(kc(1), xp1);
   load_a(kc(0), a0);
-  store_x(x0, xs0, sx0);
+  store_x(xp0, xs[0][0], sx[0][0]);
+  store_x(xp1, xs[0][1], sx[0][1]);
   lds_barrier();
-  if constexpr (PD == 1) {
-    int64_t i = 0;
-    for (; i + 2 <= nck; i += 2) {
-      step(i, a0, a1, x0, x1);
-      step(i + 1, a1, a0, x1, x0);
-    }
-    if (i < nck) step(i, a0, a1, x0, x1);
-  } else {
-    u32x4 a2[LRB][AW];
-    load_a(kc(1), a1);
-    int64_t i = 0;
-    for (; i + 6 <= nck; i += 6) {
-      step(i, a0, a2, x0, x1);
-      step(i + 1, a1, a0, x1, x0);
-      step(i + 2, a2, a1, x0, x1);
-      step(i + 3, a0, a2, x1, x0);
-      step(i + 4, a1, a0, x0, x1);
-      step(i + 5, a2, a1, x1, x0);
-    }
-    if (i < nck) step(i, a0, a2, x0, x1);
-    if (i + 1 < nck) step(i + 1, a1, a0, x1, x0);
-    if (i + 2 < nck) step(i + 2, a2, a1, x0, x1);
-    if (i + 3 < nck) step(i + 3, a0, a2, x1, x0);
-    if (i + 4 < nck) step(i + 4, a1, a0, x0, x1);
+  int64_t i = 0;
+  int buf = 0;
+  for (; i + 2 <= nck; i += 2) {
+    load_x(kc(i + 2), xp0);
+    load_x(kc(i + 3), xp1);
+    load_a(kc(i + 1), a1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(xs[buf][0], sx[buf][0], a0, kc(i));
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(kc(i + 2), a0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(xs[buf][1], sx[buf][1], a1, kc(i + 1));
+    __builtin_amdgcn_sched_barrier(0);
+    store_x(xp0, xs[buf ^ 1][0], sx[buf ^ 1][0]);
+    store_x(xp1, xs[buf ^ 1][1], sx[buf ^ 1][1]);
+    lds_barrier();
+    buf ^= 1;
   }
+  if (i < nck) compute(xs[buf][0], sx[buf][0], a0, kc(i));   // odd count: the last chunk, already staged
 
   float* o = out + (int64_t)split * part_stride;
 #pragma unroll
