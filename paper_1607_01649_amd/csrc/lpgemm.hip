@@ -205,8 +205,7 @@ __global__ __launch_bounds__(256) void lp_nn_kernel(const uint8_t* __restrict__ 
   constexpr int NF = NB * NFI;                        // fragment blocks per chunk
   static_assert(NF % 4 == 0, "fragment blocks must split evenly over the waves");
   constexpr int NXW = NF / 4;                         // fragment loads per wave per chunk
-  // Double buffer for X (and the fp8 scales of its columns).
-  // X fragments (and fp8 column scales) staged two chunks at a time: buffer b, chunk h of the pair
+  // X fragments (and the fp8 scales of its columns), two buffers of two chunks: buffer b, chunk h of the pair
   __shared__ u32x4 xs[2][2][NF][64];
   __shared__ float sx[2][2][KIND == 1 ? 256 : 1];
   typedef Mma<float> M;
