@@ -285,8 +285,11 @@ __global__ __launch_bounds__(256) void lp_nn_kernel(const uint8_t* __restrict__ 
         }
       }
     } else {
-      // the wave's rows lie in one tile; a wave-uniform index makes this a scalar load
-      const int sidx = __builtin_amdgcn_readfirstlane((int)((rbase / 128) * s_row + (k0 / LKC) * s_k));
+      // the wave's rows lie in one tile; a wave-uniform index makes this a scalar load.  A wave wholly past the
+      // last row works on the clamped row rows - 1 (never stored), so it takes that row's tile: the index stays
+      // inside the ceil(rows / 128) tile rows of the table.
+      const int64_t trow = min(rbase, rows - 1) / 128;
+      const int sidx = __builtin_amdgcn_readfirstlane((int)(trow * s_row + (k0 / LKC) * s_k));
       const int sa = e8m0_of(sA[sidx]);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
