@@ -42,8 +42,7 @@ typedef enum {
   RSVD_E_WORKSPACE = -2,    /* workspace null or smaller than rsvd_workspace_size            */
   RSVD_E_HIP = -3,          /* a HIP runtime call failed                                       */
   RSVD_E_NONFINITE = -4,    /* NaN or Inf met in the computation; outputs undefined            */
-  RSVD_E_UNSUPPORTED = -5,  /* valid but not built (e.g. a dtype combination)                  */
-  RSVD_E_BREAKDOWN = -6     /* Cholesky of a Gram matrix broke down even after the shifted retry */
+  RSVD_E_UNSUPPORTED = -5   /* valid but not built (e.g. a dtype combination)                  */
 } rsvd_status;
 
 typedef enum {
@@ -112,7 +111,7 @@ typedef struct {
   int32_t p_used, q_used;
   int32_t rank_out;        /* columns written to U and V                              */
   int32_t fallback_steps;  /* growth steps of the blocked range finder               */
-  int32_t orth_retries;    /* Gram Cholesky breakdowns recovered by a shifted retry  */
+  int32_t reserved0;       /* always 0                                                */
   int32_t status;          /* same value as the return code                          */
   double err_bound;        /* certificate value (absolute); 0 when eps == 0           */
   double sigma1;           /* D(1)                                                    */
@@ -122,7 +121,12 @@ typedef struct {
                               and A^T*X (HIP events around each launch)              */
   int32_t nn_launches, tn_launches;
   int32_t jacobi_sweeps;   /* sweeps of the small SVD                                 */
-  int32_t dropped_cols;    /* numerically dependent columns met by CholeskyQR          */
+  int32_t dropped_cols;    /* numerically dependent columns met by CholeskyQR: a Gram
+                              pivot <= l u^2 G_jj (u the unit roundoff of the data)
+                              gives a zero column of the basis instead of a failure
+                              (no retry), so for a rank-deficient A the basis spans
+                              its numerical range and the columns of U and V past
+                              that rank are zero, with zero singular values          */
   double frob_residual;    /* after a fallback: sqrt(||A||_F^2 - ||B||_F^2) (Section 12.4
                               downdating) of the grown basis; -1 otherwise            */
 } rsvd_info;
@@ -203,10 +207,12 @@ rsvd_status rsvd_plan(const rsvd_desc* d, void* d_ws, size_t ws_bytes, void* str
  * per step (Figure 12, residual applied implicitly, each new block projected
  * against the basis twice) until the bound holds or max_rank is reached; all
  * columns of the grown basis are then returned (rank_out = its width).
- * Errors: RSVD_E_ARG (nothing enqueued), RSVD_E_HIP, RSVD_E_NONFINITE,
- * RSVD_E_BREAKDOWN; RSVD_NOT_CERTIFIED (> 0) when eps is missed at max_rank.
+ * Errors: RSVD_E_ARG (nothing enqueued), RSVD_E_HIP, RSVD_E_NONFINITE;
+ * RSVD_NOT_CERTIFIED (> 0) when eps is missed at max_rank.
  * Reported only when h_info != NULL or eps > 0: device-side conditions
- * (non-finite values, Cholesky breakdown) need a synchronisation to be seen.
+ * (non-finite values) need a synchronisation to be seen.  CholeskyQR never
+ * fails on rank deficiency: dependent columns are dropped and counted in
+ * rsvd_info.dropped_cols.
  */
 rsvd_status rsvd_factor(rsvd_plan_t plan, const void* d_A, int64_t lda, const double* d_Omega,
                         void* d_U, int64_t ldu, double* d_S, void* d_V, int64_t ldv,

@@ -86,7 +86,8 @@ rsvd_status rsvd_k_cholesky(int32_t l, const double* d_G, int64_t ldg, double ta
  * holds the largest sweep count.  l <= 128 runs in one workgroup with X in
  * LDS; larger l (up to 1024) runs block one-sided Jacobi over many
  * workgroups and needs d_scratch (rsvd_k_scratch_bytes(l) bytes; may be NULL
- * for l <= 128); that form synchronises `stream` once per sweep.
+ * for l <= 128); that form enqueues 20 sweeps, the ones after
+ * convergence returning at once, and never synchronises the host.
  * Errors: RSVD_E_ARG, RSVD_E_HIP.
  */
 rsvd_status rsvd_k_small_svd(int32_t l, const double* d_R, double* d_sigma, double* d_Uhat, int32_t* d_flags,

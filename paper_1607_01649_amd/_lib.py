@@ -18,7 +18,6 @@ RSVD_E_WORKSPACE = -2
 RSVD_E_HIP = -3
 RSVD_E_NONFINITE = -4
 RSVD_E_UNSUPPORTED = -5
-RSVD_E_BREAKDOWN = -6
 
 RSVD_F64, RSVD_F32, RSVD_BF16, RSVD_FP8_E4M3 = 0, 1, 2, 3
 RSVD_RETURN_RANK_L = 0x1
@@ -45,7 +44,7 @@ class rsvd_desc(ctypes.Structure):
 class rsvd_info(ctypes.Structure):
     _fields_ = [
         ("p_used", ctypes.c_int32), ("q_used", ctypes.c_int32), ("rank_out", ctypes.c_int32),
-        ("fallback_steps", ctypes.c_int32), ("orth_retries", ctypes.c_int32), ("status", ctypes.c_int32),
+        ("fallback_steps", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("status", ctypes.c_int32),
         ("err_bound", ctypes.c_double), ("sigma1", ctypes.c_double),
         ("stage_ms", ctypes.c_float * 8),
         ("nn_ms", ctypes.c_float), ("tn_ms", ctypes.c_float),

@@ -17,12 +17,16 @@
 // in the one-workgroup kernel.
 //
 // Jacobi (block one-sided, X = R^T): the columns are split into blocks of W;
-// the blocks are paired by the round-robin (circle) ordering, one workgroup
-// per pair holds the pair's 2W columns in LDS and runs inner one-sided Jacobi
-// sweeps (the same rotation and test as jacobi.hip) over all of its column
-// pairs.  A sweep of nbk-1 rounds meets every pair of blocks, hence every
-// pair of columns; sweeps repeat until one passes in which no workgroup had to
-// rotate in its first inner sweep.
+// the blocks are paired by the round-robin (circle) ordering, and one
+// workgroup per pair forms the Gram matrix of the pair's 2W columns, runs one
+// cyclic Jacobi sweep on it (the rotations the columns would take, with the
+// same rotation and test as jacobi.hip), and applies the accumulated
+// rotation to the columns.  A sweep of nbk-1 rounds meets every pair of
+// blocks, hence every pair of columns; sweeps repeat until one passes in
+// which no workgroup rotated.  The sweeps are enqueued up front and those
+// after convergence return at once: no host synchronisation.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace rsvd {
@@ -337,7 +341,7 @@ __device__ __forceinline__ int bj_player(int pos, int round, int le) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (le - 1);
 }
 
-// xs: column p of X at xs[p*ldx + i], i < l.
+// xs: column p of X at xs[p*ldx + i], i < LP (rows l .. LP-1 and columns past l are zero).
 __global__ void bj_init_kernel(const double* __restrict__ R, int l, int LP, double* __restrict__ xs, int ldx,
                                int ncols) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -346,87 +350,186 @@ __global__ void bj_init_kernel(const double* __restrict__ R, int l, int LP, doub
   xs[t] = (p < l && i < l) ? R[(int64_t)p * LP + i] : 0.0;
 }
 
-template <int W>
-__global__ __launch_bounds__(512) void bj_round_kernel(double* __restrict__ xs, int ldx, int l, int nbk, int round,
-                                                       double tol, int inner_max, int* __restrict__ rot) {
-  extern __shared__ double xl[];   // 2W columns, column c at xl[c*l + i]
-  constexpr int G = 512 / W;       // lanes per column pair
-  constexpr int NI = (W == 16 ? 600 : 1024) / G + 1;   // per-lane slice length bound (l <= 600 resp. 1024)
-  __shared__ int any_rot;
-  const int tid = threadIdx.x;
-  const int g = blockIdx.x;
-  const int bI = bj_player(g, round, nbk), bJ = bj_player(nbk - 1 - g, round, nbk);
-  auto gcol = [&](int c) { return c < W ? bI * W + c : bJ * W + (c - W); };
-  for (int t = tid; t < 2 * W * l; t += 512) {
-    const int c = t / l, i = t - (t / l) * l;
-    const int gc = gcol(c);
-    xl[t] = (gc < l) ? xs[(int64_t)gc * ldx + i] : 0.0;
+// Rotation of the column pair (p, q) from its Gram entries alpha = x_p.x_p, beta = x_q.x_q, gamma = x_p.x_q,
+// with x_p' = c x_p - s x_q, x_q' = s x_p + c x_q (then x_p'.x_q' = 0 and the squared norms move by -/+ t
+// gamma).  No rotation (c = 1, s = t = 0) when the pair is orthogonal to tol or a column is zero.
+__device__ __forceinline__ bool bj_rotation(double al, double be, double ga, double tol, double& c, double& s,
+                                            double& t) {
+  if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+    const double zeta = (be - al) / (2.0 * ga);
+    t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = c * t;
+    return true;
   }
-  const int pi = tid / G, sub = tid - (tid / G) * G;
-  int first = 0;
-  for (int s = 0; s < inner_max; ++s) {
-    __syncthreads();
-    if (tid == 0) any_rot = 0;
-    __syncthreads();
-    for (int ir = 0; ir < 2 * W - 1; ++ir) {
-      const int p = bj_player(pi, ir, 2 * W), q = bj_player(2 * W - 1 - pi, ir, 2 * W);
-      if (gcol(p) < l && gcol(q) < l) {   // uniform within the pair group
-        double* xp = xl + p * l;
-        double* xq = xl + q * l;
-        // the lane's slice of both columns, loaded at once (unrolled, predicated) and kept for the rotation
-        double av[NI], bv[NI];
-        double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-        for (int u = 0; u < NI; ++u) {
-          const int i = sub + u * G;
-          av[u] = (i < l) ? xp[i] : 0.0;
-          bv[u] = (i < l) ? xq[i] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < NI; ++u) {
-          al += av[u] * av[u]; be += bv[u] * bv[u]; ga += av[u] * bv[u];
-        }
-#pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, G);
-          be += __shfl_xor(be, o, G);
-          ga += __shfl_xor(ga, o, G);
-        }
-        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          const double sn = c * t;
-#pragma unroll
-          for (int u = 0; u < NI; ++u) {
-            const int i = sub + u * G;
-            if (i < l) {
-              xp[i] = c * av[u] - sn * bv[u];
-              xq[i] = sn * av[u] + c * bv[u];
-            }
-          }
-          if (sub == 0) any_rot = 1;
-        }
-      }
-      __syncthreads();
-    }
-    const int r = any_rot;
-    if (s == 0) first = r;
-    if (!r) break;
-  }
-  __syncthreads();
-  if (tid == 0 && first) atomicAdd(rot, 1);
-  for (int t = tid; t < 2 * W * l; t += 512) {
-    const int c = t / l, i = t - (t / l) * l;
-    const int gc = gcol(c);
-    if (gc < l) xs[(int64_t)gc * ldx + i] = xl[t];
-  }
+  c = 1.0;
+  s = 0.0;
+  t = 0.0;
+  return false;
 }
 
-__global__ void bj_flags_kernel(int* flags, int sweeps, int nonconv) {
+// One pair step of the block one-sided Jacobi on the NC = 2W columns of block pair g of this round:
+//   1. G = X^T X of the pair's columns on the FP64 MFMA (each wave a share of the 16-row slabs, the wave
+//      partials summed in a fixed order through LDS);
+//   2. one cyclic Jacobi sweep on G in LDS (NC - 1 rounds of NC/2 disjoint rotations, circle order): each
+//      rotation is the one the columns themselves would take (G's entries are their inner products), G is
+//      carried along as J^T G J (2 x 2 blocks, the pair's own block updated exactly), and V = J_1 J_2 ... is
+//      accumulated;
+//   3. X <- X V on the FP64 MFMA, slab by slab in place.
+// A sweep that reaches this kernel after a sweep with no rotation anywhere (rot[sweep - 1] == 0) returns at
+// once, so a fixed number of sweeps can be enqueued without reading the count back on the host.
+template <int W>
+__global__ __launch_bounds__(512) void bj_round_kernel(double* __restrict__ xs, int ldx, int l, int LP, int nbk,
+                                                       int round, double tol, int* __restrict__ rot, int sweep) {
+  constexpr int NC = 2 * W;                 // columns of the block pair
+  constexpr int NT = NC / 16;               // 16-column MFMA tiles (1 or 2)
+  constexpr int NTT = NT * (NT + 1) / 2;    // tiles on and above the diagonal of G
+  constexpr int NP = NC / 2;                // disjoint inner pairs per round
+  extern __shared__ double lds[];
+  double* red = lds;                        // [8 waves][NTT tiles][256]
+  double* gb = red + 8 * NTT * 256;         // two NC x NC buffers of G (row-major)
+  double* vm = gb + 2 * NC * NC;            // V, NC x NC row-major
+  __shared__ int any_rot;
+  if (sweep > 0 && __hip_atomic_load(rot + sweep - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ci = lane & 15, g = lane >> 4;
+  const int bI = bj_player(blockIdx.x, round, nbk), bJ = bj_player(nbk - 1 - blockIdx.x, round, nbk);
+  auto gcol = [&](int c) { return c < W ? bI * W + c : bJ * W + (c - W); };
+  const int nslab = LP / 16;
+
+  // 1. Gram.  Lane (ci, g) of slab sl loads rows 16 sl + 4 g + e (e = 0..3) of pair column 16 t + ci; MFMA
+  // step e takes contraction index g <-> row 16 sl + 4 g + e for both operands.
+  {
+    const double* colp[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) colp[t] = xs + (int64_t)gcol(16 * t + ci) * ldx + 4 * g;
+    f64x4 acc[NTT];
+#pragma unroll
+    for (int t = 0; t < NTT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int sl = wave; sl < nslab; sl += 8) {
+      double x[NT][4];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const double2 a = *reinterpret_cast<const double2*>(colp[t] + 16 * sl);
+        const double2 b = *reinterpret_cast<const double2*>(colp[t] + 16 * sl + 2);
+        x[t][0] = a.x; x[t][1] = a.y; x[t][2] = b.x; x[t][3] = b.y;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0][e], x[0][e], acc[0], 0, 0, 0);
+        if constexpr (NT == 2) {
+          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0][e], x[1][e], acc[1], 0, 0, 0);
+          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1][e], x[1][e], acc[2], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NTT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(wave * NTT + t) * 256 + r * 64 + lane] = acc[t][r];
+  }
+  if (tid == 0) any_rot = 0;
+  for (int e = tid; e < NC * NC; e += 512) vm[e] = (e / NC == e % NC) ? 1.0 : 0.0;
+  __syncthreads();
+  // Wave partials summed in wave order.  Accumulator element r of lane L holds G(L/16 + 4 r, L % 16) of its
+  // tile; tile index 0 = (0,0), 1 = (0,1), 2 = (1,1).  The entries on and above the diagonal are kept and
+  // mirrored, so G is exactly symmetric.
+  for (int e = tid; e < NTT * 256; e += 512) {
+    const int t = e >> 8, idx = e & 255, r = idx >> 6, L = idx & 63;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) v += red[(w * NTT + t) * 256 + idx];
+    const int ta = (t == 2) ? 1 : 0, tb = (t == 0) ? 0 : 1;
+    const int a = 16 * ta + (L >> 4) + 4 * r, b = 16 * tb + (L & 15);
+    if (ta != tb || a <= b) {
+      gb[a * NC + b] = v;
+      gb[b * NC + a] = v;
+    }
+  }
+  __syncthreads();
+
+  // 2. One inner sweep on G.
+  int cur = 0;
+  for (int ir = 0; ir < NC - 1; ++ir) {
+    const double* G = gb + cur * NC * NC;
+    double* Gn = gb + (cur ^ 1) * NC * NC;
+    if (tid < NP * NP) {
+      const int kr = tid / NP, kc = tid - (tid / NP) * NP;
+      const int pr = bj_player(kr, ir, NC), qr = bj_player(NC - 1 - kr, ir, NC);
+      const int pc = bj_player(kc, ir, NC), qc = bj_player(NC - 1 - kc, ir, NC);
+      double cr, sr, tr, cc, sc, tc;
+      const double ar = G[pr * NC + pr], br = G[qr * NC + qr], gr = G[pr * NC + qr];
+      const bool rr = bj_rotation(ar, br, gr, tol, cr, sr, tr);
+      if (kr == kc) {
+        if (rr) {
+          Gn[pr * NC + pr] = ar - tr * gr;
+          Gn[qr * NC + qr] = br + tr * gr;
+          Gn[pr * NC + qr] = 0.0;
+          Gn[qr * NC + pr] = 0.0;
+          any_rot = 1;
+        } else {
+          Gn[pr * NC + pr] = ar;
+          Gn[qr * NC + qr] = br;
+          Gn[pr * NC + qr] = gr;
+          Gn[qr * NC + pr] = gr;
+        }
+      } else {
+        bj_rotation(G[pc * NC + pc], G[qc * NC + qc], G[pc * NC + qc], tol, cc, sc, tc);
+        const double b00 = G[pr * NC + pc], b01 = G[pr * NC + qc], b10 = G[qr * NC + pc], b11 = G[qr * NC + qc];
+        // B J_c, then J_r^T (B J_c)
+        const double t00 = b00 * cc - b01 * sc, t01 = b00 * sc + b01 * cc;
+        const double t10 = b10 * cc - b11 * sc, t11 = b10 * sc + b11 * cc;
+        Gn[pr * NC + pc] = cr * t00 - sr * t10;
+        Gn[pr * NC + qc] = cr * t01 - sr * t11;
+        Gn[qr * NC + pc] = sr * t00 + cr * t10;
+        Gn[qr * NC + qc] = sr * t01 + cr * t11;
+      }
+    } else if (tid >= 256) {
+      for (int item = tid - 256; item < NC * NP; item += 256) {
+        const int i = item / NP, k = item - (item / NP) * NP;
+        const int p = bj_player(k, ir, NC), q = bj_player(NC - 1 - k, ir, NC);
+        double c, sn, t;
+        if (bj_rotation(G[p * NC + p], G[q * NC + q], G[p * NC + q], tol, c, sn, t)) {
+          const double vp = vm[i * NC + p], vq = vm[i * NC + q];
+          vm[i * NC + p] = c * vp - sn * vq;
+          vm[i * NC + q] = sn * vp + c * vq;
+        }
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const bool rotated = any_rot != 0;
+
+  // 3. X <- X V: output tile jt of slab sl is D(j, i) = sum_k V(k, 16 jt + j) X(16 sl + i, k), with the A
+  // operand V^T read from LDS and the B operand X^T (16 lanes read 16 consecutive rows of one column).
+  if (rotated) {
+    for (int sl = wave; sl < nslab; sl += 8) {
+      const int i = 16 * sl + ci;
+      double xv[NC / 4];
+#pragma unroll
+      for (int st = 0; st < NC / 4; ++st) xv[st] = xs[(int64_t)gcol(4 * st + g) * ldx + i];
+#pragma unroll
+      for (int jt = 0; jt < NT; ++jt) {
+        f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int st = 0; st < NC / 4; ++st)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vm[(4 * st + g) * NC + 16 * jt + ci], xv[st], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xs[(int64_t)gcol(16 * jt + g + 4 * r) * ldx + i] = acc[r];
+      }
+    }
+  }
+  if (tid == 0 && rotated) atomicAdd(rot + sweep, 1);
+}
+
+// flags[3] = sweeps run (the first with no rotation included), flags[2] += 1 if every enqueued sweep rotated.
+__global__ void bj_flags_kernel(int* flags, const int* rot, int cap) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (nonconv) atomicAdd(&flags[2], 1);
-    atomicMax(&flags[3], sweeps);
+    int s = 0;
+    while (s < cap && rot[s] != 0) ++s;
+    if (s == cap) atomicAdd(&flags[2], 1);
+    atomicMax(&flags[3], s < cap ? s + 1 : cap);
   }
 }
 
@@ -438,56 +541,59 @@ template <typename TU>
 hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, double* sigma, double* uhat_d,
                                   TU* uhat_p, TU* vhat_p, hipStream_t s);
 
+// Sweeps enqueued for the block form: the rounds of a sweep after the converged one return at once, so only
+// the launches themselves are spent past convergence (at l = 520 the FP32-data tolerance converges in 7).
+constexpr int kBlockedSweepCap = 20;
+
+template <int W>
+constexpr size_t bj_lds_bytes() {
+  return (size_t)(8 * ((2 * W / 16) * (2 * W / 16 + 1) / 2) * 256 + 3 * (2 * W) * (2 * W)) * sizeof(double);
+}
+
 template <typename TU>
 hipError_t launch_jacobi_blocked(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma,
                                  double* uhat_d, TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s) {
-  const int W = (2 * 16 * l * 8 <= 150 * 1024) ? 16 : 8;
+  // W = 16 (32-column pair steps) up to l = 600, W = 8 beyond (the block count stays within the circle
+  // method's range and the columns past l within the scratch).
+  const int W = l <= 600 ? 16 : 8;
   int nbk = (l + W - 1) / W;
   nbk += nbk & 1;
   const int ldx = LP;
   double* xs = scratch;
   int* rot = reinterpret_cast<int*>(scratch + (size_t)(LP + 32) * LP);
-  const size_t lds = (size_t)2 * W * l * sizeof(double);
   static bool attr16 = false, attr8 = false;
   if (W == 16 && !attr16) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bj_round_kernel<16>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bj_lds_bytes<16>());
     if (e != hipSuccess) return e;
     attr16 = true;
   }
   if (W == 8 && !attr8) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bj_round_kernel<8>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bj_lds_bytes<8>());
     if (e != hipSuccess) return e;
     attr8 = true;
   }
   const int ncols = nbk * W;
+  if (ncols > LP + 32 || LP % 16 != 0) return hipErrorInvalidValue;
   const int64_t tot = (int64_t)ncols * ldx;
   hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R, l, LP, xs, ldx, ncols);
   hipError_t e = launch_fill_int(rot, 64, 0, s);
   if (e != hipSuccess) return e;
-  const int inner_max = 1;
-  int sweep = 0;
-  bool converged = (l < 2);
-  for (; sweep < max_sweeps && sweep < 64 && !converged; ++sweep) {
+  const int cap = std::min(std::max(max_sweeps, 1), kBlockedSweepCap);
+  for (int sweep = 0; sweep < cap; ++sweep) {
     for (int round = 0; round < nbk - 1; ++round) {
       if (W == 16)
-        hipLaunchKernelGGL((bj_round_kernel<16>), dim3((unsigned)(nbk / 2)), dim3(512), lds, s, xs, ldx, l, nbk,
-                           round, tol, inner_max, rot + sweep);
+        hipLaunchKernelGGL((bj_round_kernel<16>), dim3((unsigned)(nbk / 2)), dim3(512), bj_lds_bytes<16>(), s, xs,
+                           ldx, l, LP, nbk, round, tol, rot, sweep);
       else
-        hipLaunchKernelGGL((bj_round_kernel<8>), dim3((unsigned)(nbk / 2)), dim3(512), lds, s, xs, ldx, l, nbk,
-                           round, tol, inner_max, rot + sweep);
+        hipLaunchKernelGGL((bj_round_kernel<8>), dim3((unsigned)(nbk / 2)), dim3(512), bj_lds_bytes<8>(), s, xs,
+                           ldx, l, LP, nbk, round, tol, rot, sweep);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int h = 1;
-    e = hipMemcpyAsync(&h, rot + sweep, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    converged = (h == 0);
   }
-  hipLaunchKernelGGL(bj_flags_kernel, dim3(1), dim3(64), 0, s, flags, sweep, converged ? 0 : 1);
+  hipLaunchKernelGGL(bj_flags_kernel, dim3(1), dim3(64), 0, s, flags, rot, cap);
   return jacobi_epilogue_launch<TU>(xs, ldx, l, LP, sigma, uhat_d, uhat_p, vhat_p, s);
 }
 

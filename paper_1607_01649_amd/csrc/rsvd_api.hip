@@ -709,7 +709,6 @@ const char* rsvd_status_str(int s) {
     case RSVD_E_HIP: return "RSVD_E_HIP";
     case RSVD_E_NONFINITE: return "RSVD_E_NONFINITE";
     case RSVD_E_UNSUPPORTED: return "RSVD_E_UNSUPPORTED";
-    case RSVD_E_BREAKDOWN: return "RSVD_E_BREAKDOWN";
     default: return "RSVD_UNKNOWN_STATUS";
   }
 }
@@ -798,7 +797,6 @@ rsvd_status factor_fixed(rsvd_plan_t p, const void* d_A, int64_t lda, const doub
       h_info->err_bound = p->err_bound;
       h_info->frob_residual = p->frob_res;
       h_info->sigma1 = s1;
-      h_info->orth_retries = 0;
       if (p->timing) {
         for (int i = 0; i < 5; ++i) (void)hipEventElapsedTime(&h_info->stage_ms[i], p->ev[i], p->ev[i + 1]);
         const int last = d.eps > 0.0 ? 7 : 5;

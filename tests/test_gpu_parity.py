@@ -211,6 +211,10 @@ FP8_CASES = [
     (3000, 1500, 300, 0.5, 20, 10, 2, "fp8", "fp8"),
     (1237, 901, 200, 1.0, 12, 8, 1, "fp8", "f32"),
     (2048, 1024, 256, 0.5, 50, 14, 2, "fp8", "fp8"),
+    # FP8 sketch with a bf16 projection (two low-precision copies of A)
+    (3000, 1500, 300, 0.5, 20, 10, 2, "fp8", "bf16"),
+    # m mod 256 in [1, 128]: the last row block has waves wholly past the last row
+    (1068, 700, 200, 1.0, 16, 8, 1, "fp8", "fp8"),
 ]
 
 
@@ -233,6 +237,99 @@ def test_factor_fp8_matches_the_quantisation_aware_oracle(m, n, rank, alpha, k, 
     assert max_rel_sigma(S, qa.D, k) <= 1e-3
     print(f"fp8 format error vs plain oracle: max rel sigma {max_rel_sigma(S, plain.D, k):.2e}")
     assert max_rel_sigma(S, plain.D, k) <= 0.1
+
+
+def test_factor_fp8_at_l520_matches_the_quantisation_aware_oracle():
+    """The 65536^2 workload's shape of the method (k = 500, p = 20, q = 3,
+    exponential decay sigma_j = exp(-j/150)) at 6000 x 5000: l = 520 takes
+    three 192-column groups per FP8 product, the blocked Cholesky and the
+    block Jacobi, all on FP8-derived data; m mod 256 = 112 puts waves past the
+    last row.  Against the oracle on identically quantised operands the
+    singular values agree to 1e-3 sigma_1 (a normwise gate: one-step E4M3
+    differences in thin operands whose FP32 and FP64 values straddle a
+    rounding boundary perturb B by a small multiple of 2^-4 of those entries);
+    the format error against the plain FP64 oracle is reported."""
+    from oracle import quant
+    m, n, k, p, q = 6000, 5000, 500, 20, 3
+    sigma = gen.spectrum("exp", 1000, tau=150.0)
+    A32 = gen.low_rank_matrix(m, n, sigma, 1e-3 / math.sqrt(n), seed=61).astype(np.float32)
+    G = gen.gaussian_matrix(n, k + p, seed=62)
+    print(f"case fp8 l=520 {m}x{n}", flush=True)
+    U, S, V, info = run_factor(A32, k, p, q, "f32", omega=G, sketch_dtype="fp8", proj_dtype="fp8")
+    assert info.status == 0 and info.jacobi_sweeps >= 1
+    qa = quant.rsvd_quantized(A32, G, q, "fp8", "fp8")
+    plain = orc.rsvd(A32.astype(np.float64), G, q)
+    norm_err = float(np.max(np.abs(S[:k] - qa.D[:k]))) / qa.D[0]
+    print(f"fp8 l=520: max |sigma - sigma_qa| / sigma_1 = {norm_err:.2e}, "
+          f"max rel vs qa {max_rel_sigma(S, qa.D, k):.2e}, format error vs plain {max_rel_sigma(S, plain.D, k):.2e}")
+    assert norm_err <= 1e-3
+    assert max_rel_sigma(S, plain.D, k) <= 0.1
+    # the factors are orthonormal to FP32 accuracy and reproduce the rank-k residual of the oracle
+    assert orth_error(U) <= 1e-4 and orth_error(V) <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rank_deficient_input(dtype):
+    """A of exact rank 10 (small integers, so Y = A Omega with an integer
+    Omega is exact) with k + p = 30: the Gram matrices of CholeskyQR are
+    exactly singular.  Nothing fails; with FP32 data the dependent columns
+    fall below the pivot threshold (l u^2 G_jj) and are dropped (counted), and
+    the basis spans the range of A: the ten nonzero singular values are exact
+    to rounding, the others vanish (columns of U and V past the rank are zero
+    when dropped)."""
+    g = np.random.default_rng(4)
+    m, n, r, k, p = 500, 400, 10, 20, 10
+    A = (g.integers(-2, 3, (m, r)) @ g.integers(-2, 3, (r, n))).astype(np.float64)
+    omega = g.integers(-2, 3, (n, k + p)).astype(np.float64)
+    s_true = np.linalg.svd(A, compute_uv=False)
+    assert s_true[r - 1] > 1.0 and s_true[r] < 1e-10 * s_true[0]
+    Ain = A if dtype == "f64" else A.astype(np.float32)
+    U, S, V, info = run_factor(Ain, k, p, 1, dtype, omega=omega)
+    assert info.status == 0
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert max_rel_sigma(S, s_true, r) <= tol
+    assert np.all(np.abs(S[r:k]) <= tol * S[0])
+    Ut = np.linalg.svd(A)[0][:, :r]
+    assert subspace_sin(Ut, U[:, :r]) <= (1e-10 if dtype == "f64" else 1e-4)
+    assert np.linalg.norm(A - (U * S) @ V.T, 2) <= tol * S[0]
+    if dtype == "f32":
+        assert info.dropped_cols >= k + p - r
+        assert np.all(U[:, r:k] == 0.0) and np.all(S[r:k] == 0.0)
+
+
+def test_factor_at_l200_is_capturable_in_a_graph():
+    """With eps = 0 and no info requested, rsvd_factor enqueues everything on
+    the plan's stream without a host synchronisation, also at l > 128 (blocked
+    Cholesky and block Jacobi): the call captures into a HIP graph, and every
+    replay reproduces the eager result bit for bit."""
+    import torch
+    from paper_1607_01649_amd import RSVD, rsvd_factor
+    dev = device()
+    m, n, k, p, q = 1500, 1200, 190, 10, 1
+    sigma = gen.spectrum("poly", 600, alpha=0.5)
+    A = torch.from_numpy(gen.low_rank_matrix(m, n, sigma, 1e-6, seed=8).astype(np.float32)).to(dev)
+    s = torch.cuda.Stream(dev)
+    with torch.cuda.stream(s):
+        solver = RSVD(m, n, k, p, q, dtype="f32", device=dev, seed=11)
+        U = torch.zeros(m, k, dtype=torch.float32, device=dev)
+        S = torch.zeros(k, dtype=torch.float64, device=dev)
+        V = torch.zeros(n, k, dtype=torch.float32, device=dev)
+        st, _ = rsvd_factor(solver.plan, A, U, S, V, want_info=False)
+        assert st == 0
+    s.synchronize()
+    ref = (U.clone(), S.clone(), V.clone())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        st2, _ = rsvd_factor(solver.plan, A, U, S, V, want_info=False)
+    assert st2 == 0
+    for rep in range(3):
+        U.zero_(); S.zero_(); V.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(U, ref[0]) and torch.equal(S, ref[1]) and torch.equal(V, ref[2]), rep
+    ref_o = orc.rsvd_seeded(A.double().cpu().numpy(), k, p, q, seed=11)
+    assert max_rel_sigma(S.cpu().numpy(), ref_o.D, k) <= 1e-4
 
 
 # ---------------------------------------------------------------- certificate and fallback
