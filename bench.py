@@ -128,9 +128,40 @@ def spectral_residual(A, U, S, V, iters=40, seed=0):
     return est
 
 
+def host_cpu():
+    """CPU model, physical cores (distinct (package, core) pairs) and the CPUs this process may run on."""
+    model, cores = "unknown", set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model == "unknown":
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except Exception:
+        allowed = os.cpu_count() or 1
+    return {"cpu_model": model, "physical_cores": len(cores) or None, "cpus_allowed": allowed}
+
+
 def cpu_baseline(A_gpu, k, p, q, rows, seed, min_seconds=10.0, max_runs=20):
     """The FP64 numpy oracle (Figure 5 + Stage B, untuned) on a bounded row
-    sample of the same matrix, repeated until about min_seconds of CPU work."""
+    sample of the same matrix with the same Omega, repeated until about
+    min_seconds of CPU work.  Returns the baseline record and the oracle's
+    rank-k result (for the per-path comparison when the sample is all rows)."""
     from oracle import rsvd as orc
     from oracle import philox
     try:
@@ -143,20 +174,43 @@ def cpu_baseline(A_gpu, k, p, q, rows, seed, min_seconds=10.0, max_runs=20):
     n = A.shape[1]
     G = philox.gaussian(n, k + p, seed, philox.STREAM_OMEGA)
     runs, tot = 0, 0.0
+    res = None
     while runs < max_runs and (runs == 0 or tot < min_seconds):
         t0 = time.perf_counter()
-        orc.rsvd(A, G, q).truncate(k)
+        res = orc.rsvd(A, G, q).truncate(k)
         tot += time.perf_counter() - t0
         runs += 1
     dt = tot / runs
     flops = 2.0 * rows * n * (k + p) * (2 * q + 2)
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle (numpy float64, Figure 5 + Stage B) on the first {rows} of {A_gpu.shape[0]} rows, "
-                      f"same n, k, p, q; {runs} run(s), {tot:.1f} s in total, {dt:.2f} s per run; "
-                      f"flops counted as 2*rows*n*l*(2q+2)"}
+    rec = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"oracle (numpy float64, Figure 5 + Stage B) on the first {rows} of {A_gpu.shape[0]} rows, "
+                     f"same n, k, p, q and Omega; {runs} run(s), {tot:.1f} s in total, {dt:.2f} s per run; "
+                     f"flops counted as 2*rows*n*l*(2q+2)"}
+    rec.update(host_cpu())
+    return rec, (res if rows == A_gpu.shape[0] else None)
 
 
-def run_path(A, cfg, sketch, proj, steps, warmup, seed):
+def vs_oracle(ref, S, U):
+    """Error of one path's rank-k result against the FP64 oracle's on the same A and Omega: largest relative
+    singular-value error, and the sine of the largest principal angle between the left subspaces."""
+    Sg = np.asarray(S, dtype=np.float64)
+    rel = np.abs(Sg - ref.D) / ref.D
+    M = ref.U.T @ np.asarray(U, dtype=np.float64)
+    cmin = float(np.linalg.svd(M, compute_uv=False).min())
+    return {"sigma_rel_err_max": float(rel.max()), "sigma_rel_err_at_k": float(rel[-1]),
+            "sin_theta_U": math.sqrt(max(0.0, 1.0 - min(cmin, 1.0) ** 2))}
+
+
+def vs_planted(sig, S):
+    """Singular values of a noise-free planted matrix against the planted ones (their exact values up to the
+    float32 rounding of A): largest error relative to sigma_j and to sigma_1."""
+    Sg = np.asarray(S, dtype=np.float64)
+    s = np.asarray(sig[:len(Sg)], dtype=np.float64)
+    return {"sigma_rel_err_max": float((np.abs(Sg - s) / s).max()),
+            "sigma_err_max_over_sigma1": float(np.abs(Sg - s).max() / s[0])}
+
+
+def run_path(A, cfg, sketch, proj, steps, warmup, seed, keep_u=True):
     """Time `steps` factorisations with the given operand precisions; returns
     the measurements and the last factors."""
     import torch
@@ -185,8 +239,14 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed):
     passes = 2 * q + 2
     avg_nn = nn_ms / max(nn_n, 1) * 1e-3
     avg_tn = tn_ms / max(tn_n, 1) * 1e-3
-    # column tiles of 16 per workgroup of the low-precision product (bf16 at most 7, FP8 an even count <= 8)
-    lp_nb = min(7, (l + 15) // 16) if sketch == "bf16" else (min(8, (l + 15) // 16) + 1) // 2 * 2
+    # column tiles of 16 per workgroup of the low-precision product: bf16 at most 7; FP8 an even count <= 12,
+    # the fewest column groups first
+    nt = (l + 15) // 16
+    if sketch == "bf16":
+        lp_nb = min(7, nt)
+    else:
+        groups = (nt + 11) // 12
+        lp_nb = ((nt + groups - 1) // groups + 1) // 2 * 2
     names = {"f32": ("nn_kernel (Y = A X, FP32 MFMA)", "tn_kernel (Z = A^T Q, FP32 MFMA)"),
              "f64": ("nn_kernel (Y = A X, FP64 MFMA)", "tn_kernel (Z = A^T Q, FP64 MFMA)"),
              "bf16": ("lp_nn_kernel<0,%d,4,1> (Y = bf16(A) X)" % lp_nb, "lp_nn_kernel<0,%d,4,1> (Z = bf16(A)^T Q)" % lp_nb),
@@ -219,9 +279,11 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed):
     err = spectral_residual(A, U, S, V)
     tte = {"eps": f"{fac}*sigma_{{k+1}}", "eps_abs": eps_abs, "achieved_err": err, "reached": bool(err <= eps_abs),
            "time_ms": dt * 1e3 if err <= eps_abs else None}
+    S_host = S.double().cpu().numpy()
+    U_host = U.double().cpu().numpy() if keep_u else None
     del solver, U, S, V
     torch.cuda.empty_cache()
-    return {"sketch_dtype": sketch, "proj_dtype": proj, "ms_per_step": dt * 1e3,
+    return {"_S": S_host, "_U": U_host, "sketch_dtype": sketch, "proj_dtype": proj, "ms_per_step": dt * 1e3,
             "tflops": flops_pass * passes / dt / 1e12, "stage_ms": [round(x, 4) for x in info.stage_ms],
             "jacobi_sweeps": info.jacobi_sweeps, "time_to_eps": tte, "roofline": roof}
 
@@ -300,6 +362,10 @@ def main():
     ap.add_argument("--paths", default="bf16,f32", help="comma list; the first one is the headline")
     ap.add_argument("--cpu-rows", type=int, default=1 << 30, help="row sample of the CPU oracle (default: all rows)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--also", default="expdecay_65536:fp8",
+                    help="comma list of workload:sketch[/proj] legs timed after the headline ('' for none)")
+    ap.add_argument("--leg-steps", type=int, default=5)
+    ap.add_argument("--leg-warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--batched-wg", type=int, default=0, help="workgroups of the batched launch (0 = library default)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -337,7 +403,7 @@ def main():
     res = {}
     print(f"[bench] {args.workload}: matrix ready", file=sys.stderr, flush=True)
     for pth in paths:
-        res[pth] = run_path(A, cfg, pth, pth, args.steps, args.warmup, args.seed)
+        res[pth] = run_path(A, cfg, pth, pth, args.steps, args.warmup, args.seed, keep_u=not args.no_cpu)
         print(f"[bench] path {pth}: {res[pth]['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
     head = res[paths[0]]
     out = {"metric": METRIC, "value": head["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -347,7 +413,43 @@ def main():
                       "sketch_dtype": paths[0], "proj_dtype": paths[0], "a_dtype": cfg.dtype},
            "time_to_eps": head["time_to_eps"], "roofline": head["roofline"], "paths": res}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(A, cfg.k, cfg.p, cfg.q, args.cpu_rows, args.seed)
+        out["cpu_baseline"], ref = cpu_baseline(A, cfg.k, cfg.p, cfg.q, args.cpu_rows, args.seed)
+        print("[bench] cpu oracle done", file=sys.stderr, flush=True)
+        if ref is not None:
+            for pth in paths:
+                res[pth]["vs_fp64_oracle"] = vs_oracle(ref, res[pth]["_S"], res[pth]["_U"])
+    if cfg.noise_std == 0.0:
+        for pth in paths:
+            res[pth]["vs_planted_sigma"] = vs_planted(cfg.sigma(), res[pth]["_S"])
+    for pth in paths:
+        res[pth].pop("_S")
+        res[pth].pop("_U")
+    del A
+    torch.cuda.empty_cache()
+    # further legs: other workloads and operand formats, each with its own roofline (not part of `value`)
+    legs = {}
+    for leg in [x for x in args.also.split(",") if x]:
+        wl, _, fmt = leg.partition(":")
+        sk, _, pj = fmt.partition("/")
+        pj = pj or sk
+        c2 = gen.config(wl)
+        A2 = c2.matrix(seed=args.seed, device=str(dev))
+        A2 = A2.to(torch.float32) if c2.dtype == "f32" else A2
+        torch.cuda.synchronize()
+        print(f"[bench] {wl}: matrix ready", file=sys.stderr, flush=True)
+        r = run_path(A2, c2, sk, pj, args.leg_steps, args.leg_warmup, args.seed, keep_u=False)
+        if c2.noise_std == 0.0:
+            r["vs_planted_sigma"] = vs_planted(c2.sigma(), r["_S"])
+        r.pop("_S")
+        r.pop("_U")
+        r.update({"workload": wl, "m": c2.m, "n": c2.n, "k": c2.k, "p": c2.p, "q": c2.q,
+                  "steps": args.leg_steps, "warmup": args.leg_warmup})
+        legs[leg] = r
+        print(f"[bench] leg {leg}: {r['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
+        del A2
+        torch.cuda.empty_cache()
+    if legs:
+        out["legs"] = legs
     print(json.dumps(out), flush=True)
 
 
