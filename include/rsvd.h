@@ -223,6 +223,35 @@ rsvd_status rsvd_factor(rsvd_plan_t plan, const void* d_A, int64_t lda, const do
 void rsvd_destroy(rsvd_plan_t plan);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * fixed-rank factorisation of rsvd_factor (eps == 0, h_info == NULL) with no
+ * plan and no caller workspace.  Arguments d_A .. ldv as for rsvd_factor;
+ * stream is a hipStream_t.  The workspace is one library-held device array of
+ * RSVD_NOALLOC_WORKSPACE_BYTES per device (taken at the first call on that
+ * device, held until the process ends); the call allocates nothing and is
+ * asynchronous (enqueues kernels and device-to-device copies only).
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (two streams, two host threads) race and give undefined
+ * results.  The array keeps the last call's contents; nothing in it needs
+ * to start at zero.
+ * Limits: fixed p, q >= 0 (no selector), eps == 0 (no certificate or
+ * growth), no RSVD_TIMING, and rsvd_workspace_size(d) at most
+ * RSVD_NOALLOC_WORKSPACE_BYTES (for instance 2000 x 2000 in FP64 at
+ * k + p = 30 needs 6 MiB, 4000 x 3000 in FP32 at k + p = 128 needs 35 MiB,
+ * 20000 x 20000 in FP32 at k + p = 110 needs 308 MiB and is refused; the
+ * low-precision paths only for small A, whose converted copies live in the
+ * workspace).  Non-finite input is not reported (use
+ * rsvd_factor with h_info for that).
+ * Errors: RSVD_E_ARG (as rsvd_factor, or a limit above), RSVD_E_WORKSPACE
+ * (the description needs more than the array), RSVD_E_UNSUPPORTED (dtype
+ * combination, or device ordinal >= 64), RSVD_E_HIP.
+ */
+#define RSVD_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+rsvd_status rsvd_factor_noalloc(const rsvd_desc* d, const void* d_A, int64_t lda, const double* d_Omega,
+                                void* d_U, int64_t ldu, double* d_S, void* d_V, int64_t ldv, void* stream);
+
+/*
  * Attach selector parameters to a plan made with p = q = -1: d_theta
  * (device, RSVD_MLP_NPARAM floats, caller-owned, must stay valid while the
  * plan is used) and the probability threshold tau in (0, 1).

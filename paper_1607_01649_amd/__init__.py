@@ -91,6 +91,15 @@ def rsvd_factor(plan, A: torch.Tensor, U: torch.Tensor, S: torch.Tensor, V: Opti
     return st, info
 
 
+def rsvd_factor_noalloc(desc: rsvd_desc, A: torch.Tensor, U: torch.Tensor, S: torch.Tensor,
+                        V: Optional[torch.Tensor], omega: Optional[torch.Tensor] = None, stream=None) -> int:
+    """The fixed-rank factorisation in the library's own per-device workspace
+    (no plan, no allocation); returns the status."""
+    return _lib.lib().rsvd_factor_noalloc(ctypes.byref(desc), _ptr(A), A.stride(0), _ptr(omega), _ptr(U),
+                                          U.stride(0), _ptr(S), _ptr(V), V.stride(0) if V is not None else 0,
+                                          _stream_handle(A.device, stream))
+
+
 def rsvd_destroy(plan) -> None:
     _lib.lib().rsvd_destroy(plan)
 

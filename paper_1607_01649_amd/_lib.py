@@ -66,6 +66,8 @@ SIGNATURES = [
     ("rsvd_factor", ctypes.c_int, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p,
                                    _i64, ctypes.POINTER(rsvd_info)]),
     ("rsvd_destroy", None, [_c_void_p]),
+    ("rsvd_factor_noalloc", ctypes.c_int, [ctypes.POINTER(rsvd_desc), _c_void_p, _i64, _c_void_p, _c_void_p, _i64,
+                                           _c_void_p, _c_void_p, _i64, _c_void_p]),
     ("rsvd_gaussian", ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, _i64, _i64, _i64, ctypes.c_int32, _c_void_p,
                                      _i64, _c_void_p]),
     ("rsvd_philox4x32_10", ctypes.c_int, [_i64, _c_void_p, ctypes.c_uint32, ctypes.c_uint32, _c_void_p,

@@ -127,4 +127,10 @@ template <typename TO>
 hipError_t launch_rowmajor_to_panel(const double* src, int64_t rows, int64_t cols, int64_t ld_src, TO* dst,
                                     int64_t ld_dst, hipStream_t s);
 
+// rsvd_api.hip: one fixed-rank factorisation (eps == 0, fixed p and q, no timing) in a caller-given
+// workspace, with a plan built on the stack; RSVD_E_WORKSPACE when the description needs more than
+// ws_bytes.  The same launch sequence as rsvd_plan + rsvd_factor with h_info == NULL.
+int factor_in_workspace(const void* desc, void* ws, size_t ws_bytes, hipStream_t st, const void* A, int64_t lda,
+                        const double* omega, void* U, int64_t ldu, double* S, void* V, int64_t ldv);
+
 }  // namespace rsvd

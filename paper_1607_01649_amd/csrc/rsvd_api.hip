@@ -823,6 +823,29 @@ rsvd_status factor_fixed(rsvd_plan_t p, const void* d_A, int64_t lda, const doub
   return s;
 }
 
+}  // namespace
+
+int rsvd::factor_in_workspace(const void* desc, void* ws, size_t ws_bytes, hipStream_t st, const void* d_A,
+                              int64_t lda, const double* d_Omega, void* d_U, int64_t ldu, double* d_S, void* d_V,
+                              int64_t ldv) {
+  const rsvd_desc* d = static_cast<const rsvd_desc*>(desc);
+  if (!validate(d) || !d_A || !d_U || !d_S) return RSVD_E_ARG;
+  if (selector_mode(d) || d->eps != 0.0 || (d->flags & RSVD_TIMING)) return RSVD_E_ARG;
+  rsvd_status s = supported(d);
+  if (s != RSVD_OK) return s;
+  rsvd_plan_s p{};
+  p.d = *d;
+  p.L = make_layout(d);
+  if (!ws || p.L.total > ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return RSVD_E_WORKSPACE;
+  p.st = st;
+  p.ws = static_cast<char*>(ws);
+  p.timing = false;
+  if (hipGetDevice(&p.device) != hipSuccess) return RSVD_E_HIP;
+  return factor_fixed(&p, d_A, lda, d_Omega, d_U, ldu, d_S, d_V, ldv, nullptr);
+}
+
+namespace {
+
 // Modelled time (ms) of the plain method at (p, q); see include/rsvd.h.
 double sel_cost_ms(int64_t m, int64_t n, int k, int p, int q) {
   const double l = (double)std::min<int64_t>({(int64_t)k + p, m, n});

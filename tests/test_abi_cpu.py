@@ -134,3 +134,13 @@ def test_selector_and_network_entries_reject_bad_arguments(lib):
     assert lib.rsvd_mlp_backward(f, 4, f, f, f, f, f, f, f, f, None, None) == -1
     assert lib.rsvd_mlp_adam(f, f, f, f, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1     # step must be >= 1
     assert lib.rsvd_mlp_adam(f, f, f, f, 10, 1e-3, 1.0, 0.999, 1e-8, 1, None) == -1     # beta1 < 1
+
+
+def test_no_alloc_entry_checks_its_limits_before_touching_the_device(lib):
+    f = ctypes.c_void_p(4096)
+    big = _desc(m=20000, n=20000, k=100, p=10, q=2)
+    assert lib.rsvd_factor_noalloc(ctypes.byref(big), f, 20000, None, f, 100, f, None, 0, None) == -2
+    for kw in (dict(eps=1e-3, max_rank=40), dict(p=-1, q=-1), dict(flags=2), dict(k=0)):
+        d = _desc(**kw)
+        assert lib.rsvd_factor_noalloc(ctypes.byref(d), f, 800, None, f, 40, f, None, 0, None) == -1
+    assert lib.rsvd_factor_noalloc(None, f, 800, None, f, 40, f, None, 0, None) == -1
