@@ -3,19 +3,14 @@
 //
 // orth(Y) (Section 2.3: any unpivoted orthonormalisation will do) is computed
 // as CholeskyQR: G = Y^T Y = R^T R, Q = Y R^-1.  This kernel factors G and at
-// the same time builds R^-T by applying every elimination step to an identity
-// block, so the triangular apply that follows is a plain panel product with
-// R^-1 and no sequential back-substitution is needed.
+// the same time builds R^-T (the elimination applied to an identity block), so
+// the triangular apply that follows is a plain panel product with R^-1.
 //
-// Elimination is run in the unscaled (L D L^T) form: at step j every row
-// a > j is updated from the still-unscaled row j,
-//     U(a, b) -= U(j, a) U(j, b) / d_j          (b >= a, the trailing block)
-//     T(a, b) -= U(j, a) T(j, b) / d_j          (b <= j, the identity block)
-// with d_j = U(j, j); the steps are grouped in panels of 16 pivots (below).
-// At the end R = D^-1/2 U and R^-T = D^-1/2 T.
-//
-// Storage: register blocks, l <= 128; larger l goes to the blocked
-// multi-workgroup form in blocked.hip.
+// l <= 128: right-looking block Cholesky over 16 x 16 blocks held in LDS.  The
+// diagonal blocks are factored by one wave in registers (unscaled elimination,
+// pivot d_j = U(j, j), R = D^-1/2 U, R^-T = D^-1/2 T); the block row solve,
+// the trailing update and the carried inverse run on the FP64 MFMA.  Larger l
+// goes to the blocked multi-workgroup form in blocked.hip.
 //
 // Numerically dependent columns (pivot <= tau_rel * G_jj) are dropped: they
 // take no part in later eliminations, row j of R and column j of R^-1 come out
@@ -27,259 +22,315 @@
 
 namespace rsvd {
 
-constexpr int kCholThreads = 1024;
+constexpr int kCholThreads = 512;   // eight waves
+constexpr int kCholWaves = kCholThreads / 64;
+constexpr int kCholB = 16;          // block size (one FP64 MFMA tile)
+constexpr int kWdPitch = 17;        // LDS pitch of a diagonal block of W (odd: conflict-free column reads)
 
-// Value of lane `src` (wave-uniform) of a double held in a VGPR.
-__device__ __forceinline__ double lane_f64(double v, int src) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, src);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+// 1/x for finite x > 0: hardware estimate and two Newton steps.
+__device__ __forceinline__ double chol_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
 }
 
-constexpr int kCholNB = 16;     // pivots per panel
-constexpr int kCholPitch = 132; // LDS pitch of a published panel row (16-byte aligned quads)
+// Value of lane X of the caller's 16-lane row (64-bit DPP move with row_newbcast, gfx90a and later).
+template <int X>
+__device__ __forceinline__ double row_lane_f64(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + X, 0xF, 0xF, false);
+}
 
-// l <= 128: thread t owns the 4 x 4 register blocks U[4][4] and T[4][4] of
-// rows a0..a0+3 and columns b0..b0+3.  A wave covers a 32 x 32 tile (wave w:
-// row band w / 4, column band w % 4), so whole waves skip what is dead for
-// them (rows all before the panel, U columns all before it, T columns all
-// after it).  U starts as G's upper triangle, T as the identity.
-// The pivots are taken in panels P = [p0, p0+16), with three barriers per
-// panel instead of one per pivot:
-//   1. the owners of the panel rows publish [U(P, :) T(P, :)] to LDS;
-//   2. the panel rows are eliminated among themselves pivot by pivot, one
-//      lane per column: lanes 0..15 of each of waves 0..3 hold the 16 x 16
-//      diagonal block (so the pivot and the pivot row's entries reach every
-//      lane of the wave by lane broadcast, with no barrier, and each lane
-//      divides its own entry by the pivot meanwhile), the other lanes hold
-//      the U columns right of the block and the T columns up to the panel's
-//      end;
-//   3. every trailing row a takes the panel's pivots at once,
-//      [U(a, :) T(a, :)] -= sum_j U(j, a) / d_j [U(j, :) T(j, :)] over the
-//      final panel rows, and the panel rows take their final values.
-// This is the elimination of one pivot at a time regrouped (each update uses
-// the pivot row as it stands after the earlier pivots, as before); only the
-// order in which a trailing entry receives the panel's 16 terms changes.
+// u[X] = lane X's value of w, for X = X0 .. 15.
+template <int X0, int X>
+__device__ __forceinline__ void row_gather(double (&u)[16], double w) {
+  if constexpr (X < 16) {
+    u[X] = row_lane_f64<X>(w);
+    row_gather<X0, X + 1>(u, w);
+  }
+}
+
+// Factorisation of one 16 x 16 diagonal block by one wave, in registers.  Every 16-lane row holds the
+// block (the four rows compute the same): lane c holds column c of the symmetric block, v[x] = A(x, c),
+// and column c of T, t[x] (the identity at the start).  Unscaled elimination with pivot d_j = A(j, j):
+//     A(x, c) -= A(x, j) A(j, c) / d_j      (x > j, c > j)
+//     T(x, c) -= A(x, j) T(j, c) / d_j      (x > j)
+// A(j, c) and T(j, c) are the lane's own entries; A(x, j) = A(j, x) (the trailing block stays symmetric)
+// is lane x's entry j, taken by a row broadcast, as is the pivot; the loops over x start past j at
+// compile time.  R = D^-1/2 U and R^-T = D^-1/2 T.  A pivot takes part only when d_j > tau_rel G_jj and
+// d_j > 0 with j < nv (a NaN fails the test); otherwise 1/d_j is taken as 0, so that its row of R and its
+// row and column of R^-T come out zero.  Lane j keeps d_j and 1/d_j (dj, dl).
+template <int J>
+__device__ __forceinline__ void chol_pivot(double (&v)[16], double (&t)[16], double& dj, double& dl, double tg,
+                                           int nv, int c) {
+  const double d = row_lane_f64<J>(v[J]);
+  const double thr = row_lane_f64<J>(tg);   // tau_rel G_jj
+  double u[16];
+  row_gather<J + 1, J + 1>(u, v[J]);
+  const bool keep = (J < nv) & (d > thr) & (d > 0.0) & (d < 1.79769313486231570815e308);
+  const double dinv = keep ? chol_rcp(d) : 0.0;
+  const double f = (c <= J) ? 0.0 : v[J] * dinv;
+  const double ft = t[J] * dinv;
+#pragma unroll
+  for (int x = J + 1; x < 16; ++x) {
+    v[x] -= u[x] * f;
+    t[x] -= u[x] * ft;
+    asm volatile("" : "+v"(t[x]));   // update T now: deferring it keeps every broadcast value live
+  }
+  dj = (c == J) ? d : dj;
+  dl = (c == J) ? dinv : dl;
+}
+
+template <int J>
+__device__ __forceinline__ void chol_pivots(double (&v)[16], double (&t)[16], double& dj, double& dl, double tg,
+                                            int nv, int c) {
+  if constexpr (J < kCholB) {
+    chol_pivot<J>(v, t, dj, dl, tg, nv, c);
+    chol_pivots<J + 1>(v, t, dj, dl, tg, nv, c);
+  }
+}
+
+// Row scale of R and R^-T: out[x] = lane x's value of r.
+template <int X>
+__device__ __forceinline__ void row_all(double (&out)[16], double r) {
+  if constexpr (X < 16) {
+    out[X] = row_lane_f64<X>(r);
+    row_all<X + 1>(out, r);
+  }
+}
+
+// Diagonal block at blk (leading dimension ldb, the symmetric block in both triangles) -> R_JJ into blk
+// (zero below the diagonal) and W_JJ = R_JJ^-T into wblk (pitch kWdPitch, zero above the diagonal).
+// gd: the original diagonal entries of the block's columns.  One wave.  Pivots past nv (padding) are not
+// counted; a valid pivot that does not take part is counted as dropped (flags[1]) or, when d_j or G_jj
+// is not finite, as non-finite (flags[0]).
+__device__ __forceinline__ void chol_block(double* __restrict__ blk, int ldb, const double* __restrict__ gd, int nv,
+                                           double tau_rel, int lane, double* __restrict__ wblk, int& bad,
+                                           int& dropped) {
+  const int c = lane & 15;
+  double v[16], t[16];
+#pragma unroll
+  for (int x = 0; x < 16; ++x) {
+    v[x] = blk[x * ldb + c];
+    t[x] = (x == c) ? 1.0 : 0.0;
+  }
+  const double g0 = gd[c];
+  double dj = 0.0, dl = 0.0;
+  chol_pivots<0>(v, t, dj, dl, tau_rel * g0, nv, c);
+  const bool valid = c < nv && lane < 16;
+  const bool nonfinite = valid && !(fabs(dj) <= 1.79769313486231570815e308 && fabs(g0) <= 1.79769313486231570815e308);
+  const bool drop = valid && !nonfinite && dl == 0.0;
+  bad += __builtin_popcountll(__ballot(nonfinite));
+  dropped += __builtin_popcountll(__ballot(drop));
+  double rs[16];
+  row_all<0>(rs, dl > 0.0 ? sqrt(dl) : 0.0);
+  if (lane < 16) {
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+      blk[x * ldb + c] = (c >= x) ? v[x] * rs[x] : 0.0;
+      wblk[x * kWdPitch + c] = (c <= x) ? t[x] * rs[x] : 0.0;
+    }
+  }
+}
+
+// One 16 x 16 FP64 MFMA product D = C + sum_k A(i, k) B(k, j) over k < 16, with lane (g, i) supplying
+// A(i, 4 s + g) and B(4 s + g, i) at step s; element e of lane (g, j) of the result is D(g + 4 e, j).
+__device__ __forceinline__ f64x4 mma16(const double* __restrict__ A, int sai, int sak, const double* __restrict__ B,
+                                       int sbk, int sbj, f64x4 acc, int lane, double sign) {
+  const int g = lane >> 4, i = lane & 15;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + g;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * A[i * sai + k * sak], B[k * sbk + i * sbj], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// l <= 128: one workgroup of eight waves, G in LDS as an LP x (LP + 1) matrix M of 16 x 16 blocks.  The
+// blocks on and above the diagonal hold A (the trailing matrix) and become R; the blocks below it hold T
+// (the accumulated elimination of the identity) and become R^-T, whose diagonal blocks live apart in Wd.
+// Right-looking block Cholesky with the inverse carried along (block forward substitution of R^T X = I):
+//   block column J, with R_JJ and W_JJ = R_JJ^-T from the factorisation of the diagonal block:
+//     P(J): R_JK = W_JJ A_JK (K > J) and W_JM = W_JJ T_JM (M < J)            [one MFMA task per wave]
+//     T(J): A_KL -= R_JK^T R_JL (J < K <= L), T_KM -= R_JK^T W_JM (K > J, M <= J); wave 0 first updates
+//           block (J+1, J+1) and factors it, in registers, while the others take the remaining blocks.
+// Two barriers per block column.  The elimination is the pivot-by-pivot one regrouped by blocks, with the
+// same drop rule (against the original diagonal) and the same unscaled pivots inside each block.
 template <typename TQ>
-__global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(const double* __restrict__ g, int64_t ldg, int l,
-                                                                   int LP, double tau_rel, TQ* __restrict__ rinv_p,
-                                                                   double* __restrict__ r_out,
-                                                                   const double* __restrict__ r_prev,
-                                                                   int* __restrict__ flags) {
-  __shared__ double dinvP[kCholNB];                          // 1/d_j, 0 for a dropped pivot
-  __shared__ double DblkIn[kCholNB * (kCholNB + 1)];         // diagonal block as published
-  __shared__ double Dblk[kCholNB * (kCholNB + 1)];           // eliminated diagonal block (upper)
+__global__ __launch_bounds__(kCholThreads) void chol_blk_kernel(const double* __restrict__ g, int64_t ldg, int l,
+                                                                 int LP, double tau_rel, TQ* __restrict__ rinv_p,
+                                                                 double* __restrict__ r_out,
+                                                                 const double* __restrict__ r_prev,
+                                                                 int* __restrict__ flags) {
+  extern __shared__ __align__(16) double chol_lds[];
+  const int MP = LP + 1;
+  const int nb = LP / kCholB;
+  double* M = chol_lds;                    // LP x MP
+  double* Wd = chol_lds + LP * MP;         // nb blocks of 16 x kWdPitch
   __shared__ double gdiag[128];
-  __shared__ double rsd[128];     // 1/sqrt(d_j), 0 for a dropped column
-  // dynamic LDS: the panel rows [Up | Tp] during the elimination, then (when r_out
-  // is wanted) U as LP x LP for the output
-  extern __shared__ __align__(16) double chol_dyn[];
-  double* Up = chol_dyn;                          // U part of the panel rows
-  double* Tp = chol_dyn + kCholNB * kCholPitch;   // T part of the panel rows
-  double* Ufull = chol_dyn;
-  const int tid = threadIdx.x;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63;   // wave index in a scalar register
-  const int a0 = 32 * (wv >> 2) + 4 * (ln >> 3), b0 = 32 * (wv & 3) + 4 * (ln & 7);
-  const int rlast = 32 * (wv >> 2) + 31, cfirst = 32 * (wv & 3), clast = cfirst + 31;
-  double U[4][4], T[4][4];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lg = lane >> 4, lc = lane & 15;
+
+  // load: A blocks (on and above the block diagonal) from G (symmetric, both triangles stored); T blocks
+  // (below) zero.  A thread takes four consecutive rows a .. a+3 of column b (one block), loaded before
+  // any store.
+  {
+    const int ng = LP / 4;                       // row quads per column
+    const int nitem = LP * ng;
+    constexpr int kIt = 128 * 32 / kCholThreads;  // items per thread at LP = 128
+    double gv[kIt][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int it = 0; it < kIt; ++it) {
+      const int item = tid + kCholThreads * it;
+      const int b = item / ng, a = 4 * (item - (item / ng) * ng);
+      const bool up = item < nitem && b < l && (a >> 4) <= (b >> 4);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      int a = a0 + i, b = b0 + k;
-      U[i][k] = (a < l && b < l && a <= b) ? g[(int64_t)b * ldg + a] : 0.0;
-      T[i][k] = (a == b) ? 1.0 : 0.0;
-      if (a == b && a < l) gdiag[a] = U[i][k];
+      for (int e = 0; e < 4; ++e) gv[it][e] = (up && a + e < l) ? g[(int64_t)b * ldg + a + e] : 0.0;
     }
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int item = tid + kCholThreads * it;
+      if (item >= nitem) continue;
+      const int b = item / ng, a = 4 * (item - (item / ng) * ng);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) M[(a + e) * MP + b] = gv[it][e];
+      if ((b & ~3) == a) {
+        const int e = b & 3;
+        gdiag[b] = e == 0 ? gv[it][0] : e == 1 ? gv[it][1] : e == 2 ? gv[it][2] : gv[it][3];
+      }
+    }
+  }
+  __syncthreads();
   int bad = 0, dropped = 0;
-  for (int p0 = 0; p0 < l; p0 += kCholNB) {
-    const int np = min(kCholNB, l - p0), pe = p0 + np;
-    // 1. publish the panel rows
-    if (a0 + 3 >= p0 && a0 < pe) {
+  // Iteration J (from -1): T(J) -- the trailing update by block row J (none for J = -1) by waves 1..3 and,
+  // by wave 0, the update and factorisation of diagonal block J+1 -- then P(J+1).
+  for (int J = -1; J < nb - 1; ++J) {
+    const int r0 = kCholB * J, r1 = r0 + kCholB;
+    const double* WJ = Wd + (J < 0 ? 0 : J) * kCholB * kWdPitch;
+    if (wv == 0) {
+      double* dblk = M + r1 * MP + r1;
+      if (J >= 0) {
+        const double* rk = M + r0 * MP + r1;   // R_{J, J+1}
+        f64x4 acc;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int a = a0 + i;
-        if (a >= p0 && a < pe)
+        for (int e = 0; e < 4; ++e) acc[e] = dblk[(lg + 4 * e) * MP + lc];
+        acc = mma16(rk, 1, MP, rk, MP, 1, acc, lane, -1.0);
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int b = b0 + k;
-            // Up holds the columns right of the panel (zero elsewhere); the diagonal block
-            // goes to DblkIn
-            Up[(a - p0) * kCholPitch + b] = (b >= pe) ? U[i][k] : 0.0;
-            if (b >= p0 && b < pe) DblkIn[(a - p0) * (kCholNB + 1) + b - p0] = (b >= a) ? U[i][k] : 0.0;
-            Tp[(a - p0) * kCholPitch + b] = T[i][k];
-          }
+        for (int e = 0; e < 4; ++e) dblk[(lg + 4 * e) * MP + lc] = acc[e];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+      chol_block(dblk, MP, gdiag + r1, l - r1, tau_rel, lane, Wd + (J + 1) * kCholB * kWdPitch, bad, dropped);
+    } else if (J >= 0) {
+      const int nt = nb - 1 - J;                    // block rows below J
+      const int nupper = nt * (nt + 1) / 2 - 1;     // trailing A blocks except (J+1, J+1)
+      const int ntask = nupper + nt * (J + 1);
+      for (int task = wv - 1; task < ntask; task += kCholWaves - 1) {
+        int K, L;
+        const double* bop;
+        int sbk;
+        if (task < nupper) {
+          // upper blocks (K, L), J < K <= L, in row order, (J+1, J+1) skipped
+          int t = task + 1, k = 0;
+          while (t >= nt - k) { t -= nt - k; ++k; }
+          K = J + 1 + k;
+          L = K + t;
+          bop = M + r0 * MP + kCholB * L;
+          sbk = MP;
+        } else {
+          const int t = task - nupper;
+          K = J + 1 + t / (J + 1);
+          L = t - (t / (J + 1)) * (J + 1);          // M <= J
+          bop = (L == J) ? WJ : M + r0 * MP + kCholB * L;
+          sbk = (L == J) ? kWdPitch : MP;
+        }
+        double* cblk = M + kCholB * K * MP + kCholB * L;
+        const double* rk = M + r0 * MP + kCholB * K;   // R_JK
+        f64x4 acc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = cblk[(lg + 4 * e) * MP + lc];
+        acc = mma16(rk, 1, MP, bop, sbk, 1, acc, lane, -1.0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cblk[(lg + 4 * e) * MP + lc] = acc[e];
       }
     }
     __syncthreads();
-    // 2+3. the panel's pivots, one at a time, over all columns of the panel rows.  Waves
-    // 0..3 each hold the diagonal block's columns in lanes 0..15 (each wave factors it, so
-    // the multipliers come by lane broadcast within the wave) and, in lanes 16..63, the U
-    // columns right of the block and the T columns up to the panel's end (48 per wave).
-    if (wv < 4) {
-      const int c = ln;
-      const int nuc = LP - pe;
-      const int o = 48 * wv + (c - 16);
-      double* colp = nullptr;   // this lane's column of [Up | Tp] (pitch kCholPitch)
-      if (c < 16) colp = (c < np) ? DblkIn + c : nullptr;
-      else if (o < nuc) colp = Up + pe + o;
-      else if (o - nuc < pe) colp = Tp + (o - nuc);
-      double col[kCholNB];
-      const int pitch = (c < 16) ? kCholNB + 1 : kCholPitch;
+    // P(J+1): block row J+1 of R (right of the diagonal) and of W (left of it)
+    const int Jn = J + 1;
+    const double* WJn = Wd + Jn * kCholB * kWdPitch;
+    for (int task = wv; task < nb - 1; task += kCholWaves) {
+      const int col = task < Jn ? task : task + 1;   // the block column, Jn skipped
+      double* blk = M + r1 * MP + kCholB * col;
+      f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+      acc = mma16(WJn, kWdPitch, 1, blk, MP, 1, acc, lane, 1.0);
 #pragma unroll
-      for (int a = 0; a < kCholNB; ++a) col[a] = (colp && a < np) ? colp[a * pitch] : 0.0;
-      const double gdl = (c < np) ? gdiag[p0 + c] : 0.0;   // lane j: G_jj of pivot j
-      const int lim = (c < 16) ? c : kCholNB - 1;   // diagonal-block lanes keep to the upper triangle
-#pragma unroll
-      for (int j = 0; j < kCholNB; ++j) {
-        if (j < np) {
-          const double d = lane_f64(col[j], j);
-          const double gd = lane_f64(gdl, j);
-          const bool nonfinite = !isfinite(d) || !isfinite(gd);
-          const bool drop = nonfinite || !(d > tau_rel * gd) || !(d > 0.0);
-          // 1/d_j: hardware estimate and two Newton steps
-          double r = __builtin_amdgcn_rcp(d);
-          r = fma(r, fma(-d, r, 1.0), r);
-          r = fma(r, fma(-d, r, 1.0), r);
-          const double dinv = drop ? 0.0 : r;
-          if (tid == 0) {
-            dinvP[j] = dinv;
-            bad += nonfinite;
-            dropped += (drop && !nonfinite);
-          }
-          // U(a, c) -= U(j, a) * (U(j, c) / d_j), the pivot row's entries by broadcast
-          const double t = col[j] * dinv;
-#pragma unroll
-          for (int a = j + 1; a < kCholNB; ++a) {
-            const double ua = lane_f64(col[j], a);   // U(p0+j, p0+a)
-            if (a <= lim) col[a] -= ua * t;
-          }
-        }
-        asm volatile("" ::: "memory");
-      }
-      if (c < 16) {
-        if (wv == 0 && c < np)   // the eliminated diagonal block
-#pragma unroll
-          for (int a = 0; a < kCholNB; ++a)
-            if (a < np) Dblk[a * (kCholNB + 1) + c] = col[a];
-      } else if (colp) {
-#pragma unroll
-        for (int a = 0; a < kCholNB; ++a)
-          if (a < np) colp[a * kCholPitch] = col[a];
-      }
-    }
-    __syncthreads();
-    // 3. final panel rows; trailing rows take the panel's pivots.  In Up the columns left
-    // of pe are zero and in Tp the entries right of each row's diagonal are zero (they
-    // stay exactly zero through the elimination), so f, ub and tb below need no masks.
-    if (tid < np) rsd[p0 + tid] = dinvP[tid] > 0.0 ? sqrt(dinvP[tid]) : 0.0;
-    if (rlast >= p0) {   // uniform over the wave
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int a = a0 + i;
-        if (a >= p0 && a < pe)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int b = b0 + k;
-            if (b >= pe) U[i][k] = Up[(a - p0) * kCholPitch + b];
-            else if (b >= a) U[i][k] = Dblk[(a - p0) * (kCholNB + 1) + b - p0];
-            T[i][k] = Tp[(a - p0) * kCholPitch + b];
-          }
-      }
-      if (rlast >= pe) {
-        // U is needed on and above the diagonal, T on and below it
-        const bool doU = clast >= pe && (wv >> 2) <= (wv & 3), doT = cfirst < pe && (wv & 3) <= (wv >> 2);
-#pragma unroll 2
-        for (int j = 0; j < np; ++j) {
-          const double dj = dinvP[j];   // 0 for a dropped pivot: no elimination
-          const double* uj = Up + j * kCholPitch;
-          const double* tj = Tp + j * kCholPitch;
-          double f[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) f[i] = uj[a0 + i] * dj;
-          if (doU) {
-            double ub[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) ub[k] = uj[b0 + k];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-              for (int k = 0; k < 4; ++k) U[i][k] -= f[i] * ub[k];
-          }
-          if (doT) {
-            double tb[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) tb[k] = tj[b0 + k];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-              for (int k = 0; k < 4; ++k) T[i][k] -= f[i] * tb[k];
-          }
-        }
-      }
+      for (int e = 0; e < 4; ++e) blk[(lg + 4 * e) * MP + lc] = acc[e];
     }
     __syncthreads();
   }
-  if (bad) atomicAdd(&flags[0], bad);
-  if (dropped) atomicAdd(&flags[1], dropped);
-  // R^-1 in panel layout: rinv_p[c*LP + k] = R^-T(c, k) = T(c, k) / sqrt(d_c); identity on padding.
-  if (a0 < LP && b0 < LP) {
+  if (wv == 0 && lane == 0) {
+    if (bad) atomicAdd(&flags[0], bad);
+    if (dropped) atomicAdd(&flags[1], dropped);
+  }
+  // R^-1 in panel layout: rinv_p[c*LP + k] = R^-T(c, k); identity on padding.  A thread writes four
+  // consecutive entries (one block).
+  const int ng = LP / 4;
+  for (int item = tid; item < LP * ng; item += kCholThreads) {
+    const int cc = item / ng, k0 = 4 * (item - (item / ng) * ng);
+    const int bc = cc >> 4, bk = k0 >> 4;
+    double v[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int e = 0; e < 4; ++e) {
+      const int kk = k0 + e;
+      if (cc >= l || kk >= l) v[e] = (cc == kk) ? 1.0 : 0.0;
+      else if (bc == bk) v[e] = Wd[bc * kCholB * kWdPitch + (cc & 15) * kWdPitch + (kk & 15)];
+      else v[e] = (bk < bc) ? M[cc * MP + kk] : 0.0;
+    }
+    TQ* o = rinv_p + (int64_t)cc * LP + k0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        int c = a0 + i, kk = b0 + k;
+    for (int e = 0; e < 4; ++e) o[e] = static_cast<TQ>(v[e]);
+  }
+  if (!r_out) return;
+  if (!r_prev) {
+    for (int item = tid; item < LP * ng; item += kCholThreads) {
+      const int x = item / ng, y0 = 4 * (item - (item / ng) * ng);
+      double* o = r_out + (int64_t)x * LP + y0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int y = y0 + e;
         double v;
-        if (c >= l || kk >= l) v = (c == kk) ? 1.0 : 0.0;
-        else v = (kk <= c) ? T[i][k] * rsd[c] : 0.0;
-        rinv_p[c * LP + kk] = static_cast<TQ>(v);
+        if (x >= l || y >= l) v = (x == y) ? 1.0 : 0.0;
+        else v = ((x >> 4) <= (y >> 4)) ? M[x * MP + y] : 0.0;
+        o[e] = v;
       }
-  }
-  if (r_out) {
-    if (a0 < LP && b0 < LP) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Ufull[(a0 + i) * LP + b0 + k] = U[i][k];
     }
-    __syncthreads();
-    // R = D^-1/2 U, or D^-1/2 U R_prev when the previous pass's factor is given (the product
-    // of the two passes of CholeskyQR2): each thread its own 4 x 4 block; k runs over
-    // [a0, b0+3], the terms outside [a, b] being exact zeros (U masked left of its diagonal,
-    // R_prev upper triangular with identity padding).
-    if (a0 < LP && b0 < LP) {
-      double acc[4][4];
+    return;
+  }
+  // R R_prev (the product of the two passes of CholeskyQR2), block (I, Jb) for I <= Jb: the sum over
+  // I <= K <= Jb of R_IK R_prev_KJb (both upper triangular; R_prev has identity padding).
+  const int nblk = nb * (nb + 1) / 2;
+  for (int task = wv; task < nblk; task += kCholWaves) {
+    int t = task, I = 0;
+    while (t >= nb - I) { t -= nb - I; ++I; }
+    const int Jb = I + t;
+    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int K = I; K <= Jb; ++K)
+      acc = mma16(M + kCholB * I * MP + kCholB * K, MP, 1, r_prev + (int64_t)kCholB * K * LP + kCholB * Jb, LP, 1,
+                  acc, lane, 1.0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+    for (int e = 0; e < 4; ++e) {
+      const int x = kCholB * I + lg + 4 * e, y = kCholB * Jb + lc;
+      r_out[(int64_t)x * LP + y] = (x >= l || y >= l) ? ((x == y) ? 1.0 : 0.0) : acc[e];
+    }
+  }
+  for (int task = wv; task < nb * nb; task += kCholWaves) {   // blocks below the diagonal
+    const int I = task / nb, Jb = task - (task / nb) * nb;
+    if (I <= Jb) continue;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[i][k] = 0.0;
-      if (r_prev) {
-        const int kend = min(b0 + 3, l - 1);
-#pragma unroll 4
-        for (int k = a0; k <= kend; ++k) {
-          const double2 p01 = *reinterpret_cast<const double2*>(r_prev + (int64_t)k * LP + b0);
-          const double2 p23 = *reinterpret_cast<const double2*>(r_prev + (int64_t)k * LP + b0 + 2);
-          const double p[4] = {p01.x, p01.y, p23.x, p23.y};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const double u = (k >= a0 + i) ? Ufull[(a0 + i) * LP + k] : 0.0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] += u * p[j];
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int a = a0 + i, b = b0 + j;
-          double v;
-          if (a >= l || b >= l) v = (a == b) ? 1.0 : 0.0;
-          else if (b < a || rsd[a] == 0.0) v = 0.0;
-          else v = (r_prev ? acc[i][j] : Ufull[a * LP + b]) * rsd[a];
-          r_out[a * LP + b] = v;
-        }
+    for (int e = 0; e < 4; ++e) {
+      const int x = kCholB * I + lg + 4 * e, y = kCholB * Jb + lc;
+      r_out[(int64_t)x * LP + y] = 0.0;
     }
   }
 }
@@ -289,16 +340,17 @@ hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_r
                        const double* r_prev, double* scratch, int* flags, hipStream_t s) {
   if (l < 1 || l > 1024) return hipErrorInvalidValue;
   if (LP <= 128) {
+    if (LP % kCholB != 0) return hipErrorInvalidValue;
     static bool attr_set = false;
     if (!attr_set) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_panel_kernel<TQ>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_blk_kernel<TQ>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (128 * 129 + 8 * kCholB * kWdPitch) * (int)sizeof(double));
       if (e != hipSuccess) return e;
       attr_set = true;
     }
-    size_t sh = 2 * kCholNB * kCholPitch * sizeof(double);
-    if (r_out) sh = std::max(sh, (size_t)LP * LP * sizeof(double));
-    hipLaunchKernelGGL((chol_panel_kernel<TQ>), dim3(1), dim3(kCholThreads), sh, s, g, ldg, l, LP, tau_rel, rinv_p,
+    const size_t sh = ((size_t)LP * (LP + 1) + (size_t)(LP / kCholB) * kCholB * kWdPitch) * sizeof(double);
+    hipLaunchKernelGGL((chol_blk_kernel<TQ>), dim3(1), dim3(kCholThreads), sh, s, g, ldg, l, LP, tau_rel, rinv_p,
                        r_out, r_prev, flags);
   } else {
     if (!scratch) return hipErrorInvalidValue;
