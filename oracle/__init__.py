@@ -19,6 +19,8 @@ Modules
            rounding used by the quantisation-aware mode.
   mlp      float64 forward/backward of the (p, q) selector network.
   batched  per-block tolerance driver for the batched workload.
+  srft     the structured test matrix of Section 6 (random signs, Walsh-
+           Hadamard transform, subsampled columns) and Figure 5 with it.
 
 Parity status of each function is listed in its docstring; every function
 here is pinned by a ``-m "not gpu"`` test unless it says "parity unpinned".
