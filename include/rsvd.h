@@ -55,6 +55,7 @@ typedef enum {
 /* rsvd_desc.flags */
 #define RSVD_RETURN_RANK_L 0x1u  /* return all l = k+p columns instead of the k leading ones   */
 #define RSVD_TIMING        0x2u  /* record per-stage HIP events; rsvd_info.stage_ms filled    */
+#define RSVD_SKETCH_SRHT   0x4u  /* first sketch with the structured test matrix (see below)  */
 
 /*
  * Problem description.
@@ -91,7 +92,22 @@ typedef enum {
  *   max_rank    when eps > 0: largest basis the fallback may grow to, and the
  *               column capacity U and V must have (>= k+p; 0 -> k+p, i.e. no
  *               growth).
- *   flags       RSVD_RETURN_RANK_L | RSVD_TIMING.
+ *   flags       RSVD_RETURN_RANK_L | RSVD_TIMING | RSVD_SKETCH_SRHT.
+ *
+ * RSVD_SKETCH_SRHT (Section 6; Section 14, item (1)): the first sketch is
+ * Y = A Omega with the structured test matrix Omega = D F S in real form:
+ * N = 2^ceil(log2 n) (A's rows zero-padded to N), D = diag of random signs,
+ * F = H_N / sqrt(N) with the Walsh-Hadamard matrix H_N(i, k) =
+ * (-1)^popcount(i & k), S = k+p distinct columns of the N x N identity
+ * drawn by a seeded Fisher-Yates shuffle (Philox4x32-10, key = seed, stream
+ * 10: sign i = lowest bit of word i mod 4 of counter (i div 4, 0, 10, 0);
+ * shuffle step j swaps entries j and j + floor(u_j (N - j) / 2^32) of the
+ * identity permutation, u_j = word j mod 4 of counter (j div 4, 1, 10, 0)).
+ * It is computed by a fast transform in one pass over A (O(m n log l));
+ * the power steps, Stage B, the certificate and the fallback (Gaussian
+ * blocks, stream 4, continuing at column k+p) are unchanged.  Needs
+ * sketch_dtype == a_dtype, n <= 32768 (F32) or 16384 (F64), fixed p and q
+ * (no selector); RSVD_E_ARG otherwise.
  */
 typedef struct {
   int64_t m, n;

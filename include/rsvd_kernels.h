@@ -162,6 +162,23 @@ rsvd_status rsvd_k_product_fp8(int64_t rows, int64_t K, const uint8_t* d_A8, int
                                int64_t s_row, int64_t s_k, const float* d_X, int64_t ldx, int32_t ncols,
                                float* d_out, int64_t ldo, void* d_scratch, void* stream);
 
+/*
+ * The structured test matrix of Section 6 in real form and the sketch with it
+ * (the draw and the transform that rsvd_factor runs under RSVD_SKETCH_SRHT):
+ *   d_signs  (device, n entries of prec) <- d_i in {+1, -1}
+ *   d_subset (device, l int32)           <- s_0 .. s_{l-1}, distinct, < N
+ *   d_Y      (device, m x l row-major, ldy >= l, prec) <- A Omega,
+ *            Omega = (D H_N S / sqrt(N))[:n, :], N = 2^ceil(log2 n)
+ * for A (m x n row-major, lda >= n, prec = RSVD_F32 or RSVD_F64).  The draw
+ * (Philox4x32-10, key = seed, stream 10) is the one documented with
+ * RSVD_SKETCH_SRHT in rsvd.h.  1 <= l <= min(1024, N); n <= 32768 (F32) or
+ * 16384 (F64).  Arithmetic in prec (the transform adds and subtracts only).
+ * Errors: RSVD_E_ARG, RSVD_E_HIP.
+ */
+rsvd_status rsvd_k_srht_sketch(int32_t prec, int64_t m, int64_t n, const void* d_A, int64_t lda, int32_t l,
+                               uint64_t seed, void* d_signs, int32_t* d_subset, void* d_Y, int64_t ldy,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

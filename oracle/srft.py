@@ -99,12 +99,40 @@ def sketch(A: np.ndarray, l: int, seed: int) -> np.ndarray:
     return A @ omega(A.shape[1], l, seed)
 
 
+def fwht(X: np.ndarray) -> np.ndarray:
+    """H_N X for an N x c array X (N a power of two), by butterflies over the bits of the index: at bit h
+    the pair (i, i + 2^h), i without bit h, becomes (x_i + x_{i+2^h}, x_i - x_{i+2^h})."""
+    Y = np.array(X, dtype=np.float64, copy=True)
+    N = Y.shape[0]
+    h = 1
+    while h < N:
+        for start in range(0, N, 2 * h):
+            a = Y[start:start + h].copy()
+            b = Y[start + h:start + 2 * h].copy()
+            Y[start:start + h] = a + b
+            Y[start + h:start + 2 * h] = a - b
+        h *= 2
+    return Y
+
+
+def sketch_rows(A: np.ndarray, l: int, seed: int) -> np.ndarray:
+    """Y = A Omega computed row by row as (H_N (d .* a_r))(S) / sqrt(N), for shapes where the explicit
+    Omega would not fit; the same quantity as ``sketch``."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    N = padded_size(n)
+    X = np.zeros((N, m))
+    X[:n] = (A * signs(n, seed)).T
+    return fwht(X)[subset(N, l, seed)].T / math.sqrt(N)
+
+
 def rsvd_srht(A: np.ndarray, k: int, p: int, q: int, seed: int):
     """Figure 5 with the test matrix of Section 6 (l = k + p): Q = orth(A Omega),
     q times { W = orth(A^T Q); Q = orth(A W) }, then Stage B.  Rank-(k+p)
     result (truncate with ``.truncate(k)``)."""
     A = np.asarray(A, dtype=np.float64)
-    Q = orth(sketch(A, k + p, seed))
+    Y = sketch(A, k + p, seed) if padded_size(A.shape[1]) <= 4096 else sketch_rows(A, k + p, seed)
+    Q = orth(Y)
     for _ in range(q):
         W = orth(A.T @ Q)
         Q = orth(A @ W)

@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (  # noqa: F401
     RSVD_BATCHED_CLASSES, RSVD_BATCHED_TILE_VARIANTS, RSVD_BF16, RSVD_E_ARG, RSVD_E_HIP, RSVD_E_NONFINITE, RSVD_E_UNSUPPORTED, RSVD_E_WORKSPACE,
     RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RSVD_MLP_NPARAM, RSVD_NOT_CERTIFIED, RSVD_OK, RSVD_RETURN_RANK_L,
-    RSVD_SEL_NQ, RSVD_SEL_P, RSVD_TIMING, RSVDError, STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info,
+    RSVD_SEL_NQ, RSVD_SEL_P, RSVD_SKETCH_SRHT, RSVD_TIMING, RSVDError, STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info,
     status_str,
 )
 
@@ -98,6 +98,21 @@ def rsvd_factor_noalloc(desc: rsvd_desc, A: torch.Tensor, U: torch.Tensor, S: to
     return _lib.lib().rsvd_factor_noalloc(ctypes.byref(desc), _ptr(A), A.stride(0), _ptr(omega), _ptr(U),
                                           U.stride(0), _ptr(S), _ptr(V), V.stride(0) if V is not None else 0,
                                           _stream_handle(A.device, stream))
+
+
+def rsvd_k_srht_sketch(A: torch.Tensor, l: int, seed: int, stream=None):
+    """The structured sketch of Section 6 on its own: returns (Y, signs, subset) with Y = A Omega (m x l),
+    the signs (n) and the column subset (l, int32), computed by the library's kernels."""
+    m, n = A.shape
+    prec = RSVD_F64 if A.dtype == torch.float64 else RSVD_F32
+    Y = torch.empty(m, l, dtype=A.dtype, device=A.device)
+    sg = torch.empty(n, dtype=A.dtype, device=A.device)
+    sub = torch.empty(l, dtype=torch.int32, device=A.device)
+    st = _lib.lib().rsvd_k_srht_sketch(prec, m, n, _ptr(A), A.stride(0), int(l), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                       _ptr(sg), _ptr(sub), _ptr(Y), Y.stride(0), _stream_handle(A.device, stream))
+    if st != RSVD_OK:
+        raise RSVDError(st, "rsvd_k_srht_sketch")
+    return Y, sg, sub
 
 
 def rsvd_destroy(plan) -> None:

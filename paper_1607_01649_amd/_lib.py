@@ -22,6 +22,7 @@ RSVD_E_UNSUPPORTED = -5
 RSVD_F64, RSVD_F32, RSVD_BF16, RSVD_FP8_E4M3 = 0, 1, 2, 3
 RSVD_RETURN_RANK_L = 0x1
 RSVD_TIMING = 0x2
+RSVD_SKETCH_SRHT = 0x4
 
 STREAM_OMEGA = 4
 STREAM_PROBE = 5
@@ -100,6 +101,8 @@ SIGNATURES = [
     ("rsvd_mlp_adam", ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, ctypes.c_int32, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _c_void_p]),
     # include/rsvd_kernels.h
+    ("rsvd_k_srht_sketch", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, ctypes.c_int32,
+                                          ctypes.c_uint64, _c_void_p, _c_void_p, _c_void_p, _i64, _c_void_p]),
     ("rsvd_k_product_nn", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, _c_void_p, _i64,
                                          ctypes.c_int32, _c_void_p, _i64, _c_void_p]),
     ("rsvd_k_product_tn", ctypes.c_int, [ctypes.c_int32, _i64, _i64, _c_void_p, _i64, _c_void_p, _i64,

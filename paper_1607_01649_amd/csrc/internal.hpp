@@ -127,6 +127,14 @@ template <typename TO>
 hipError_t launch_rowmajor_to_panel(const double* src, int64_t rows, int64_t cols, int64_t ld_src, TO* dst,
                                     int64_t ld_dst, hipStream_t s);
 
+// srht.hip -- the structured test matrix of Section 6 (signs, subset) and the sketch Y = A Omega.
+int srht_max_n(int es);
+template <typename T>
+hipError_t launch_srht_setup(uint64_t seed, int n, int l, T* signs, int* subset, hipStream_t s);
+template <typename T>
+hipError_t launch_srht_sketch(const T* A, int64_t lda, int64_t m, int n, const T* signs, const int* subset, int l,
+                              T* out, int64_t osr, int64_t osc, hipStream_t s);
+
 // rsvd_api.hip: one fixed-rank factorisation (eps == 0, fixed p and q, no timing) in a caller-given
 // workspace, with a plan built on the stack; RSVD_E_WORKSPACE when the description needs more than
 // ws_bytes.  The same launch sequence as rsvd_plan + rsvd_factor with h_info == NULL.

@@ -139,4 +139,25 @@ rsvd_status rsvd_k_product_fp8(int64_t rows, int64_t K, const uint8_t* A8, int64
   return RSVD_OK;
 }
 
+rsvd_status rsvd_k_srht_sketch(int32_t prec, int64_t m, int64_t n, const void* A, int64_t lda, int32_t l,
+                               uint64_t seed, void* signs, int32_t* subset, void* Y, int64_t ldy, void* stream) {
+  if (!A || !signs || !subset || !Y || m < 1 || n < 1 || lda < n || l < 1 || l > 1024 || ldy < l) return RSVD_E_ARG;
+  if (prec != RSVD_F32 && prec != RSVD_F64) return RSVD_E_ARG;
+  if (n > srht_max_n(prec == RSVD_F64 ? 8 : 4)) return RSVD_E_ARG;
+  int64_t N = 1;
+  while (N < n) N *= 2;
+  if (l > N) return RSVD_E_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (prec == RSVD_F64) {
+    K_TRY(launch_srht_setup<double>(seed, (int)n, l, (double*)signs, subset, s));
+    K_TRY(launch_srht_sketch<double>((const double*)A, lda, m, (int)n, (const double*)signs, subset, l, (double*)Y,
+                                     ldy, 1, s));
+  } else {
+    K_TRY(launch_srht_setup<float>(seed, (int)n, l, (float*)signs, subset, s));
+    K_TRY(launch_srht_sketch<float>((const float*)A, lda, m, (int)n, (const float*)signs, subset, l, (float*)Y, ldy,
+                                    1, s));
+  }
+  return RSVD_OK;
+}
+
 }  // extern "C"

@@ -55,7 +55,8 @@ struct Layout {
   int s_nn, s_tn, s_gm, s_gn, s_nn16, s_tn16;
   int64_t ld16, ldT;   // leading dimensions of the bf16 copies of A and A^T
   size_t a16, a16t, a8, a8t, s8, xq, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
-      rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, sel, total;
+      rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, sel, srht_sgn, srht_sub,
+      total;
 };
 
 int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
@@ -97,6 +98,10 @@ bool validate(const rsvd_desc* d) {
   if (d->max_rank > 0 && d->max_rank < l) return false;
   if (d->max_rank > std::min<int64_t>(std::min(d->m, d->n), 1024)) return false;
   if (d->m > (int64_t)1 << 40 || d->n > (int64_t)1 << 40) return false;
+  if (d->flags & RSVD_SKETCH_SRHT) {
+    if (sel || d->sketch_dtype != d->a_dtype) return false;
+    if (d->n > srht_max_n(d->a_dtype == RSVD_F64 ? 8 : 4)) return false;
+  }
   return true;
 }
 
@@ -196,6 +201,9 @@ Layout make_layout(const rsvd_desc* d) {
   L.frob = take(1040 * 8);
   L.flags = take(kFlags * sizeof(int));
   L.sel = take(kSelFloats * sizeof(float));
+  const bool srht = (d->flags & RSVD_SKETCH_SRHT) != 0;
+  L.srht_sgn = take(srht ? (size_t)d->n * L.es : 256);
+  L.srht_sub = take(srht ? 1024 * sizeof(int) : 256);
   L.total = off;
   return L;
 }
@@ -524,13 +532,23 @@ template <typename T> struct Path {
         HIP_TRY(launch_to_fp8(A, lda, m, n, P.at<uint8_t>(L.a8), L.ld16, P.at<uint8_t>(L.a8t), L.ldT,
                               P.at<float>(L.s8), flags + 4, st));
     }
-    // Figure 5 (1): Gaussian test matrix.
-    if (omega_in)
-      HIP_TRY(launch_rowmajor_to_panel<T>(omega_in, n, l, l, omega, L.ldn, st));
-    else
-      HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, l, 0, omega, 1, L.ldn, st));
+    if ((P.d.flags & RSVD_SKETCH_SRHT) && !omega_in) {
+      // Section 6: Y = A Omega with the structured test matrix, one pass over A.
+      T* sgn = P.at<T>(L.srht_sgn);
+      int* sub = P.at<int>(L.srht_sub);
+      HIP_TRY(launch_srht_setup<T>(P.d.seed, (int)n, l, sgn, sub, st));
+      int ev = gemm_begin(0);
+      HIP_TRY(launch_srht_sketch<T>(A, lda, m, (int)n, sgn, sub, l, Y, 1, L.ldm, st));
+      gemm_end(ev);
+    } else {
+      // Figure 5 (1): Gaussian test matrix.
+      if (omega_in)
+        HIP_TRY(launch_rowmajor_to_panel<T>(omega_in, n, l, l, omega, L.ldn, st));
+      else
+        HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, l, 0, omega, 1, L.ldn, st));
+      RS_TRY(apply_a(A, lda, omega, l, Y, sk));
+    }
     // (2): Q = orth(A Omega).
-    RS_TRY(apply_a(A, lda, omega, l, Y, sk));
     RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q));
     mark(1);
     // (3)-(6): q power steps with re-orthonormalisation.

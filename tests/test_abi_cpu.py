@@ -144,3 +144,13 @@ def test_no_alloc_entry_checks_its_limits_before_touching_the_device(lib):
         d = _desc(**kw)
         assert lib.rsvd_factor_noalloc(ctypes.byref(d), f, 800, None, f, 40, f, None, 0, None) == -1
     assert lib.rsvd_factor_noalloc(None, f, 800, None, f, 40, f, None, 0, None) == -1
+
+
+def test_structured_sketch_rejected_where_not_supported(lib):
+    from paper_1607_01649_amd import RSVD_SKETCH_SRHT
+    for kw in (dict(m=100, n=40000), dict(m=100, n=20000, a_dtype="f64"), dict(m=100, n=500, sketch_dtype="bf16"),
+               dict(m=100, n=500, p=-1, q=-1)):
+        st, _ = _ws(lib, _desc(flags=RSVD_SKETCH_SRHT, **kw))
+        assert st == -1, kw
+    st, need = _ws(lib, _desc(m=100, n=500, flags=RSVD_SKETCH_SRHT))
+    assert st == 0 and need > _ws(lib, _desc(m=100, n=500))[1]

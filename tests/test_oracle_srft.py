@@ -149,3 +149,9 @@ def test_random_signs_center_every_entry():
     for seed in range(T):
         acc += srft.omega(n, l, seed) * math.sqrt(srft.padded_size(n))
     assert np.abs(acc / T).max() < 5.0 / math.sqrt(T)
+
+
+@pytest.mark.parametrize("n,l", [(1, 1), (37, 10), (256, 40), (1000, 110)])
+def test_row_by_row_sketch_equals_the_definition(n, l):
+    A = np.random.default_rng(n).standard_normal((23, n))
+    assert np.allclose(srft.sketch_rows(A, l, seed=3), srft.sketch(A, l, seed=3), atol=1e-12, rtol=0)
