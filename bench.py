@@ -210,14 +210,14 @@ def vs_planted(sig, S):
             "sigma_err_max_over_sigma1": float(np.abs(Sg - s).max() / s[0])}
 
 
-def run_path(A, cfg, sketch, proj, steps, warmup, seed, keep_u=True):
+def run_path(A, cfg, sketch, proj, steps, warmup, seed, keep_u=True, flags=0):
     """Time `steps` factorisations with the given operand precisions; returns
     the measurements and the last factors."""
     import torch
     from paper_1607_01649_amd import RSVD, RSVD_TIMING
     m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
     l = k + p
-    solver = RSVD(m, n, k, p, q, dtype=cfg.dtype, device=A.device, seed=seed, flags=RSVD_TIMING,
+    solver = RSVD(m, n, k, p, q, dtype=cfg.dtype, device=A.device, seed=seed, flags=RSVD_TIMING | flags,
                   sketch_dtype=sketch, proj_dtype=proj)
     for _ in range(warmup):
         U, S, V, info = solver(A)
@@ -286,6 +286,29 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed, keep_u=True):
     return {"_S": S_host, "_U": U_host, "sketch_dtype": sketch, "proj_dtype": proj, "ms_per_step": dt * 1e3,
             "tflops": flops_pass * passes / dt / 1e12, "stage_ms": [round(x, 4) for x in info.stage_ms],
             "jacobi_sweeps": info.jacobi_sweeps, "time_to_eps": tte, "roofline": roof}
+
+
+def srht_roofline(A, l, seed, reps=10):
+    """The structured sketch (Section 6) on its own: the library's kernel-level entry (draw and one-pass
+    transform) timed with HIP events on the current stream; HBM-bound, algorithmic bytes = A once + Y."""
+    import torch
+    from paper_1607_01649_amd import rsvd_k_srht_sketch
+    for _ in range(2):
+        rsvd_k_srht_sketch(A, l, seed)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rsvd_k_srht_sketch(A, l, seed)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    m, n = A.shape
+    nbytes = m * n * A.element_size() + m * l * A.element_size()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None, "kernel": "srht_sketch_kernel (Y = A D H S / sqrt(N), one pass)", "avg_launch_ms": ms,
+            "algorithmic_bytes_per_launch": nbytes}
 
 
 def run_batched(args):
@@ -359,7 +382,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="slowdecay_50000x20000")
-    ap.add_argument("--paths", default="bf16,f32", help="comma list; the first one is the headline")
+    ap.add_argument("--paths", default="bf16,f32,f32+srht",
+                    help="comma list of operand formats, '+srht' for the structured first sketch; the first one is "
+                         "the headline")
     ap.add_argument("--cpu-rows", type=int, default=1 << 30, help="row sample of the CPU oracle (default: all rows)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--also", default="expdecay_65536:fp8",
@@ -402,8 +427,14 @@ def main():
     paths = [p for p in args.paths.split(",") if p]
     res = {}
     print(f"[bench] {args.workload}: matrix ready", file=sys.stderr, flush=True)
+    from paper_1607_01649_amd import RSVD_SKETCH_SRHT
     for pth in paths:
-        res[pth] = run_path(A, cfg, pth, pth, args.steps, args.warmup, args.seed, keep_u=not args.no_cpu)
+        fmt, _, var = pth.partition("+")
+        fl = RSVD_SKETCH_SRHT if var == "srht" else 0
+        res[pth] = run_path(A, cfg, fmt, fmt, args.steps, args.warmup, args.seed, keep_u=not args.no_cpu, flags=fl)
+        if var == "srht":
+            res[pth]["sketch"] = "structured (Section 6: random signs, Walsh-Hadamard, subsampled columns)"
+            res[pth]["srht_roofline"] = srht_roofline(A, cfg.k + cfg.p, args.seed)
         print(f"[bench] path {pth}: {res[pth]['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
     head = res[paths[0]]
     out = {"metric": METRIC, "value": head["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -417,7 +448,8 @@ def main():
         print("[bench] cpu oracle done", file=sys.stderr, flush=True)
         if ref is not None:
             for pth in paths:
-                res[pth]["vs_fp64_oracle"] = vs_oracle(ref, res[pth]["_S"], res[pth]["_U"])
+                key = "vs_fp64_oracle" if "+" not in pth else "vs_fp64_oracle_gaussian_omega"
+                res[pth][key] = vs_oracle(ref, res[pth]["_S"], res[pth]["_U"])
     if cfg.noise_std == 0.0:
         for pth in paths:
             res[pth]["vs_planted_sigma"] = vs_planted(cfg.sigma(), res[pth]["_S"])
