@@ -21,6 +21,8 @@ Modules
   batched  per-block tolerance driver for the batched workload.
   srft     the structured test matrix of Section 6 (random signs, Walsh-
            Hadamard transform, subsampled columns) and Figure 5 with it.
+  nystrom  the Nystrom eigenvalue decomposition of Section 9 for symmetric
+           positive semidefinite matrices, with a dropping Cholesky.
 
 Parity status of each function is listed in its docstring; every function
 here is pinned by a ``-m "not gpu"`` test unless it says "parity unpinned".
