@@ -56,6 +56,7 @@ typedef enum {
 #define RSVD_RETURN_RANK_L 0x1u  /* return all l = k+p columns instead of the k leading ones   */
 #define RSVD_TIMING        0x2u  /* record per-stage HIP events; rsvd_info.stage_ms filled    */
 #define RSVD_SKETCH_SRHT   0x4u  /* first sketch with the structured test matrix (see below)  */
+#define RSVD_NYSTROM       0x8u  /* Nystrom eigendecomposition of a psd matrix (see below)     */
 
 /*
  * Problem description.
@@ -92,7 +93,7 @@ typedef enum {
  *   max_rank    when eps > 0: largest basis the fallback may grow to, and the
  *               column capacity U and V must have (>= k+p; 0 -> k+p, i.e. no
  *               growth).
- *   flags       RSVD_RETURN_RANK_L | RSVD_TIMING | RSVD_SKETCH_SRHT.
+ *   flags       RSVD_RETURN_RANK_L | RSVD_TIMING | RSVD_SKETCH_SRHT | RSVD_NYSTROM.
  *
  * RSVD_SKETCH_SRHT (Section 6; Section 14, item (1)): the first sketch is
  * Y = A Omega with the structured test matrix Omega = D F S in real form:
@@ -108,6 +109,18 @@ typedef enum {
  * blocks, stream 4, continuing at column k+p) are unchanged.  Needs
  * sketch_dtype == a_dtype, n <= 32768 (F32) or 16384 (F64), fixed p and q
  * (no selector); RSVD_E_ARG otherwise.
+ *
+ * RSVD_NYSTROM (Section 9 and its figure): for a symmetric positive
+ * semidefinite A (m == n), the eigendecomposition A ~= U diag(S) U^T by the
+ * Nystrom method: Q from Stage A (q = 0 is the figure as printed; q >= 1
+ * adds Figure 5's power steps), B1 = A Q (operands in proj_dtype), B2 =
+ * Q^T B1 accumulated in FP64 and made exactly symmetric, B2 = C^T C
+ * (Cholesky, pivots at or below (k+p) u times the diagonal dropped and
+ * counted in dropped_cols, which counts nothing else here), F = B1 C^-1, the SVD F = U Sigma W^T (FP64, as Stage B),
+ * S = Sigma^2 (descending, >= 0).  d_U gets U (n x r), d_V (if not NULL)
+ * the same U, so that U diag(S) V^T is the approximation.  Needs m == n,
+ * eps == 0 and fixed p, q (RSVD_E_ARG otherwise); A's symmetry is assumed,
+ * not checked.
  */
 typedef struct {
   int64_t m, n;

@@ -23,6 +23,7 @@ RSVD_F64, RSVD_F32, RSVD_BF16, RSVD_FP8_E4M3 = 0, 1, 2, 3
 RSVD_RETURN_RANK_L = 0x1
 RSVD_TIMING = 0x2
 RSVD_SKETCH_SRHT = 0x4
+RSVD_NYSTROM = 0x8
 
 STREAM_OMEGA = 4
 STREAM_PROBE = 5

@@ -116,6 +116,8 @@ hipError_t launch_batched(int nblk, const int* m, const int* n, const float* con
 
 // misc.hip
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+hipError_t launch_symmetrize(double* G, int64_t ldg, int l, hipStream_t s);
+hipError_t launch_square(const double* in, double* out, int n, hipStream_t s);
 template <typename T>
 hipError_t launch_axpy_panel(T* Y, int64_t ldy, const T* X, int64_t ldx, int64_t rows, int ncols, T alpha,
                              hipStream_t s);

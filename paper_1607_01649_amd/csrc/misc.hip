@@ -137,4 +137,35 @@ template hipError_t launch_colnorm<double>(const double*, int64_t, int64_t, int,
 template hipError_t launch_frob2<float>(const float*, int64_t, int64_t, int64_t, double*, double*, hipStream_t);
 template hipError_t launch_frob2<double>(const double*, int64_t, int64_t, int64_t, double*, double*, hipStream_t);
 
+// G <- (G + G^T) / 2 on the leading l x l block of a column-major matrix (ld ldg): one thread per pair
+// (i, j), i <= j, so each entry is read before either of the pair is written.
+__global__ void symmetrize_kernel(double* __restrict__ G, int64_t ldg, int l) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)l * l) return;
+  const int i = (int)(t / l), j = (int)(t - (t / l) * l);
+  if (i > j) return;
+  const double v = 0.5 * (G[(int64_t)j * ldg + i] + G[(int64_t)i * ldg + j]);
+  G[(int64_t)j * ldg + i] = v;
+  G[(int64_t)i * ldg + j] = v;
+}
+
+hipError_t launch_symmetrize(double* G, int64_t ldg, int l, hipStream_t s) {
+  const int64_t work = (int64_t)l * l;
+  if (work <= 0) return hipSuccess;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, G, ldg, l);
+  return hipGetLastError();
+}
+
+// out[i] = in[i]^2, i < n
+__global__ void square_kernel(const double* __restrict__ in, double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] * in[i];
+}
+
+hipError_t launch_square(const double* in, double* out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(square_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
 }  // namespace rsvd

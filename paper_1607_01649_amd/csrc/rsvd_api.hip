@@ -19,7 +19,8 @@ namespace {
 
 constexpr int kRedGroup = 16;   // partials summed per first-level reduction group
 // device status words: [0] non-finite pivot, [1] dropped columns, [2] Jacobi
-// not converged, [3] Jacobi sweeps, [4] non-finite entry of A (conversion)
+// not converged, [3] Jacobi sweeps, [4] non-finite entry of A (conversion),
+// [8] and [9] non-finite and dropped pivots of the Nystrom core factor B2 = C^T C
 constexpr int kFlags = 64;
 // selector: grid of oversampling values (power steps 0 .. kSelNQ-1), and floats of selector scratch
 // (network input 16, hidden activations 64 + 64, logits 40)
@@ -98,6 +99,9 @@ bool validate(const rsvd_desc* d) {
   if (d->max_rank > 0 && d->max_rank < l) return false;
   if (d->max_rank > std::min<int64_t>(std::min(d->m, d->n), 1024)) return false;
   if (d->m > (int64_t)1 << 40 || d->n > (int64_t)1 << 40) return false;
+  if (d->flags & RSVD_NYSTROM) {
+    if (sel || d->m != d->n || d->eps != 0.0) return false;
+  }
   if (d->flags & RSVD_SKETCH_SRHT) {
     if (sel || d->sketch_dtype != d->a_dtype) return false;
     if (d->n > srht_max_n(d->a_dtype == RSVD_F64 ? 8 : 4)) return false;
@@ -612,8 +616,53 @@ template <typename T> struct Path {
     return RSVD_OK;
   }
 
+  // Section 9: the Nystrom eigendecomposition of a symmetric positive semidefinite A (m == n).
+  rsvd_status run_nystrom(const T* A, int64_t lda, const double* omega_in, T* U, int64_t ldu, double* S, T* V,
+                          int64_t ldv, int kout) {
+    const int64_t n = P.d.n;
+    const int l = L.l, LPc = lp16(l);
+    int* flags = P.at<int>(L.flags);
+    P.rank_out = kout;
+    P.fallback_steps = 0;
+    P.err_bound = 0.0;
+    P.frob_res = -1.0;
+    mark(0);
+    HIP_TRY(launch_fill_int(flags, kFlags, 0, st));
+    RS_TRY(stage_a(A, lda, omega_in));   // steps 1-3: Q (n x l panel)
+    T* Q = P.at<T>(L.Q);
+    T* B1 = P.at<T>(L.T);
+    T* Bt = P.at<T>(L.Bt);
+    RS_TRY(apply_a(A, lda, Q, l, B1, P.d.proj_dtype));   // step 4: B1 = A Q
+    mark(3);
+    // B2 = Q^T B1 with FP64 accumulation, made exactly symmetric
+    double* G = P.at<double>(L.G);
+    double* gp = P.at<double>(L.gpart);
+    HIP_TRY((launch_nn<T, T, double, double>(Q, L.ldm, l, n, B1, L.ldm, l, gp, LPc, (int64_t)LPc * LPc, L.s_gm,
+                                             st)));
+    HIP_TRY((launch_reduce<double, double>(gp, L.s_gm, (int64_t)LPc * LPc, LPc, l, l, G, LPc, st)));
+    HIP_TRY(launch_symmetrize(G, LPc, l, st));
+    // step 5: B2 = C^T C; B2 is the Gram matrix of A^(1/2) Q, accurate to u relative to its diagonal, so
+    // a pivot at or below l u of it is dependent and dropped (counted apart from the CholeskyQR steps)
+    const double u = sizeof(T) == 8 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+    HIP_TRY(launch_chol<T>(G, LPc, l, LPc, (double)l * u, P.at<T>(L.rinv), nullptr, nullptr, P.at<double>(L.scr_chol),
+                           flags + 8, st));
+    // step 6: F = B1 C^-1, into the B^T panel (m == n: the two panels share their leading dimension)
+    HIP_TRY(apply_rinv(B1, L.ldm, n, l, P.at<T>(L.rinv), LPc, Bt));
+    // step 7: SVD of F, as the SVD of F^T held as its panel F: F^T = U_hat Sigma W^T
+    RS_TRY(small_svd(l));
+    mark(4);
+    // U = F U_hat Sigma^-1 (the left singular vectors of F), S = Sigma^2 (step 8), V = U
+    HIP_TRY((launch_tn<T, T, T, T>(Bt, L.ldn, l, n, P.at<T>(L.vhat_p), LPc, kout, U, ldu, 0, 1, true, st)));
+    if (V)
+      HIP_TRY((launch_tn<T, T, T, T>(Bt, L.ldn, l, n, P.at<T>(L.vhat_p), LPc, kout, V, ldv, 0, 1, true, st)));
+    HIP_TRY(launch_square(P.at<double>(L.sigma), S, kout, st));
+    mark(5);
+    return RSVD_OK;
+  }
+
   rsvd_status run(const T* A, int64_t lda, const double* omega_in, T* U, int64_t ldu, double* S, T* V, int64_t ldv,
                   int kout) {
+    if (P.d.flags & RSVD_NYSTROM) return run_nystrom(A, lda, omega_in, U, ldu, S, V, ldv, kout);
     const int64_t m = P.d.m, n = P.d.n;
     const int l = L.l;
     T* omega = P.at<T>(L.omega);
@@ -803,7 +852,7 @@ rsvd_status factor_fixed(rsvd_plan_t p, const void* d_A, int64_t lda, const doub
     int flags[kFlags];
     HIP_TRY(hipMemcpyAsync(flags, p->ws + p->L.flags, sizeof(flags), hipMemcpyDeviceToHost, p->st));
     HIP_TRY(hipStreamSynchronize(p->st));
-    if (flags[0] > 0 || flags[4] != 0) s = RSVD_E_NONFINITE;
+    if (flags[0] > 0 || flags[4] != 0 || flags[8] > 0) s = RSVD_E_NONFINITE;
     if (h_info) {
       memset(h_info, 0, sizeof(*h_info));
       double s1 = 0.0;
@@ -832,7 +881,7 @@ rsvd_status factor_fixed(rsvd_plan_t p, const void* d_A, int64_t lda, const doub
         }
       }
       h_info->jacobi_sweeps = flags[3];
-      h_info->dropped_cols = flags[1];
+      h_info->dropped_cols = (d.flags & RSVD_NYSTROM) ? flags[9] : flags[1];
       h_info->status = s;
     }
     RSVD_LOGF("factor done: status=%d nonfinite=%d dropped=%d jacobi_nonconv=%d bound=%g rank=%d", (int)s, flags[0],
