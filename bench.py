@@ -270,9 +270,9 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed, keep_u=True, flags=0):
     roof.update({"traffic": traffic_per_launch(sketch, cfg.name), "kernel": names[0] if dom_nn else names[1],
                  "avg_launch_ms": avg * 1e3,
                  "launches_per_step": (nn_n + tn_n) / steps,
-                 "other_kernel": {"name": names[1] if dom_nn else names[0],
-                                  "avg_launch_ms": (avg_tn if dom_nn else avg_nn) * 1e3,
-                                  "achieved_tflops": flops_pass / (avg_tn if dom_nn else avg_nn) / 1e12}})
+                 "other_kernel": None if min(nn_n, tn_n) == 0 else
+                 {"name": names[1] if dom_nn else names[0], "avg_launch_ms": (avg_tn if dom_nn else avg_nn) * 1e3,
+                  "achieved_tflops": flops_pass / (avg_tn if dom_nn else avg_nn) / 1e12}})
     sig = cfg.sigma()
     fac = EPS_FACTOR.get(cfg.name, 1.15)
     eps_abs = fac * sig[k]
@@ -387,8 +387,9 @@ def main():
                          "the headline")
     ap.add_argument("--cpu-rows", type=int, default=1 << 30, help="row sample of the CPU oracle (default: all rows)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--also", default="expdecay_65536:fp8",
-                    help="comma list of workload:sketch[/proj] legs timed after the headline ('' for none)")
+    ap.add_argument("--also", default="expdecay_65536:fp8,psd_20000:f32+nystrom",
+                    help="comma list of workload:sketch[/proj][+srht|+nystrom] legs timed after the headline "
+                         "('' for none)")
     ap.add_argument("--leg-steps", type=int, default=5)
     ap.add_argument("--leg-warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=1)
@@ -460,8 +461,11 @@ def main():
     torch.cuda.empty_cache()
     # further legs: other workloads and operand formats, each with its own roofline (not part of `value`)
     legs = {}
+    from paper_1607_01649_amd import RSVD_NYSTROM
+    variant_flags = {"": 0, "srht": RSVD_SKETCH_SRHT, "nystrom": RSVD_NYSTROM}
     for leg in [x for x in args.also.split(",") if x]:
         wl, _, fmt = leg.partition(":")
+        fmt, _, var = fmt.partition("+")
         sk, _, pj = fmt.partition("/")
         pj = pj or sk
         c2 = gen.config(wl)
@@ -469,7 +473,10 @@ def main():
         A2 = A2.to(torch.float32) if c2.dtype == "f32" else A2
         torch.cuda.synchronize()
         print(f"[bench] {wl}: matrix ready", file=sys.stderr, flush=True)
-        r = run_path(A2, c2, sk, pj, args.leg_steps, args.leg_warmup, args.seed, keep_u=False)
+        r = run_path(A2, c2, sk, pj, args.leg_steps, args.leg_warmup, args.seed, keep_u=False,
+                     flags=variant_flags[var])
+        if var == "nystrom":
+            r["method"] = "Nystrom eigendecomposition (Section 9): A ~= U diag(S) U^T"
         if c2.noise_std == 0.0:
             r["vs_planted_sigma"] = vs_planted(c2.sigma(), r["_S"])
         r.pop("_S")

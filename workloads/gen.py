@@ -119,6 +119,21 @@ def low_rank_matrix(m: int, n: int, sigma: np.ndarray, noise_std: float, seed: i
     return a
 
 
+def psd_matrix(n: int, lam: np.ndarray, seed: int, dtype=np.float64, device: Optional[str] = None):
+    """A = U diag(lam) U^T, exactly symmetric, U the orthonormal factor of ``low_rank_matrix`` (host
+    recipe); on a device the product is formed in float32 and symmetrised there."""
+    u = orthonormal_factor(n, len(lam), seed, _STREAM_U)
+    if device is None:
+        a = (u * lam) @ u.T
+        return (0.5 * (a + a.T)).astype(dtype)
+    import torch
+    tu = torch.from_numpy(u.astype(np.float32)).to(device)
+    a = (tu * torch.from_numpy(np.asarray(lam, np.float32)).to(device)) @ tu.T
+    del tu
+    a.add_(a.T.contiguous()).mul_(0.5)
+    return a
+
+
 def kernel_block(mb: int, nb: int, seed: int, block_id: int) -> np.ndarray:
     """K_ij = log |x_i - y_j| (float64 evaluation, float32 result)."""
     x, y = kernel_points(mb, nb, seed, block_id)
@@ -221,6 +236,7 @@ class WorkloadConfig:
     q: int
     dtype: str            # "f64" or "f32": dtype of A, U, V
     description: str
+    psd: bool = False     # A = U diag(sigma) U^T (symmetric positive semidefinite, m == n)
 
     def sigma(self) -> np.ndarray:
         return self.spectrum(self.rank)
@@ -237,6 +253,8 @@ class WorkloadConfig:
         their factors on the device (``orthonormal_factor_device``)."""
         dt = np.float64 if self.dtype == "f64" else np.float32
         big = max(self.m, self.n) > 32768
+        if self.psd:
+            return psd_matrix(self.n, self.sigma(), seed, dt, device)
         return low_rank_matrix(self.m, self.n, self.sigma(), self.noise_std, seed, dt, device,
                                device_factors=big and device is not None)
 
@@ -255,6 +273,10 @@ CONFIGS = {
     "expdecay_65536": WorkloadConfig(
         "expdecay_65536", 65536, 65536, 4096, lambda r: spectrum("exp", r, tau=150.0), 0.0,
         500, 20, 3, "f32", "A = U diag(exp(-j/150)) V^T, 65536^2 rank 4096, k=500 p=20 q=3"),
+    # Nystrom eigendecomposition (Section 9), 20000 x 20000 PSD, rank 2000, lambda_j = 1/j (noise-free).
+    "psd_20000": WorkloadConfig(
+        "psd_20000", 20000, 20000, 2000, lambda r: spectrum("poly", r, alpha=1.0), 0.0,
+        100, 10, 0, "f32", "A = U diag(1/j) U^T, 20000^2 PSD rank 2000, k=100 p=10 q=0", psd=True),
 }
 
 
