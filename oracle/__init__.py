@@ -23,6 +23,9 @@ Modules
            Hadamard transform, subsampled columns) and Figure 5 with it.
   nystrom  the Nystrom eigenvalue decomposition of Section 9 for symmetric
            positive semidefinite matrices, with a dropping Cholesky.
+  singlepass  the single-pass factorisations of Section 5 (symmetric EVD
+           and general SVD, each entry of A read once), least squares on
+           the vectorised systems.
 
 Parity status of each function is listed in its docstring; every function
 here is pinned by a ``-m "not gpu"`` test unless it says "parity unpinned".
