@@ -57,6 +57,8 @@ typedef enum {
 #define RSVD_TIMING        0x2u  /* record per-stage HIP events; rsvd_info.stage_ms filled    */
 #define RSVD_SKETCH_SRHT   0x4u  /* first sketch with the structured test matrix (see below)  */
 #define RSVD_NYSTROM       0x8u  /* Nystrom eigendecomposition of a psd matrix (see below)     */
+#define RSVD_SINGLE_PASS   0x10u /* single-pass SVD of a general matrix (see below)            */
+#define RSVD_SINGLE_PASS_SYM 0x20u /* single-pass EVD of a symmetric matrix (see below)        */
 
 /*
  * Problem description.
@@ -121,6 +123,29 @@ typedef enum {
  * the same U, so that U diag(S) V^T is the approximation.  Needs m == n,
  * eps == 0 and fixed p, q (RSVD_E_ARG otherwise); A's symmetry is assumed,
  * not checked.
+ *
+ * RSVD_SINGLE_PASS (Section 5.2 and its figure): the SVD of a general A from
+ * one pass over it.  G_c (n x l, stream 4, or d_Omega) and G_r (m x l, stream
+ * 11) Gaussian; Y_c = A G_c and Y_r = A^T G_r; Q_c, Q_r = the k dominant left
+ * singular vectors of Y_c, Y_r (FP64 small SVD, as Stage B); the k x k core C
+ * = the least-squares solution of the joint system (G_r^T Q_c) C = Y_r^T Q_r,
+ * C (Q_r^T G_c) = Q_c^T Y_c (both residuals weighted equally; products
+ * accumulated in FP64; solved through its normal equations, entries of C along
+ * directions that neither equation set determines are zero); C = U_hat D
+ * V_hat^T; U = Q_c U_hat, V = Q_r V_hat.  Each pair (u_j, v_j) is unique up
+ * to a common sign.
+ *
+ * RSVD_SINGLE_PASS_SYM (Section 5.1 and its figure): the EVD A ~= U diag(S)
+ * U^T of a symmetric A (m == n; symmetry assumed, not checked): G (n x l,
+ * stream 4, or d_Omega), Y = A G, Q = the k dominant left singular vectors of
+ * Y, C = the least-squares solution of C (Q^T G) = Q^T Y over symmetric C, C =
+ * U_hat D U_hat^T, U = Q U_hat.  S holds the signed eigenvalues ordered by
+ * decreasing magnitude; d_V (if not NULL) gets U.
+ *
+ * Both need q == 0, eps == 0, fixed p (no selector), sketch_dtype ==
+ * proj_dtype (the sketch operand format; no projection pass) and neither
+ * RSVD_RETURN_RANK_L, RSVD_SKETCH_SRHT nor RSVD_NYSTROM (RSVD_E_ARG
+ * otherwise); the two flags exclude each other.
  */
 typedef struct {
   int64_t m, n;

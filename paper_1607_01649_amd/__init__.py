@@ -17,7 +17,8 @@ from . import _lib
 from ._lib import (  # noqa: F401
     RSVD_BATCHED_CLASSES, RSVD_BATCHED_TILE_VARIANTS, RSVD_BF16, RSVD_E_ARG, RSVD_E_HIP, RSVD_E_NONFINITE, RSVD_E_UNSUPPORTED, RSVD_E_WORKSPACE,
     RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RSVD_MLP_NPARAM, RSVD_NOT_CERTIFIED, RSVD_OK, RSVD_RETURN_RANK_L,
-    RSVD_NYSTROM, RSVD_SEL_NQ, RSVD_SEL_P, RSVD_SKETCH_SRHT, RSVD_TIMING, RSVDError, STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info,
+    RSVD_NYSTROM, RSVD_SEL_NQ, RSVD_SEL_P, RSVD_SINGLE_PASS, RSVD_SINGLE_PASS_SYM, RSVD_SKETCH_SRHT,
+    RSVD_TIMING, RSVDError, STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info,
     status_str,
 )
 

@@ -24,6 +24,8 @@ RSVD_RETURN_RANK_L = 0x1
 RSVD_TIMING = 0x2
 RSVD_SKETCH_SRHT = 0x4
 RSVD_NYSTROM = 0x8
+RSVD_SINGLE_PASS = 0x10
+RSVD_SINGLE_PASS_SYM = 0x20
 
 STREAM_OMEGA = 4
 STREAM_PROBE = 5

@@ -114,6 +114,21 @@ hipError_t launch_batched(int nblk, const int* m, const int* n, const float* con
                           const int64_t* offV, int* rank, int* status, int* order, int* queue, double* scratch,
                           int nwg, const int* tiles, int class_mask, hipStream_t s);
 
+// singlepass.hip -- small FP64 steps of the single-pass factorisations (column-major, op = transpose when set):
+// out (M x N) = op(A) op(B) [+ out], column j divided by inv_scale[j] (0 where inv_scale[j] <= 0) when given.
+template <typename TO>
+hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
+                             bool tb, TO* out, int64_t ldo, bool acc, const double* inv_scale, hipStream_t s);
+// X(i, j) /= a_i + b_j (zero where a_i + b_j <= cut_rel (a_0 + b_0)).
+hipError_t launch_sylv_divide(double* X, int64_t ldx, int k1, int k2, const double* a, const double* b,
+                              double cut_rel, hipStream_t s);
+// out = in^T for an rows x cols FP64 matrix.
+hipError_t launch_transpose64(const double* in, int64_t ldi, int rows, int cols, double* out, int64_t ldo,
+                              hipStream_t s);
+// out[j] = X(:, j) . Y(:, j).
+hipError_t launch_coldot(const double* X, const double* Y, int64_t ld, int rows, int ncols, double* out,
+                         hipStream_t s);
+
 // misc.hip
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 hipError_t launch_symmetrize(double* G, int64_t ldg, int l, hipStream_t s);

@@ -57,7 +57,7 @@ struct Layout {
   int64_t ld16, ldT;   // leading dimensions of the bf16 copies of A and A^T
   size_t a16, a16t, a8, a8t, s8, xq, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
       rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, sel, srht_sgn, srht_sub,
-      total;
+      gr, sp, total;
 };
 
 int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
@@ -101,6 +101,12 @@ bool validate(const rsvd_desc* d) {
   if (d->m > (int64_t)1 << 40 || d->n > (int64_t)1 << 40) return false;
   if (d->flags & RSVD_NYSTROM) {
     if (sel || d->m != d->n || d->eps != 0.0) return false;
+  }
+  if (const uint32_t spf = d->flags & (RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM)) {
+    if (spf == (RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM)) return false;
+    if (sel || d->q != 0 || d->eps != 0.0 || d->sketch_dtype != d->proj_dtype) return false;
+    if (d->flags & (RSVD_RETURN_RANK_L | RSVD_SKETCH_SRHT | RSVD_NYSTROM)) return false;
+    if ((spf & RSVD_SINGLE_PASS_SYM) && d->m != d->n) return false;
   }
   if (d->flags & RSVD_SKETCH_SRHT) {
     if (sel || d->sketch_dtype != d->a_dtype) return false;
@@ -194,7 +200,8 @@ Layout make_layout(const rsvd_desc* d) {
   L.R = take(LPM * LPM * 8);
   L.rinv = take(LPM * LPM * L.es);
   L.rinv_d = take(LPM * LPM * 8);
-  L.Q1d = take(LPM * L.ldn * 8);
+  const bool single_pass = (d->flags & (RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM)) != 0;
+  L.Q1d = take(LPM * (single_pass ? std::max(L.ldm, L.ldn) : L.ldn) * 8);
   L.sigma = take(LPM * 8);
   L.uhat_d = take(LPM * LPM * 8);
   L.uhat_p = take(LPM * LPM * L.es);
@@ -208,6 +215,9 @@ Layout make_layout(const rsvd_desc* d) {
   const bool srht = (d->flags & RSVD_SKETCH_SRHT) != 0;
   L.srht_sgn = take(srht ? (size_t)d->n * L.es : 256);
   L.srht_sub = take(srht ? 1024 * sizeof(int) : 256);
+  // single pass: the row-space test matrix G_r (m x l panel) and the FP64 k x k core (13 LP x LP matrices)
+  L.gr = take((d->flags & RSVD_SINGLE_PASS) ? Wd * L.ldm * L.es : 256);
+  L.sp = take(single_pass ? 13 * LP * LP * 8 : 256);
   L.total = off;
   return L;
 }
@@ -409,10 +419,12 @@ template <typename T> struct Path {
   }
 
   // SVD of B (nc x n, held as the panel B^T): FP64 CholeskyQR2 of B^T, Jacobi on R^T.
-  rsvd_status small_svd(int nc) {
-    const int64_t n = P.d.n;
+  rsvd_status small_svd(int nc) { return small_svd_panel(P.at<T>(L.Bt), L.ldn, P.d.n, nc, L.s_gn); }
+
+  // The same for any nc-column panel X (rows x nc, leading dimension ld) in place of B^T: leaves sigma, U_hat
+  // (uhat_d, uhat_p) and vhat_p = U_hat diag(sigma)^-1, so that X vhat_p holds X's left singular vectors.
+  rsvd_status small_svd_panel(const T* X, int64_t ld, int64_t rows, int nc, int splits) {
     const int LPc = lp16(nc);
-    T* Bt = P.at<T>(L.Bt);
     double* G = P.at<double>(L.G);
     double* R1 = P.at<double>(L.R1);
     double* R = P.at<double>(L.R);
@@ -422,12 +434,12 @@ template <typename T> struct Path {
     double* gp2 = P.at<double>(L.gpart2);
     double* scr = P.at<double>(L.scr_chol);
     int* flags = P.at<int>(L.flags);
-    HIP_TRY(launch_gram<T>(Bt, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
-    HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
+    HIP_TRY(launch_gram<T>(X, ld, rows, nc, gp, LPc, (int64_t)LPc * LPc, splits, st));
+    HIP_TRY(launch_reduce2<double>(gp, splits, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R1, nullptr, scr, flags, st));
-    HIP_TRY(launch_apply_upper(Bt, L.ldn, nc, n, rinv_d, LPc, nc, Q1d, L.ldn, st));   // R1^-1 upper triangular
-    HIP_TRY(launch_gram<double>(Q1d, L.ldn, n, nc, gp, LPc, (int64_t)LPc * LPc, L.s_gn, st));
-    HIP_TRY(launch_reduce2<double>(gp, L.s_gn, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
+    HIP_TRY(launch_apply_upper(X, ld, nc, rows, rinv_d, LPc, nc, Q1d, ld, st));   // R1^-1 upper triangular
+    HIP_TRY(launch_gram<double>(Q1d, ld, rows, nc, gp, LPc, (int64_t)LPc * LPc, splits, st));
+    HIP_TRY(launch_reduce2<double>(gp, splits, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, gp2, G, LPc, st));
     HIP_TRY(launch_chol<double>(G, LPc, nc, LPc, tau, rinv_d, R, R1, scr, flags, st));
     // Jacobi stops when every pair's cosine is below tol: l u for FP64 data; for FP32 data (whose own
     // rounding is 6e-8) 1e-10 already leaves U_hat orthogonal and sigma exact far below that, and saves
@@ -514,6 +526,24 @@ template <typename T> struct Path {
     return pow(c_alpha * mx, 1.0 / (2 * s + 1));
   }
 
+  // Low-precision copies of A (bf16, or FP8 with tile scales) for the formats the description asks for; the
+  // scan for non-finite entries of A is counted in flags[4].
+  rsvd_status prep_lowp(const T* A, int64_t lda) {
+    const int64_t m = P.d.m, n = P.d.n;
+    int* flags = P.at<int>(L.flags);
+    if (uses_bf16(&P.d)) {
+      if constexpr (sizeof(T) == 4)
+        HIP_TRY(launch_to_bf16(A, lda, m, n, P.at<uint16_t>(L.a16), L.ld16, P.at<uint16_t>(L.a16t), L.ldT, flags + 4,
+                               st));
+    }
+    if (uses_fp8(&P.d)) {
+      if constexpr (sizeof(T) == 4)
+        HIP_TRY(launch_to_fp8(A, lda, m, n, P.at<uint8_t>(L.a8), L.ld16, P.at<uint8_t>(L.a8t), L.ldT,
+                              P.at<float>(L.s8), flags + 4, st));
+    }
+    return RSVD_OK;
+  }
+
   // Stage A (Figure 5): input preparation, Omega, Q = orth(A Omega) and q power steps with
   // re-orthonormalisation after every application of A or A^T; leaves Q (m x l panel).
   rsvd_status stage_a(const T* A, int64_t lda, const double* omega_in) {
@@ -526,16 +556,7 @@ template <typename T> struct Path {
     T* Wp = P.at<T>(L.Wp);
     int* flags = P.at<int>(L.flags);
     const int sk = P.d.sketch_dtype;
-    if (uses_bf16(&P.d)) {
-      if constexpr (sizeof(T) == 4)
-        HIP_TRY(launch_to_bf16(A, lda, m, n, P.at<uint16_t>(L.a16), L.ld16, P.at<uint16_t>(L.a16t), L.ldT, flags + 4,
-                               st));
-    }
-    if (uses_fp8(&P.d)) {
-      if constexpr (sizeof(T) == 4)
-        HIP_TRY(launch_to_fp8(A, lda, m, n, P.at<uint8_t>(L.a8), L.ld16, P.at<uint8_t>(L.a8t), L.ldT,
-                              P.at<float>(L.s8), flags + 4, st));
-    }
+    RS_TRY(prep_lowp(A, lda));
     if ((P.d.flags & RSVD_SKETCH_SRHT) && !omega_in) {
       // Section 6: Y = A Omega with the structured test matrix, one pass over A.
       T* sgn = P.at<T>(L.srht_sgn);
@@ -660,9 +681,160 @@ template <typename T> struct Path {
     return RSVD_OK;
   }
 
+  // C (na x nb, FP64, C[j*ldc + i] = (Xa^T Xb)(i, j)) for panels Xa, Xb of `rows` rows, FP64 accumulation, split
+  // over the rows and summed in fixed order.
+  rsvd_status tprod64(const T* Xa, int na, const T* Xb, int nb, int64_t ld, int64_t rows, int splits, double* C,
+                      int ldc) {
+    double* gp = P.at<double>(L.gpart);
+    HIP_TRY((launch_nn<T, T, double, double>(Xa, ld, na, rows, Xb, ld, nb, gp, ldc, (int64_t)ldc * nb, splits, st)));
+    HIP_TRY((launch_reduce<double, double>(gp, splits, (int64_t)ldc * nb, ldc, na, nb, C, ldc, st)));
+    return RSVD_OK;
+  }
+
+  // Q_out = the k dominant left singular vectors of the l-column panel Y (rows x l), and Nt = Y^T Q_out (l x k,
+  // FP64, leading dimension lp16(l)).  Y is overwritten by its CholeskyQR2 basis Q (Y = Q R); R (kept in FP64,
+  // transposed into Rc, l x l column-major) has left singular vectors W (Jacobi on its columns), Q_out = Q W_k
+  // and Nt = R^T W_k.
+  rsvd_status dominant_left(T* Y, int64_t ld, int64_t rows, int l, int k, int splits, T* Q_out, double* Nt,
+                            double* Rc) {
+    const int LPl = lp16(l);
+    double* G = P.at<double>(L.G);
+    double* R1 = P.at<double>(L.R1);
+    double* R = P.at<double>(L.R);
+    T* rinv = P.at<T>(L.rinv);
+    T* tmp = P.at<T>(L.T);
+    int* flags = P.at<int>(L.flags);
+    double* scr = P.at<double>(L.scr_chol);
+    RS_TRY(gram(Y, ld, rows, l, splits, G));
+    HIP_TRY(launch_chol<T>(G, LPl, l, LPl, tau, rinv, R1, nullptr, scr, flags, st));
+    HIP_TRY(apply_rinv(Y, ld, rows, l, rinv, LPl, tmp));
+    RS_TRY(gram(tmp, ld, rows, l, splits, G));
+    HIP_TRY(launch_chol<T>(G, LPl, l, LPl, tau, rinv, R, R1, scr, flags, st));   // R = R2 R1, row-major
+    HIP_TRY(apply_rinv(tmp, ld, rows, l, rinv, LPl, Y));
+    HIP_TRY(launch_transpose64(R, LPl, l, l, Rc, LPl, st));
+    const double tol = (double)l * 2.220446049250313e-16;
+    double* uhat_d = P.at<double>(L.uhat_d);
+    T* uhat_p = P.at<T>(L.uhat_p);
+    HIP_TRY(launch_jacobi<T>(Rc, l, LPl, tol, 60, P.at<double>(L.sigma), uhat_d, uhat_p, (T*)nullptr,
+                             P.at<double>(L.scr_jac), flags, st));
+    HIP_TRY((launch_tn<T, T, T, T>(Y, ld, l, rows, uhat_p, LPl, k, Q_out, ld, 0, 1, false, st)));
+    HIP_TRY(launch_small_gemm<double>(l, k, l, Rc, LPl, true, uhat_d, LPl, false, Nt, LPl, false, nullptr, st));
+    return RSVD_OK;
+  }
+
+  // Single-pass factorisations (Section 5): the general SVD of Section 5.2's figure, or with RSVD_SINGLE_PASS_SYM
+  // the symmetric EVD of Section 5.1's figure.  A is read by the sketches only.
+  rsvd_status run_single_pass(const T* A, int64_t lda, const double* omega_in, T* U, int64_t ldu, double* S, T* V,
+                              int64_t ldv, int kout) {
+    const int64_t m = P.d.m, n = P.d.n;
+    const int l = L.l, k = P.d.k, LPl = lp16(l), LPk = lp16(k);
+    const bool sym = (P.d.flags & RSVD_SINGLE_PASS_SYM) != 0;
+    int* flags = P.at<int>(L.flags);
+    P.rank_out = kout;
+    P.fallback_steps = 0;
+    P.err_bound = 0.0;
+    P.frob_res = -1.0;
+    mark(0);
+    HIP_TRY(launch_fill_int(flags, kFlags, 0, st));
+    RS_TRY(prep_lowp(A, lda));
+    // steps 1-2: test matrices and the sketches Y_c = A G_c, Y_r = A^T G_r
+    T* Gc = P.at<T>(L.omega);
+    T* Gr = P.at<T>(L.gr);
+    T* Yc = P.at<T>(L.Y);
+    T* Yr = P.at<T>(L.Z);
+    if (omega_in)
+      HIP_TRY(launch_rowmajor_to_panel<T>(omega_in, n, l, l, Gc, L.ldn, st));
+    else
+      HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, l, 0, Gc, 1, L.ldn, st));
+    if (!sym) HIP_TRY(launch_gaussian<T>(P.d.seed, 11u, m, l, 0, Gr, 1, L.ldm, st));
+    RS_TRY(apply_a(A, lda, Gc, l, Yc, P.d.sketch_dtype));
+    if (!sym) RS_TRY(apply_at(A, lda, Gr, l, Yr, P.d.sketch_dtype));
+    mark(1);
+    double* sp = P.at<double>(L.sp);
+    const size_t L2 = (size_t)L.LP * L.LP;
+    double* M1 = sp;
+    double* N1 = sp + L2;
+    double* M2t = sp + 2 * L2;
+    double* N2t = sp + 3 * L2;
+    double* P1 = sp + 4 * L2;
+    double* P2 = sp + 5 * L2;
+    double* Sm = sp + 6 * L2;
+    double* Z1 = sp + 7 * L2;
+    double* Z2 = sp + 8 * L2;
+    double* T1 = sp + 9 * L2;
+    double* Cm = sp + 10 * L2;
+    double* Wm = sp + 11 * L2;
+    double* a1 = sp + 12 * L2;
+    double* a2 = a1 + L.LP;
+    double* scr = P.at<double>(L.scr_jac);
+    const double tol = (double)k * 2.220446049250313e-16;
+    // step 3: Q_c (Q_r) = the k dominant left singular vectors of Y_c (Y_r): with Y = Q R (CholeskyQR2, Q
+    // overwriting Y) and W_k the k dominant left singular vectors of R, Q_c = Q W_k; this stays orthonormal
+    // when k exceeds the numerical rank of Y.  It also gives Y^T Q_c = R^T W_k (l x k) without a pass over Y.
+    // Equation sets held as l x k panels (FP64): M1 = G_r^T Q_c, N1 = Y_r^T Q_r, M2^T = G_c^T Q_r, N2^T =
+    // Y_c^T Q_c (symmetric form: M^T = G^T Q, N^T = Y^T Q in the last two).
+    T* Qc = P.at<T>(L.Q);
+    T* Qr = P.at<T>(L.Wp);
+    RS_TRY(dominant_left(Yc, L.ldm, m, l, k, L.s_gm, Qc, N2t, T1));
+    if (!sym) RS_TRY(dominant_left(Yr, L.ldn, n, l, k, L.s_gn, Qr, N1, T1));
+    mark(2);
+    if (sym) {
+      RS_TRY(tprod64(Gc, l, Qc, k, L.ldn, n, L.s_gn, M2t, LPl));
+      mark(3);
+      // P = M M^T, S = N M^T + M N^T
+      HIP_TRY(launch_small_gemm<double>(k, k, l, M2t, LPl, true, M2t, LPl, false, P1, LPk, false, nullptr, st));
+      HIP_TRY(launch_small_gemm<double>(k, k, l, N2t, LPl, true, M2t, LPl, false, Sm, LPk, false, nullptr, st));
+      HIP_TRY(launch_small_gemm<double>(k, k, l, M2t, LPl, true, N2t, LPl, false, Sm, LPk, true, nullptr, st));
+      HIP_TRY(launch_jacobi<double>(P1, k, LPk, tol, 60, a1, Z1, (double*)nullptr, (double*)nullptr, scr, flags, st));
+      Z2 = Z1;
+      a2 = a1;
+    } else {
+      RS_TRY(tprod64(Gr, l, Qc, k, L.ldm, m, L.s_gm, M1, LPl));
+      RS_TRY(tprod64(Gc, l, Qr, k, L.ldn, n, L.s_gn, M2t, LPl));
+      mark(3);
+      // P1 = M1^T M1, P2 = M2 M2^T, S = M1^T N1 + N2 M2^T
+      HIP_TRY(launch_small_gemm<double>(k, k, l, M1, LPl, true, M1, LPl, false, P1, LPk, false, nullptr, st));
+      HIP_TRY(launch_small_gemm<double>(k, k, l, M2t, LPl, true, M2t, LPl, false, P2, LPk, false, nullptr, st));
+      HIP_TRY(launch_small_gemm<double>(k, k, l, M1, LPl, true, N1, LPl, false, Sm, LPk, false, nullptr, st));
+      HIP_TRY(launch_small_gemm<double>(k, k, l, N2t, LPl, true, M2t, LPl, false, Sm, LPk, true, nullptr, st));
+      HIP_TRY(launch_jacobi<double>(P1, k, LPk, tol, 60, a1, Z1, (double*)nullptr, (double*)nullptr, scr, flags, st));
+      HIP_TRY(launch_jacobi<double>(P2, k, LPk, tol, 60, a2, Z2, (double*)nullptr, (double*)nullptr, scr, flags, st));
+    }
+    // P1 C + C P2 = S: C = Z1 [(Z1^T S Z2) ./ (a_i + b_j)] Z2^T
+    HIP_TRY(launch_small_gemm<double>(k, k, k, Z1, LPk, true, Sm, LPk, false, T1, LPk, false, nullptr, st));
+    HIP_TRY(launch_small_gemm<double>(k, k, k, T1, LPk, false, Z2, LPk, false, Wm, LPk, false, nullptr, st));
+    HIP_TRY(launch_sylv_divide(Wm, LPk, k, k, a1, a2, tol, st));
+    HIP_TRY(launch_small_gemm<double>(k, k, k, Z1, LPk, false, Wm, LPk, false, T1, LPk, false, nullptr, st));
+    HIP_TRY(launch_small_gemm<double>(k, k, k, T1, LPk, false, Z2, LPk, true, Cm, LPk, false, nullptr, st));
+    if (sym) HIP_TRY(launch_symmetrize(Cm, LPk, k, st));
+    // step 5: C = U_hat D V_hat^T: Jacobi on C gives its left singular vectors and singular values
+    double* sigma = P.at<double>(L.sigma);
+    double* uhat_d = P.at<double>(L.uhat_d);
+    T* uhat_p = P.at<T>(L.uhat_p);
+    T* vhat_p = P.at<T>(L.vhat_p);
+    HIP_TRY(launch_jacobi<T>(Cm, k, LPk, tol, 60, sigma, uhat_d, uhat_p, (T*)nullptr, scr, flags, st));
+    mark(4);
+    // step 6: U = Q_c U_hat; V = Q_r V_hat with V_hat = C^T U_hat diag(sigma)^-1 (symmetric form: V = U and the
+    // signed eigenvalues u_hat_j^T C u_hat_j)
+    HIP_TRY((launch_tn<T, T, T, T>(Qc, L.ldm, k, m, uhat_p, LPk, kout, U, ldu, 0, 1, true, st)));
+    if (sym) {
+      HIP_TRY(launch_small_gemm<double>(k, k, k, Cm, LPk, false, uhat_d, LPk, false, Wm, LPk, false, nullptr, st));
+      HIP_TRY(launch_coldot(uhat_d, Wm, LPk, k, kout, S, st));
+      if (V) HIP_TRY((launch_tn<T, T, T, T>(Qc, L.ldm, k, m, uhat_p, LPk, kout, V, ldv, 0, 1, true, st)));
+    } else {
+      HIP_TRY(launch_small_gemm<T>(k, k, k, Cm, LPk, true, uhat_d, LPk, false, vhat_p, LPk, false, sigma, st));
+      if (V) HIP_TRY((launch_tn<T, T, T, T>(Qr, L.ldn, k, n, vhat_p, LPk, kout, V, ldv, 0, 1, true, st)));
+      HIP_TRY(hipMemcpyAsync(S, sigma, (size_t)kout * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    mark(5);
+    return RSVD_OK;
+  }
+
   rsvd_status run(const T* A, int64_t lda, const double* omega_in, T* U, int64_t ldu, double* S, T* V, int64_t ldv,
                   int kout) {
     if (P.d.flags & RSVD_NYSTROM) return run_nystrom(A, lda, omega_in, U, ldu, S, V, ldv, kout);
+    if (P.d.flags & (RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM))
+      return run_single_pass(A, lda, omega_in, U, ldu, S, V, ldv, kout);
     const int64_t m = P.d.m, n = P.d.n;
     const int l = L.l;
     T* omega = P.at<T>(L.omega);

@@ -161,3 +161,21 @@ def test_nystrom_needs_a_square_matrix_and_no_certificate(lib):
     assert _ws(lib, _desc(m=800, n=800, flags=RSVD_NYSTROM))[0] == 0
     for kw in (dict(m=1000, n=800), dict(m=800, n=800, eps=1e-3, max_rank=40), dict(m=800, n=800, p=-1, q=-1)):
         assert _ws(lib, _desc(flags=RSVD_NYSTROM, **kw))[0] == -1, kw
+
+
+def test_single_pass_descriptions(lib):
+    from paper_1607_01649_amd import (RSVD_NYSTROM, RSVD_RETURN_RANK_L, RSVD_SINGLE_PASS, RSVD_SINGLE_PASS_SYM,
+                                      RSVD_SKETCH_SRHT)
+    assert _ws(lib, _desc(q=0, flags=RSVD_SINGLE_PASS))[0] == 0
+    assert _ws(lib, _desc(m=800, q=0, flags=RSVD_SINGLE_PASS_SYM))[0] == 0
+    bad = [dict(q=1, flags=RSVD_SINGLE_PASS),
+           dict(q=0, eps=1e-2, max_rank=40, flags=RSVD_SINGLE_PASS),
+           dict(q=0, flags=RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM),
+           dict(q=0, flags=RSVD_SINGLE_PASS_SYM),                      # m != n
+           dict(q=0, flags=RSVD_SINGLE_PASS | RSVD_RETURN_RANK_L),
+           dict(q=0, flags=RSVD_SINGLE_PASS | RSVD_SKETCH_SRHT),
+           dict(m=800, q=0, flags=RSVD_SINGLE_PASS_SYM | RSVD_NYSTROM),
+           dict(q=0, sketch_dtype="bf16", proj_dtype="f32", flags=RSVD_SINGLE_PASS),
+           dict(p=-1, q=-1, flags=RSVD_SINGLE_PASS)]
+    for kw in bad:
+        assert _ws(lib, _desc(**kw))[0] == -1, kw

@@ -1,0 +1,109 @@
+"""GPU parity of the single-pass factorisations (Section 5) through the C ABI
+against the oracle on the same test matrices: the general SVD of Section 5.2
+and the symmetric EVD of Section 5.1 in FP64 and FP32, at ragged sizes, and
+exact recovery of a matrix of rank <= k.  Singular and eigenvectors are
+unique up to sign, so the unique quantities are compared: the values, the
+products U D V^T, and each column pair after aligning its sign."""
+import numpy as np
+import pytest
+
+from oracle import singlepass as sp
+from tests.gpu_helpers import run_factor
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _flags(sym=False):
+    from paper_1607_01649_amd import RSVD_SINGLE_PASS, RSVD_SINGLE_PASS_SYM
+    return RSVD_SINGLE_PASS_SYM if sym else RSVD_SINGLE_PASS
+
+
+def _aligned_col_err(X, Xr, ncols):
+    s = np.sign(np.sum(X[:, :ncols] * Xr[:, :ncols], axis=0))
+    s[s == 0] = 1.0
+    return float(np.max(np.linalg.norm(X[:, :ncols] * s - Xr[:, :ncols], axis=0))), s
+
+
+@pytest.mark.parametrize("m,n,k,p,alpha", [(400, 300, 10, 10, 2.0), (517, 333, 7, 13, 1.5), (1000, 700, 30, 30, 2.0),
+                                           (300, 900, 16, 20, 1.0)])
+def test_general_f64_matches_the_oracle(m, n, k, p, alpha):
+    sig = gen.spectrum("poly", min(m, n) // 2, alpha=alpha)
+    A = gen.low_rank_matrix(m, n, sig, 1e-6, seed=m + n)
+    seed = 7
+    U, S, V, info = run_factor(A, k, p, 0, "f64", seed=seed, flags=_flags())
+    Ur, Dr, Vr, _ = sp.single_pass_gen_seeded(A, k, p, seed)
+    assert info.status == 0
+    assert np.abs(S - Dr).max() <= 1e-10 * Dr[0]
+    assert np.abs((U * S) @ V.T - (Ur * Dr) @ Vr.T).max() <= 1e-10 * Dr[0]
+    # the leading columns (gaps of this spectrum >= 1e-2 sigma_1) pair by pair, one sign per pair
+    eu, s = _aligned_col_err(U, Ur, 3)
+    ev = float(np.max(np.linalg.norm(V[:, :3] * s - Vr[:, :3], axis=0)))
+    assert eu <= 1e-8 and ev <= 1e-8
+
+
+@pytest.mark.parametrize("n,k,p", [(400, 10, 10), (517, 9, 14), (900, 40, 40)])
+def test_symmetric_f64_matches_the_oracle(n, k, p):
+    lam = gen.spectrum("poly", n // 2, alpha=1.5) * np.where(np.arange(n // 2) % 3 == 1, -1.0, 1.0)
+    U0 = gen.orthonormal_factor(n, n // 2, n, 1)
+    A = (U0 * lam) @ U0.T
+    A = 0.5 * (A + A.T)
+    seed = 3
+    U, S, V, info = run_factor(A, k, p, 0, "f64", seed=seed, flags=_flags(sym=True))
+    Ur, Dr, _ = sp.single_pass_sym_seeded(A, k, p, seed)
+    assert info.status == 0
+    assert np.abs(S - Dr).max() <= 1e-10 * abs(Dr[0])
+    assert np.abs((U * S) @ U.T - (Ur * Dr) @ Ur.T).max() <= 1e-10 * abs(Dr[0])
+    assert np.array_equal(U, V)
+    assert np.allclose(U.T @ U, np.eye(k), atol=1e-10)
+
+
+def test_general_f32_matches_the_oracle():
+    m, n, k, p = 3000, 2000, 40, 40
+    sig = gen.spectrum("poly", 800, alpha=1.5)
+    A = gen.low_rank_matrix(m, n, sig, 1e-5, seed=4).astype(np.float32)
+    seed = 9
+    U, S, V, info = run_factor(A, k, p, 0, "f32", seed=seed, flags=_flags())
+    Ur, Dr, Vr, _ = sp.single_pass_gen_seeded(A.astype(np.float64), k, p, seed)
+    err_s = np.abs(S - Dr).max() / Dr[0]
+    err_p = np.abs((U * S) @ V.T - (Ur * Dr) @ Vr.T).max() / Dr[0]
+    print(f"f32 general: sigma err {err_s:.2e}, product err {err_p:.2e} (relative to sigma_1)")
+    # FP32 sketches: each entry a sum over n terms, about sqrt(n) u_32 relative to sigma_1; 4 times that
+    tol = 4.0 * np.sqrt(n) * 5.96e-8
+    assert info.status == 0
+    assert err_s <= tol and err_p <= tol
+
+
+def test_symmetric_f32_matches_the_oracle():
+    n, k, p = 2500, 30, 30
+    lam = gen.spectrum("poly", 600, alpha=1.5) * np.where(np.arange(600) % 4 == 2, -1.0, 1.0)
+    U0 = gen.orthonormal_factor(n, 600, 5, 1)
+    A = ((U0 * lam) @ U0.T).astype(np.float32)
+    A = 0.5 * (A + A.T)
+    U, S, V, info = run_factor(A, k, p, 0, "f32", seed=2, flags=_flags(sym=True))
+    Ur, Dr, _ = sp.single_pass_sym_seeded(A.astype(np.float64), k, p, 2)
+    err_s = np.abs(S - Dr).max() / abs(Dr[0])
+    err_p = np.abs((U * S) @ U.T - (Ur * Dr) @ Ur.T).max() / abs(Dr[0])
+    print(f"f32 symmetric: eigenvalue err {err_s:.2e}, product err {err_p:.2e} (relative to |lambda_1|)")
+    tol = 4.0 * np.sqrt(n) * 5.96e-8
+    assert info.status == 0
+    assert err_s <= tol and err_p <= tol
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_exact_at_rank_at_most_k(sym):
+    n, r, k, p = 500, 6, 10, 10
+    if sym:
+        lam = np.array([2.0, -1.5, 1.0, 0.5, -0.25, 0.125])
+        U0 = gen.orthonormal_factor(n, r, 1, 1)
+        A = (U0 * lam) @ U0.T
+        A = 0.5 * (A + A.T)
+        ref = lam[np.argsort(-np.abs(lam))]
+    else:
+        ref = np.logspace(0, -2, r)
+        A = gen.low_rank_matrix(n + 100, n, ref, 0.0, seed=2)
+    U, S, V, info = run_factor(A, k, p, 0, "f64", seed=1, flags=_flags(sym))
+    assert info.status == 0
+    assert np.abs(S[:r] - ref).max() <= 1e-12
+    assert np.abs(S[r:]).max() <= 1e-12
+    assert np.abs(A - (U * S) @ V.T).max() <= 1e-12
