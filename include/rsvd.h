@@ -143,7 +143,9 @@ typedef enum {
  * decreasing magnitude; d_V (if not NULL) gets U.
  *
  * Both need q == 0, eps == 0, fixed p (no selector), sketch_dtype ==
- * proj_dtype (the sketch operand format; no projection pass) and neither
+ * proj_dtype equal to a_dtype or RSVD_BF16 (then G_c and G_r are rounded to
+ * bf16 values before use, so the equations see the matrices the sketches
+ * were formed with; no projection pass) and neither
  * RSVD_RETURN_RANK_L, RSVD_SKETCH_SRHT nor RSVD_NYSTROM (RSVD_E_ARG
  * otherwise); the two flags exclude each other.
  */

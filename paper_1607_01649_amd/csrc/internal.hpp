@@ -122,6 +122,8 @@ hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, 
 // X(i, j) /= a_i + b_j (zero where a_i + b_j <= cut_rel (a_0 + b_0)).
 hipError_t launch_sylv_divide(double* X, int64_t ldx, int k1, int k2, const double* a, const double* b,
                               double cut_rel, hipStream_t s);
+// x[i] <- bf16 rounding of x[i] (nearest, ties to even), stored in binary32.
+hipError_t launch_round_bf16(float* x, int64_t n, hipStream_t s);
 // out = in^T for an rows x cols FP64 matrix.
 hipError_t launch_transpose64(const double* in, int64_t ldi, int rows, int cols, double* out, int64_t ldo,
                               hipStream_t s);

@@ -105,6 +105,7 @@ bool validate(const rsvd_desc* d) {
   if (const uint32_t spf = d->flags & (RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM)) {
     if (spf == (RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM)) return false;
     if (sel || d->q != 0 || d->eps != 0.0 || d->sketch_dtype != d->proj_dtype) return false;
+    if (d->sketch_dtype != d->a_dtype && d->sketch_dtype != RSVD_BF16) return false;
     if (d->flags & (RSVD_RETURN_RANK_L | RSVD_SKETCH_SRHT | RSVD_NYSTROM)) return false;
     if ((spf & RSVD_SINGLE_PASS_SYM) && d->m != d->n) return false;
   }
@@ -747,6 +748,14 @@ template <typename T> struct Path {
     else
       HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, l, 0, Gc, 1, L.ldn, st));
     if (!sym) HIP_TRY(launch_gaussian<T>(P.d.seed, 11u, m, l, 0, Gr, 1, L.ldm, st));
+    if (P.d.sketch_dtype == RSVD_BF16) {
+      // the bf16 product rounds its thin operand: round G_c and G_r here, so that the equations of step 4 use
+      // the test matrices the sketches were formed with
+      if constexpr (sizeof(T) == 4) {
+        HIP_TRY(launch_round_bf16(Gc, (int64_t)l * L.ldn, st));
+        if (!sym) HIP_TRY(launch_round_bf16(Gr, (int64_t)l * L.ldm, st));
+      }
+    }
     RS_TRY(apply_a(A, lda, Gc, l, Yc, P.d.sketch_dtype));
     if (!sym) RS_TRY(apply_at(A, lda, Gr, l, Yr, P.d.sketch_dtype));
     mark(1);

@@ -106,7 +106,23 @@ __global__ __launch_bounds__(256) void transpose64_kernel(const double* __restri
   out[(int64_t)i * ldo + j] = in[(int64_t)j * ldi + i];
 }
 
+// x <- the bfloat16 value nearest to x (ties to even), kept in binary32: a test matrix drawn for a bf16
+// sketch, so that the least-squares equations use the matrix the sketch was formed with.
+__global__ __launch_bounds__(256) void round_bf16_kernel(float* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  uint32_t u = __float_as_uint(x[i]);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  x[i] = __uint_as_float(u & 0xFFFF0000u);
+}
+
 }  // namespace
+
+hipError_t launch_round_bf16(float* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(round_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_transpose64(const double* in, int64_t ldi, int rows, int cols, double* out, int64_t ldo,
                               hipStream_t s) {

@@ -168,6 +168,7 @@ def test_single_pass_descriptions(lib):
                                       RSVD_SKETCH_SRHT)
     assert _ws(lib, _desc(q=0, flags=RSVD_SINGLE_PASS))[0] == 0
     assert _ws(lib, _desc(m=800, q=0, flags=RSVD_SINGLE_PASS_SYM))[0] == 0
+    assert _ws(lib, _desc(q=0, sketch_dtype="bf16", proj_dtype="bf16", flags=RSVD_SINGLE_PASS))[0] == 0
     bad = [dict(q=1, flags=RSVD_SINGLE_PASS),
            dict(q=0, eps=1e-2, max_rank=40, flags=RSVD_SINGLE_PASS),
            dict(q=0, flags=RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM),
@@ -176,6 +177,7 @@ def test_single_pass_descriptions(lib):
            dict(q=0, flags=RSVD_SINGLE_PASS | RSVD_SKETCH_SRHT),
            dict(m=800, q=0, flags=RSVD_SINGLE_PASS_SYM | RSVD_NYSTROM),
            dict(q=0, sketch_dtype="bf16", proj_dtype="f32", flags=RSVD_SINGLE_PASS),
+           dict(q=0, sketch_dtype="fp8", proj_dtype="fp8", flags=RSVD_SINGLE_PASS),
            dict(p=-1, q=-1, flags=RSVD_SINGLE_PASS)]
     for kw in bad:
         assert _ws(lib, _desc(**kw))[0] == -1, kw

@@ -107,3 +107,36 @@ def test_exact_at_rank_at_most_k(sym):
     assert np.abs(S[:r] - ref).max() <= 1e-12
     assert np.abs(S[r:]).max() <= 1e-12
     assert np.abs(A - (U * S) @ V.T).max() <= 1e-12
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_bf16_sketch_matches_the_oracle_on_rounded_operands(sym):
+    """bf16 sketches: the product uses bf16(A) and the bf16-rounded test matrices with FP32 accumulation; the
+    oracle in FP64 on the same rounded operands, so what remains is the FP32 accumulation (about sqrt(n) u_32
+    relative to sigma_1)."""
+    from oracle import philox, quant
+    m, n, k, p, seed = 2400, 1800, 30, 30, 5
+    if sym:
+        m = n
+        lam = gen.spectrum("poly", 500, alpha=1.5)
+        U0 = gen.orthonormal_factor(n, 500, 8, 1)
+        A = ((U0 * lam) @ U0.T).astype(np.float32)
+        A = 0.5 * (A + A.T)
+    else:
+        A = gen.low_rank_matrix(m, n, gen.spectrum("poly", 600, alpha=1.5), 1e-5, seed=6).astype(np.float32)
+    U, S, V, info = run_factor(A, k, p, 0, "f32", seed=seed, flags=_flags(sym), sketch_dtype="bf16",
+                               proj_dtype="bf16")
+    Aq = quant.bf16_round(A.astype(np.float64))
+    Gc = quant.bf16_round(philox.gaussian(n, k + p, seed, philox.STREAM_OMEGA))
+    if sym:
+        Ur, Dr, _ = sp.single_pass_sym(Aq, Gc, k)
+        Vr = Ur
+    else:
+        Gr = quant.bf16_round(philox.gaussian(m, k + p, seed, sp.STREAM_GR))
+        Ur, Dr, Vr, _ = sp.single_pass_gen(Aq, Gc, Gr, k)
+    err_s = np.abs(S - Dr).max() / abs(Dr[0])
+    err_p = np.abs((U * S) @ V.T - (Ur * Dr) @ Vr.T).max() / abs(Dr[0])
+    print(f"bf16 {'symmetric' if sym else 'general'}: value err {err_s:.2e}, product err {err_p:.2e}")
+    tol = 4.0 * np.sqrt(n) * 5.96e-8
+    assert info.status == 0
+    assert err_s <= tol and err_p <= tol
