@@ -11,6 +11,7 @@ HBM.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -387,7 +388,7 @@ def main():
                          "the headline")
     ap.add_argument("--cpu-rows", type=int, default=1 << 30, help="row sample of the CPU oracle (default: all rows)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--also", default="expdecay_65536:fp8,psd_20000:f32+nystrom",
+    ap.add_argument("--also", default="expdecay_65536:fp8,psd_20000:f32+nystrom,slowdecay_50000x20000:bf16+singlepass",
                     help="comma list of workload:sketch[/proj][+srht|+nystrom] legs timed after the headline "
                          "('' for none)")
     ap.add_argument("--leg-steps", type=int, default=5)
@@ -461,14 +462,17 @@ def main():
     torch.cuda.empty_cache()
     # further legs: other workloads and operand formats, each with its own roofline (not part of `value`)
     legs = {}
-    from paper_1607_01649_amd import RSVD_NYSTROM
-    variant_flags = {"": 0, "srht": RSVD_SKETCH_SRHT, "nystrom": RSVD_NYSTROM}
+    from paper_1607_01649_amd import RSVD_NYSTROM, RSVD_SINGLE_PASS, RSVD_SINGLE_PASS_SYM
+    variant_flags = {"": 0, "srht": RSVD_SKETCH_SRHT, "nystrom": RSVD_NYSTROM, "singlepass": RSVD_SINGLE_PASS,
+                     "singlepass_sym": RSVD_SINGLE_PASS_SYM}
     for leg in [x for x in args.also.split(",") if x]:
         wl, _, fmt = leg.partition(":")
         fmt, _, var = fmt.partition("+")
         sk, _, pj = fmt.partition("/")
         pj = pj or sk
         c2 = gen.config(wl)
+        if var.startswith("singlepass"):
+            c2 = dataclasses.replace(c2, q=0)   # one pass over A: no power steps
         A2 = c2.matrix(seed=args.seed, device=str(dev))
         A2 = A2.to(torch.float32) if c2.dtype == "f32" else A2
         torch.cuda.synchronize()
@@ -477,6 +481,8 @@ def main():
                      flags=variant_flags[var])
         if var == "nystrom":
             r["method"] = "Nystrom eigendecomposition (Section 9): A ~= U diag(S) U^T"
+        elif var == "singlepass":
+            r["method"] = "single-pass SVD (Section 5.2): Y_c = A G_c, Y_r = A^T G_r, least-squares core"
         if c2.noise_std == 0.0:
             r["vs_planted_sigma"] = vs_planted(c2.sigma(), r["_S"])
         r.pop("_S")

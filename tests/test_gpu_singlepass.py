@@ -140,3 +140,39 @@ def test_bf16_sketch_matches_the_oracle_on_rounded_operands(sym):
     tol = 4.0 * np.sqrt(n) * 5.96e-8
     assert info.status == 0
     assert err_s <= tol and err_p <= tol
+
+
+def test_general_at_the_headline_shape():
+    """The 50000 x 20000 FP32 slow-decay workload: with k = 20, p = 20 against the oracle in FP64 on the same
+    matrix and test matrices (sqrt(n) u_32 relative to sigma_1, 4 times); in the launch the bench times (k = 100,
+    p = 10, bf16 and FP32 sketches) through properties that hold at any size: orthonormal factors and descending
+    non-negative values."""
+    import torch
+    from paper_1607_01649_amd import RSVD
+    from tests.gpu_helpers import device
+    cfg = gen.config("slowdecay_50000x20000")
+    A = cfg.matrix(seed=1, device=str(device()))
+    m, n = cfg.m, cfg.n
+    solver = RSVD(m, n, 20, 20, 0, dtype="f32", device=device(), seed=3, flags=_flags())
+    U, S, V, info = solver(A)
+    torch.cuda.synchronize()
+    assert info.status == 0
+    Ah = A.double().cpu().numpy()
+    Ur, Dr, Vr, _ = sp.single_pass_gen_seeded(Ah, 20, 20, 3)
+    del Ah
+    S = S.cpu().numpy()
+    err = np.abs(S - Dr).max() / Dr[0]
+    print(f"50000 x 20000, k = 20: sigma err {err:.2e} (relative to sigma_1)")
+    assert err <= 4.0 * np.sqrt(n) * 5.96e-8
+    for sk in ("bf16", "f32"):
+        solver = RSVD(m, n, cfg.k, cfg.p, 0, dtype="f32", device=device(), seed=1, flags=_flags(), sketch_dtype=sk,
+                      proj_dtype=sk)
+        U, S, V, info = solver(A)
+        torch.cuda.synchronize()
+        assert info.status == 0
+        U, V, S = U.double(), V.double(), S.cpu().numpy()
+        eu = float(torch.linalg.matrix_norm(U.T @ U - torch.eye(cfg.k, device=U.device, dtype=U.dtype), ord=2))
+        ev = float(torch.linalg.matrix_norm(V.T @ V - torch.eye(cfg.k, device=V.device, dtype=V.dtype), ord=2))
+        print(f"{sk}: ||U^T U - I|| = {eu:.2e}, ||V^T V - I|| = {ev:.2e}")
+        assert eu <= 1e-4 and ev <= 1e-4
+        assert np.all(np.diff(S) <= 0) and S[-1] >= 0
