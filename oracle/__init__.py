@@ -23,6 +23,8 @@ Modules
            Hadamard transform, subsampled columns) and Figure 5 with it.
   nystrom  the Nystrom eigenvalue decomposition of Section 9 for symmetric
            positive semidefinite matrices, with a dropping Cholesky.
+  idcur    partial column-pivoted QR, the column / row ID, the randomized
+           row ID and the randomized CUR of Sections 10-11.
   singlepass  the single-pass factorisations of Section 5 (symmetric EVD
            and general SVD, each entry of A read once), least squares on
            the vectorised systems.
