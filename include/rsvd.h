@@ -59,6 +59,7 @@ typedef enum {
 #define RSVD_NYSTROM       0x8u  /* Nystrom eigendecomposition of a psd matrix (see below)     */
 #define RSVD_SINGLE_PASS   0x10u /* single-pass SVD of a general matrix (see below)            */
 #define RSVD_SINGLE_PASS_SYM 0x20u /* single-pass EVD of a symmetric matrix (see below)        */
+#define RSVD_ID_CUR        0x40u /* plan for rsvd_row_id / rsvd_cur (see there)                */
 
 /*
  * Problem description.
@@ -273,6 +274,36 @@ rsvd_status rsvd_plan(const rsvd_desc* d, void* d_ws, size_t ws_bytes, void* str
 rsvd_status rsvd_factor(rsvd_plan_t plan, const void* d_A, int64_t lda, const double* d_Omega,
                         void* d_U, int64_t ldu, double* d_S, void* d_V, int64_t ldv,
                         rsvd_info* h_info);
+
+/*
+ * Randomized row interpolative decomposition (Section 10.4, the figure with
+ * q power steps): A ~= X A(I_s, :) with I_s k row indices and X (m x k) the
+ * interpolation matrix (X(I_s, :) = I_k).  The plan's description must carry
+ * RSVD_ID_CUR, k + p <= 128, eps == 0, sketch_dtype == proj_dtype == a_dtype
+ * (RSVD_E_ARG otherwise).  The sample is Y = A G (G: n x (k+p) Gaussian,
+ * stream 4, or d_Omega), and for q >= 1 Y = A orth(A^T orth(Y)) q times
+ * (Figure 5's last sketch before its final orthonormalisation: the span of
+ * (A A^T)^q A G, kept stable); [I_s, X] = the row ID of Y by k steps of
+ * column-pivoted QR of Y^T (largest residual norm first, lowest index on
+ * ties; FP64), X = (S11^-1 S)^T.  d_Is: k int32 (device), d_X: m x k
+ * row-major (ldx >= k) in a_dtype.  Asynchronous when h_info == NULL.
+ */
+rsvd_status rsvd_row_id(rsvd_plan_t plan, const void* d_A, int64_t lda, const double* d_Omega,
+                        int32_t* d_Is, void* d_X, int64_t ldx, rsvd_info* h_info);
+
+/*
+ * Randomized CUR (Section 11 and its figure): A ~= A(:, J_s) U A(I_s, :).
+ * Plan as for rsvd_row_id.  The row sample Y (k+p x n) is the sample above
+ * for A^T (G: m x (k+p), stream 4); [J_s, Z] = the column ID of Y (k steps
+ * of column-pivoted QR, Z = S11^-1 S); I_s = the k pivots of the
+ * column-pivoted QR of A(:, J_s)^T; U (k x k) = the least-squares solution
+ * of U A(I_s, :) = Z through its normal equations (R = A(I_s, :), R R^T = V
+ * diag(lambda) V^T by Jacobi, eigenvalues at or below k u lambda_1 dropped:
+ * the minimum-norm solution where R is rank deficient).  d_Js, d_Is: k
+ * int32 each (device); d_U: k x k row-major FP64 (ldu >= k).
+ */
+rsvd_status rsvd_cur(rsvd_plan_t plan, const void* d_A, int64_t lda, int32_t* d_Js, double* d_U, int64_t ldu,
+                     int32_t* d_Is, rsvd_info* h_info);
 
 /* Release a plan (host memory and events only; the workspace stays the
  * caller's). NULL is ignored. */

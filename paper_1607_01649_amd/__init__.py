@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (  # noqa: F401
     RSVD_BATCHED_CLASSES, RSVD_BATCHED_TILE_VARIANTS, RSVD_BF16, RSVD_E_ARG, RSVD_E_HIP, RSVD_E_NONFINITE, RSVD_E_UNSUPPORTED, RSVD_E_WORKSPACE,
     RSVD_F32, RSVD_F64, RSVD_FP8_E4M3, RSVD_MLP_NPARAM, RSVD_NOT_CERTIFIED, RSVD_OK, RSVD_RETURN_RANK_L,
-    RSVD_NYSTROM, RSVD_SEL_NQ, RSVD_SEL_P, RSVD_SINGLE_PASS, RSVD_SINGLE_PASS_SYM, RSVD_SKETCH_SRHT,
+    RSVD_ID_CUR, RSVD_NYSTROM, RSVD_SEL_NQ, RSVD_SEL_P, RSVD_SINGLE_PASS, RSVD_SINGLE_PASS_SYM, RSVD_SKETCH_SRHT,
     RSVD_TIMING, RSVDError, STREAM_CERT, STREAM_OMEGA, STREAM_PROBE, rsvd_desc, rsvd_info,
     status_str,
 )
@@ -231,6 +231,33 @@ class RSVD:
             k = info.rank_out
             return U[:, :k], S[:k], V[:, :k], info
         return U, S, V, None
+
+    def row_id(self, A: torch.Tensor, omega: Optional[torch.Tensor] = None, want_info: bool = True):
+        """Randomized row ID (plan made with RSVD_ID_CUR): returns (I_s (k, int32), X (m x k), info) with
+        A ~= X A(I_s, :)."""
+        k = self.desc.k
+        Is = torch.empty(k, dtype=torch.int32, device=self.device)
+        X = torch.empty(self.desc.m, k, dtype=self.tdtype, device=self.device)
+        info = rsvd_info() if want_info else None
+        st = _lib.lib().rsvd_row_id(self.plan, _ptr(A), A.stride(0), _ptr(omega), _ptr(Is), _ptr(X), X.stride(0),
+                                    ctypes.byref(info) if info is not None else None)
+        if st < 0:
+            raise RSVDError(st, "rsvd_row_id")
+        return Is, X, info
+
+    def cur(self, A: torch.Tensor, want_info: bool = True):
+        """Randomized CUR (plan made with RSVD_ID_CUR): returns (J_s, U (k x k, float64), I_s, info) with
+        A ~= A(:, J_s) U A(I_s, :)."""
+        k = self.desc.k
+        Js = torch.empty(k, dtype=torch.int32, device=self.device)
+        Is = torch.empty(k, dtype=torch.int32, device=self.device)
+        U = torch.empty(k, k, dtype=torch.float64, device=self.device)
+        info = rsvd_info() if want_info else None
+        st = _lib.lib().rsvd_cur(self.plan, _ptr(A), A.stride(0), _ptr(Js), _ptr(U), U.stride(0), _ptr(Is),
+                                 ctypes.byref(info) if info is not None else None)
+        if st < 0:
+            raise RSVDError(st, "rsvd_cur")
+        return Js, U, Is, info
 
     def __del__(self):
         p = getattr(self, "plan", None)

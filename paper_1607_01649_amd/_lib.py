@@ -26,6 +26,7 @@ RSVD_SKETCH_SRHT = 0x4
 RSVD_NYSTROM = 0x8
 RSVD_SINGLE_PASS = 0x10
 RSVD_SINGLE_PASS_SYM = 0x20
+RSVD_ID_CUR = 0x40
 
 STREAM_OMEGA = 4
 STREAM_PROBE = 5
@@ -70,6 +71,10 @@ SIGNATURES = [
     ("rsvd_factor", ctypes.c_int, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p,
                                    _i64, ctypes.POINTER(rsvd_info)]),
     ("rsvd_destroy", None, [_c_void_p]),
+    ("rsvd_row_id", ctypes.c_int, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p, _c_void_p, _i64,
+                                   ctypes.POINTER(rsvd_info)]),
+    ("rsvd_cur", ctypes.c_int, [_c_void_p, _c_void_p, _i64, _c_void_p, _c_void_p, _i64, _c_void_p,
+                                ctypes.POINTER(rsvd_info)]),
     ("rsvd_factor_noalloc", ctypes.c_int, [ctypes.POINTER(rsvd_desc), _c_void_p, _i64, _c_void_p, _c_void_p, _i64,
                                            _c_void_p, _c_void_p, _i64, _c_void_p]),
     ("rsvd_gaussian", ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, _i64, _i64, _i64, ctypes.c_int32, _c_void_p,

@@ -131,6 +131,30 @@ hipError_t launch_transpose64(const double* in, int64_t ldi, int rows, int cols,
 hipError_t launch_coldot(const double* X, const double* Y, int64_t ld, int rows, int ncols, double* out,
                          hipStream_t s);
 
+// idcur.hip -- k steps of column-pivoted QR of the l x N matrix whose columns are the rows of an N x l panel Y
+// (l <= cpqr_max_rows()): pivots J, q vectors Q (l x k, leading dimension LQ), S = Q^T Y (k x N, row i at
+// S + i * ldS); scratch nrm2, orig (N doubles each), blkmax/blkidx (cpqr_blocks(N) each), counter (one word).
+int cpqr_max_rows();
+int64_t cpqr_blocks(int64_t N);
+template <typename T>
+hipError_t launch_cpqr(const T* Y, int64_t ld, int64_t N, int l, int k, double* Q, int LQ, double* S, int64_t ldS,
+                       double* nrm2, double* orig, double* blkmax, int* blkidx, unsigned* counter, int* J,
+                       hipStream_t s);
+// Z = S11^-1 S (k x N, row i at Z + i * ldZ) and/or X = Z^T (N x k row-major), S11 = S(:, J) into the k x k
+// scratch S11 (leading dimension LK).
+template <typename TX>
+hipError_t launch_id_solve(const double* S, int64_t ldS, int64_t N, int k, const int* J, double* S11, int LK,
+                           double* Z, int64_t ldZ, TX* X, int64_t ldx, hipStream_t s);
+// out (m x k panel) = A(:, J); out (n x k FP64 panel) = A(I, :)^T.
+template <typename T>
+hipError_t launch_gather_cols(const T* A, int64_t lda, int64_t m, const int* J, int k, T* out, int64_t ldo,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_gather_rows(const T* A, int64_t lda, int64_t n, const int* I, int k, double* out, int64_t ldo,
+                              hipStream_t s);
+// v[i] = 0 where v[i] <= rel v[0].
+hipError_t launch_cut_small(double* v, int n, double rel, hipStream_t s);
+
 // misc.hip
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 hipError_t launch_symmetrize(double* G, int64_t ldg, int l, hipStream_t s);

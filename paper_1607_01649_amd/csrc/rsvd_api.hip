@@ -57,7 +57,8 @@ struct Layout {
   int64_t ld16, ldT;   // leading dimensions of the bf16 copies of A and A^T
   size_t a16, a16t, a8, a8t, s8, xq, omega, gc, Y, T, Q, Z, Wp, Bt, agc, E, tmpr, zr, tmpn, small, small2, part, gpart, gpart2, G, R1, R, rinv,
       rinv_d, Q1d, sigma, uhat_d, uhat_p, vhat_p, scr_chol, scr_jac, norms, frob, flags, sel, srht_sgn, srht_sub,
-      gr, sp, total;
+      gr, sp, cp_S, cp_nrm, cp_orig, cp_bmax, cp_bidx, cp_cnt, cp_Q, cp_J, cp_Z, cp_small, total;
+  int64_t ldS;   // leading dimension of the pivoted QR's S (rows of length max(m, n))
 };
 
 int pick_splits(int64_t tiles, int64_t K, int64_t target, int64_t min_chunk) {
@@ -108,6 +109,12 @@ bool validate(const rsvd_desc* d) {
     if (d->sketch_dtype != d->a_dtype && d->sketch_dtype != RSVD_BF16) return false;
     if (d->flags & (RSVD_RETURN_RANK_L | RSVD_SKETCH_SRHT | RSVD_NYSTROM)) return false;
     if ((spf & RSVD_SINGLE_PASS_SYM) && d->m != d->n) return false;
+  }
+  if (d->flags & RSVD_ID_CUR) {
+    if (sel || d->eps != 0.0 || d->sketch_dtype != d->a_dtype || d->proj_dtype != d->a_dtype) return false;
+    if (l > cpqr_max_rows()) return false;
+    if (d->flags & (RSVD_RETURN_RANK_L | RSVD_SKETCH_SRHT | RSVD_NYSTROM | RSVD_SINGLE_PASS | RSVD_SINGLE_PASS_SYM))
+      return false;
   }
   if (d->flags & RSVD_SKETCH_SRHT) {
     if (sel || d->sketch_dtype != d->a_dtype) return false;
@@ -219,6 +226,22 @@ Layout make_layout(const rsvd_desc* d) {
   // single pass: the row-space test matrix G_r (m x l panel) and the FP64 k x k core (13 LP x LP matrices)
   L.gr = take((d->flags & RSVD_SINGLE_PASS) ? Wd * L.ldm * L.es : 256);
   L.sp = take(single_pass ? 13 * LP * LP * 8 : 256);
+  // interpolative decompositions: the pivoted QR's S (k rows of length max(m, n)), norms, block maxima, q vectors,
+  // pivots (two sets), CUR's Z (k x n) and its k x k matrices
+  const bool idc = (d->flags & RSVD_ID_CUR) != 0;
+  const int64_t nmax = std::max(d->m, d->n);
+  L.ldS = round_up(nmax, 64);
+  const size_t nbk = idc ? (size_t)cpqr_blocks(nmax) : 1;
+  L.cp_S = take(idc ? (size_t)d->k * L.ldS * 8 : 256);
+  L.cp_nrm = take(idc ? (size_t)nmax * 8 : 256);
+  L.cp_orig = take(idc ? (size_t)nmax * 8 : 256);
+  L.cp_bmax = take(nbk * 8);
+  L.cp_bidx = take(nbk * sizeof(int));
+  L.cp_cnt = take(sizeof(unsigned));
+  L.cp_Q = take(idc ? LP * LP * 8 : 256);
+  L.cp_J = take(idc ? 2 * LP * sizeof(int) : 256);
+  L.cp_Z = take(idc ? (size_t)d->k * L.ldn * 8 : 256);
+  L.cp_small = take(idc ? 6 * LP * LP * 8 : 256);
   L.total = off;
   return L;
 }
@@ -689,6 +712,132 @@ template <typename T> struct Path {
     double* gp = P.at<double>(L.gpart);
     HIP_TRY((launch_nn<T, T, double, double>(Xa, ld, na, rows, Xb, ld, nb, gp, ldc, (int64_t)ldc * nb, splits, st)));
     HIP_TRY((launch_reduce<double, double>(gp, splits, (int64_t)ldc * nb, ldc, na, nb, C, ldc, st)));
+    return RSVD_OK;
+  }
+
+  // Sample of the interpolative decompositions (Section 10.4): Y = A X0 (X0: the n x l test matrix), then q times
+  // Y = A orth(A^T orth(Y)); leaves Y (m x l panel).
+  rsvd_status id_sample_cols(const T* A, int64_t lda, const double* omega_in) {
+    const int64_t n = P.d.n;
+    const int l = L.l;
+    T* omega = P.at<T>(L.omega);
+    T* Y = P.at<T>(L.Y);
+    T* Q = P.at<T>(L.Q);
+    T* Z = P.at<T>(L.Z);
+    T* Wp = P.at<T>(L.Wp);
+    const int dt = P.d.a_dtype;
+    if (omega_in)
+      HIP_TRY(launch_rowmajor_to_panel<T>(omega_in, n, l, l, omega, L.ldn, st));
+    else
+      HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, l, 0, omega, 1, L.ldn, st));
+    RS_TRY(apply_a(A, lda, omega, l, Y, dt));
+    for (int it = 0; it < P.d.q; ++it) {
+      RS_TRY(orth(Y, L.ldm, P.d.m, l, L.s_gm, Q));
+      RS_TRY(apply_at(A, lda, Q, l, Z, dt));
+      RS_TRY(orth(Z, L.ldn, n, l, L.s_gn, Wp));
+      RS_TRY(apply_a(A, lda, Wp, l, Y, dt));
+    }
+    return RSVD_OK;
+  }
+
+  // The same for A^T (the row sample of the CUR figure): Z = A^T G (G: m x l, stream 4), then q times
+  // Z = A^T orth(A orth(Z)); leaves Z (n x l panel).
+  rsvd_status id_sample_rows(const T* A, int64_t lda) {
+    const int64_t m = P.d.m;
+    const int l = L.l;
+    T* Y = P.at<T>(L.Y);
+    T* Q = P.at<T>(L.Q);
+    T* Z = P.at<T>(L.Z);
+    T* Wp = P.at<T>(L.Wp);
+    const int dt = P.d.a_dtype;
+    HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, m, l, 0, Q, 1, L.ldm, st));
+    RS_TRY(apply_at(A, lda, Q, l, Z, dt));
+    for (int it = 0; it < P.d.q; ++it) {
+      RS_TRY(orth(Z, L.ldn, P.d.n, l, L.s_gn, Wp));
+      RS_TRY(apply_a(A, lda, Wp, l, Y, dt));
+      RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q));
+      RS_TRY(apply_at(A, lda, Q, l, Z, dt));
+    }
+    return RSVD_OK;
+  }
+
+  // k steps of column-pivoted QR of the short wide matrix whose columns are the rows of the panel Y (N x nr);
+  // pivots into J, S into the plan's S.
+  rsvd_status cpqr(const T* Y, int64_t ld, int64_t N, int nr, int k, int* J) {
+    HIP_TRY(launch_cpqr<T>(Y, ld, N, nr, k, P.at<double>(L.cp_Q), lp16(nr), P.at<double>(L.cp_S), L.ldS,
+                           P.at<double>(L.cp_nrm), P.at<double>(L.cp_orig), P.at<double>(L.cp_bmax),
+                           P.at<int>(L.cp_bidx), P.at<unsigned>(L.cp_cnt), J, st));
+    return RSVD_OK;
+  }
+
+  rsvd_status row_id(const T* A, int64_t lda, const double* omega_in, int32_t* Is, T* X, int64_t ldx) {
+    const int k = P.d.k;
+    HIP_TRY(launch_fill_int(P.at<int>(L.flags), kFlags, 0, st));
+    mark(0);
+    RS_TRY(id_sample_cols(A, lda, omega_in));
+    mark(1);
+    int* J = P.at<int>(L.cp_J);
+    RS_TRY(cpqr(P.at<T>(L.Y), L.ldm, P.d.m, L.l, k, J));
+    mark(2);
+    HIP_TRY(launch_id_solve<T>(P.at<double>(L.cp_S), L.ldS, P.d.m, k, J, P.at<double>(L.cp_small), lp16(k), nullptr,
+                               0, X, ldx, st));
+    HIP_TRY(hipMemcpyAsync(Is, J, (size_t)k * sizeof(int), hipMemcpyDeviceToDevice, st));
+    mark(3);
+    mark(4);
+    mark(5);
+    return RSVD_OK;
+  }
+
+  rsvd_status cur(const T* A, int64_t lda, int32_t* Js, double* Uo, int64_t ldu, int32_t* Is) {
+    const int64_t m = P.d.m, n = P.d.n;
+    const int k = P.d.k, LK = lp16(k);
+    int* flags = P.at<int>(L.flags);
+    HIP_TRY(launch_fill_int(flags, kFlags, 0, st));
+    mark(0);
+    RS_TRY(id_sample_rows(A, lda));
+    mark(1);
+    int* J0 = P.at<int>(L.cp_J);
+    int* J1 = J0 + L.LP;
+    double* sm = P.at<double>(L.cp_small);
+    const size_t K2 = (size_t)L.LP * L.LP;
+    double* S11 = sm;
+    double* M = sm + K2;
+    double* H = sm + 2 * K2;
+    double* V = sm + 3 * K2;
+    double* T1 = sm + 4 * K2;
+    double* lam = sm + 5 * K2;
+    double* Zm = P.at<double>(L.cp_Z);
+    // [J_s, Z] = column ID of the row sample (its columns are the rows of the n x l panel)
+    RS_TRY(cpqr(P.at<T>(L.Z), L.ldn, n, L.l, k, J0));
+    HIP_TRY(launch_id_solve<double>(P.at<double>(L.cp_S), L.ldS, n, k, J0, S11, LK, Zm, L.ldn, (double*)nullptr, 0,
+                                    st));
+    mark(2);
+    // I_s = the pivots of A(:, J_s)^T: its columns are the rows of the m x k panel C = A(:, J_s)
+    T* C = P.at<T>(L.Q);
+    HIP_TRY(launch_gather_cols<T>(A, lda, m, J0, k, C, L.ldm, st));
+    RS_TRY(cpqr(C, L.ldm, m, k, k, J1));
+    mark(3);
+    // U = Z R^+ with R = A(I_s, :): M = Z R^T, H = R R^T = V diag(lam) V^T, U = M V diag(lam)^+ V^T
+    double* Rt = P.at<double>(L.Q1d);
+    double* gp = P.at<double>(L.gpart);
+    HIP_TRY(launch_gather_rows<T>(A, lda, n, J1, k, Rt, L.ldn, st));
+    HIP_TRY((launch_nn<double, double, double, double>(Zm, L.ldn, k, n, Rt, L.ldn, k, gp, LK, (int64_t)LK * k, L.s_gn,
+                                                       st)));
+    HIP_TRY((launch_reduce<double, double>(gp, L.s_gn, (int64_t)LK * k, LK, k, k, M, LK, st)));
+    HIP_TRY((launch_nn<double, double, double, double>(Rt, L.ldn, k, n, Rt, L.ldn, k, gp, LK, (int64_t)LK * k, L.s_gn,
+                                                       st)));
+    HIP_TRY((launch_reduce<double, double>(gp, L.s_gn, (int64_t)LK * k, LK, k, k, H, LK, st)));
+    const double tol = (double)k * 2.220446049250313e-16;
+    HIP_TRY(launch_jacobi<double>(H, k, LK, tol, 60, lam, V, (double*)nullptr, (double*)nullptr,
+                                  P.at<double>(L.scr_jac), flags, st));
+    HIP_TRY(launch_cut_small(lam, k, tol, st));
+    HIP_TRY(launch_small_gemm<double>(k, k, k, M, LK, false, V, LK, false, T1, LK, false, lam, st));
+    HIP_TRY(launch_small_gemm<double>(k, k, k, T1, LK, false, V, LK, true, H, LK, false, nullptr, st));
+    HIP_TRY(launch_transpose64(H, LK, k, k, Uo, ldu, st));
+    HIP_TRY(hipMemcpyAsync(Js, J0, (size_t)k * sizeof(int), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(Is, J1, (size_t)k * sizeof(int), hipMemcpyDeviceToDevice, st));
+    mark(4);
+    mark(5);
     return RSVD_OK;
   }
 
@@ -1169,6 +1318,65 @@ rsvd_status rsvd_factor(rsvd_plan_t p, const void* d_A, int64_t lda, const doubl
   p->q_used = qc;
   DescSwap swap(p, derived_desc(&p->d, pc, qc));
   return factor_fixed(p, d_A, lda, nullptr, d_U, ldu, d_S, d_V, ldv, h_info);
+}
+
+// Shared tail of the decomposition entry points: device status words, and h_info when asked for.
+static rsvd_status finish_call(rsvd_plan_t p, rsvd_status s, rsvd_info* h_info) {
+  if (s < 0 || !h_info) return s;
+  int flags[kFlags];
+  HIP_TRY(hipMemcpyAsync(flags, p->ws + p->L.flags, sizeof(flags), hipMemcpyDeviceToHost, p->st));
+  HIP_TRY(hipStreamSynchronize(p->st));
+  if (flags[0] > 0 || flags[4] != 0) s = RSVD_E_NONFINITE;
+  memset(h_info, 0, sizeof(*h_info));
+  h_info->p_used = p->d.p;
+  h_info->q_used = p->d.q;
+  h_info->rank_out = p->d.k;
+  h_info->frob_residual = -1.0;
+  if (p->timing) {
+    for (int i = 0; i < 5; ++i) (void)hipEventElapsedTime(&h_info->stage_ms[i], p->ev[i], p->ev[i + 1]);
+    (void)hipEventElapsedTime(&h_info->stage_ms[7], p->ev[0], p->ev[5]);
+    for (int i = 0; i < p->ngemm; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, p->gev[2 * i], p->gev[2 * i + 1]);
+      if (p->gkind[i] == 0) { h_info->nn_ms += ms; h_info->nn_launches++; }
+      else { h_info->tn_ms += ms; h_info->tn_launches++; }
+    }
+  }
+  h_info->jacobi_sweeps = flags[3];
+  h_info->dropped_cols = flags[1];
+  h_info->status = s;
+  return s;
+}
+
+rsvd_status rsvd_row_id(rsvd_plan_t p, const void* d_A, int64_t lda, const double* d_Omega, int32_t* d_Is, void* d_X,
+                        int64_t ldx, rsvd_info* h_info) {
+  if (!p || !d_A || !d_Is || !d_X || !(p->d.flags & RSVD_ID_CUR) || lda < p->d.n || ldx < p->d.k) return RSVD_E_ARG;
+  p->ngemm = 0;
+  rsvd_status s;
+  if (p->d.a_dtype == RSVD_F64) {
+    Path<double> path(*p);
+    s = path.row_id(static_cast<const double*>(d_A), lda, d_Omega, d_Is, static_cast<double*>(d_X), ldx);
+  } else {
+    Path<float> path(*p);
+    s = path.row_id(static_cast<const float*>(d_A), lda, d_Omega, d_Is, static_cast<float*>(d_X), ldx);
+  }
+  return finish_call(p, s, h_info);
+}
+
+rsvd_status rsvd_cur(rsvd_plan_t p, const void* d_A, int64_t lda, int32_t* d_Js, double* d_U, int64_t ldu,
+                     int32_t* d_Is, rsvd_info* h_info) {
+  if (!p || !d_A || !d_Js || !d_U || !d_Is || !(p->d.flags & RSVD_ID_CUR) || lda < p->d.n || ldu < p->d.k)
+    return RSVD_E_ARG;
+  p->ngemm = 0;
+  rsvd_status s;
+  if (p->d.a_dtype == RSVD_F64) {
+    Path<double> path(*p);
+    s = path.cur(static_cast<const double*>(d_A), lda, d_Js, d_U, ldu, d_Is);
+  } else {
+    Path<float> path(*p);
+    s = path.cur(static_cast<const float*>(d_A), lda, d_Js, d_U, ldu, d_Is);
+  }
+  return finish_call(p, s, h_info);
 }
 
 rsvd_status rsvd_selector_set(rsvd_plan_t p, const float* d_theta, float tau) {

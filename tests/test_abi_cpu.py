@@ -181,3 +181,16 @@ def test_single_pass_descriptions(lib):
            dict(p=-1, q=-1, flags=RSVD_SINGLE_PASS)]
     for kw in bad:
         assert _ws(lib, _desc(**kw))[0] == -1, kw
+
+
+def test_id_cur_descriptions(lib):
+    from paper_1607_01649_amd import RSVD_ID_CUR, RSVD_SINGLE_PASS
+    assert _ws(lib, _desc(q=1, flags=RSVD_ID_CUR))[0] == 0
+    assert _ws(lib, _desc(q=1, flags=RSVD_ID_CUR))[1] > _ws(lib, _desc(q=1))[1]
+    bad = [dict(k=100, p=40, flags=RSVD_ID_CUR),                      # k + p > 128
+           dict(eps=1e-2, max_rank=40, flags=RSVD_ID_CUR),
+           dict(sketch_dtype="bf16", proj_dtype="bf16", flags=RSVD_ID_CUR),
+           dict(q=0, flags=RSVD_ID_CUR | RSVD_SINGLE_PASS),
+           dict(p=-1, q=-1, flags=RSVD_ID_CUR)]
+    for kw in bad:
+        assert _ws(lib, _desc(**kw))[0] == -1, kw

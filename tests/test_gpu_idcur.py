@@ -1,0 +1,89 @@
+"""GPU parity of the interpolative and CUR decompositions (Sections 10-11)
+through the C ABI against the oracle on the same test matrices: the pivots
+bit for bit (integer decisions taken in FP64 on both sides), the
+interpolation matrix X and CUR's U element by element, at ragged sizes with
+q = 0 and q = 1, FP64 and FP32 data, and exactness at rank k."""
+import numpy as np
+import pytest
+
+from oracle import idcur
+from tests.gpu_helpers import device
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(m, n, k, p, q, dt, seed):
+    from paper_1607_01649_amd import RSVD, RSVD_ID_CUR
+    return RSVD(m, n, k, p, q, dtype=dt, device=device(), seed=seed, flags=RSVD_ID_CUR)
+
+
+def _to_dev(A, dt):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(A)).to(device(), torch.float64 if dt == "f64" else torch.float32)
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(600, 400, 10, 8, 0), (517, 333, 7, 9, 1), (1200, 900, 30, 20, 1),
+                                       (300, 700, 12, 12, 0)])
+def test_row_id_f64_matches_the_oracle(m, n, k, p, q):
+    import torch
+    A = gen.low_rank_matrix(m, n, gen.spectrum("poly", min(m, n) // 2, alpha=1.5), 1e-6, seed=m + q)
+    seed = 5 + q
+    Is, X, info = _solver(m, n, k, p, q, "f64", seed).row_id(_to_dev(A, "f64"))
+    torch.cuda.synchronize()
+    Ir, Xr = idcur.randomized_row_id_seeded(A, k, p, q, seed)
+    assert info.status == 0
+    assert np.array_equal(Is.cpu().numpy(), Ir)
+    X = X.cpu().numpy()
+    assert np.abs(X - Xr).max() <= 1e-9 * max(1.0, np.abs(Xr).max())
+    assert np.allclose(X[Ir, :], np.eye(k), atol=1e-12)
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(600, 450, 8, 8, 0), (517, 389, 10, 6, 1)])
+def test_cur_f64_matches_the_oracle(m, n, k, p, q):
+    import torch
+    A = gen.low_rank_matrix(m, n, gen.spectrum("poly", min(m, n) // 2, alpha=1.0), 1e-6, seed=n + q)
+    seed = 9 + q
+    Js, U, Is, info = _solver(m, n, k, p, q, "f64", seed).cur(_to_dev(A, "f64"))
+    torch.cuda.synchronize()
+    Jr, Ur, Ir = idcur.randomized_cur_seeded(A, k, p, q, seed)
+    assert info.status == 0
+    assert np.array_equal(Js.cpu().numpy(), Jr) and np.array_equal(Is.cpu().numpy(), Ir)
+    U = U.cpu().numpy()
+    # U = Z R^+ through the normal equations: about u cond(R)^2 relative to |U|
+    R = A[Ir, :]
+    c = np.linalg.cond(R)
+    assert np.abs(U - Ur).max() <= 100 * 2.2e-16 * c * c * np.abs(Ur).max()
+
+
+def test_row_id_f32_matches_the_oracle():
+    import torch
+    m, n, k, p, q = 2000, 1500, 20, 12, 1
+    A = gen.low_rank_matrix(m, n, gen.spectrum("poly", 500, alpha=1.5), 1e-5, seed=3).astype(np.float32)
+    Is, X, info = _solver(m, n, k, p, q, "f32", 2).row_id(_to_dev(A, "f32"))
+    torch.cuda.synchronize()
+    Ir, Xr = idcur.randomized_row_id_seeded(A.astype(np.float64), k, p, q, 2)
+    assert info.status == 0
+    assert np.array_equal(Is.cpu().numpy(), Ir)
+    err = np.abs(X.cpu().numpy() - Xr).max()
+    print(f"f32 row ID: max |X - X_oracle| = {err:.2e}")
+    assert err <= 1e-4 * max(1.0, np.abs(Xr).max())
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_exact_at_rank_k(dt):
+    import torch
+    m, n, k, p = 800, 500, 9, 7
+    A = gen.low_rank_matrix(m, n, np.logspace(0, -2, k), 0.0, seed=4)
+    if dt == "f32":
+        A = A.astype(np.float32)
+    s = _solver(m, n, k, p, 0, dt, 1)
+    Is, X, _ = s.row_id(_to_dev(A, dt))
+    Js, U, Is2, _ = s.cur(_to_dev(A, dt))
+    torch.cuda.synchronize()
+    Is, X = Is.cpu().numpy(), X.double().cpu().numpy()
+    Js, U, Is2 = Js.cpu().numpy(), U.cpu().numpy(), Is2.cpu().numpy()
+    A64 = A.astype(np.float64)
+    tol = 1e-10 if dt == "f64" else 1e-5
+    assert np.abs(A64 - X @ A64[Is, :]).max() <= tol
+    assert np.abs(A64 - A64[:, Js] @ U @ A64[Is2, :]).max() <= tol
