@@ -289,6 +289,53 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed, keep_u=True, flags=0):
             "jacobi_sweeps": info.jacobi_sweeps, "time_to_eps": tte, "roofline": roof}
 
 
+def run_id_leg(A, cfg, kind, steps, warmup, seed):
+    """Randomized row ID (Section 10.4) or CUR (Section 11) on the workload's matrix: time per call (HIP events
+    on the plan's stream bracket the timed calls), the pivoted-QR share (RSVD_TIMING stage events) and the
+    untimed spectral error of the result against sigma_{k+1}."""
+    import torch
+    from paper_1607_01649_amd import RSVD, RSVD_ID_CUR, RSVD_TIMING
+    m, n, k, p, q = cfg.m, cfg.n, cfg.k, cfg.p, cfg.q
+    solver = RSVD(m, n, k, p, q, dtype=cfg.dtype, device=A.device, seed=seed, flags=RSVD_ID_CUR | RSVD_TIMING)
+    call = (lambda: solver.row_id(A)) if kind == "rowid" else (lambda: solver.cur(A))
+    for _ in range(warmup):
+        out = call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stage = np.zeros(8)
+    for _ in range(steps):
+        out = call()
+        stage += np.array(out[-1].stage_ms)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stage /= steps
+    g = torch.Generator(device=A.device)
+    g.manual_seed(0)
+    x = torch.randn(n, 1, generator=g, device=A.device, dtype=torch.float64)
+    if kind == "rowid":
+        Is, X, _ = out
+        R = A[Is.long()].double()
+        fwd = lambda v: (A @ v.float()).double() - X.double() @ (R @ v)
+        adj = lambda w: (A.T @ w.float()).double() - R.T @ (X.double().T @ w)
+    else:
+        Js, U, Is, _ = out
+        C = A[:, Js.long()].double()
+        R = A[Is.long()].double()
+        fwd = lambda v: (A @ v.float()).double() - C @ (U @ (R @ v))
+        adj = lambda w: (A.T @ w.float()).double() - R.T @ (U.T @ (C.T @ w))
+    est = 0.0
+    for _ in range(40):
+        x = x / torch.linalg.norm(x)
+        x = adj(fwd(x))
+        est = math.sqrt(float(torch.linalg.norm(x)))
+    sig = cfg.sigma()
+    label = "randomized row ID (Section 10.4)" if kind == "rowid" else "randomized CUR (Section 11)"
+    return {"method": label, "ms_per_step": dt * 1e3, "stage_ms": [round(float(v), 4) for v in stage],
+            "stages": "sample (Stage A products), pivoted QR, solve / second pivoted QR, U, -, -, -, total",
+            "spectral_error": est, "sigma_k+1": float(sig[k]), "error_over_sigma_k+1": est / float(sig[k]),
+            "workload": cfg.name, "m": m, "n": n, "k": k, "p": p, "q": q, "steps": steps, "warmup": warmup}
+
+
 def srht_roofline(A, l, seed, reps=10):
     """The structured sketch (Section 6) on its own: the library's kernel-level entry (draw and one-pass
     transform) timed with HIP events on the current stream; HBM-bound, algorithmic bytes = A once + Y."""
@@ -388,7 +435,8 @@ def main():
                          "the headline")
     ap.add_argument("--cpu-rows", type=int, default=1 << 30, help="row sample of the CPU oracle (default: all rows)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--also", default="expdecay_65536:fp8,psd_20000:f32+nystrom,slowdecay_50000x20000:bf16+singlepass",
+    ap.add_argument("--also", default="expdecay_65536:fp8,psd_20000:f32+nystrom,slowdecay_50000x20000:bf16+singlepass,"
+                                      "slowdecay_50000x20000:f32+rowid,slowdecay_50000x20000:f32+cur",
                     help="comma list of workload:sketch[/proj][+srht|+nystrom] legs timed after the headline "
                          "('' for none)")
     ap.add_argument("--leg-steps", type=int, default=5)
@@ -473,6 +521,15 @@ def main():
         c2 = gen.config(wl)
         if var.startswith("singlepass"):
             c2 = dataclasses.replace(c2, q=0)   # one pass over A: no power steps
+        if var in ("rowid", "cur"):
+            A2 = c2.matrix(seed=args.seed, device=str(dev))
+            A2 = A2.to(torch.float32) if c2.dtype == "f32" else A2
+            torch.cuda.synchronize()
+            legs[leg] = run_id_leg(A2, c2, var, args.leg_steps, args.leg_warmup, args.seed)
+            print(f"[bench] leg {leg}: {legs[leg]['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
+            del A2
+            torch.cuda.empty_cache()
+            continue
         A2 = c2.matrix(seed=args.seed, device=str(dev))
         A2 = A2.to(torch.float32) if c2.dtype == "f32" else A2
         torch.cuda.synchronize()

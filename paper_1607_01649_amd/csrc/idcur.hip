@@ -156,9 +156,19 @@ __global__ __launch_bounds__(kCpThreads) void cpqr_step_kernel(const T* __restri
   double v = -1.0;
   int ci = -1;
   if (c < N) {
-    double s = 0.0;
-    for (int t = 0; t < l; ++t) s += qs[t] * static_cast<double>(Y[(int64_t)t * ld + c]);
+    // four independent partial sums, so that the column's loads are in flight together
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int t = 0;
+    for (; t + 4 <= l; t += 4) {
+      s0 += qs[t] * static_cast<double>(Y[(int64_t)t * ld + c]);
+      s1 += qs[t + 1] * static_cast<double>(Y[(int64_t)(t + 1) * ld + c]);
+      s2 += qs[t + 2] * static_cast<double>(Y[(int64_t)(t + 2) * ld + c]);
+      s3 += qs[t + 3] * static_cast<double>(Y[(int64_t)(t + 3) * ld + c]);
+    }
+    for (; t < l; ++t) s0 += qs[t] * static_cast<double>(Y[(int64_t)t * ld + c]);
+    const double s = (s0 + s1) + (s2 + s3);
     S[(int64_t)j * ldS + c] = s;
+    if (j + 1 >= k) return;   // the last step elects no pivot: its norms are not needed
     double r = nrm2[c];
     if (r >= 0.0) {
       r -= s * s;
@@ -176,7 +186,7 @@ __global__ __launch_bounds__(kCpThreads) void cpqr_step_kernel(const T* __restri
       ci = (int)c;
     }
   }
-  if (j + 1 >= k) return;
+  if (j + 1 >= k) return;   // uniform: every thread of every block leaves here on the last step
   block_argmax(v, ci, sv, sc);
   if (tid == 0) {
     blkmax[blockIdx.x] = v;
@@ -225,15 +235,15 @@ __global__ __launch_bounds__(kSolveThreads) void id_solve_kernel(const double* _
   }
 }
 
-// out (m x k panel) column t = A(:, J[t]).
+// out (m x k panel) column t = A(:, J[t]): the lanes of a wave read one row of A (its k chosen entries lie
+// within that row, so a wave touches one row's pages rather than one page per row), four rows per block.
 template <typename T>
 __global__ __launch_bounds__(256) void gather_cols_kernel(const T* __restrict__ A, int64_t lda, int64_t m,
                                                           const int* __restrict__ J, int k, T* __restrict__ out,
                                                           int64_t ldo) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int t = blockIdx.y;
-  if (r >= m || t >= k) return;
-  out[(int64_t)t * ldo + r] = A[r * lda + J[t]];
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= m) return;
+  for (int t = threadIdx.x & 63; t < k; t += 64) out[(int64_t)t * ldo + r] = A[r * lda + J[t]];
 }
 
 // out (n x k panel, FP64) column t = A(I[t], :)^T.
@@ -300,8 +310,8 @@ template <typename T>
 hipError_t launch_gather_cols(const T* A, int64_t lda, int64_t m, const int* J, int k, T* out, int64_t ldo,
                               hipStream_t s) {
   if (m <= 0 || k <= 0) return hipSuccess;
-  hipLaunchKernelGGL((gather_cols_kernel<T>), dim3((unsigned)((m + 255) / 256), (unsigned)k), dim3(256), 0, s, A, lda,
-                     m, J, k, out, ldo);
+  hipLaunchKernelGGL((gather_cols_kernel<T>), dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, lda, m, J, k, out,
+                     ldo);
   return hipGetLastError();
 }
 template hipError_t launch_gather_cols<float>(const float*, int64_t, int64_t, const int*, int, float*, int64_t,

@@ -87,3 +87,22 @@ def test_exact_at_rank_k(dt):
     tol = 1e-10 if dt == "f64" else 1e-5
     assert np.abs(A64 - X @ A64[Is, :]).max() <= tol
     assert np.abs(A64 - A64[:, Js] @ U @ A64[Is2, :]).max() <= tol
+
+
+def test_row_id_at_the_headline_shape():
+    """The 50000 x 20000 FP32 slow-decay workload, k = 100, p = 10 (q = 0, so the oracle finishes in seconds):
+    pivots bit for bit against the oracle in FP64 on the same matrix, X element by element."""
+    import torch
+    cfg = gen.config("slowdecay_50000x20000")
+    A = cfg.matrix(seed=1, device=str(device()))
+    Is, X, info = _solver(cfg.m, cfg.n, cfg.k, cfg.p, 0, "f32", 1).row_id(A)
+    torch.cuda.synchronize()
+    assert info.status == 0
+    Ir, Xr = idcur.randomized_row_id_seeded(A.double().cpu().numpy(), cfg.k, cfg.p, 0, 1)
+    Is = Is.cpu().numpy()
+    same = int(np.sum(Is == Ir))
+    print(f"50000 x 20000 row ID: {same} of {cfg.k} pivots equal")
+    assert np.array_equal(Is, Ir)
+    err = np.abs(X.cpu().numpy() - Xr).max()
+    print(f"max |X - X_oracle| = {err:.2e}")
+    assert err <= 1e-3 * max(1.0, np.abs(Xr).max())
