@@ -91,9 +91,11 @@ def traffic_summary(fetch_dir, write_dir, out_path, calib_bytes, kernel_prefix="
              "Two rocprofv3 counter passes over the same bench command (repository root, MI355X), each counter",
              "scaled by what it reads for a plain copy of a known size (an elementwise torch kernel, `--copy-calibration`):",
              "", "    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'lp_nn|Functor' -d gpurun_out/pmc_fetch -o run "
-             f"--output-format csv -- python -u bench.py --paths bf16 --steps 1 --warmup 0 --no-cpu --copy-calibration {calib_bytes}",
+             "--output-format csv -- python -u bench.py --paths bf16 --steps 1 --warmup 0 --no-cpu --also '' "
+             f"--copy-calibration {calib_bytes}",
              "    rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'lp_nn|Functor' -d gpurun_out/pmc_write -o run "
-             f"--output-format csv -- python -u bench.py --paths bf16 --steps 1 --warmup 0 --no-cpu --copy-calibration {calib_bytes}",
+             "--output-format csv -- python -u bench.py --paths bf16 --steps 1 --warmup 0 --no-cpu --also '' "
+             f"--copy-calibration {calib_bytes}",
              f"    python bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write {calib_bytes}", "",
              "| counter | copy scale | launches | bytes per launch (scaled) |", "|---|---|---|---|"]
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
@@ -477,11 +479,16 @@ def main():
     paths = [p for p in args.paths.split(",") if p]
     res = {}
     print(f"[bench] {args.workload}: matrix ready", file=sys.stderr, flush=True)
-    from paper_1607_01649_amd import RSVD_SKETCH_SRHT
+    from paper_1607_01649_amd import RSVD_NYSTROM, RSVD_SINGLE_PASS, RSVD_SINGLE_PASS_SYM, RSVD_SKETCH_SRHT
+    variant_flags = {"": 0, "srht": RSVD_SKETCH_SRHT, "nystrom": RSVD_NYSTROM, "singlepass": RSVD_SINGLE_PASS,
+                     "singlepass_sym": RSVD_SINGLE_PASS_SYM}
     for pth in paths:
         fmt, _, var = pth.partition("+")
-        fl = RSVD_SKETCH_SRHT if var == "srht" else 0
-        res[pth] = run_path(A, cfg, fmt, fmt, args.steps, args.warmup, args.seed, keep_u=not args.no_cpu, flags=fl)
+        if var not in variant_flags:
+            raise SystemExit(f"unknown path variant '{var}' (row ID and CUR run as --also legs)")
+        cfg_p = dataclasses.replace(cfg, q=0) if var.startswith("singlepass") else cfg
+        res[pth] = run_path(A, cfg_p, fmt, fmt, args.steps, args.warmup, args.seed, keep_u=not args.no_cpu,
+                            flags=variant_flags[var])
         if var == "srht":
             res[pth]["sketch"] = "structured (Section 6: random signs, Walsh-Hadamard, subsampled columns)"
             res[pth]["srht_roofline"] = srht_roofline(A, cfg.k + cfg.p, args.seed)
@@ -498,21 +505,26 @@ def main():
         print("[bench] cpu oracle done", file=sys.stderr, flush=True)
         if ref is not None:
             for pth in paths:
-                key = "vs_fp64_oracle" if "+" not in pth else "vs_fp64_oracle_gaussian_omega"
-                res[pth][key] = vs_oracle(ref, res[pth]["_S"], res[pth]["_U"])
+                if "+" not in pth:
+                    res[pth]["vs_fp64_oracle"] = vs_oracle(ref, res[pth]["_S"], res[pth]["_U"])
+                elif pth.endswith("+srht"):
+                    res[pth]["vs_fp64_oracle_gaussian_omega"] = vs_oracle(ref, res[pth]["_S"], res[pth]["_U"])
     if cfg.noise_std == 0.0:
         for pth in paths:
             res[pth]["vs_planted_sigma"] = vs_planted(cfg.sigma(), res[pth]["_S"])
     for pth in paths:
         res[pth].pop("_S")
         res[pth].pop("_U")
-    del A
     torch.cuda.empty_cache()
+
+    def leg_matrix(c2):
+        """The leg's matrix: the headline's when the workload is the same (no second generation)."""
+        if c2.name == args.workload:
+            return A
+        M = c2.matrix(seed=args.seed, device=str(dev))
+        return M.to(torch.float32) if c2.dtype == "f32" else M
     # further legs: other workloads and operand formats, each with its own roofline (not part of `value`)
     legs = {}
-    from paper_1607_01649_amd import RSVD_NYSTROM, RSVD_SINGLE_PASS, RSVD_SINGLE_PASS_SYM
-    variant_flags = {"": 0, "srht": RSVD_SKETCH_SRHT, "nystrom": RSVD_NYSTROM, "singlepass": RSVD_SINGLE_PASS,
-                     "singlepass_sym": RSVD_SINGLE_PASS_SYM}
     for leg in [x for x in args.also.split(",") if x]:
         wl, _, fmt = leg.partition(":")
         fmt, _, var = fmt.partition("+")
@@ -522,16 +534,14 @@ def main():
         if var.startswith("singlepass"):
             c2 = dataclasses.replace(c2, q=0)   # one pass over A: no power steps
         if var in ("rowid", "cur"):
-            A2 = c2.matrix(seed=args.seed, device=str(dev))
-            A2 = A2.to(torch.float32) if c2.dtype == "f32" else A2
+            A2 = leg_matrix(c2)
             torch.cuda.synchronize()
             legs[leg] = run_id_leg(A2, c2, var, args.leg_steps, args.leg_warmup, args.seed)
             print(f"[bench] leg {leg}: {legs[leg]['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
             del A2
             torch.cuda.empty_cache()
             continue
-        A2 = c2.matrix(seed=args.seed, device=str(dev))
-        A2 = A2.to(torch.float32) if c2.dtype == "f32" else A2
+        A2 = leg_matrix(c2)
         torch.cuda.synchronize()
         print(f"[bench] {wl}: matrix ready", file=sys.stderr, flush=True)
         r = run_path(A2, c2, sk, pj, args.leg_steps, args.leg_warmup, args.seed, keep_u=False,
@@ -550,6 +560,7 @@ def main():
         print(f"[bench] leg {leg}: {r['ms_per_step']:.2f} ms per step", file=sys.stderr, flush=True)
         del A2
         torch.cuda.empty_cache()
+    del A
     if legs:
         out["legs"] = legs
     print(json.dumps(out), flush=True)
