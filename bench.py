@@ -252,8 +252,8 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed, keep_u=True, flags=0):
         lp_nb = ((nt + groups - 1) // groups + 1) // 2 * 2
     names = {"f32": ("nn_kernel (Y = A X, FP32 MFMA)", "tn_kernel (Z = A^T Q, FP32 MFMA)"),
              "f64": ("nn_kernel (Y = A X, FP64 MFMA)", "tn_kernel (Z = A^T Q, FP64 MFMA)"),
-             "bf16": ("lp_nn_kernel<0,%d,4,1> (Y = bf16(A) X)" % lp_nb, "lp_nn_kernel<0,%d,4,1> (Z = bf16(A)^T Q)" % lp_nb),
-             "fp8": ("lp_nn_kernel<1,%d,4,1> (Y = fp8(A) X)" % lp_nb, "lp_nn_kernel<1,%d,4,1> (Z = fp8(A)^T Q)" % lp_nb)}[sketch]
+             "bf16": ("lp_nn_kernel<0,%d,4,1,true> (Y = bf16(A) X)" % lp_nb, "lp_nn_kernel<0,%d,4,1,true> (Z = bf16(A)^T Q)" % lp_nb),
+             "fp8": ("lp_nn_kernel<1,%d,4,1,true> (Y = fp8(A) X)" % lp_nb, "lp_nn_kernel<1,%d,4,1,true> (Z = fp8(A)^T Q)" % lp_nb)}[sketch]
     dom_nn = nn_ms >= tn_ms
     avg = avg_nn if dom_nn else avg_tn
     # algorithmic bytes of one product: A once in its operand format, the thin FP32 operand and result

@@ -13,6 +13,8 @@
 // quantised as it is staged: one scale per 128-row segment of each column.
 //
 // The product itself is in lpgemm.hip.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "lowp_common.hpp"
 
@@ -22,7 +24,7 @@ namespace rsvd {
 // ------------------------------------------------------------------ conversion
 
 // One 128 x 128 tile per block (256 threads): scale, A8 rows, and A8T rows through LDS.
-template <bool VEC>
+template <bool VEC, bool TILED>
 __global__ __launch_bounds__(256) void to_fp8_kernel(const float* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                      uint8_t* __restrict__ A8, int64_t ld8, uint8_t* __restrict__ A8T,
                                                      int64_t ldT, float* __restrict__ scale, int ntc,
@@ -63,7 +65,8 @@ __global__ __launch_bounds__(256) void to_fp8_kernel(const float* __restrict__ A
   __syncthreads();
   const float amax = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
   const int ex = fp8_scale_exp(amax);
-  if (t == 0) scale[(int64_t)blockIdx.y * ntc + blockIdx.x] = ldexpf(1.0f, ex);
+  // (the tiled form's grid reaches past the scale table to zero the padding of the last row block)
+  if (t == 0 && (!TILED || (i0 < ldT && j0 < ld8))) scale[(int64_t)blockIdx.y * ntc + blockIdx.x] = ldexpf(1.0f, ex);
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) {
     const int ii = rg + 8 * rr;
@@ -75,9 +78,37 @@ __global__ __launch_bounds__(256) void to_fp8_kernel(const float* __restrict__ A
       tile[ii][4 * c4 + e] = (uint8_t)c;
       w |= c << (8 * e);
     }
-    if (i < m) *reinterpret_cast<uint32_t*>(A8 + i * ld8 + j0 + 4 * c4) = w;
+    if (!TILED && i < m) *reinterpret_cast<uint32_t*>(A8 + i * ld8 + j0 + 4 * c4) = w;
   }
   __syncthreads();
+  if constexpr (TILED) {
+    // 16-byte units (16 codes): A8 (row i0 + ii, indices j0 + 16 cu ..) and A8T (row j0 + jj, indices i0 + 16 ru ..),
+    // four of each per thread
+    const int64_t rbA = lp_tiled_rows(m) / kTileRows, rbT = lp_tiled_rows(n) / kTileRows;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int u = t + 256 * h;
+      const int ii = u >> 3, cu = u & 7;
+      const int64_t r = i0 + ii, k = j0 + 16 * cu;
+      if (r < rbA * kTileRows && k < ld8) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&tile[ii][16 * cu]);
+        *reinterpret_cast<uint4*>(A8 + 16 * lp_tiled_unit<1>(r, k, rbA)) = make_uint4(src[0], src[1], src[2], src[3]);
+      }
+      const int jj = u >> 3, ru = u & 7;
+      const int64_t rt = j0 + jj, kt = i0 + 16 * ru;
+      if (rt < rbT * kTileRows && kt < ldT) {
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r0 = 16 * ru + 4 * q;
+          w[q] = (uint32_t)tile[r0][jj] | ((uint32_t)tile[r0 + 1][jj] << 8) | ((uint32_t)tile[r0 + 2][jj] << 16) |
+                 ((uint32_t)tile[r0 + 3][jj] << 24);
+        }
+        *reinterpret_cast<uint4*>(A8T + 16 * lp_tiled_unit<1>(rt, kt, rbT)) = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+    return;
+  }
   // transposed: thread t writes 64 bytes of row j0 + t/2 of A8T (columns i0 + 64 (t%2) ..)
   const int jj = t >> 1, half = t & 1;
   const int64_t j = j0 + jj;
@@ -104,10 +135,35 @@ hipError_t launch_to_fp8(const float* A, int64_t lda, int64_t m, int64_t n, uint
   dim3 grid((unsigned)ntc, (unsigned)(ldT / 128));
   const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   if (vec)
-    hipLaunchKernelGGL(to_fp8_kernel<true>, grid, dim3(256), 0, s, A, lda, m, n, A8, ld8, A8T, ldT, scale, ntc, flag);
-  else
-    hipLaunchKernelGGL(to_fp8_kernel<false>, grid, dim3(256), 0, s, A, lda, m, n, A8, ld8, A8T, ldT, scale, ntc,
+    hipLaunchKernelGGL((to_fp8_kernel<true, false>), grid, dim3(256), 0, s, A, lda, m, n, A8, ld8, A8T, ldT, scale, ntc,
                        flag);
+  else
+    hipLaunchKernelGGL((to_fp8_kernel<false, false>), grid, dim3(256), 0, s, A, lda, m, n, A8, ld8, A8T, ldT, scale,
+                       ntc, flag);
+  return hipGetLastError();
+}
+
+size_t fp8_tiled_bytes(int64_t rows, int64_t K) {
+  return (size_t)lp_tiled_rows(rows) * (size_t)((K + kTileK - 1) / kTileK * kTileK);
+}
+
+// The same codes and scales with A8 and A8T in the tiled layout (lowp_common.hpp); the scale table is that of
+// launch_to_fp8 ((ldT / 128) x (ld8 / 128), ld8 = n and ldT = m rounded up to 128).
+hipError_t launch_to_fp8_tiled(const float* A, int64_t lda, int64_t m, int64_t n, uint8_t* A8, uint8_t* A8T,
+                               float* scale, int* flag, hipStream_t s) {
+  if ((reinterpret_cast<uintptr_t>(A8) & 15) != 0 || (reinterpret_cast<uintptr_t>(A8T) & 15) != 0)
+    return hipErrorInvalidValue;
+  const int64_t ld8 = (n + kTileK - 1) / kTileK * kTileK, ldT = (m + kTileK - 1) / kTileK * kTileK;
+  const int ntc = (int)(ld8 / 128);
+  const int64_t cols = std::max(ld8, lp_tiled_rows(n)), rows = std::max(ldT, lp_tiled_rows(m));
+  dim3 grid((unsigned)(cols / 128), (unsigned)(rows / 128));
+  const bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  if (vec)
+    hipLaunchKernelGGL((to_fp8_kernel<true, true>), grid, dim3(256), 0, s, A, lda, m, n, A8, ld8, A8T, ldT, scale, ntc,
+                       flag);
+  else
+    hipLaunchKernelGGL((to_fp8_kernel<false, true>), grid, dim3(256), 0, s, A, lda, m, n, A8, ld8, A8T, ldT, scale,
+                       ntc, flag);
   return hipGetLastError();
 }
 

@@ -60,6 +60,11 @@ hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, doub
 // and the FP8 MFMA product with an FP32 panel quantised per 128-row segment of each column.
 hipError_t launch_to_fp8(const float* A, int64_t lda, int64_t m, int64_t n, uint8_t* A8, int64_t ld8, uint8_t* A8T,
                          int64_t ldT, float* scale, int* flag, hipStream_t s);
+// The same codes and scales with A8 (m x n) and A8T (n x m) in the tiled layout of lowp_common.hpp
+// (fp8_tiled_bytes(m, n) and fp8_tiled_bytes(n, m) bytes).
+size_t fp8_tiled_bytes(int64_t rows, int64_t K);
+hipError_t launch_to_fp8_tiled(const float* A, int64_t lda, int64_t m, int64_t n, uint8_t* A8, uint8_t* A8T,
+                               float* scale, int* flag, hipStream_t s);
 // lpgemm.hip -- products of a low-precision copy of A (kind 0: bf16, 1: E4M3 with tile scales, scale of row
 // block rb and contraction block kb at sA[rb * s_row + kb * s_k]) with an FP32 panel converted once into
 // FP64-accumulated Gram Y^T Y of an nc-column panel (FP32 or FP64), split-K partials as launch_nn (gram.hip);
@@ -73,9 +78,10 @@ size_t lp_scratch_bytes(int kind, int64_t K, int ncols);
 int lp_splits_used(int64_t K, int splits);
 int64_t lp_row_workgroups(int kind, int64_t rows, int ncols);
 int lp_resident_workgroups();
-hipError_t launch_nn_lp(int kind, const void* A, int64_t lda, const float* sA, int64_t s_row, int64_t s_k,
-                        int64_t rows, int64_t K, const float* X, int64_t ldx, int ncols, void* scratch, float* out,
-                        int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
+// tiled: A in the tiled layout of lowp_common.hpp (lda unused), else row-major.
+hipError_t launch_nn_lp(int kind, bool tiled, const void* A, int64_t lda, const float* sA, int64_t s_row,
+                        int64_t s_k, int64_t rows, int64_t K, const float* X, int64_t ldx, int ncols, void* scratch,
+                        float* out, int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
 
 // mlp.hip -- the selector network (16 -> 64 -> 64 -> 40, FP32) and its training steps.
 int mlp_param_count();
@@ -97,6 +103,10 @@ hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_swe
 // multiples of 128 columns).
 hipError_t launch_to_bf16(const float* A, int64_t lda, int64_t m, int64_t n, uint16_t* A16, int64_t ld16,
                           uint16_t* A16T, int64_t ldT, int* flag, hipStream_t s);
+// Both copies in the tiled layout of lowp_common.hpp (bf16_tiled_bytes(m, n) and bf16_tiled_bytes(n, m) bytes).
+size_t bf16_tiled_bytes(int64_t rows, int64_t K);
+hipError_t launch_to_bf16_tiled(const float* A, int64_t lda, int64_t m, int64_t n, uint16_t* A16, uint16_t* A16T,
+                                int* flag, hipStream_t s);
 
 
 // batched.hip

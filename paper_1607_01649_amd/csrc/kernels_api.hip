@@ -114,7 +114,7 @@ rsvd_status rsvd_k_product_bf16(int64_t rows, int64_t K, const uint16_t* A16, in
   if (!A16 || !X || !out || !scratch || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K || lda % 128 ||
       ldx < K || ldo < rows || (reinterpret_cast<uintptr_t>(scratch) & 255))
     return RSVD_E_ARG;
-  K_TRY(launch_nn_lp(0, A16, lda, nullptr, 0, 0, rows, K, X, ldx, ncols, scratch, out, ldo, 0, 1,
+  K_TRY(launch_nn_lp(0, false, A16, lda, nullptr, 0, 0, rows, K, X, ldx, ncols, scratch, out, ldo, 0, 1,
                      reinterpret_cast<hipStream_t>(stream)));
   return RSVD_OK;
 }
@@ -134,7 +134,7 @@ rsvd_status rsvd_k_product_fp8(int64_t rows, int64_t K, const uint8_t* A8, int64
   if (!A8 || !scale || !X || !out || !scratch || rows < 1 || K < 1 || ncols < 1 || ncols > 1024 || lda < K ||
       lda % 128 || ldx < K || ldo < rows || s_row < 0 || s_k < 0 || (reinterpret_cast<uintptr_t>(scratch) & 255))
     return RSVD_E_ARG;
-  K_TRY(launch_nn_lp(1, A8, lda, scale, s_row, s_k, rows, K, X, ldx, ncols, scratch, out, ldo, 0, 1,
+  K_TRY(launch_nn_lp(1, false, A8, lda, scale, s_row, s_k, rows, K, X, ldx, ncols, scratch, out, ldo, 0, 1,
                      reinterpret_cast<hipStream_t>(stream)));
   return RSVD_OK;
 }

@@ -45,4 +45,26 @@ __device__ __forceinline__ int fp8_scale_exp(float amax) {
   return e < -127 ? -127 : e;
 }
 
+// Tiled layout of a low-precision copy (rows x K, elements of EB bytes) for the library's products: blocks of
+// 256 rows x 128 contraction indices (one workgroup's rows and one chunk, 32 KB per byte of element width),
+// block (c, rb) = (k / 128, r / 256) at block index c * rblocks + rb, so that a workgroup streams one
+// contiguous block per chunk; inside a block, 16-byte units in the order the product's waves load them:
+// wave w = (r % 256) / 64, row block b = (r % 64) / 16, unit a of the lane's 32 contraction indices, lane
+// 16 g + (r % 16) with g = (k % 128) / 32.  Rows past the end and indices past K are zero.
+constexpr int kTileRows = 256;
+constexpr int kTileK = 128;
+template <int EB>
+__host__ __device__ __forceinline__ int64_t lp_tiled_unit(int64_t r, int64_t k, int64_t rblocks) {
+  constexpr int EPU = 16 / EB;       // elements per 16-byte unit
+  constexpr int AW = 32 / EPU;       // units per lane per row block per chunk
+  constexpr int UPB = kTileRows * kTileK * EB / 16;
+  const int64_t c = k / kTileK, rb = r / kTileRows;
+  const int rr = (int)(r - rb * kTileRows), kk = (int)(k - c * kTileK);
+  const int w = rr >> 6, b = (rr >> 4) & 3, li = rr & 15, g = kk >> 5, a = (kk & 31) / EPU;
+  return (c * rblocks + rb) * UPB + ((w * 4 + b) * AW + a) * 64 + g * 16 + li;
+}
+__host__ __device__ __forceinline__ int64_t lp_tiled_rows(int64_t rows) {
+  return (rows + kTileRows - 1) / kTileRows * kTileRows;
+}
+
 }  // namespace rsvd

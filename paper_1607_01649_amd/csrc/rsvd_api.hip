@@ -175,11 +175,12 @@ Layout make_layout(const rsvd_desc* d) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };
   const bool b16 = uses_bf16(d);
-  L.a16 = take(b16 ? (size_t)d->m * L.ld16 * 2 : 256);
-  L.a16t = take(b16 ? (size_t)d->n * L.ldT * 2 : 256);
+  // the low-precision copies are in the tiled layout (rows padded to 256, contraction to 128)
+  L.a16 = take(b16 ? bf16_tiled_bytes(d->m, d->n) : 256);
+  L.a16t = take(b16 ? bf16_tiled_bytes(d->n, d->m) : 256);
   const bool b8 = uses_fp8(d);
-  L.a8 = take(b8 ? (size_t)d->m * L.ld16 : 256);
-  L.a8t = take(b8 ? (size_t)d->n * L.ldT : 256);
+  L.a8 = take(b8 ? fp8_tiled_bytes(d->m, d->n) : 256);
+  L.a8t = take(b8 ? fp8_tiled_bytes(d->n, d->m) : 256);
   L.s8 = take(b8 ? (size_t)(L.ld16 / 128) * (L.ldT / 128) * sizeof(float) : 256);
   // converted thin operand of a low-precision product (widest panel, longest contraction)
   L.xq = take((b16 || b8) ? lp_scratch_bytes(b16 ? 0 : 1, std::max(d->m, d->n), std::max({L.W, L.LPmax, 16})) : 256);
@@ -378,13 +379,13 @@ template <typename T> struct Path {
     if (dt == RSVD_BF16) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_nn16;
-        HIP_TRY(launch_nn_lp(0, P.at<uint16_t>(L.a16), L.ld16, nullptr, 0, 0, m, n, X, L.ldn, nc, P.at<char>(L.xq),
+        HIP_TRY(launch_nn_lp(0, true, P.at<uint16_t>(L.a16), L.ld16, nullptr, 0, 0, m, n, X, L.ldn, nc, P.at<char>(L.xq),
                              S == 1 ? Y : part, L.ldm, (int64_t)LPc * L.ldm, S, st));
       }
     } else if (dt == RSVD_FP8_E4M3) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_nn16;
-        HIP_TRY(launch_nn_lp(1, P.at<uint8_t>(L.a8), L.ld16, P.at<float>(L.s8), L.ld16 / 128, 1, m, n, X, L.ldn, nc,
+        HIP_TRY(launch_nn_lp(1, true, P.at<uint8_t>(L.a8), L.ld16, P.at<float>(L.s8), L.ld16 / 128, 1, m, n, X, L.ldn, nc,
                              P.at<char>(L.xq), S == 1 ? Y : part, L.ldm, (int64_t)LPc * L.ldm, S, st));
       }
     } else {
@@ -406,13 +407,13 @@ template <typename T> struct Path {
     if (dt == RSVD_BF16) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_tn16;
-        HIP_TRY(launch_nn_lp(0, P.at<uint16_t>(L.a16t), L.ldT, nullptr, 0, 0, n, m, Qp, L.ldm, nc, P.at<char>(L.xq),
+        HIP_TRY(launch_nn_lp(0, true, P.at<uint16_t>(L.a16t), L.ldT, nullptr, 0, 0, n, m, Qp, L.ldm, nc, P.at<char>(L.xq),
                              S == 1 ? Z : part, L.ldn, (int64_t)LPc * L.ldn, S, st));
       }
     } else if (dt == RSVD_FP8_E4M3) {
       if constexpr (sizeof(T) == 4) {
         S = L.s_tn16;
-        HIP_TRY(launch_nn_lp(1, P.at<uint8_t>(L.a8t), L.ldT, P.at<float>(L.s8), 1, L.ld16 / 128, n, m, Qp, L.ldm, nc,
+        HIP_TRY(launch_nn_lp(1, true, P.at<uint8_t>(L.a8t), L.ldT, P.at<float>(L.s8), 1, L.ld16 / 128, n, m, Qp, L.ldm, nc,
                              P.at<char>(L.xq), S == 1 ? Z : part, L.ldn, (int64_t)LPc * L.ldn, S, st));
       }
     } else {
@@ -557,13 +558,12 @@ template <typename T> struct Path {
     int* flags = P.at<int>(L.flags);
     if (uses_bf16(&P.d)) {
       if constexpr (sizeof(T) == 4)
-        HIP_TRY(launch_to_bf16(A, lda, m, n, P.at<uint16_t>(L.a16), L.ld16, P.at<uint16_t>(L.a16t), L.ldT, flags + 4,
-                               st));
+        HIP_TRY(launch_to_bf16_tiled(A, lda, m, n, P.at<uint16_t>(L.a16), P.at<uint16_t>(L.a16t), flags + 4, st));
     }
     if (uses_fp8(&P.d)) {
       if constexpr (sizeof(T) == 4)
-        HIP_TRY(launch_to_fp8(A, lda, m, n, P.at<uint8_t>(L.a8), L.ld16, P.at<uint8_t>(L.a8t), L.ldT,
-                              P.at<float>(L.s8), flags + 4, st));
+        HIP_TRY(launch_to_fp8_tiled(A, lda, m, n, P.at<uint8_t>(L.a8), P.at<uint8_t>(L.a8t), P.at<float>(L.s8),
+                                    flags + 4, st));
     }
     return RSVD_OK;
   }
