@@ -4,15 +4,22 @@
 // of the one-workgroup kernels in chol.hip and jacobi.hip; only the schedule
 // changes, so that the work of a step is spread over many compute units.
 //
-// Cholesky (right-looking, 64 x 64 blocks, working matrix M row-major LB x LB):
+// Cholesky (right-looking, 64 x 64 blocks, working matrix M row-major LB x LB),
+// with the elimination also applied to an identity block, E (= R^-T at the
+// end, lower triangular, kept in the strictly lower blocks of X), as the
+// one-workgroup kernel of chol.hip does:
 //   for each block column J:
 //     factor the diagonal block (one workgroup, the same unscaled elimination
 //     with the identity block as chol.hip, dependent columns dropped against
-//     the original diagonal) -> R_JJ and S_JJ = R_JJ^-1;
-//     R_JK = S_JJ^T M_JK for the blocks K > J of the block row;
-//     M_KL -= R_JK^T R_JL for J < K <= L.
-//   R^-1 by block back-substitution: X_JJ = S_JJ and, for I from the bottom,
-//     X_IJ = -S_II sum_{I < K <= J} R_IK X_KJ  (all J > I at once).
+//     the original diagonal) -> R_JJ and S_JJ = R_JJ^-1 (X's diagonal block;
+//     E_JJ = S_JJ^T);
+//     R_JK = S_JJ^T M_JK for the blocks K > J of the block row, and
+//     E_JM = S_JJ^T E_JM for the blocks M < J (one launch);
+//     M_KL -= R_JK^T R_JL for J < K <= L, and E_KM -= R_JK^T E_JM for K > J,
+//     M <= J (one launch).
+//   R^-1(k, c) (k <= c) is then S_JJ(k, c) inside a diagonal block and E(c, k)
+//   elsewhere: no separate back substitution (it was eight sequential
+//   launches at l = 520).
 // Dropped columns give zero rows of R and zero rows and columns of R^-1, as
 // in the one-workgroup kernel.
 //
@@ -34,12 +41,13 @@ namespace rsvd {
 constexpr int CB = 64;   // Cholesky block
 
 __global__ void bc_init_kernel(const double* __restrict__ g, int64_t ldg, int l, int LB, double* __restrict__ M,
-                               double* __restrict__ gdiag) {
+                               double* __restrict__ X, double* __restrict__ gdiag) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)LB * LB) return;
   const int a = (int)(t / LB), b = (int)(t - (t / LB) * LB);
   const double v = (a <= b && b < l) ? g[(int64_t)b * ldg + a] : 0.0;
   M[t] = v;
+  X[t] = 0.0;   // the identity's elimination starts from zero off the diagonal blocks
   if (a == b) gdiag[a] = v;
 }
 
@@ -142,17 +150,19 @@ __device__ __forceinline__ void tile_tn(const double (*As)[CB + 1], const double
   }
 }
 
-// R_JK = S_JJ^T M_JK for the blocks K = J+1+blockIdx.x.
-__global__ __launch_bounds__(256) void bc_panel_kernel(double* __restrict__ M, const double* __restrict__ X, int LB,
-                                                       int j0) {
+// R_JK = S_JJ^T M_JK for the blocks K = J+1+blockIdx.x (blockIdx.x < nr), and E_JM = S_JJ^T E_JM for
+// M = blockIdx.x - nr < J.
+__global__ __launch_bounds__(256) void bc_panel_kernel(double* __restrict__ M, double* __restrict__ X, int LB, int j0,
+                                                       int nr) {
   __shared__ double Ss[CB][CB + 1];
   __shared__ double Gs[CB][CB + 1];
   const int tid = threadIdx.x;
-  const int k0 = j0 + CB * (1 + blockIdx.x);
+  const bool erow = (int)blockIdx.x >= nr;
+  double* blk = erow ? X + (int64_t)j0 * LB + CB * ((int)blockIdx.x - nr) : M + (int64_t)j0 * LB + j0 + CB * (1 + blockIdx.x);
   for (int t = tid; t < CB * CB; t += 256) {
     const int r = t / CB, c = t - (t / CB) * CB;
     Ss[r][c] = X[(int64_t)(j0 + r) * LB + j0 + c];
-    Gs[r][c] = M[(int64_t)(j0 + r) * LB + k0 + c];
+    Gs[r][c] = blk[(int64_t)r * LB + c];
   }
   __syncthreads();
   const int a0 = 4 * (tid >> 4), b0 = 4 * (tid & 15);
@@ -161,22 +171,43 @@ __global__ __launch_bounds__(256) void bc_panel_kernel(double* __restrict__ M, c
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) M[(int64_t)(j0 + a0 + i) * LB + k0 + b0 + k] = acc[i][k];
+    for (int k = 0; k < 4; ++k) blk[(int64_t)(a0 + i) * LB + b0 + k] = acc[i][k];
 }
 
-// M_KL -= R_JK^T R_JL for J < K <= L; blockIdx.x enumerates the pairs (K, L).
-__global__ __launch_bounds__(256) void bc_trail_kernel(double* __restrict__ M, int LB, int j0, int nr) {
+// M_KL -= R_JK^T R_JL for J < K <= L (the first nr (nr + 1) / 2 workgroups enumerate the pairs (K, L)), and
+// E_KM -= R_JK^T E_JM for K > J, M <= J (the rest, nr (J + 1) of them; E_JJ = S_JJ^T).
+__global__ __launch_bounds__(256) void bc_trail_kernel(double* __restrict__ M, double* __restrict__ X, int LB, int j0,
+                                                       int nr) {
   __shared__ double As[CB][CB + 1];
   __shared__ double Bs[CB][CB + 1];
   const int tid = threadIdx.x;
-  int idx = blockIdx.x, kb = 0;
-  while (idx >= nr - kb) { idx -= nr - kb; ++kb; }
-  const int lb = kb + idx;
-  const int k0 = j0 + CB * (1 + kb), l0 = j0 + CB * (1 + lb);
-  for (int t = tid; t < CB * CB; t += 256) {
-    const int r = t / CB, c = t - (t / CB) * CB;
-    As[r][c] = M[(int64_t)(j0 + r) * LB + k0 + c];
-    Bs[r][c] = M[(int64_t)(j0 + r) * LB + l0 + c];
+  const int jb = j0 / CB;
+  const int npair = nr * (nr + 1) / 2;
+  int k0;
+  double* out;
+  if ((int)blockIdx.x < npair) {
+    int idx = blockIdx.x, kb = 0;
+    while (idx >= nr - kb) { idx -= nr - kb; ++kb; }
+    const int lb = kb + idx;
+    k0 = j0 + CB * (1 + kb);
+    const int l0 = j0 + CB * (1 + lb);
+    for (int t = tid; t < CB * CB; t += 256) {
+      const int r = t / CB, c = t - (t / CB) * CB;
+      As[r][c] = M[(int64_t)(j0 + r) * LB + k0 + c];
+      Bs[r][c] = M[(int64_t)(j0 + r) * LB + l0 + c];
+    }
+    out = M + (int64_t)k0 * LB + l0;
+  } else {
+    const int idx = (int)blockIdx.x - npair;
+    const int kb = idx / (jb + 1), mb = idx - (idx / (jb + 1)) * (jb + 1);
+    k0 = j0 + CB * (1 + kb);
+    const int m0 = CB * mb;
+    for (int t = tid; t < CB * CB; t += 256) {
+      const int r = t / CB, c = t - (t / CB) * CB;
+      As[r][c] = M[(int64_t)(j0 + r) * LB + k0 + c];
+      Bs[r][c] = mb < jb ? X[(int64_t)(j0 + r) * LB + m0 + c] : X[(int64_t)(j0 + c) * LB + j0 + r];   // E_JJ = S_JJ^T
+    }
+    out = X + (int64_t)k0 * LB + m0;
   }
   __syncthreads();
   const int a0 = 4 * (tid >> 4), b0 = 4 * (tid & 15);
@@ -185,45 +216,7 @@ __global__ __launch_bounds__(256) void bc_trail_kernel(double* __restrict__ M, i
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) M[(int64_t)(k0 + a0 + i) * LB + l0 + b0 + k] -= acc[i][k];
-}
-
-// X_IJ = -S_II sum_{I < K <= J} R_IK X_KJ for J = I+1+blockIdx.x.
-__global__ __launch_bounds__(256) void bc_inv_kernel(const double* __restrict__ M, double* __restrict__ X, int LB,
-                                                     int ib) {
-  __shared__ double As[CB][CB + 1];
-  __shared__ double Bs[CB][CB + 1];
-  const int tid = threadIdx.x;
-  const int jb = ib + 1 + blockIdx.x;
-  const int i0 = ib * CB, jc = jb * CB;
-  const int a0 = 4 * (tid >> 4), b0 = 4 * (tid & 15);
-  double acc[4][4] = {};
-  for (int kb = ib + 1; kb <= jb; ++kb) {
-    __syncthreads();
-    for (int t = tid; t < CB * CB; t += 256) {
-      const int r = t / CB, c = t - (t / CB) * CB;
-      As[c][r] = M[(int64_t)(i0 + r) * LB + kb * CB + c];   // As[t][a] = R_IK(a, t)
-      Bs[r][c] = X[(int64_t)(kb * CB + r) * LB + jc + c];
-    }
-    __syncthreads();
-    tile_tn(As, Bs, a0, b0, acc);
-  }
-  __syncthreads();
-  for (int t = tid; t < CB * CB; t += 256) {
-    const int r = t / CB, c = t - (t / CB) * CB;
-    As[c][r] = X[(int64_t)(i0 + r) * LB + i0 + c];   // As[t][a] = S_II(a, t)
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Bs[a0 + i][b0 + k] = acc[i][k];
-  __syncthreads();
-  double out[4][4] = {};
-  tile_tn(As, Bs, a0, b0, out);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) X[(int64_t)(i0 + a0 + i) * LB + jc + b0 + k] = -out[i][k];
+    for (int k = 0; k < 4; ++k) out[(int64_t)(a0 + i) * LB + b0 + k] -= acc[i][k];
 }
 
 // rinv_p[c*LP + k] = R^-1(k, c) for c, k < l; the identity on the padding.
@@ -234,7 +227,8 @@ __global__ void bc_rinv_out_kernel(const double* __restrict__ X, int LB, int l, 
   const int c = (int)(t / LP), k = (int)(t - (t / LP) * LP);
   double v;
   if (c >= l || k >= l) v = (c == k) ? 1.0 : 0.0;
-  else v = (k <= c) ? X[(int64_t)k * LB + c] : 0.0;   // X's blocks below the diagonal are never written
+  else if (k > c) v = 0.0;
+  else v = (k / CB == c / CB) ? X[(int64_t)k * LB + c] : X[(int64_t)c * LB + k];   // S_JJ, or E(c, k)
   rinv_p[t] = static_cast<TQ>(v);
 }
 
@@ -305,20 +299,19 @@ hipError_t launch_chol_blocked(const double* g, int64_t ldg, int l, int LP, doub
   double* X = M + (size_t)LB * LB;
   double* gdiag = X + (size_t)LB * LB;
   const int64_t ll = (int64_t)LB * LB;
-  hipLaunchKernelGGL(bc_init_kernel, dim3((unsigned)((ll + 255) / 256)), dim3(256), 0, s, g, ldg, l, LB, M, gdiag);
-  // X's blocks above the diagonal are all written by the back-substitution; the ones below are never
-  // written and never read.
+  hipLaunchKernelGGL(bc_init_kernel, dim3((unsigned)((ll + 255) / 256)), dim3(256), 0, s, g, ldg, l, LB, M, X,
+                     gdiag);
+  // X: S_JJ on the diagonal blocks, E below them; its blocks above the diagonal are never read.
   for (int jb = 0; jb < nbk; ++jb) {
     const int j0 = jb * CB;
     hipLaunchKernelGGL(bc_diag_kernel, dim3(1), dim3(256), 0, s, M, LB, j0, l, gdiag, tau, X, flags);
     const int nr = nbk - 1 - jb;
-    if (nr > 0) {
-      hipLaunchKernelGGL(bc_panel_kernel, dim3((unsigned)nr), dim3(256), 0, s, M, X, LB, j0);
-      hipLaunchKernelGGL(bc_trail_kernel, dim3((unsigned)(nr * (nr + 1) / 2)), dim3(256), 0, s, M, LB, j0, nr);
-    }
+    if (nr + jb > 0)
+      hipLaunchKernelGGL(bc_panel_kernel, dim3((unsigned)(nr + jb)), dim3(256), 0, s, M, X, LB, j0, nr);
+    if (nr > 0)
+      hipLaunchKernelGGL(bc_trail_kernel, dim3((unsigned)(nr * (nr + 1) / 2 + nr * (jb + 1))), dim3(256), 0, s, M, X,
+                         LB, j0, nr);
   }
-  for (int ib = nbk - 2; ib >= 0; --ib)
-    hipLaunchKernelGGL(bc_inv_kernel, dim3((unsigned)(nbk - 1 - ib)), dim3(256), 0, s, M, X, LB, ib);
   const int64_t lp2 = (int64_t)LP * LP;
   hipLaunchKernelGGL((bc_rinv_out_kernel<TQ>), dim3((unsigned)((lp2 + 255) / 256)), dim3(256), 0, s, X, LB, l, LP,
                      rinv_p);
