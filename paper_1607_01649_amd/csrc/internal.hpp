@@ -96,6 +96,18 @@ hipError_t launch_sel_features(const double* sigma, int k, float* x, hipStream_t
 
 // jacobi.hip
 template <typename TU>
+struct JacobiProblem {
+  const double* R;     // the l x l matrix (column-major, leading dimension LP)
+  double* sigma;
+  double* uhat_d;
+  TU* uhat_p;          // may be null
+  TU* vhat_p;          // may be null
+};
+// Two independent problems of the same size (LP <= 128) in one launch, one workgroup each.
+template <typename TU>
+hipError_t launch_jacobi2(const JacobiProblem<TU>& a, const JacobiProblem<TU>& b, int l, int LP, double tol,
+                          int max_sweeps, int* flags, hipStream_t s);
+template <typename TU>
 hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma, double* uhat_d,
                          TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s);
 

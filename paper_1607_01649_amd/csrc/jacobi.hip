@@ -129,10 +129,10 @@ __device__ void jacobi_epilogue(const double* xs, int LX, int l, int LP, double*
 }
 
 template <typename TU, int NH>
-__global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__ R, int l, int LP, double tol,
-                                                       int max_sweeps, double* __restrict__ sigma,
-                                                       double* __restrict__ uhat_d, TU* __restrict__ uhat_p,
-                                                       TU* __restrict__ vhat_p, int* __restrict__ flags) {
+__device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l, int LP, double tol, int max_sweeps,
+                                            double* __restrict__ sigma, double* __restrict__ uhat_d,
+                                            TU* __restrict__ uhat_p, TU* __restrict__ vhat_p,
+                                            int* __restrict__ flags) {
   // A lane of a pair group holds rows 2 sub + 32 h and the next one, h < NH; LX = 32 NH >= LP.
   constexpr int LX = 32 * NH;
   extern __shared__ double2 smem2[];   // 16-byte aligned: accessed as double2
@@ -221,6 +221,22 @@ __global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__
   jacobi_epilogue<TU>(xs, LX, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
 }
 
+template <typename TU, int NH>
+__global__ __launch_bounds__(1024) void jacobi_kernel(const double* __restrict__ R, int l, int LP, double tol,
+                                                       int max_sweeps, double* __restrict__ sigma,
+                                                       double* __restrict__ uhat_d, TU* __restrict__ uhat_p,
+                                                       TU* __restrict__ vhat_p, int* __restrict__ flags) {
+  jacobi_body<TU, NH>(R, l, LP, tol, max_sweeps, sigma, uhat_d, uhat_p, vhat_p, flags);
+}
+
+// Two independent problems of the same size in one launch, one workgroup each.
+template <typename TU, int NH>
+__global__ __launch_bounds__(1024) void jacobi2_kernel(JacobiProblem<TU> a, JacobiProblem<TU> b, int l, int LP,
+                                                        double tol, int max_sweeps, int* __restrict__ flags) {
+  const JacobiProblem<TU>& p = blockIdx.x == 0 ? a : b;
+  jacobi_body<TU, NH>(p.R, l, LP, tol, max_sweeps, p.sigma, p.uhat_d, p.uhat_p, p.vhat_p, flags);
+}
+
 template <typename TU>
 __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* __restrict__ xs, int l, int LP,
                                                               double* __restrict__ sigma, double* __restrict__ uhat_d,
@@ -274,6 +290,37 @@ hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_swe
   }
   return hipGetLastError();
 }
+
+template <typename TU>
+hipError_t launch_jacobi2(const JacobiProblem<TU>& a, const JacobiProblem<TU>& b, int l, int LP, double tol,
+                          int max_sweeps, int* flags, hipStream_t s) {
+  if (l < 1 || LP > 128 || LP < l) return hipErrorInvalidValue;
+  const int nh = (LP + 31) / 32;
+  static bool attr_set = false;
+  if (!attr_set) {
+    const void* fns[4] = {reinterpret_cast<const void*>(&jacobi2_kernel<TU, 1>),
+                          reinterpret_cast<const void*>(&jacobi2_kernel<TU, 2>),
+                          reinterpret_cast<const void*>(&jacobi2_kernel<TU, 3>),
+                          reinterpret_cast<const void*>(&jacobi2_kernel<TU, 4>)};
+    for (const void* f : fns) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 128 * 8);
+      if (e != hipSuccess) return e;
+    }
+    attr_set = true;
+  }
+  const size_t sh = (size_t)LP * (32 * nh) * sizeof(double);
+  switch (nh) {
+    case 1: hipLaunchKernelGGL((jacobi2_kernel<TU, 1>), dim3(2), dim3(1024), sh, s, a, b, l, LP, tol, max_sweeps, flags); break;
+    case 2: hipLaunchKernelGGL((jacobi2_kernel<TU, 2>), dim3(2), dim3(1024), sh, s, a, b, l, LP, tol, max_sweeps, flags); break;
+    case 3: hipLaunchKernelGGL((jacobi2_kernel<TU, 3>), dim3(2), dim3(1024), sh, s, a, b, l, LP, tol, max_sweeps, flags); break;
+    default: hipLaunchKernelGGL((jacobi2_kernel<TU, 4>), dim3(2), dim3(1024), sh, s, a, b, l, LP, tol, max_sweeps, flags); break;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_jacobi2<float>(const JacobiProblem<float>&, const JacobiProblem<float>&, int, int, double,
+                                          int, int*, hipStream_t);
+template hipError_t launch_jacobi2<double>(const JacobiProblem<double>&, const JacobiProblem<double>&, int, int,
+                                           double, int, int*, hipStream_t);
 
 template hipError_t launch_jacobi<float>(const double*, int, int, double, int, double*, double*, float*, float*,
                                          double*, int*, hipStream_t);

@@ -827,7 +827,7 @@ template <typename T> struct Path {
     HIP_TRY((launch_nn<double, double, double, double>(Rt, L.ldn, k, n, Rt, L.ldn, k, gp, LK, (int64_t)LK * k, L.s_gn,
                                                        st)));
     HIP_TRY((launch_reduce<double, double>(gp, L.s_gn, (int64_t)LK * k, LK, k, k, H, LK, st)));
-    const double tol = (double)k * 2.220446049250313e-16;
+    const double tol = small_tol(k);
     HIP_TRY(launch_jacobi<double>(H, k, LK, tol, 60, lam, V, (double*)nullptr, (double*)nullptr,
                                   P.at<double>(L.scr_jac), flags, st));
     HIP_TRY(launch_cut_small(lam, k, tol, st));
@@ -841,12 +841,11 @@ template <typename T> struct Path {
     return RSVD_OK;
   }
 
-  // Q_out = the k dominant left singular vectors of the l-column panel Y (rows x l), and Nt = Y^T Q_out (l x k,
-  // FP64, leading dimension lp16(l)).  Y is overwritten by its CholeskyQR2 basis Q (Y = Q R); R (kept in FP64,
-  // transposed into Rc, l x l column-major) has left singular vectors W (Jacobi on its columns), Q_out = Q W_k
-  // and Nt = R^T W_k.
-  rsvd_status dominant_left(T* Y, int64_t ld, int64_t rows, int l, int k, int splits, T* Q_out, double* Nt,
-                            double* Rc) {
+  // The k dominant left singular vectors of an l-column panel Y (rows x l) in two halves around the Jacobi
+  // SVD of R: Y = Q R (CholeskyQR2, Q overwriting Y; R kept in FP64 and transposed into Rc, l x l
+  // column-major), W = the left singular vectors of R (Jacobi on its columns), then Q_out = Q W_k and Nt =
+  // Y^T Q_out = R^T W_k (l x k, FP64, leading dimension lp16(l)).
+  rsvd_status dominant_left_prep(T* Y, int64_t ld, int64_t rows, int l, int splits, double* Rc) {
     const int LPl = lp16(l);
     double* G = P.at<double>(L.G);
     double* R1 = P.at<double>(L.R1);
@@ -862,14 +861,20 @@ template <typename T> struct Path {
     HIP_TRY(launch_chol<T>(G, LPl, l, LPl, tau, rinv, R, R1, scr, flags, st));   // R = R2 R1, row-major
     HIP_TRY(apply_rinv(tmp, ld, rows, l, rinv, LPl, Y));
     HIP_TRY(launch_transpose64(R, LPl, l, l, Rc, LPl, st));
-    const double tol = (double)l * 2.220446049250313e-16;
-    double* uhat_d = P.at<double>(L.uhat_d);
-    T* uhat_p = P.at<T>(L.uhat_p);
-    HIP_TRY(launch_jacobi<T>(Rc, l, LPl, tol, 60, P.at<double>(L.sigma), uhat_d, uhat_p, (T*)nullptr,
-                             P.at<double>(L.scr_jac), flags, st));
+    return RSVD_OK;
+  }
+  rsvd_status dominant_left_finish(const T* Y, int64_t ld, int64_t rows, int l, int k, const double* Rc,
+                                   const double* uhat_d, const T* uhat_p, T* Q_out, double* Nt) {
+    const int LPl = lp16(l);
     HIP_TRY((launch_tn<T, T, T, T>(Y, ld, l, rows, uhat_p, LPl, k, Q_out, ld, 0, 1, false, st)));
     HIP_TRY(launch_small_gemm<double>(l, k, l, Rc, LPl, true, uhat_d, LPl, false, Nt, LPl, false, nullptr, st));
     return RSVD_OK;
+  }
+
+  // Jacobi stopping tolerance for the small FP64 problems of the single pass and the ID/CUR core: n u for FP64
+  // data; for FP32 data 1e-10 (the rule of Stage B's small SVD: the data's own rounding is 6e-8).
+  double small_tol(int n) const {
+    return std::max((double)n * 2.220446049250313e-16, sizeof(T) == 4 ? 1e-10 : 0.0);
   }
 
   // Single-pass factorisations (Section 5): the general SVD of Section 5.2's figure, or with RSVD_SINGLE_PASS_SYM
@@ -925,16 +930,38 @@ template <typename T> struct Path {
     double* a1 = sp + 12 * L2;
     double* a2 = a1 + L.LP;
     double* scr = P.at<double>(L.scr_jac);
-    const double tol = (double)k * 2.220446049250313e-16;
-    // step 3: Q_c (Q_r) = the k dominant left singular vectors of Y_c (Y_r): with Y = Q R (CholeskyQR2, Q
-    // overwriting Y) and W_k the k dominant left singular vectors of R, Q_c = Q W_k; this stays orthonormal
-    // when k exceeds the numerical rank of Y.  It also gives Y^T Q_c = R^T W_k (l x k) without a pass over Y.
-    // Equation sets held as l x k panels (FP64): M1 = G_r^T Q_c, N1 = Y_r^T Q_r, M2^T = G_c^T Q_r, N2^T =
-    // Y_c^T Q_c (symmetric form: M^T = G^T Q, N^T = Y^T Q in the last two).
+    const double tol = small_tol(k);
+    // step 3: Q_c (Q_r) = the k dominant left singular vectors of Y_c (Y_r); Q_c = (CholeskyQR2 basis of Y_c) x
+    // (left singular vectors of its R) stays orthonormal when k exceeds the numerical rank of Y_c, and gives
+    // Y_c^T Q_c = R^T W_k without a pass over Y_c.  The two Jacobi SVDs run in one launch.  Equation sets held
+    // as l x k panels (FP64): M1 = G_r^T Q_c, N1 = Y_r^T Q_r, M2^T = G_c^T Q_r, N2^T = Y_c^T Q_c (symmetric
+    // form: M^T = G^T Q, N^T = Y^T Q in the last two).
     T* Qc = P.at<T>(L.Q);
     T* Qr = P.at<T>(L.Wp);
-    RS_TRY(dominant_left(Yc, L.ldm, m, l, k, L.s_gm, Qc, N2t, T1));
-    if (!sym) RS_TRY(dominant_left(Yr, L.ldn, n, l, k, L.s_gn, Qr, N1, T1));
+    double* uhat_d = P.at<double>(L.uhat_d);
+    T* uhat_p = P.at<T>(L.uhat_p);
+    const double tol_l = small_tol(l);
+    RS_TRY(dominant_left_prep(Yc, L.ldm, m, l, L.s_gm, T1));
+    if (sym) {
+      HIP_TRY(launch_jacobi<T>(T1, l, LPl, tol_l, 60, P.at<double>(L.sigma), uhat_d, uhat_p, (T*)nullptr, scr, flags,
+                               st));
+      RS_TRY(dominant_left_finish(Yc, L.ldm, m, l, k, T1, uhat_d, uhat_p, Qc, N2t));
+    } else {
+      // the second problem's outputs in space that step 4 fills later (Cm, Wm, P1, a2)
+      RS_TRY(dominant_left_prep(Yr, L.ldn, n, l, L.s_gn, Cm));
+      T* uhat_p_r = reinterpret_cast<T*>(P1);
+      if (LPl <= 128) {
+        const JacobiProblem<T> pc{T1, P.at<double>(L.sigma), uhat_d, uhat_p, nullptr};
+        const JacobiProblem<T> pr{Cm, a2, Wm, uhat_p_r, nullptr};
+        HIP_TRY(launch_jacobi2<T>(pc, pr, l, LPl, tol_l, 60, flags, st));
+      } else {
+        HIP_TRY(launch_jacobi<T>(T1, l, LPl, tol_l, 60, P.at<double>(L.sigma), uhat_d, uhat_p, (T*)nullptr, scr,
+                                 flags, st));
+        HIP_TRY(launch_jacobi<T>(Cm, l, LPl, tol_l, 60, a2, Wm, uhat_p_r, (T*)nullptr, scr, flags, st));
+      }
+      RS_TRY(dominant_left_finish(Yc, L.ldm, m, l, k, T1, uhat_d, uhat_p, Qc, N2t));
+      RS_TRY(dominant_left_finish(Yr, L.ldn, n, l, k, Cm, Wm, uhat_p_r, Qr, N1));
+    }
     mark(2);
     if (sym) {
       RS_TRY(tprod64(Gc, l, Qc, k, L.ldn, n, L.s_gn, M2t, LPl));
@@ -950,13 +977,21 @@ template <typename T> struct Path {
       RS_TRY(tprod64(Gr, l, Qc, k, L.ldm, m, L.s_gm, M1, LPl));
       RS_TRY(tprod64(Gc, l, Qr, k, L.ldn, n, L.s_gn, M2t, LPl));
       mark(3);
-      // P1 = M1^T M1, P2 = M2 M2^T, S = M1^T N1 + N2 M2^T
+      // P1 = M1^T M1, P2 = M2 M2^T, S = M1^T N1 + N2 M2^T; the two eigendecompositions in one launch
       HIP_TRY(launch_small_gemm<double>(k, k, l, M1, LPl, true, M1, LPl, false, P1, LPk, false, nullptr, st));
       HIP_TRY(launch_small_gemm<double>(k, k, l, M2t, LPl, true, M2t, LPl, false, P2, LPk, false, nullptr, st));
       HIP_TRY(launch_small_gemm<double>(k, k, l, M1, LPl, true, N1, LPl, false, Sm, LPk, false, nullptr, st));
       HIP_TRY(launch_small_gemm<double>(k, k, l, N2t, LPl, true, M2t, LPl, false, Sm, LPk, true, nullptr, st));
-      HIP_TRY(launch_jacobi<double>(P1, k, LPk, tol, 60, a1, Z1, (double*)nullptr, (double*)nullptr, scr, flags, st));
-      HIP_TRY(launch_jacobi<double>(P2, k, LPk, tol, 60, a2, Z2, (double*)nullptr, (double*)nullptr, scr, flags, st));
+      if (LPk <= 128) {
+        const JacobiProblem<double> p1{P1, a1, Z1, nullptr, nullptr};
+        const JacobiProblem<double> p2{P2, a2, Z2, nullptr, nullptr};
+        HIP_TRY(launch_jacobi2<double>(p1, p2, k, LPk, tol, 60, flags, st));
+      } else {
+        HIP_TRY(launch_jacobi<double>(P1, k, LPk, tol, 60, a1, Z1, (double*)nullptr, (double*)nullptr, scr, flags,
+                                      st));
+        HIP_TRY(launch_jacobi<double>(P2, k, LPk, tol, 60, a2, Z2, (double*)nullptr, (double*)nullptr, scr, flags,
+                                      st));
+      }
     }
     // P1 C + C P2 = S: C = Z1 [(Z1^T S Z2) ./ (a_i + b_j)] Z2^T
     HIP_TRY(launch_small_gemm<double>(k, k, k, Z1, LPk, true, Sm, LPk, false, T1, LPk, false, nullptr, st));
@@ -967,8 +1002,6 @@ template <typename T> struct Path {
     if (sym) HIP_TRY(launch_symmetrize(Cm, LPk, k, st));
     // step 5: C = U_hat D V_hat^T: Jacobi on C gives its left singular vectors and singular values
     double* sigma = P.at<double>(L.sigma);
-    double* uhat_d = P.at<double>(L.uhat_d);
-    T* uhat_p = P.at<T>(L.uhat_p);
     T* vhat_p = P.at<T>(L.vhat_p);
     HIP_TRY(launch_jacobi<T>(Cm, k, LPk, tol, 60, sigma, uhat_d, uhat_p, (T*)nullptr, scr, flags, st));
     mark(4);
