@@ -82,12 +82,19 @@ rsvd_status rsvd_k_cholesky(int32_t l, const double* d_G, int64_t ldg, double ta
  * leading l x l block read.  Writes d_sigma (LP values, descending, zeros
  * past l) and d_Uhat (LP x LP, column j of U_hat at d_Uhat[j*LP .. +LP)),
  * each column signed so that its entry of largest magnitude is positive.
+ * A column whose norm is at most l u ||X||_F (numerically zero: X of lower
+ * rank) takes no rotation and comes out as sigma = 0 with a zero column of
+ * d_Uhat, as an exactly zero column does.
  * d_flags[2] counts a sweep limit reached before convergence, d_flags[3]
  * holds the largest sweep count.  l <= 128 runs in one workgroup with X in
  * LDS; larger l (up to 1024) runs block one-sided Jacobi over many
  * workgroups and needs d_scratch (rsvd_k_scratch_bytes(l) bytes; may be NULL
- * for l <= 128); that form enqueues 20 sweeps, the ones after
- * convergence returning at once, and never synchronises the host.
+ * for l <= 128); that form runs up to 60 sweeps in one persistent launch
+ * (its workgroups, at most 64, must all be resident: RSVD_E_HIP if the
+ * device cannot hold them), stops after the first sweep without a rotation,
+ * and never synchronises the host.  A grid barrier wait of that launch is
+ * bounded at two seconds; running out of it counts in d_flags[0] and
+ * d_flags[2].
  * Errors: RSVD_E_ARG, RSVD_E_HIP.
  */
 rsvd_status rsvd_k_small_svd(int32_t l, const double* d_R, double* d_sigma, double* d_Uhat, int32_t* d_flags,

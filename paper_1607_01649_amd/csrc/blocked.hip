@@ -30,8 +30,10 @@
 // same rotation and test as jacobi.hip), and applies the accumulated
 // rotation to the columns.  A sweep of nbk-1 rounds meets every pair of
 // blocks, hence every pair of columns; sweeps repeat until one passes in
-// which no workgroup rotated.  The sweeps are enqueued up front and those
-// after convergence return at once: no host synchronisation.
+// which no workgroup rotated.  All sweeps run in one persistent launch
+// (workgroup g takes block pair g of every round, grid barriers between the
+// rounds), which stops by itself after the converged sweep: no host
+// synchronisation, and no launches spent past convergence.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -343,50 +345,103 @@ __global__ void bj_init_kernel(const double* __restrict__ R, int l, int LP, doub
   xs[t] = (p < l && i < l) ? R[(int64_t)p * LP + i] : 0.0;
 }
 
-// Rotation of the column pair (p, q) from its Gram entries alpha = x_p.x_p, beta = x_q.x_q, gamma = x_p.x_q,
-// with x_p' = c x_p - s x_q, x_q' = s x_p + c x_q (then x_p'.x_q' = 0 and the squared norms move by -/+ t
-// gamma).  No rotation (c = 1, s = t = 0) when the pair is orthogonal to tol or a column is zero.
-__device__ __forceinline__ bool bj_rotation(double al, double be, double ga, double tol, double& c, double& s,
-                                            double& t) {
-  if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
-    const double zeta = (be - al) / (2.0 * ga);
-    t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    c = 1.0 / sqrt(1.0 + t * t);
-    s = c * t;
-    return true;
-  }
-  c = 1.0;
-  s = 0.0;
-  t = 0.0;
-  return false;
+// 1/x and 1/sqrt(x) for finite x > 0: the hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double bj_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double bj_rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
 }
 
-// One pair step of the block one-sided Jacobi on the NC = 2W columns of block pair g of this round:
+// Control words: the per-sweep rotation counts (sweeps < kBlockedSweepCap), then the deflation bound
+// (a double in words 60-61), the barrier's arrival count and the time-out flag.
+constexpr int kBjCtlWords = 64;
+constexpr int kBjCtlThr2 = 60;      // tol^2 ||X||_F^2, as a double
+constexpr int kBjCtlBarrier = 62;   // arrivals at the grid barrier, cumulative
+constexpr int kBjCtlTimeout = 63;   // set when a barrier wait ran out of time
+constexpr int kBlockedSweepCap = 60;
+
+// *thr2 = tol^2 ||X||_F^2 (one workgroup of 1024 threads, partial sums in a fixed order): a column whose
+// squared norm is at or below it is numerically zero (no rotation; sigma = 0 and a zero vector).
+__global__ __launch_bounds__(1024) void bj_fro_kernel(const double* __restrict__ xs, int ldx, int l, double tol,
+                                                      double* __restrict__ thr2) {
+  __shared__ double part[16];
+  double f = 0.0;
+  for (int p = 0; p < l; ++p)
+    for (int i = threadIdx.x; i < l; i += 1024) f = fma(xs[(int64_t)p * ldx + i], xs[(int64_t)p * ldx + i], f);
+  f = wave_sum(f);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += part[w];
+    *thr2 = tol * tol * t;
+  }
+}
+
+// Grid-wide barrier between the rounds of the persistent kernel.  Every workgroup of the grid is resident
+// (the host checks the occupancy before the launch), so the wait ends; it is still bounded by tick_limit
+// ticks of the constant wall clock, after which the caller gives up.  The stores of every thread are made
+// visible at agent scope before the arrival (the L2 caches of the compute dies are not coherent for plain
+// stores), and every thread acquires at agent scope after the wait.  Returns false (uniformly within the
+// workgroup) on time-out.
+__device__ __forceinline__ bool bj_grid_barrier(int* count, int target, long long tick_limit, int* ok_sh) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(count, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = (long long)wall_clock64();
+    int ok = 1;
+    while (__hip_atomic_load(count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if ((long long)wall_clock64() - t0 > tick_limit) {
+        ok = 0;
+        break;
+      }
+    }
+    *ok_sh = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return *ok_sh != 0;
+}
+
+template <int W>
+struct BjShared {
+  double rc[W], rs[W], rt[W];   // the inner round's rotations, one per disjoint pair
+  int any_rot;
+  int ok;
+};
+
+// One pair step of the block one-sided Jacobi on the NC = 2W columns of block pair `pair` of round `round`:
 //   1. G = X^T X of the pair's columns on the FP64 MFMA (each wave a share of the 16-row slabs, the wave
 //      partials summed in a fixed order through LDS);
 //   2. one cyclic Jacobi sweep on G in LDS (NC - 1 rounds of NC/2 disjoint rotations, circle order): each
-//      rotation is the one the columns themselves would take (G's entries are their inner products), G is
+//      rotation is the one the columns themselves would take (G's entries are their inner products; the
+//      same test and rotation as the one-workgroup kernel), computed once per pair and inner round, G is
 //      carried along as J^T G J (2 x 2 blocks, the pair's own block updated exactly), and V = J_1 J_2 ... is
 //      accumulated;
-//   3. X <- X V on the FP64 MFMA, slab by slab in place.
-// A sweep that reaches this kernel after a sweep with no rotation anywhere (rot[sweep - 1] == 0) returns at
-// once, so a fixed number of sweeps can be enqueued without reading the count back on the host.
+//   3. X <- X V on the FP64 MFMA, slab by slab in place, if anything rotated (counted in *rot).
 template <int W>
-__global__ __launch_bounds__(512) void bj_round_kernel(double* __restrict__ xs, int ldx, int l, int LP, int nbk,
-                                                       int round, double tol, int* __restrict__ rot, int sweep) {
+__device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, int LP, int nbk, int pair, int round,
+                                             double tol, double thr2, int* __restrict__ rot, double* lds,
+                                             BjShared<W>& sh) {
   constexpr int NC = 2 * W;                 // columns of the block pair
   constexpr int NT = NC / 16;               // 16-column MFMA tiles (1 or 2)
   constexpr int NTT = NT * (NT + 1) / 2;    // tiles on and above the diagonal of G
   constexpr int NP = NC / 2;                // disjoint inner pairs per round
-  extern __shared__ double lds[];
   double* red = lds;                        // [8 waves][NTT tiles][256]
   double* gb = red + 8 * NTT * 256;         // two NC x NC buffers of G (row-major)
   double* vm = gb + 2 * NC * NC;            // V, NC x NC row-major
-  __shared__ int any_rot;
-  if (sweep > 0 && __hip_atomic_load(rot + sweep - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ci = lane & 15, g = lane >> 4;
-  const int bI = bj_player(blockIdx.x, round, nbk), bJ = bj_player(nbk - 1 - blockIdx.x, round, nbk);
+  const int bI = bj_player(pair, round, nbk), bJ = bj_player(nbk - 1 - pair, round, nbk);
   auto gcol = [&](int c) { return c < W ? bI * W + c : bJ * W + (c - W); };
   const int nslab = LP / 16;
 
@@ -421,7 +476,7 @@ __global__ __launch_bounds__(512) void bj_round_kernel(double* __restrict__ xs, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) red[(wave * NTT + t) * 256 + r * 64 + lane] = acc[t][r];
   }
-  if (tid == 0) any_rot = 0;
+  if (tid == 0) sh.any_rot = 0;
   for (int e = tid; e < NC * NC; e += 512) vm[e] = (e / NC == e % NC) ? 1.0 : 0.0;
   __syncthreads();
   // Wave partials summed in wave order.  Accumulator element r of lane L holds G(L/16 + 4 r, L % 16) of its
@@ -446,28 +501,48 @@ __global__ __launch_bounds__(512) void bj_round_kernel(double* __restrict__ xs, 
   for (int ir = 0; ir < NC - 1; ++ir) {
     const double* G = gb + cur * NC * NC;
     double* Gn = gb + (cur ^ 1) * NC * NC;
+    // a. the rotation of each disjoint pair of this inner round: rotate when |g_pq| > tol sqrt(g_pp) sqrt(g_qq)
+    // and neither column is numerically zero (g_pp, g_qq > thr2);
+    // t = tan of the angle that zeroes g_pq (the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (g_qq - g_pp) /
+    // (2 g_pq)), x_p' = c x_p - s x_q, x_q' = s x_p + c x_q.  t == 0 (an angle below the double range) means
+    // no rotation everywhere below.
+    if (tid < NP) {
+      const int p = bj_player(tid, ir, NC), q = bj_player(NC - 1 - tid, ir, NC);
+      const double al = G[p * NC + p], be = G[q * NC + q], ga = G[p * NC + q];
+      double c = 1.0, s = 0.0, t = 0.0;
+      if (al > thr2 && be > thr2 && fabs(ga) > tol * (sqrt(al) * sqrt(be))) {
+        const double zeta = (be - al) * bj_rcp(2.0 * ga);
+        if (fabs(zeta) > 1e150) {
+          t = 0.5 * bj_rcp(zeta);
+        } else {
+          const double z2 = 1.0 + zeta * zeta;
+          t = bj_rcp(fabs(zeta) + z2 * bj_rsq(z2));
+          t = zeta >= 0.0 ? t : -t;
+        }
+        c = bj_rsq(1.0 + t * t);
+        s = c * t;
+        if (t != 0.0) sh.any_rot = 1;
+      }
+      sh.rc[tid] = c;
+      sh.rs[tid] = s;
+      sh.rt[tid] = t;
+    }
+    __syncthreads();
+    // b. G <- J^T G J by 2 x 2 blocks (block (kr, kc) = rows of pair kr, columns of pair kc), V <- V J.
     if (tid < NP * NP) {
       const int kr = tid / NP, kc = tid - (tid / NP) * NP;
       const int pr = bj_player(kr, ir, NC), qr = bj_player(NC - 1 - kr, ir, NC);
       const int pc = bj_player(kc, ir, NC), qc = bj_player(NC - 1 - kc, ir, NC);
-      double cr, sr, tr, cc, sc, tc;
-      const double ar = G[pr * NC + pr], br = G[qr * NC + qr], gr = G[pr * NC + qr];
-      const bool rr = bj_rotation(ar, br, gr, tol, cr, sr, tr);
       if (kr == kc) {
-        if (rr) {
-          Gn[pr * NC + pr] = ar - tr * gr;
-          Gn[qr * NC + qr] = br + tr * gr;
-          Gn[pr * NC + qr] = 0.0;
-          Gn[qr * NC + pr] = 0.0;
-          any_rot = 1;
-        } else {
-          Gn[pr * NC + pr] = ar;
-          Gn[qr * NC + qr] = br;
-          Gn[pr * NC + qr] = gr;
-          Gn[qr * NC + pr] = gr;
-        }
+        const double ar = G[pr * NC + pr], br = G[qr * NC + qr], gr = G[pr * NC + qr];
+        const double tr = sh.rt[kr];
+        const bool rr = tr != 0.0;
+        Gn[pr * NC + pr] = rr ? ar - tr * gr : ar;
+        Gn[qr * NC + qr] = rr ? br + tr * gr : br;
+        Gn[pr * NC + qr] = rr ? 0.0 : gr;
+        Gn[qr * NC + pr] = rr ? 0.0 : gr;
       } else {
-        bj_rotation(G[pc * NC + pc], G[qc * NC + qc], G[pc * NC + qc], tol, cc, sc, tc);
+        const double cr = sh.rc[kr], sr = sh.rs[kr], cc = sh.rc[kc], sc = sh.rs[kc];
         const double b00 = G[pr * NC + pc], b01 = G[pr * NC + qc], b10 = G[qr * NC + pc], b11 = G[qr * NC + qc];
         // B J_c, then J_r^T (B J_c)
         const double t00 = b00 * cc - b01 * sc, t01 = b00 * sc + b01 * cc;
@@ -480,9 +555,9 @@ __global__ __launch_bounds__(512) void bj_round_kernel(double* __restrict__ xs, 
     } else if (tid >= 256) {
       for (int item = tid - 256; item < NC * NP; item += 256) {
         const int i = item / NP, k = item - (item / NP) * NP;
-        const int p = bj_player(k, ir, NC), q = bj_player(NC - 1 - k, ir, NC);
-        double c, sn, t;
-        if (bj_rotation(G[p * NC + p], G[q * NC + q], G[p * NC + q], tol, c, sn, t)) {
+        if (sh.rt[k] != 0.0) {
+          const int p = bj_player(k, ir, NC), q = bj_player(NC - 1 - k, ir, NC);
+          const double c = sh.rc[k], sn = sh.rs[k];
           const double vp = vm[i * NC + p], vq = vm[i * NC + q];
           vm[i * NC + p] = c * vp - sn * vq;
           vm[i * NC + q] = sn * vp + c * vq;
@@ -492,7 +567,7 @@ __global__ __launch_bounds__(512) void bj_round_kernel(double* __restrict__ xs, 
     __syncthreads();
     cur ^= 1;
   }
-  const bool rotated = any_rot != 0;
+  const bool rotated = sh.any_rot != 0;
 
   // 3. X <- X V: output tile jt of slab sl is D(j, i) = sum_k V(k, 16 jt + j) X(16 sl + i, k), with the A
   // operand V^T read from LDS and the B operand X^T (16 lanes read 16 consecutive rows of one column).
@@ -512,35 +587,78 @@ __global__ __launch_bounds__(512) void bj_round_kernel(double* __restrict__ xs, 
         for (int r = 0; r < 4; ++r) xs[(int64_t)gcol(16 * jt + g + 4 * r) * ldx + i] = acc[r];
       }
     }
+    if (tid == 0) atomicAdd(rot, 1);
   }
-  if (tid == 0 && rotated) atomicAdd(rot + sweep, 1);
 }
 
-// flags[3] = sweeps run (the first with no rotation included), flags[2] += 1 if every enqueued sweep rotated.
-__global__ void bj_flags_kernel(int* flags, const int* rot, int cap) {
+// All sweeps in one launch: workgroup g takes block pair g of every round, a grid barrier separates the
+// rounds, and the loop ends after the first sweep in which no workgroup rotated (every workgroup reads the
+// same count after that sweep's last barrier) or after cap sweeps.  ctl[s] counts the pair steps of sweep s
+// that rotated.
+template <int W>
+__global__ __launch_bounds__(512) void bj_sweeps_kernel(double* __restrict__ xs, int ldx, int LP, int nbk,
+                                                        double tol, int cap, int* __restrict__ ctl,
+                                                        long long tick_limit) {
+  extern __shared__ double lds[];
+  __shared__ BjShared<W> sh;
+  const double thr2 = *reinterpret_cast<const double*>(ctl + kBjCtlThr2);
+  int arrivals = 0;
+  for (int sweep = 0; sweep < cap; ++sweep) {
+    for (int round = 0; round < nbk - 1; ++round) {
+      bj_pair_step<W>(xs, ldx, LP, nbk, blockIdx.x, round, tol, thr2, ctl + sweep, lds, sh);
+      arrivals += gridDim.x;
+      if (!bj_grid_barrier(ctl + kBjCtlBarrier, arrivals, tick_limit, &sh.ok)) {
+        if (threadIdx.x == 0) __hip_atomic_store(ctl + kBjCtlTimeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
+    }
+    if (__hip_atomic_load(ctl + sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+  }
+}
+
+// flags[3] = sweeps run (the first with no rotation included), flags[2] += 1 if every sweep run rotated; a
+// barrier time-out counts in flags[0] and flags[2].
+__global__ void bj_flags_kernel(int* flags, const int* ctl, int cap) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     int s = 0;
-    while (s < cap && rot[s] != 0) ++s;
-    if (s == cap) atomicAdd(&flags[2], 1);
+    while (s < cap && ctl[s] != 0) ++s;
+    const bool timeout = ctl[kBjCtlTimeout] != 0;
+    if (s == cap || timeout) atomicAdd(&flags[2], 1);
+    if (timeout) atomicAdd(&flags[0], 1);
     atomicMax(&flags[3], s < cap ? s + 1 : cap);
   }
 }
 
 size_t jacobi_blocked_scratch_bytes(int LP) {
-  return (size_t)(LP + 32) * LP * sizeof(double) + 64 * sizeof(int);
+  return (size_t)(LP + 32) * LP * sizeof(double) + kBjCtlWords * sizeof(int);
 }
 
 template <typename TU>
-hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, double* sigma, double* uhat_d,
-                                  TU* uhat_p, TU* vhat_p, hipStream_t s);
-
-// Sweeps enqueued for the block form: the rounds of a sweep after the converged one return at once, so only
-// the launches themselves are spent past convergence (at l = 520 the FP32-data tolerance converges in 7).
-constexpr int kBlockedSweepCap = 20;
+hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, const double* thr2, double* sigma,
+                                  double* uhat_d, TU* uhat_p, TU* vhat_p, hipStream_t s);
 
 template <int W>
 constexpr size_t bj_lds_bytes() {
   return (size_t)(8 * ((2 * W / 16) * (2 * W / 16 + 1) / 2) * 256 + 3 * (2 * W) * (2 * W)) * sizeof(double);
+}
+
+// Sets the kernel's LDS limit once and checks that `grid` workgroups of it fit on the device at once (the
+// barrier needs every workgroup resident).
+template <int W>
+hipError_t bj_prepare(int grid) {
+  static int resident = -1;   // workgroups the device holds at once, -1 until known
+  if (resident < 0) {
+    const void* f = reinterpret_cast<const void*>(&bj_sweeps_kernel<W>);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bj_lds_bytes<W>());
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 512, bj_lds_bytes<W>())) != hipSuccess)
+      return e;
+    resident = cus * per_cu;
+  }
+  return grid <= resident ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
 }
 
 template <typename TU>
@@ -553,41 +671,31 @@ hipError_t launch_jacobi_blocked(const double* R, int l, int LP, double tol, int
   nbk += nbk & 1;
   const int ldx = LP;
   double* xs = scratch;
-  int* rot = reinterpret_cast<int*>(scratch + (size_t)(LP + 32) * LP);
-  static bool attr16 = false, attr8 = false;
-  if (W == 16 && !attr16) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bj_round_kernel<16>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bj_lds_bytes<16>());
-    if (e != hipSuccess) return e;
-    attr16 = true;
-  }
-  if (W == 8 && !attr8) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bj_round_kernel<8>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bj_lds_bytes<8>());
-    if (e != hipSuccess) return e;
-    attr8 = true;
-  }
+  int* ctl = reinterpret_cast<int*>(scratch + (size_t)(LP + 32) * LP);
   const int ncols = nbk * W;
   if (ncols > LP + 32 || LP % 16 != 0) return hipErrorInvalidValue;
+  const int grid = nbk / 2;
+  hipError_t e = W == 16 ? bj_prepare<16>(grid) : bj_prepare<8>(grid);
+  if (e != hipSuccess) return e;
+  int dev = 0, khz = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess) return e;
+  const long long tick_limit = (long long)std::max(khz, 1000) * 2000;   // two seconds per barrier wait
   const int64_t tot = (int64_t)ncols * ldx;
   hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, R, l, LP, xs, ldx, ncols);
-  hipError_t e = launch_fill_int(rot, 64, 0, s);
-  if (e != hipSuccess) return e;
+  if ((e = launch_fill_int(ctl, kBjCtlWords, 0, s)) != hipSuccess) return e;
+  double* thr2 = reinterpret_cast<double*>(ctl + kBjCtlThr2);
+  hipLaunchKernelGGL(bj_fro_kernel, dim3(1), dim3(1024), 0, s, xs, ldx, l, tol, thr2);
   const int cap = std::min(std::max(max_sweeps, 1), kBlockedSweepCap);
-  for (int sweep = 0; sweep < cap; ++sweep) {
-    for (int round = 0; round < nbk - 1; ++round) {
-      if (W == 16)
-        hipLaunchKernelGGL((bj_round_kernel<16>), dim3((unsigned)(nbk / 2)), dim3(512), bj_lds_bytes<16>(), s, xs,
-                           ldx, l, LP, nbk, round, tol, rot, sweep);
-      else
-        hipLaunchKernelGGL((bj_round_kernel<8>), dim3((unsigned)(nbk / 2)), dim3(512), bj_lds_bytes<8>(), s, xs,
-                           ldx, l, LP, nbk, round, tol, rot, sweep);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(bj_flags_kernel, dim3(1), dim3(64), 0, s, flags, rot, cap);
-  return jacobi_epilogue_launch<TU>(xs, ldx, l, LP, sigma, uhat_d, uhat_p, vhat_p, s);
+  if (W == 16)
+    hipLaunchKernelGGL((bj_sweeps_kernel<16>), dim3((unsigned)grid), dim3(512), bj_lds_bytes<16>(), s, xs, ldx, LP,
+                       nbk, tol, cap, ctl, tick_limit);
+  else
+    hipLaunchKernelGGL((bj_sweeps_kernel<8>), dim3((unsigned)grid), dim3(512), bj_lds_bytes<8>(), s, xs, ldx, LP,
+                       nbk, tol, cap, ctl, tick_limit);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(bj_flags_kernel, dim3(1), dim3(64), 0, s, flags, ctl, cap);
+  return jacobi_epilogue_launch<TU>(xs, ldx, l, LP, thr2, sigma, uhat_d, uhat_p, vhat_p, s);
 }
 
 template hipError_t launch_jacobi_blocked<float>(const double*, int, int, double, int, double*, double*, float*,

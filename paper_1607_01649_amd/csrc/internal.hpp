@@ -53,8 +53,8 @@ template <typename TU>
 hipError_t launch_jacobi_blocked(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma,
                                  double* uhat_d, TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s);
 template <typename TU>
-hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, double* sigma, double* uhat_d,
-                                  TU* uhat_p, TU* vhat_p, hipStream_t s);
+hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, const double* thr2, double* sigma,
+                                  double* uhat_d, TU* uhat_p, TU* vhat_p, hipStream_t s);
 
 // fp8.hip -- block-scaled OCP E4M3 copies of A (128 x 128 tile scales, shared by A8 and its transpose)
 // and the FP8 MFMA product with an FP32 panel quantised per 128-row segment of each column.

@@ -13,7 +13,14 @@
 // floor(l/2) disjoint pairs, processed in parallel by groups of 16 lanes (64
 // pairs at once in a 1024-thread block); l-1 (or l) rounds make a sweep.
 // Sweeps repeat until no pair needs a rotation (|x_p . x_q| <= tol * ||x_p||
-// ||x_q||).  The round is bound by instruction issue on one CU, so it is kept
+// ||x_q||).  A column whose norm is at most tol * ||X||_F is numerically zero
+// (rank deficiency, below what the stopping test can resolve against the
+// other columns): it takes no rotation, and it is returned as sigma = 0 with a
+// zero u_hat column, as an exactly zero column is.  A rotation only ever
+// shrinks the smaller column of its pair, so such a column stays below the
+// bound, and the rounding-level columns of a rank-deficient X no longer need
+// the many sweeps it takes to make them mutually orthogonal.  The round is
+// bound by instruction issue on one CU, so it is kept
 // lean: the squared norms are computed at the start of a sweep and then
 // updated exactly as the rotation changes them (||x_p||^2 - t g, ||x_q||^2 +
 // t g), so a pair only forms its dot product; the reductions use DPP lane
@@ -67,20 +74,21 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return y;
 }
 
-// Norms, order, signs and outputs of the converged columns (column p of X at
-// xs[p*LP + i]): sigma descending, u_hat = x / sigma signed so that its entry
-// of largest magnitude (lowest index on ties) is positive, v_hat = u_hat / sigma.  Column p of X is at
+// Norms, order, signs and outputs of the converged columns: sigma descending, u_hat = x / sigma signed so
+// that its entry of largest magnitude (lowest index on ties) is positive, v_hat = u_hat / sigma; a column
+// with squared norm at most thr2 (numerically zero) gives sigma = 0 and zero vectors.  Column p of X is at
 // xs[p*LX + i]; the outputs have leading dimension LP.
 template <typename TU>
-__device__ void jacobi_epilogue(const double* xs, int LX, int l, int LP, double* nrm, int* rnk, double* __restrict__ sigma,
-                                double* __restrict__ uhat_d, TU* __restrict__ uhat_p, TU* __restrict__ vhat_p) {
+__device__ void jacobi_epilogue(const double* xs, int LX, int l, int LP, double thr2, double* nrm, int* rnk,
+                                double* __restrict__ sigma, double* __restrict__ uhat_d, TU* __restrict__ uhat_p,
+                                TU* __restrict__ vhat_p) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
   for (int p = w; p < l; p += nw) {
     double s = 0.0;
     for (int i = lane; i < l; i += 64) s += xs[p * LX + i] * xs[p * LX + i];
     s = wave_sum(s);
-    if (lane == 0) nrm[p] = sqrt(s);
+    if (lane == 0) nrm[p] = s > thr2 ? sqrt(s) : 0.0;
   }
   __syncthreads();
   for (int p = tid; p < l; p += nt) {
@@ -141,6 +149,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
   __shared__ double nrm2[1024];   // squared column norms, kept current through the sweep
   __shared__ int rnk[1024];
   __shared__ int rotated;
+  __shared__ double thr2_sh;   // tol^2 ||X||_F^2: squared norm at or below which a column is numerically zero
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
   const int slot = tid / kPairLanes, sub = tid % kPairLanes, nslots = nt / kPairLanes;
@@ -155,6 +164,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
   const double tol2 = tol * tol;
   int sweep = 0;
   bool converged = (l < 2);
+  if (tid == 0) thr2_sh = 0.0;
   for (; sweep < max_sweeps && !converged; ++sweep) {
     __syncthreads();
     if (tid == 0) rotated = 0;
@@ -165,6 +175,16 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
       if (lane == 0) nrm2[p] = ss;
     }
     __syncthreads();
+    if (sweep == 0) {
+      // ||X||_F^2 (invariant under the rotations), summed in column order
+      if (tid == 0) {
+        double f = 0.0;
+        for (int p = 0; p < l; ++p) f += nrm2[p];
+        thr2_sh = tol2 * f;
+      }
+      __syncthreads();
+    }
+    const double thr2 = thr2_sh;
     for (int round = 0; round < m1; ++round) {
       for (int pi = slot; pi < npairs; pi += nslots) {
         // circle method: position 0 stays, the others advance by one each round
@@ -188,7 +208,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
         for (int h = 0; h < NH; ++h) ga += av[h].x * bv[h].x + av[h].y * bv[h].y;
         ga = group_sum(ga);
         const double al = nrm2[p], be = nrm2[q];
-        if (al > 0.0 && be > 0.0 && ga * ga > tol2 * (al * be)) {
+        if (al > thr2 && be > thr2 && ga * ga > tol2 * (al * be)) {
           // t = tan of the angle zeroing the off-diagonal of [[al, ga], [ga, be]] (the smaller root)
           const double d = be - al;
           const double h2 = d * d + 4.0 * ga * ga;
@@ -218,7 +238,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
   }
   __syncthreads();
 
-  jacobi_epilogue<TU>(xs, LX, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
+  jacobi_epilogue<TU>(xs, LX, l, LP, thr2_sh, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
 }
 
 template <typename TU, int NH>
@@ -239,25 +259,26 @@ __global__ __launch_bounds__(1024) void jacobi2_kernel(JacobiProblem<TU> a, Jaco
 
 template <typename TU>
 __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* __restrict__ xs, int l, int LP,
+                                                              const double* __restrict__ thr2,
                                                               double* __restrict__ sigma, double* __restrict__ uhat_d,
                                                               TU* __restrict__ uhat_p, TU* __restrict__ vhat_p) {
   __shared__ double nrm[1024];
   __shared__ int rnk[1024];
-  jacobi_epilogue<TU>(xs, LP, l, LP, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
+  jacobi_epilogue<TU>(xs, LP, l, LP, *thr2, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
 }
 
 template <typename TU>
-hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, double* sigma, double* uhat_d,
-                                  TU* uhat_p, TU* vhat_p, hipStream_t s) {
+hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, const double* thr2, double* sigma,
+                                  double* uhat_d, TU* uhat_p, TU* vhat_p, hipStream_t s) {
   if (ldx != LP) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((jacobi_finish_kernel<TU>), dim3(1), dim3(1024), 0, s, xs, l, LP, sigma, uhat_d, uhat_p,
+  hipLaunchKernelGGL((jacobi_finish_kernel<TU>), dim3(1), dim3(1024), 0, s, xs, l, LP, thr2, sigma, uhat_d, uhat_p,
                      vhat_p);
   return hipGetLastError();
 }
-template hipError_t jacobi_epilogue_launch<float>(const double*, int, int, int, double*, double*, float*, float*,
-                                                  hipStream_t);
-template hipError_t jacobi_epilogue_launch<double>(const double*, int, int, int, double*, double*, double*, double*,
-                                                   hipStream_t);
+template hipError_t jacobi_epilogue_launch<float>(const double*, int, int, int, const double*, double*, double*,
+                                                  float*, float*, hipStream_t);
+template hipError_t jacobi_epilogue_launch<double>(const double*, int, int, int, const double*, double*, double*,
+                                                   double*, double*, hipStream_t);
 
 template <typename TU>
 hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma, double* uhat_d,

@@ -218,6 +218,41 @@ def test_small_svd_matches_lapack(l):
     assert flags.cpu().numpy()[2] == 0
 
 
+@pytest.mark.parametrize("l,r", [(100, 60), (150, 100), (200, 120), (700, 500)])
+def test_small_svd_of_a_dense_rank_deficient_matrix(l, r):
+    """X = M^T M with M of rank r < l (dense columns; l - r singular values at rounding level): the one-sided
+    Jacobi converges, columns whose norm falls to tol ||X||_F or below (tol = l u) come out as sigma = 0 with
+    a zero U_hat column, and the others are orthonormal.  l > 128 is the block form (W = 8 at l = 700)."""
+    import torch
+    g = np.random.default_rng(l + r)
+    M = g.standard_normal((l + 50, r)) @ g.standard_normal((r, l))
+    X = M.T @ M
+    LP = (l + 15) // 16 * 16
+    Rp = np.zeros((LP, LP))
+    Rp[:l, :l] = X.T                                      # row p of R = column p of X
+    scr = _scratch(l)
+    dR = _t(Rp, torch.float64)
+    sig = torch.zeros(LP, dtype=torch.float64, device=device())
+    Uh = torch.zeros(LP * LP, dtype=torch.float64, device=device())
+    flags = torch.zeros(4, dtype=torch.int32, device=device())
+    assert _lib().rsvd_k_small_svd(l, _p(dR), _p(sig), _p(Uh), _p(flags), _p(scr), None) == 0
+    f = flags.cpu().numpy()
+    s = sig.cpu().numpy()[:l]
+    U = Uh.cpu().numpy().reshape(LP, LP).T[:l, :l]
+    ref = np.linalg.svd(X, compute_uv=False)
+    nz = s > 0
+    print(f"l={l} r={r}: sweeps {f[3]}, nonzero sigma {nz.sum()}", flush=True)
+    assert f[0] == 0 and f[2] == 0
+    assert np.abs(s - ref).max() <= 1e-12 * ref[0]
+    assert nz.sum() >= r and np.all(nz[:nz.sum()])          # zeros only at the end
+    assert np.all(s[~nz] == 0) and np.all(U[:, ~nz] == 0)
+    assert np.all(ref[~nz] <= l * 2.3e-16 * np.linalg.norm(X))
+    Un = U[:, nz]
+    assert np.linalg.norm(Un.T @ Un - np.eye(nz.sum())) <= 1e-10
+    # U_hat^T X X^T U_hat is diagonal up to the stopping test (|x_p . x_q| <= l u ||x_p|| ||x_q||)
+    assert np.linalg.norm((U.T @ X) @ (X.T @ U) - np.diag(s ** 2)) <= 1e-16 * l * l * ref[0] ** 2
+
+
 def test_convert_bf16_is_bit_exact():
     import torch
     from oracle import quant

@@ -107,3 +107,15 @@ def test_nystrom_at_the_full_psd_workload():
     assert np.all(np.diff(S) <= 0)
     lam = cfg.sigma()
     assert np.all(S <= lam[:k] * (1 + 1e-4))
+
+
+def test_nystrom_past_128_columns():
+    """l = 200: the blocked Cholesky (with its drop rule) for B2 and the block Jacobi of the small SVD."""
+    n, k, p = 1000, 160, 40
+    lam = np.arange(1, n + 1, dtype=float) ** -1.5
+    A = _psd(n, lam, 14)
+    U, S, V, info = run_factor(A, k, p, 0, "f64", seed=6, flags=_flags())
+    Ur, Lr, dropped = nys.nystrom_seeded(A, k, p, 0, 6)
+    assert info.status == 0 and info.dropped_cols == dropped == 0
+    assert max_rel_sigma(S, Lr, k) <= 1e-9
+    assert np.abs((U * S) @ U.T - (Ur[:, :k] * Lr[:k]) @ Ur[:, :k].T).max() <= 1e-10

@@ -176,3 +176,51 @@ def test_general_at_the_headline_shape():
         print(f"{sk}: ||U^T U - I|| = {eu:.2e}, ||V^T V - I|| = {ev:.2e}")
         assert eu <= 1e-4 and ev <= 1e-4
         assert np.all(np.diff(S) <= 0) and S[-1] >= 0
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_single_pass_past_128_columns(sym):
+    """l = 140: the blocked Cholesky and the block Jacobi for the two l x l problems (unpaired above 128 columns),
+    against the oracle in FP64 (k = 40 keeps the oracle's vectorised least squares small)."""
+    n, k, p = 900, 40, 100
+    if sym:
+        lam = gen.spectrum("poly", 400, alpha=1.5) * np.where(np.arange(400) % 5 == 3, -1.0, 1.0)
+        U0 = gen.orthonormal_factor(n, 400, 12, 1)
+        A = (U0 * lam) @ U0.T
+        A = 0.5 * (A + A.T)
+    else:
+        A = gen.low_rank_matrix(1100, n, gen.spectrum("poly", 450, alpha=1.5), 1e-6, seed=13)
+    U, S, V, info = run_factor(A, k, p, 0, "f64", seed=4, flags=_flags(sym))
+    print("GPU factorisation done", flush=True)
+    if sym:
+        Ur, Dr, _ = sp.single_pass_sym_seeded(A, k, p, 4)
+        Vr = Ur
+    else:
+        Ur, Dr, Vr, _ = sp.single_pass_gen_seeded(A, k, p, 4)
+    assert info.status == 0
+    assert np.abs(S - Dr).max() <= 1e-9 * abs(Dr[0])
+    assert np.abs((U * S) @ V.T - (Ur * Dr) @ Vr.T).max() <= 1e-9 * abs(Dr[0])
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_single_pass_with_a_core_past_128(sym):
+    """k = 150, p = 50: the k x k core (eigendecompositions, SVD of C) on the block Jacobi; checked by exact
+    recovery of a matrix of rank 100 (the oracle's vectorised least squares is out of reach at this k).  The
+    core comes from normal equations, which square the conditioning of the Gaussian equation matrices
+    (kappa ~ (sqrt(l) + sqrt(k)) / (sqrt(l) - sqrt(k)) ~ 14 here): kappa^2 l u ~ 1e-11, bound 1e-10."""
+    n, r, k, p = 700, 100, 150, 50
+    if sym:
+        lam = np.logspace(0, -3, r) * np.where(np.arange(r) % 4 == 1, -1.0, 1.0)
+        U0 = gen.orthonormal_factor(n, r, 15, 1)
+        A = (U0 * lam) @ U0.T
+        A = 0.5 * (A + A.T)
+        ref = lam[np.argsort(-np.abs(lam), kind="stable")]
+    else:
+        ref = np.logspace(0, -3, r)
+        A = gen.low_rank_matrix(n + 150, n, ref, 0.0, seed=16)
+    U, S, V, info = run_factor(A, k, p, 0, "f64", seed=2, flags=_flags(sym))
+    print("GPU factorisation done", flush=True)
+    assert info.status == 0
+    assert np.abs(S[:r] - ref).max() <= 1e-10
+    assert np.abs(S[r:]).max() <= 1e-10
+    assert np.abs(A - (U * S) @ V.T).max() <= 1e-10
