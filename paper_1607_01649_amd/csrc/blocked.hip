@@ -9,10 +9,10 @@
 // end, lower triangular, kept in the strictly lower blocks of X), as the
 // one-workgroup kernel of chol.hip does:
 //   for each block column J:
-//     factor the diagonal block (one workgroup, the same unscaled elimination
-//     with the identity block as chol.hip, dependent columns dropped against
-//     the original diagonal) -> R_JJ and S_JJ = R_JJ^-1 (X's diagonal block;
-//     E_JJ = S_JJ^T);
+//     factor the diagonal block (one workgroup running the one-workgroup
+//     kernel's block elimination of chol.hip on the 64 x 64 block, dependent
+//     columns dropped against the original diagonal) -> R_JJ and
+//     S_JJ = R_JJ^-1 (X's diagonal block; E_JJ = S_JJ^T);
 //     R_JK = S_JJ^T M_JK for the blocks K > J of the block row, and
 //     E_JM = S_JJ^T E_JM for the blocks M < J (one launch);
 //     M_KL -= R_JK^T R_JL for J < K <= L, and E_KM -= R_JK^T E_JM for K > J,
@@ -51,87 +51,6 @@ __global__ void bc_init_kernel(const double* __restrict__ g, int64_t ldg, int l,
   M[t] = v;
   X[t] = 0.0;   // the identity's elimination starts from zero off the diagonal blocks
   if (a == b) gdiag[a] = v;
-}
-
-// Diagonal block J (rows/columns j0 .. j0+63) of M: 256 threads, thread t owns the 4 x 4
-// register blocks of U and T at rows 4*(t/16), columns 4*(t%16).
-__global__ __launch_bounds__(256) void bc_diag_kernel(double* __restrict__ M, int LB, int j0, int l,
-                                                      const double* __restrict__ gdiag, double tau,
-                                                      double* __restrict__ X, int* __restrict__ flags) {
-  __shared__ double urow[2][CB];
-  __shared__ double trow[2][CB];
-  __shared__ double rs[CB];
-  const int tid = threadIdx.x;
-  const int a0 = 4 * (tid >> 4), b0 = 4 * (tid & 15);
-  const int nv = min(CB, l - j0);
-  double U[4][4], T[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int a = a0 + i, b = b0 + k;
-      U[i][k] = (a <= b && b < nv) ? M[(int64_t)(j0 + a) * LB + j0 + b] : 0.0;
-      T[i][k] = (a == b) ? 1.0 : 0.0;
-    }
-  if (a0 == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { urow[0][b0 + k] = U[0][k]; trow[0][b0 + k] = T[0][k]; }
-  }
-  if (tid < CB) rs[tid] = 0.0;
-  __syncthreads();
-  int bad = 0, dropped = 0;
-  for (int j = 0; j < nv; ++j) {
-    const double* uj = urow[j & 1];
-    const double* tj = trow[j & 1];
-    const double d = uj[j];
-    const double gd = gdiag[j0 + j];
-    const bool nonfinite = !isfinite(d) || !isfinite(gd);
-    const bool drop = nonfinite || !(d > tau * gd) || !(d > 0.0);
-    bad += nonfinite;
-    dropped += (drop && !nonfinite);
-    if (!drop && a0 + 3 > j) {
-      const double invd = 1.0 / d;
-      double f[4], ub[4], tb[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) f[i] = (a0 + i > j) ? uj[a0 + i] * invd : 0.0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        ub[k] = (b0 + k > j) ? uj[b0 + k] : 0.0;
-        tb[k] = tj[b0 + k];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          U[i][k] -= f[i] * ub[k];
-          T[i][k] -= f[i] * tb[k];
-        }
-    }
-    if (tid == 0) rs[j] = drop ? 0.0 : 1.0 / sqrt(d);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (a0 + i == j + 1 && j + 1 < nv) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          urow[(j + 1) & 1][b0 + k] = U[i][k];
-          trow[(j + 1) & 1][b0 + k] = T[i][k];
-        }
-      }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (bad) atomicAdd(&flags[0], bad);
-    if (dropped) atomicAdd(&flags[1], dropped);
-  }
-  // R_JJ = D^-1/2 U (upper, in place) and R_JJ^-1 (k, c) = T(c, k) / sqrt(d_c) into X's diagonal block.
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int a = a0 + i, b = b0 + k;
-      M[(int64_t)(j0 + a) * LB + j0 + b] = (a <= b) ? U[i][k] * rs[a] : 0.0;
-      X[(int64_t)(j0 + b) * LB + j0 + a] = (b <= a) ? T[i][k] * rs[a] : 0.0;
-    }
 }
 
 // 64 x 64 tile product helper: acc(a, b) += sum_t As[t][a] * Bs[t][b] over the staged tiles
@@ -306,7 +225,8 @@ hipError_t launch_chol_blocked(const double* g, int64_t ldg, int l, int LP, doub
   // X: S_JJ on the diagonal blocks, E below them; its blocks above the diagonal are never read.
   for (int jb = 0; jb < nbk; ++jb) {
     const int j0 = jb * CB;
-    hipLaunchKernelGGL(bc_diag_kernel, dim3(1), dim3(256), 0, s, M, LB, j0, l, gdiag, tau, X, flags);
+    hipError_t e = launch_chol_diag64(M, LB, j0, l, gdiag, tau, X, flags, s);
+    if (e != hipSuccess) return e;
     const int nr = nbk - 1 - jb;
     if (nr + jb > 0)
       hipLaunchKernelGGL(bc_panel_kernel, dim3((unsigned)(nr + jb)), dim3(256), 0, s, M, X, LB, j0, nr);
@@ -372,9 +292,19 @@ constexpr int kBlockedSweepCap = 60;
 __global__ __launch_bounds__(1024) void bj_fro_kernel(const double* __restrict__ xs, int ldx, int l, double tol,
                                                       double* __restrict__ thr2) {
   __shared__ double part[16];
-  double f = 0.0;
-  for (int p = 0; p < l; ++p)
-    for (int i = threadIdx.x; i < l; i += 1024) f = fma(xs[(int64_t)p * ldx + i], xs[(int64_t)p * ldx + i], f);
+  // rows l .. ldx-1 of the first l columns are zero, so the l ldx values are summed as one flat range
+  const int64_t n = (int64_t)l * ldx;
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0;
+  int64_t t = threadIdx.x;
+  for (; t + 3 * 1024 < n; t += 4 * 1024) {
+    const double a = xs[t], b = xs[t + 1024], c = xs[t + 2048], d = xs[t + 3072];
+    f0 = fma(a, a, f0);
+    f1 = fma(b, b, f1);
+    f2 = fma(c, c, f2);
+    f3 = fma(d, d, f3);
+  }
+  for (; t < n; t += 1024) f0 = fma(xs[t], xs[t], f0);
+  double f = (f0 + f1) + (f2 + f3);
   f = wave_sum(f);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = f;
   __syncthreads();
@@ -454,20 +384,33 @@ __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, i
     f64x4 acc[NTT];
 #pragma unroll
     for (int t = 0; t < NTT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int sl = wave; sl < nslab; sl += 8) {
-      double x[NT][4];
+    // SB slabs of a wave are loaded before their MFMAs (32 values in flight per lane), so a round pays one
+    // memory latency per batch rather than one per slab.
+    constexpr int SB = NT == 2 ? 4 : 8;
+    for (int s0 = wave; s0 < nslab; s0 += 8 * SB) {
+      double x[SB][NT][4];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const double2 a = *reinterpret_cast<const double2*>(colp[t] + 16 * sl);
-        const double2 b = *reinterpret_cast<const double2*>(colp[t] + 16 * sl + 2);
-        x[t][0] = a.x; x[t][1] = a.y; x[t][2] = b.x; x[t][3] = b.y;
+      for (int b = 0; b < SB; ++b) {
+        const int sl = s0 + 8 * b;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if (sl < nslab) {
+            const double2 u = *reinterpret_cast<const double2*>(colp[t] + 16 * sl);
+            const double2 v = *reinterpret_cast<const double2*>(colp[t] + 16 * sl + 2);
+            x[b][t][0] = u.x; x[b][t][1] = u.y; x[b][t][2] = v.x; x[b][t][3] = v.y;
+          }
+        }
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0][e], x[0][e], acc[0], 0, 0, 0);
-        if constexpr (NT == 2) {
-          acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[0][e], x[1][e], acc[1], 0, 0, 0);
-          acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[1][e], x[1][e], acc[2], 0, 0, 0);
+      for (int b = 0; b < SB; ++b) {
+        if (s0 + 8 * b >= nslab) break;   // uniform in the wave
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[b][0][e], x[b][0][e], acc[0], 0, 0, 0);
+          if constexpr (NT == 2) {
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[b][0][e], x[b][1][e], acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[b][1][e], x[b][1][e], acc[2], 0, 0, 0);
+          }
         }
       }
     }
@@ -572,19 +515,36 @@ __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, i
   // 3. X <- X V: output tile jt of slab sl is D(j, i) = sum_k V(k, 16 jt + j) X(16 sl + i, k), with the A
   // operand V^T read from LDS and the B operand X^T (16 lanes read 16 consecutive rows of one column).
   if (rotated) {
-    for (int sl = wave; sl < nslab; sl += 8) {
-      const int i = 16 * sl + ci;
-      double xv[NC / 4];
+    double vf[NT][NC / 4];   // this lane's V^T operands, the same for every slab
 #pragma unroll
-      for (int st = 0; st < NC / 4; ++st) xv[st] = xs[(int64_t)gcol(4 * st + g) * ldx + i];
+    for (int jt = 0; jt < NT; ++jt)
 #pragma unroll
-      for (int jt = 0; jt < NT; ++jt) {
-        f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+      for (int st = 0; st < NC / 4; ++st) vf[jt][st] = vm[(4 * st + g) * NC + 16 * jt + ci];
+    constexpr int SX = NT == 2 ? 4 : 8;   // slabs loaded ahead per batch (32 values per lane)
+    for (int s0 = wave; s0 < nslab; s0 += 8 * SX) {
+      double xv[SX][NC / 4];
 #pragma unroll
-        for (int st = 0; st < NC / 4; ++st)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vm[(4 * st + g) * NC + 16 * jt + ci], xv[st], acc, 0, 0, 0);
+      for (int b = 0; b < SX; ++b) {
+        const int sl = s0 + 8 * b;
+        if (sl < nslab) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) xs[(int64_t)gcol(16 * jt + g + 4 * r) * ldx + i] = acc[r];
+          for (int st = 0; st < NC / 4; ++st) xv[b][st] = xs[(int64_t)gcol(4 * st + g) * ldx + 16 * sl + ci];
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < SX; ++b) {
+        const int sl = s0 + 8 * b;
+        if (sl >= nslab) break;   // uniform in the wave
+        const int i = 16 * sl + ci;
+#pragma unroll
+        for (int jt = 0; jt < NT; ++jt) {
+          f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int st = 0; st < NC / 4; ++st)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vf[jt][st], xv[b][st], acc, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xs[(int64_t)gcol(16 * jt + g + 4 * r) * ldx + i] = acc[r];
+        }
       }
     }
     if (tid == 0) atomicAdd(rot, 1);

@@ -146,6 +146,86 @@ __device__ __forceinline__ f64x4 mma16(const double* __restrict__ A, int sai, in
   return acc;
 }
 
+// The block elimination on an LP x LP matrix held in LDS (M with pitch MP, nb = LP / 16 blocks; on entry the
+// blocks on and above the block diagonal hold the symmetric matrix, both triangles of the diagonal blocks,
+// and the blocks below are zero; Wd holds nb diagonal blocks of pitch kWdPitch).  On exit the upper blocks
+// hold R, the diagonal blocks of R^-T are in Wd and its blocks below the diagonal in M.  gd: the original
+// diagonal entries (the drop rule's reference), nvalid: the columns that take part (the rest is padding).
+// All eight waves of the workgroup call it.
+__device__ __forceinline__ void chol_lds_factor(double* __restrict__ M, int MP, double* __restrict__ Wd, int nb,
+                                                int nvalid, const double* __restrict__ gd, double tau_rel,
+                                                int& bad, int& dropped) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lg = lane >> 4, lc = lane & 15;
+  // Iteration J (from -1): T(J) -- the trailing update by block row J (none for J = -1) by waves 1..3 and,
+  // by wave 0, the update and factorisation of diagonal block J+1 -- then P(J+1).
+  for (int J = -1; J < nb - 1; ++J) {
+    const int r0 = kCholB * J, r1 = r0 + kCholB;
+    const double* WJ = Wd + (J < 0 ? 0 : J) * kCholB * kWdPitch;
+    if (wv == 0) {
+      double* dblk = M + r1 * MP + r1;
+      if (J >= 0) {
+        const double* rk = M + r0 * MP + r1;   // R_{J, J+1}
+        f64x4 acc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = dblk[(lg + 4 * e) * MP + lc];
+        acc = mma16(rk, 1, MP, rk, MP, 1, acc, lane, -1.0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dblk[(lg + 4 * e) * MP + lc] = acc[e];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      }
+      chol_block(dblk, MP, gd + r1, nvalid - r1, tau_rel, lane, Wd + (J + 1) * kCholB * kWdPitch, bad, dropped);
+    } else if (J >= 0) {
+      const int nt = nb - 1 - J;                    // block rows below J
+      const int nupper = nt * (nt + 1) / 2 - 1;     // trailing A blocks except (J+1, J+1)
+      const int ntask = nupper + nt * (J + 1);
+      for (int task = wv - 1; task < ntask; task += kCholWaves - 1) {
+        int K, L;
+        const double* bop;
+        int sbk;
+        if (task < nupper) {
+          // upper blocks (K, L), J < K <= L, in row order, (J+1, J+1) skipped
+          int t = task + 1, k = 0;
+          while (t >= nt - k) { t -= nt - k; ++k; }
+          K = J + 1 + k;
+          L = K + t;
+          bop = M + r0 * MP + kCholB * L;
+          sbk = MP;
+        } else {
+          const int t = task - nupper;
+          K = J + 1 + t / (J + 1);
+          L = t - (t / (J + 1)) * (J + 1);          // M <= J
+          bop = (L == J) ? WJ : M + r0 * MP + kCholB * L;
+          sbk = (L == J) ? kWdPitch : MP;
+        }
+        double* cblk = M + kCholB * K * MP + kCholB * L;
+        const double* rk = M + r0 * MP + kCholB * K;   // R_JK
+        f64x4 acc;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = cblk[(lg + 4 * e) * MP + lc];
+        acc = mma16(rk, 1, MP, bop, sbk, 1, acc, lane, -1.0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cblk[(lg + 4 * e) * MP + lc] = acc[e];
+      }
+    }
+    __syncthreads();
+    // P(J+1): block row J+1 of R (right of the diagonal) and of W (left of it)
+    const int Jn = J + 1;
+    const double* WJn = Wd + Jn * kCholB * kWdPitch;
+    for (int task = wv; task < nb - 1; task += kCholWaves) {
+      const int col = task < Jn ? task : task + 1;   // the block column, Jn skipped
+      double* blk = M + r1 * MP + kCholB * col;
+      f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+      acc = mma16(WJn, kWdPitch, 1, blk, MP, 1, acc, lane, 1.0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) blk[(lg + 4 * e) * MP + lc] = acc[e];
+    }
+    __syncthreads();
+  }
+}
+
 // l <= 128: one workgroup of eight waves, G in LDS as an LP x (LP + 1) matrix M of 16 x 16 blocks.  The
 // blocks on and above the diagonal hold A (the trailing matrix) and become R; the blocks below it hold T
 // (the accumulated elimination of the identity) and become R^-T, whose diagonal blocks live apart in Wd.
@@ -203,72 +283,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_blk_kernel(const double* __
   }
   __syncthreads();
   int bad = 0, dropped = 0;
-  // Iteration J (from -1): T(J) -- the trailing update by block row J (none for J = -1) by waves 1..3 and,
-  // by wave 0, the update and factorisation of diagonal block J+1 -- then P(J+1).
-  for (int J = -1; J < nb - 1; ++J) {
-    const int r0 = kCholB * J, r1 = r0 + kCholB;
-    const double* WJ = Wd + (J < 0 ? 0 : J) * kCholB * kWdPitch;
-    if (wv == 0) {
-      double* dblk = M + r1 * MP + r1;
-      if (J >= 0) {
-        const double* rk = M + r0 * MP + r1;   // R_{J, J+1}
-        f64x4 acc;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = dblk[(lg + 4 * e) * MP + lc];
-        acc = mma16(rk, 1, MP, rk, MP, 1, acc, lane, -1.0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dblk[(lg + 4 * e) * MP + lc] = acc[e];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      }
-      chol_block(dblk, MP, gdiag + r1, l - r1, tau_rel, lane, Wd + (J + 1) * kCholB * kWdPitch, bad, dropped);
-    } else if (J >= 0) {
-      const int nt = nb - 1 - J;                    // block rows below J
-      const int nupper = nt * (nt + 1) / 2 - 1;     // trailing A blocks except (J+1, J+1)
-      const int ntask = nupper + nt * (J + 1);
-      for (int task = wv - 1; task < ntask; task += kCholWaves - 1) {
-        int K, L;
-        const double* bop;
-        int sbk;
-        if (task < nupper) {
-          // upper blocks (K, L), J < K <= L, in row order, (J+1, J+1) skipped
-          int t = task + 1, k = 0;
-          while (t >= nt - k) { t -= nt - k; ++k; }
-          K = J + 1 + k;
-          L = K + t;
-          bop = M + r0 * MP + kCholB * L;
-          sbk = MP;
-        } else {
-          const int t = task - nupper;
-          K = J + 1 + t / (J + 1);
-          L = t - (t / (J + 1)) * (J + 1);          // M <= J
-          bop = (L == J) ? WJ : M + r0 * MP + kCholB * L;
-          sbk = (L == J) ? kWdPitch : MP;
-        }
-        double* cblk = M + kCholB * K * MP + kCholB * L;
-        const double* rk = M + r0 * MP + kCholB * K;   // R_JK
-        f64x4 acc;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = cblk[(lg + 4 * e) * MP + lc];
-        acc = mma16(rk, 1, MP, bop, sbk, 1, acc, lane, -1.0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) cblk[(lg + 4 * e) * MP + lc] = acc[e];
-      }
-    }
-    __syncthreads();
-    // P(J+1): block row J+1 of R (right of the diagonal) and of W (left of it)
-    const int Jn = J + 1;
-    const double* WJn = Wd + Jn * kCholB * kWdPitch;
-    for (int task = wv; task < nb - 1; task += kCholWaves) {
-      const int col = task < Jn ? task : task + 1;   // the block column, Jn skipped
-      double* blk = M + r1 * MP + kCholB * col;
-      f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
-      acc = mma16(WJn, kWdPitch, 1, blk, MP, 1, acc, lane, 1.0);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) blk[(lg + 4 * e) * MP + lc] = acc[e];
-    }
-    __syncthreads();
-  }
+  chol_lds_factor(M, MP, Wd, nb, l, gdiag, tau_rel, bad, dropped);
   if (wv == 0 && lane == 0) {
     if (bad) atomicAdd(&flags[0], bad);
     if (dropped) atomicAdd(&flags[1], dropped);
@@ -333,6 +348,53 @@ __global__ __launch_bounds__(kCholThreads) void chol_blk_kernel(const double* __
       r_out[(int64_t)x * LP + y] = 0.0;
     }
   }
+}
+
+// Diagonal block J of the blocked form (l > 128): rows and columns j0 .. j0+63 of its working matrix Mg
+// (row-major, leading dimension LB; the entries on and above the block's diagonal are current) factored
+// by the same block elimination as the one-workgroup kernel: R_JJ into Mg's block (zero below its
+// diagonal) and S_JJ = R_JJ^-1 into X's diagonal block (row-major, zero below the diagonal).  gdiag: the
+// original diagonal of G (the drop rule's reference); columns past l are padding.
+__global__ __launch_bounds__(kCholThreads) void chol_diag64_kernel(double* __restrict__ Mg, int LB, int j0, int l,
+                                                                 const double* __restrict__ gdiag, double tau_rel,
+                                                                 double* __restrict__ X, int* __restrict__ flags) {
+  constexpr int D = 64, MP = D + 1, nb = D / kCholB;
+  __shared__ __align__(16) double M[D * MP];
+  __shared__ __align__(16) double Wd[nb * kCholB * kWdPitch];
+  const int tid = threadIdx.x;
+  const int nv = min(D, l - j0);
+  // the symmetric block in both triangles of the diagonal 16 x 16 blocks and above them; zero below
+  for (int e = tid; e < D * D; e += kCholThreads) {
+    const int a = e / D, b = e - (e / D) * D;
+    double v = 0.0;
+    if ((a >> 4) <= (b >> 4) && a < nv && b < nv) {
+      const int r = min(a, b), c = max(a, b);
+      v = Mg[(int64_t)(j0 + r) * LB + j0 + c];
+    }
+    M[a * MP + b] = v;
+  }
+  __syncthreads();
+  int bad = 0, dropped = 0;
+  chol_lds_factor(M, MP, Wd, nb, nv, gdiag + j0, tau_rel, bad, dropped);
+  if (tid == 0) {
+    if (bad) atomicAdd(&flags[0], bad);
+    if (dropped) atomicAdd(&flags[1], dropped);
+  }
+  for (int e = tid; e < D * D; e += kCholThreads) {
+    const int a = e / D, b = e - (e / D) * D;
+    double sv = 0.0;   // S_JJ(a, b) = R^-T(b, a)
+    if (a <= b)
+      sv = ((a >> 4) == (b >> 4)) ? Wd[(a >> 4) * kCholB * kWdPitch + (b & 15) * kWdPitch + (a & 15)] : M[b * MP + a];
+    Mg[(int64_t)(j0 + a) * LB + j0 + b] = (a <= b) ? M[a * MP + b] : 0.0;
+    X[(int64_t)(j0 + a) * LB + j0 + b] = sv;
+  }
+}
+
+hipError_t launch_chol_diag64(double* M, int LB, int j0, int l, const double* gdiag, double tau_rel, double* X,
+                              int* flags, hipStream_t s) {
+  if (j0 < 0 || j0 >= l || LB % 64 != 0 || j0 + 64 > LB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_diag64_kernel, dim3(1), dim3(kCholThreads), 0, s, M, LB, j0, l, gdiag, tau_rel, X, flags);
+  return hipGetLastError();
 }
 
 template <typename TQ>

@@ -48,6 +48,9 @@ size_t chol_blocked_scratch_doubles(int LP);
 template <typename TQ>
 hipError_t launch_chol_blocked(const double* g, int64_t ldg, int l, int LP, double tau, TQ* rinv_p, double* r_out,
                                const double* r_prev, double* scratch, int* flags, hipStream_t s);
+// 64 x 64 diagonal block of the blocked Cholesky (chol.hip): R_JJ into M, S_JJ = R_JJ^-1 into X.
+hipError_t launch_chol_diag64(double* M, int LB, int j0, int l, const double* gdiag, double tau_rel, double* X,
+                              int* flags, hipStream_t s);
 size_t jacobi_blocked_scratch_bytes(int LP);
 template <typename TU>
 hipError_t launch_jacobi_blocked(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma,

@@ -179,6 +179,34 @@ def test_cholesky_drops_dependent_columns():
     assert np.allclose(Q[:, keep].T @ Q[:, keep], np.eye(5), atol=1e-10)
 
 
+def test_blocked_cholesky_drops_dependent_columns():
+    """l = 200 (64-wide diagonal blocks, ragged last block): exactly dependent columns in the first, an inner
+    and the last diagonal block, and one whose dependence spans two blocks, are dropped; the rest of Q is
+    orthonormal."""
+    import torch
+    l = 200
+    rng = np.random.default_rng(5)
+    Y = rng.standard_normal((700, l))
+    dep = {5: (0, 3), 70: (64, 66), 100: (10, 90), 199: (130, 198)}
+    for j, (a, b) in dep.items():
+        Y[:, j] = Y[:, a] - 0.5 * Y[:, b]
+    G = Y.T @ Y
+    LP = (l + 15) // 16 * 16
+    scr = _scratch(l)
+    dG = _t(G.T, torch.float64)
+    Rinv = torch.zeros(LP * LP, dtype=torch.float64, device=device())
+    R = torch.zeros(LP * LP, dtype=torch.float64, device=device())
+    flags = torch.zeros(4, dtype=torch.int32, device=device())
+    assert _lib().rsvd_k_cholesky(l, _p(dG), l, 1e-10, _p(Rinv), _p(R), _p(flags), _p(scr), None) == 0
+    assert flags.cpu().numpy()[:2].tolist() == [0, len(dep)]
+    Ri = Rinv.cpu().numpy().reshape(LP, LP).T[:l, :l]
+    Q = Y @ Ri
+    drop = sorted(dep)
+    keep = [j for j in range(l) if j not in dep]
+    assert np.abs(Q[:, drop]).max() <= 1e-12
+    assert np.abs(Q[:, keep].T @ Q[:, keep] - np.eye(len(keep))).max() <= 1e-8
+
+
 @pytest.mark.parametrize("l", [1, 2, 7, 30, 110, 128, 131, 300, 520])
 def test_small_svd_matches_lapack(l):
     """R is the triangular factor of a matrix with singular values
