@@ -53,91 +53,91 @@ __global__ void bc_init_kernel(const double* __restrict__ g, int64_t ldg, int l,
   if (a == b) gdiag[a] = v;
 }
 
-// 64 x 64 tile product helper: acc(a, b) += sum_t As[t][a] * Bs[t][b] over the staged tiles
-// (ld CB + 1), thread t owning rows 4*(t/16) and columns 4*(t%16).
-__device__ __forceinline__ void tile_tn(const double (*As)[CB + 1], const double (*Bs)[CB + 1], int a0, int b0,
-                                        double (&acc)[4][4]) {
-#pragma unroll 4
-  for (int t = 0; t < CB; ++t) {
-    double av[4], bv[4];
+// 64 x 64 tile product on the FP64 MFMA for a workgroup of four waves: wave w accumulates the output tiles
+// (w, tb), tb = 0..3, of C(a, b) = sum_t A(t, a) B(t, b) over t < 64 into acc[tb] (element e of lane
+// (g, j) is C(16 w + g + 4 e, 16 tb + j)); fa(t, a) and fb(t, b) load the operands (straight from memory:
+// the tiles stay in L2).  sign = -1 subtracts.
+template <typename FA, typename FB>
+__device__ __forceinline__ void tile64(FA fa, FB fb, double sign, f64x4 (&acc)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) av[i] = As[t][a0 + i];
+  for (int s = 0; s < CB / 4; ++s) {
+    const int t = 4 * s + g;
+    const double av = sign * fa(t, 16 * w + i);
+    double bv[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) bv[k] = Bs[t][b0 + k];
+    for (int tb = 0; tb < 4; ++tb) bv[tb] = fb(t, 16 * tb + i);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) acc[i][k] += av[i] * bv[k];
+    for (int tb = 0; tb < 4; ++tb) acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[tb], acc[tb], 0, 0, 0);
   }
 }
 
 // R_JK = S_JJ^T M_JK for the blocks K = J+1+blockIdx.x (blockIdx.x < nr), and E_JM = S_JJ^T E_JM for
-// M = blockIdx.x - nr < J.
+// M = blockIdx.x - nr < J.  In place: every product is complete before the workgroup barrier, the stores
+// come after it.
 __global__ __launch_bounds__(256) void bc_panel_kernel(double* __restrict__ M, double* __restrict__ X, int LB, int j0,
                                                        int nr) {
-  __shared__ double Ss[CB][CB + 1];
-  __shared__ double Gs[CB][CB + 1];
-  const int tid = threadIdx.x;
   const bool erow = (int)blockIdx.x >= nr;
   double* blk = erow ? X + (int64_t)j0 * LB + CB * ((int)blockIdx.x - nr) : M + (int64_t)j0 * LB + j0 + CB * (1 + blockIdx.x);
-  for (int t = tid; t < CB * CB; t += 256) {
-    const int r = t / CB, c = t - (t / CB) * CB;
-    Ss[r][c] = X[(int64_t)(j0 + r) * LB + j0 + c];
-    Gs[r][c] = blk[(int64_t)r * LB + c];
-  }
+  const double* S = X + (int64_t)j0 * LB + j0;
+  f64x4 acc[4];
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) acc[tb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  tile64([&](int t, int a) { return S[(int64_t)t * LB + a]; }, [&](int t, int b) { return blk[(int64_t)t * LB + b]; },
+         1.0, acc);
   __syncthreads();
-  const int a0 = 4 * (tid >> 4), b0 = 4 * (tid & 15);
-  double acc[4][4] = {};
-  tile_tn(Ss, Gs, a0, b0, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) blk[(int64_t)(a0 + i) * LB + b0 + k] = acc[i][k];
+    for (int e = 0; e < 4; ++e) blk[(int64_t)(16 * w + g + 4 * e) * LB + 16 * tb + i] = acc[tb][e];
 }
 
 // M_KL -= R_JK^T R_JL for J < K <= L (the first nr (nr + 1) / 2 workgroups enumerate the pairs (K, L)), and
-// E_KM -= R_JK^T E_JM for K > J, M <= J (the rest, nr (J + 1) of them; E_JJ = S_JJ^T).
+// E_KM -= R_JK^T E_JM for K > J, M <= J (the rest, nr (J + 1) of them; E_JJ = S_JJ^T).  The output block
+// is never an operand.
 __global__ __launch_bounds__(256) void bc_trail_kernel(double* __restrict__ M, double* __restrict__ X, int LB, int j0,
                                                        int nr) {
-  __shared__ double As[CB][CB + 1];
-  __shared__ double Bs[CB][CB + 1];
-  const int tid = threadIdx.x;
   const int jb = j0 / CB;
   const int npair = nr * (nr + 1) / 2;
-  int k0;
+  const double* A;
+  const double* B;
+  int64_t sbt = LB, sbb = 1;
   double* out;
   if ((int)blockIdx.x < npair) {
     int idx = blockIdx.x, kb = 0;
     while (idx >= nr - kb) { idx -= nr - kb; ++kb; }
     const int lb = kb + idx;
-    k0 = j0 + CB * (1 + kb);
-    const int l0 = j0 + CB * (1 + lb);
-    for (int t = tid; t < CB * CB; t += 256) {
-      const int r = t / CB, c = t - (t / CB) * CB;
-      As[r][c] = M[(int64_t)(j0 + r) * LB + k0 + c];
-      Bs[r][c] = M[(int64_t)(j0 + r) * LB + l0 + c];
-    }
+    const int k0 = j0 + CB * (1 + kb), l0 = j0 + CB * (1 + lb);
+    A = M + (int64_t)j0 * LB + k0;
+    B = M + (int64_t)j0 * LB + l0;
     out = M + (int64_t)k0 * LB + l0;
   } else {
     const int idx = (int)blockIdx.x - npair;
     const int kb = idx / (jb + 1), mb = idx - (idx / (jb + 1)) * (jb + 1);
-    k0 = j0 + CB * (1 + kb);
-    const int m0 = CB * mb;
-    for (int t = tid; t < CB * CB; t += 256) {
-      const int r = t / CB, c = t - (t / CB) * CB;
-      As[r][c] = M[(int64_t)(j0 + r) * LB + k0 + c];
-      Bs[r][c] = mb < jb ? X[(int64_t)(j0 + r) * LB + m0 + c] : X[(int64_t)(j0 + c) * LB + j0 + r];   // E_JJ = S_JJ^T
+    const int k0 = j0 + CB * (1 + kb), m0 = CB * mb;
+    A = M + (int64_t)j0 * LB + k0;
+    if (mb < jb) {
+      B = X + (int64_t)j0 * LB + m0;
+    } else {   // E_JJ(t, b) = S_JJ(b, t)
+      B = X + (int64_t)j0 * LB + j0;
+      sbt = 1;
+      sbb = LB;
     }
     out = X + (int64_t)k0 * LB + m0;
   }
-  __syncthreads();
-  const int a0 = 4 * (tid >> 4), b0 = 4 * (tid & 15);
-  double acc[4][4] = {};
-  tile_tn(As, Bs, a0, b0, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, i = lane & 15;
+  f64x4 acc[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[(int64_t)(a0 + i) * LB + b0 + k] -= acc[i][k];
+    for (int e = 0; e < 4; ++e) acc[tb][e] = out[(int64_t)(16 * w + g + 4 * e) * LB + 16 * tb + i];
+  tile64([&](int t, int a) { return A[(int64_t)t * LB + a]; }, [&](int t, int b) { return B[t * sbt + b * sbb]; },
+         -1.0, acc);
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[(int64_t)(16 * w + g + 4 * e) * LB + 16 * tb + i] = acc[tb][e];
 }
 
 // rinv_p[c*LP + k] = R^-1(k, c) for c, k < l; the identity on the padding.
@@ -158,42 +158,41 @@ __global__ void bc_rinv_out_kernel(const double* __restrict__ X, int LB, int l, 
 __global__ __launch_bounds__(256) void bc_r_out_kernel(const double* __restrict__ M, int LB, int l, int LP,
                                                        const double* __restrict__ r_prev, double* __restrict__ r_out,
                                                        int nbk) {
-  __shared__ double As[CB][CB + 1];
-  __shared__ double Bs[CB][CB + 1];
   const int tid = threadIdx.x;
   int idx = blockIdx.x, ib = 0;
   while (idx >= nbk - ib) { idx -= nbk - ib; ++ib; }
   const int jb = ib + idx;
   const int i0 = ib * CB, j0 = jb * CB;
-  const int a0 = 4 * (tid >> 4), b0 = 4 * (tid & 15);
-  double acc[4][4] = {};
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, li = lane & 15;
+  f64x4 acc[4];
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) acc[tb] = f64x4{0.0, 0.0, 0.0, 0.0};
   if (r_prev) {
+    // sum over K = I .. J of M_IK R_prev_KJ: A(t, a) = M(i0 + a, k0 + t), B(t, b) = R_prev(k0 + t, j0 + b)
     for (int kb = ib; kb <= jb; ++kb) {
-      __syncthreads();
-      for (int t = tid; t < CB * CB; t += 256) {
-        const int r = t / CB, c = t - (t / CB) * CB;
-        const int kk = kb * CB + r, jj = j0 + c;
-        As[c][r] = M[(int64_t)(i0 + r) * LB + kb * CB + c];
-        Bs[r][c] = (kk < l && jj < l) ? r_prev[(int64_t)kk * LP + jj] : 0.0;
-      }
-      __syncthreads();
-      tile_tn(As, Bs, a0, b0, acc);
+      const int k0 = kb * CB;
+      tile64([&](int t, int a) { return M[(int64_t)(i0 + a) * LB + k0 + t]; },
+             [&](int t, int b) {
+               const int kk = k0 + t, jj = j0 + b;
+               return (kk < l && jj < l) ? r_prev[(int64_t)kk * LP + jj] : 0.0;
+             },
+             1.0, acc);
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[i][k] = M[(int64_t)(i0 + a0 + i) * LB + j0 + b0 + k];
+      for (int e = 0; e < 4; ++e) acc[tb][e] = M[(int64_t)(i0 + 16 * w + g + 4 * e) * LB + j0 + 16 * tb + li];
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int tb = 0; tb < 4; ++tb)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int a = i0 + a0 + i, b = j0 + b0 + k;
+    for (int e = 0; e < 4; ++e) {
+      const int a = i0 + 16 * w + g + 4 * e, b = j0 + 16 * tb + li;
       if (a >= LP || b >= LP) continue;
       double v;
       if (a >= l || b >= l) v = (a == b) ? 1.0 : 0.0;
-      else v = (b >= a) ? acc[i][k] : 0.0;
+      else v = (b >= a) ? acc[tb][e] : 0.0;
       r_out[(int64_t)a * LP + b] = v;
     }
   // the strictly lower tiles (I > J) are zero
