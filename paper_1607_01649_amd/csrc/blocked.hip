@@ -25,12 +25,14 @@
 //
 // Jacobi (block one-sided, X = R^T): the columns are split into blocks of W;
 // the blocks are paired by the round-robin (circle) ordering, and one
-// workgroup per pair forms the Gram matrix of the pair's 2W columns, runs one
-// cyclic Jacobi sweep on it (the rotations the columns would take, with the
-// same rotation and test as jacobi.hip), and applies the accumulated
-// rotation to the columns.  A sweep of nbk-1 rounds meets every pair of
-// blocks, hence every pair of columns; sweeps repeat until one passes in
-// which no workgroup rotated.  All sweeps run in one persistent launch
+// workgroup per pair forms the Gram matrix of the pair's 2W columns, runs
+// Jacobi rotations on it (the rotations the columns would take, with the
+// same rotation and test as jacobi.hip) and applies the accumulated rotation
+// to the columns: in the first round of a sweep, where every block sits in
+// one pair, a full cyclic sweep over the 2W columns; in the other rounds only
+// the pairs across the two blocks.  A sweep of nbk-1 rounds thus visits every
+// pair of columns once; sweeps repeat until one passes in which no workgroup
+// rotated.  All sweeps run in one persistent launch
 // (workgroup g takes block pair g of every round, grid barriers between the
 // rounds), which stops by itself after the converged sweep: no host
 // synchronisation, and no launches spent past convergence.
@@ -351,16 +353,21 @@ struct BjShared {
 // One pair step of the block one-sided Jacobi on the NC = 2W columns of block pair `pair` of round `round`:
 //   1. G = X^T X of the pair's columns on the FP64 MFMA (each wave a share of the 16-row slabs, the wave
 //      partials summed in a fixed order through LDS);
-//   2. one cyclic Jacobi sweep on G in LDS (NC - 1 rounds of NC/2 disjoint rotations, circle order): each
-//      rotation is the one the columns themselves would take (G's entries are their inner products; the
-//      same test and rotation as the one-workgroup kernel), computed once per pair and inner round, G is
-//      carried along as J^T G J (2 x 2 blocks, the pair's own block updated exactly), and V = J_1 J_2 ... is
-//      accumulated;
+//   2. inner rounds of NC/2 disjoint rotations on G in LDS (a full cyclic sweep in round 0 of a sweep, the
+//      cross-block pairs in the others; below): each rotation is the one the columns themselves would take
+//      (G's entries are their inner products; the same test and rotation as the one-workgroup kernel),
+//      computed once per pair and inner round, G is carried along as J^T G J (2 x 2 blocks, the pair's own
+//      block updated exactly), and V = J_1 J_2 ... is accumulated;
 //   3. X <- X V on the FP64 MFMA, slab by slab in place, if anything rotated (counted in *rot).
 template <int W>
 __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, int LP, int nbk, int pair, int round,
                                              double tol, double thr2, int* __restrict__ rot, double* lds,
                                              BjShared<W>& sh) {
+  // Inner rounds: in round 0 of a sweep (every block in exactly one pair) a full cyclic sweep over the
+  // 2W columns, NC - 1 rounds in circle order, which also meets every pair inside a block; in the other
+  // rounds only the W x W cross pairs, W rounds of W disjoint pairs (p = k, q = W + (k + ir) mod W).  Each
+  // column pair is thus visited once per sweep.
+  const bool full = round == 0;
   constexpr int NC = 2 * W;                 // columns of the block pair
   constexpr int NT = NC / 16;               // 16-column MFMA tiles (1 or 2)
   constexpr int NTT = NT * (NT + 1) / 2;    // tiles on and above the diagonal of G
@@ -439,8 +446,18 @@ __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, i
   __syncthreads();
 
   // 2. One inner sweep on G.
+  auto pq = [&](int k, int ir, int& p, int& q) {
+    if (full) {
+      p = bj_player(k, ir, NC);
+      q = bj_player(NC - 1 - k, ir, NC);
+    } else {
+      p = k;
+      q = W + ((k + ir) & (W - 1));
+    }
+  };
+  const int nir = full ? NC - 1 : W;
   int cur = 0;
-  for (int ir = 0; ir < NC - 1; ++ir) {
+  for (int ir = 0; ir < nir; ++ir) {
     const double* G = gb + cur * NC * NC;
     double* Gn = gb + (cur ^ 1) * NC * NC;
     // a. the rotation of each disjoint pair of this inner round: rotate when |g_pq| > tol sqrt(g_pp) sqrt(g_qq)
@@ -449,7 +466,8 @@ __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, i
     // (2 g_pq)), x_p' = c x_p - s x_q, x_q' = s x_p + c x_q.  t == 0 (an angle below the double range) means
     // no rotation everywhere below.
     if (tid < NP) {
-      const int p = bj_player(tid, ir, NC), q = bj_player(NC - 1 - tid, ir, NC);
+      int p, q;
+      pq(tid, ir, p, q);
       const double al = G[p * NC + p], be = G[q * NC + q], ga = G[p * NC + q];
       double c = 1.0, s = 0.0, t = 0.0;
       if (al > thr2 && be > thr2 && fabs(ga) > tol * (sqrt(al) * sqrt(be))) {
@@ -473,8 +491,9 @@ __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, i
     // b. G <- J^T G J by 2 x 2 blocks (block (kr, kc) = rows of pair kr, columns of pair kc), V <- V J.
     if (tid < NP * NP) {
       const int kr = tid / NP, kc = tid - (tid / NP) * NP;
-      const int pr = bj_player(kr, ir, NC), qr = bj_player(NC - 1 - kr, ir, NC);
-      const int pc = bj_player(kc, ir, NC), qc = bj_player(NC - 1 - kc, ir, NC);
+      int pr, qr, pc, qc;
+      pq(kr, ir, pr, qr);
+      pq(kc, ir, pc, qc);
       if (kr == kc) {
         const double ar = G[pr * NC + pr], br = G[qr * NC + qr], gr = G[pr * NC + qr];
         const double tr = sh.rt[kr];
@@ -498,7 +517,8 @@ __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, i
       for (int item = tid - 256; item < NC * NP; item += 256) {
         const int i = item / NP, k = item - (item / NP) * NP;
         if (sh.rt[k] != 0.0) {
-          const int p = bj_player(k, ir, NC), q = bj_player(NC - 1 - k, ir, NC);
+          int p, q;
+          pq(k, ir, p, q);
           const double c = sh.rc[k], sn = sh.rs[k];
           const double vp = vm[i * NC + p], vq = vm[i * NC + q];
           vm[i * NC + p] = c * vp - sn * vq;
