@@ -29,7 +29,8 @@ HBM_PEAK_GBS = 8000.0
 ELT_BYTES = {"f32": 4, "f64": 8, "bf16": 2, "fp8": 1}
 # HBM traffic of the dominant product kernel, per launch, from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a
 # plain copy kernel (see traffic_summary); used only while the kernel source is the one the counters were taken on
-TRAFFIC_FILES = {("bf16", "slowdecay_50000x20000"): "profiles/traffic_lp_nn_bf16_slowdecay_50000x20000.md"}
+TRAFFIC_FILES = {("bf16", "slowdecay_50000x20000"): "profiles/traffic_lp_nn_bf16_slowdecay_50000x20000.md",
+                 ("fp8", "expdecay_65536"): "profiles/traffic_lp_nn_fp8_expdecay_65536.md"}
 TRAFFIC_SOURCE = "paper_1607_01649_amd/csrc/lpgemm.hip"
 # time-to-eps target per workload: eps = factor * sigma_{k+1} (spectral norm of the residual)
 EPS_FACTOR = {"slowdecay_50000x20000": 1.15, "expdecay_65536": 1.10, "plain_f64_2000": 1.15}
@@ -56,12 +57,13 @@ def traffic_per_launch(sketch, workload):
     return None
 
 
-def traffic_summary(fetch_dir, write_dir, out_path, calib_bytes, kernel_prefix="rsvd::lp_nn_kernel"):
-    """Summarise two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) into out_path.  Each
-    counter is scaled by calib_bytes / counter of the first dispatch that moves a sizeable share of them:
-    --copy-calibration issues, before anything else, a fill (writes calib_bytes) and an elementwise copy (reads and
-    writes them)."""
+def traffic_summary(fetch_dir, write_dir, calib_bytes, sketch, workload, kernel_prefix="rsvd::lp_nn_kernel"):
+    """Summarise two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of the `sketch` path
+    on `workload` into its file under profiles/.  Each counter is scaled by calib_bytes / counter of the first
+    dispatch that moves a sizeable share of them: --copy-calibration issues, before anything else, a fill (writes
+    calib_bytes) and an elementwise copy (reads and writes them)."""
     import csv
+    from workloads import gen
 
     def load(d, counter):
         path = os.path.join(d, "run_counter_collection.csv")
@@ -85,24 +87,29 @@ def traffic_summary(fetch_dir, write_dir, out_path, calib_bytes, kernel_prefix="
         out[counter] = {"scale": scale, "launches": len(mine), "raw_bytes_per_launch": sum(mine) / len(mine),
                         "bytes_per_launch": scale * sum(mine) / len(mine)}
     tot = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
+    cfg = gen.config(workload)
+    alg = cfg.m * cfg.n * ELT_BYTES[sketch] + (cfg.m + cfg.n) * (cfg.k + cfg.p) * 4
     rec = {"kernel": kernel_prefix, "source_sha256": _sha256(TRAFFIC_SOURCE), "bytes_per_launch": tot,
            "fetch": out["FETCH_SIZE"], "write": out["WRITE_SIZE"], "calibration_copy_bytes": calib_bytes}
-    lines = [f"# HBM traffic of `{kernel_prefix}` (bf16 products), 50000 x 20000 workload", "",
+    run = (f"python -u bench.py --workload {workload} --paths {sketch} --steps 1 --warmup 0 --no-cpu --also '' "
+           f"--copy-calibration {calib_bytes}" + (" --matrix randn" if workload != "slowdecay_50000x20000" else ""))
+    lines = [f"# HBM traffic of `{kernel_prefix}` ({sketch} products), {cfg.m} x {cfg.n} workload ({workload})", "",
              "Two rocprofv3 counter passes over the same bench command (repository root, MI355X), each counter",
              "scaled by what it reads for a plain copy of a known size (an elementwise torch kernel, `--copy-calibration`):",
              "", "    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'lp_nn|Functor' -d gpurun_out/pmc_fetch -o run "
-             "--output-format csv -- python -u bench.py --paths bf16 --steps 1 --warmup 0 --no-cpu --also '' "
-             f"--copy-calibration {calib_bytes}",
+             "--output-format csv -- " + run,
              "    rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'lp_nn|Functor' -d gpurun_out/pmc_write -o run "
-             "--output-format csv -- python -u bench.py --paths bf16 --steps 1 --warmup 0 --no-cpu --also '' "
-             f"--copy-calibration {calib_bytes}",
-             f"    python bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write {calib_bytes}", "",
+             "--output-format csv -- " + run,
+             f"    python bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write {calib_bytes} "
+             f"--traffic-key {sketch}:{workload}", "",
              "| counter | copy scale | launches | bytes per launch (scaled) |", "|---|---|---|---|"]
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         lines.append(f"| {c} | {out[c]['scale']:.4f} | {out[c]['launches']} | {out[c]['bytes_per_launch'] / 1e9:.3f} GB |")
-    lines += ["", f"Total per launch: {tot / 1e9:.3f} GB (algorithmic: 2.031 GB; A in bf16 once, X and the result).",
+    lines += ["", f"Total per launch: {tot / 1e9:.3f} GB (algorithmic: {alg / 1e9:.3f} GB; A in {sketch} once, the "
+              f"FP32 thin operand and result; ratio {tot / alg:.2f}).",
               "bench.py reports it as `roofline.traffic` while the kernel source hash matches.", "",
               "traffic-json: " + json.dumps(rec)]
+    out_path = os.path.join(ROOT, TRAFFIC_FILES[(sketch, workload)])
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines[-6:]))
@@ -449,10 +456,16 @@ def main():
                     help="bytes of one plain device copy issued first (scale of the traffic counters)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "CALIB_BYTES"),
                     help="write the traffic summary of two rocprofv3 --pmc passes to profiles/ and exit")
+    ap.add_argument("--traffic-key", default="bf16:slowdecay_50000x20000",
+                    help="sketch:workload of the traffic summary")
+    ap.add_argument("--matrix", choices=("planted", "randn"), default="planted",
+                    help="randn: a seeded standard normal matrix of the workload's shape instead of its planted "
+                         "spectrum (for counter runs: the product kernels' traffic depends on the shapes only)")
     args = ap.parse_args()
     if args.summarize_traffic:
         fd, wd, cb = args.summarize_traffic
-        traffic_summary(fd, wd, os.path.join(ROOT, TRAFFIC_FILES[("bf16", "slowdecay_50000x20000")]), int(cb))
+        sk, _, wl = args.traffic_key.partition(":")
+        traffic_summary(fd, wd, int(cb), sk, wl)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -473,8 +486,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     cfg = gen.config(args.workload)
-    A = cfg.matrix(seed=args.seed, device=str(dev))
-    A = A.to(torch.float32) if cfg.dtype == "f32" else A
+    if args.matrix == "randn":
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed)
+        A = torch.randn(cfg.m, cfg.n, generator=g, device=dev,
+                        dtype=torch.float32 if cfg.dtype == "f32" else torch.float64)
+    else:
+        A = cfg.matrix(seed=args.seed, device=str(dev))
+        A = A.to(torch.float32) if cfg.dtype == "f32" else A
     torch.cuda.synchronize()
     paths = [p for p in args.paths.split(",") if p]
     res = {}
@@ -509,7 +528,7 @@ def main():
                     res[pth]["vs_fp64_oracle"] = vs_oracle(ref, res[pth]["_S"], res[pth]["_U"])
                 elif pth.endswith("+srht"):
                     res[pth]["vs_fp64_oracle_gaussian_omega"] = vs_oracle(ref, res[pth]["_S"], res[pth]["_U"])
-    if cfg.noise_std == 0.0:
+    if cfg.noise_std == 0.0 and args.matrix == "planted":
         for pth in paths:
             res[pth]["vs_planted_sigma"] = vs_planted(cfg.sigma(), res[pth]["_S"])
     for pth in paths:
