@@ -208,10 +208,12 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  *   probability P >= tau, the one of least expected time c(p, q) (2 - P) (a
  *   miss is taken to double the time through the fallback); if none, the
  *   most probable one.  Modelled time (ms) at l = k + p:
- *     c = 0.4 + (2q+2) 2 m n l / 6e10 + (2q+1) 0.3 max(l/128, 1)^1.5
- *         + 2.5 (l/95)^1.5
- *   (passes over A, CholeskyQR passes and the Stage B Jacobi, fitted to
- *   measured MI355X timings).
+ *     c = 0.081 + (2q+2) 2 m n l 20.9e-12 + (2q+1) 0.104 max(l/128, 1)^1.5
+ *         + 1.08 (l/95)^1.5
+ *   (passes over A, CholeskyQR passes and the Stage B Jacobi, fitted by
+ *   non-negative least squares to 120 measured MI355X timings of the plain
+ *   method on items of the selector's training distribution; median relative
+ *   error 9 %).
  */
 #define RSVD_MLP_IN 16
 #define RSVD_MLP_HIDDEN 64

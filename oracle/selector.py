@@ -57,11 +57,11 @@ def features(sig16: np.ndarray, k: int) -> np.ndarray:
 
 def cost_ms(m: int, n: int, k: int, p: int, q: int) -> float:
     """Modelled time (ms) of the plain method at (p, q) on one MI355X: a
-    fixed part, 2q+2 passes over A at 60 TFLOP/s, 2q+1 CholeskyQR passes and
-    the Stage B Jacobi, fitted to measured timings."""
+    fixed part, 2q+2 passes over A at an effective 48 TFLOP/s, 2q+1
+    CholeskyQR passes and the Stage B Jacobi, fitted to measured timings."""
     l = min(k + p, m, n)
-    return (0.4 + (2 * q + 2) * 2.0 * m * n * l / 6.0e10 + (2 * q + 1) * 0.3 * max(l / 128.0, 1.0) ** 1.5
-            + 2.5 * (l / 95.0) ** 1.5)
+    return (0.081 + (2 * q + 2) * 2.0 * m * n * l * 20.9e-12 + (2 * q + 1) * 0.104 * max(l / 128.0, 1.0) ** 1.5
+            + 1.08 * (l / 95.0) ** 1.5)
 
 
 def grid_points(m: int, n: int, k: int):

@@ -514,28 +514,19 @@ hipError_t launch_reduce(const TP* part, int S, int64_t pstride, int64_t ldp, in
   return hipGetLastError();
 }
 
-// Two-level fixed-order sum for many partials: groups of `group` partials are
-// summed into `tmp` (ceil(S/group) partials with the same stride), then those.
+// Fixed-order sum of many partials: up to 2 group partials in one pass of reduce_kernel, more in one launch of
+// reduce_tree_kernel (16 groups per entry; 196 partials of a 110 x 110 Gram: 5.7 us against two launches of
+// 6.6 us for a two-level sum through tmp, which is no longer used).
 template <typename TP>
 hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int64_t ldp, int64_t rows, int ncols,
                           TP* tmp, TP* out, int64_t ldo, hipStream_t s) {
+  (void)tmp;
   if (S <= 2 * group) return launch_reduce<TP, TP>(part, S, pstride, ldp, rows, ncols, out, ldo, s);
-  // more than 128 partials (a long panel's Gram, l <= 128): one launch, 16 groups per entry (196 partials of a
-  // 110 x 110 Gram: 5.7 us against two launches of 6.6 us)
-  if (S > 128) {
-    const int64_t n = rows * ncols;
-    hipLaunchKernelGGL((reduce_tree_kernel<TP>), dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, s, part, S,
-                       pstride, ldp, rows, ncols, out, ldo);
-    return hipGetLastError();
-  }
-  int64_t work = ((rows + 3) / 4) * ncols;
-  if (work <= 0) return hipSuccess;
-  int ng = (S + group - 1) / group;
-  hipLaunchKernelGGL((reduce_kernel<TP, TP>), dim3((unsigned)((work + 255) / 256), (unsigned)ng), dim3(256), 0, s,
-                     part, group, S, pstride, ldp, rows, ncols, tmp, ldp, pstride);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_reduce<TP, TP>(tmp, ng, pstride, ldp, rows, ncols, out, ldo, s);
+  const int64_t n = rows * ncols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((reduce_tree_kernel<TP>), dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, s, part, S, pstride,
+                     ldp, rows, ncols, out, ldo);
+  return hipGetLastError();
 }
 
 // out = A P for an upper-triangular P (the apply X <- X R^-1 of CholeskyQR): the triangular short-contraction

@@ -1279,10 +1279,10 @@ namespace {
 // Modelled time (ms) of the plain method at (p, q); see include/rsvd.h.
 double sel_cost_ms(int64_t m, int64_t n, int k, int p, int q) {
   const double l = (double)std::min<int64_t>({(int64_t)k + p, m, n});
-  const double passes = (2.0 * q + 2.0) * 2.0 * (double)m * (double)n * l / 6.0e10;
-  const double orth = (2.0 * q + 1.0) * 0.3 * pow(std::max(l / 128.0, 1.0), 1.5);
-  const double jac = 2.5 * pow(l / 95.0, 1.5);
-  return 0.4 + passes + orth + jac;
+  const double passes = (2.0 * q + 2.0) * 2.0 * (double)m * (double)n * l * 20.9e-12;
+  const double orth = (2.0 * q + 1.0) * 0.104 * pow(std::max(l / 128.0, 1.0), 1.5);
+  const double jac = 1.08 * pow(l / 95.0, 1.5);
+  return 0.081 + passes + orth + jac;
 }
 
 // Grid point of least expected time cost * (2 - prob) among those with prob >= tau (a miss is taken to

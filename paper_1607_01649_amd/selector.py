@@ -39,7 +39,7 @@ from . import (RSVD, RSVD_MLP_NPARAM, RSVD_RETURN_RANK_L, RSVD_SEL_NQ, RSVD_SEL_
 from . import _aligned_workspace
 
 EPS = 1e-3                 # relative spectral tolerance of the stream
-SEED_TRAIN, SEED_TEST = 1, 2
+SEED_TRAIN, SEED_TEST, SEED_COST = 1, 2, 3
 N_OUT = 40
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.npy")
 # training record next to the weights: threshold tau chosen on the validation items, data sizes, accuracy
@@ -78,11 +78,20 @@ def grid(m: int, n: int, k: int):
             if k + p <= cap]
 
 
+# Coefficients of the modelled time (ms), fitted by `costfit` to measured plain-method times (eps = 0) on
+# items of the stream: fixed part, ms per TFLOP of the 2q+2 passes, per CholeskyQR, per Jacobi unit.
+COST_COEF = (0.081, 20.9, 0.104, 1.08)
+
+
+def cost_terms(m, n, k, p, q):
+    """The four terms of the modelled time (their coefficients in COST_COEF)."""
+    l = min(k + p, m, n)
+    return (1.0, (2 * q + 2) * 2.0 * m * n * l / 1e12, (2 * q + 1) * max(l / 128.0, 1.0) ** 1.5, (l / 95.0) ** 1.5)
+
+
 def cost_ms(m, n, k, p, q) -> float:
     """The library's modelled time of (p, q) (include/rsvd.h)."""
-    l = min(k + p, m, n)
-    return (0.4 + (2 * q + 2) * 2.0 * m * n * l / 6.0e10 + (2 * q + 1) * 0.3 * max(l / 128.0, 1.0) ** 1.5
-            + 2.5 * (l / 95.0) ** 1.5)
+    return float(sum(c * t for c, t in zip(COST_COEF, cost_terms(m, n, k, p, q))))
 
 
 def _plan(m, n, k, p, q, device, **kw):
@@ -287,12 +296,66 @@ def summarize(rows):
                      "certified": float(np.mean([r[name]["status"] == 0 for r in rows])),
                      "no_fallback": float(np.mean([r[name]["steps"] == 0 and r[name]["status"] == 0
                                                    for r in rows]))}
+    for name in out:
+        if name == "default":
+            continue
+        d = np.array([r[name]["ms"] - r["default"]["ms"] for r in rows])
+        half = 1.96 * float(np.std(d, ddof=1)) * math.sqrt(len(d)) if len(d) > 1 else float("nan")
+        out[name]["vs_default_total_ms"] = {"diff": float(np.sum(d)), "ci95_half_width": half}
     return out
+
+
+def costfit(seed: int, items: int, device, per_item: int = 3, log=None):
+    """Times the plain method (eps = 0: no certificate, no fallback) at per_item random grid points of each of
+    `items` stream items (one warm-up call, then the median of three), and fits the coefficients of the
+    modelled time by non-negative least squares on the relative error."""
+    from scipy.optimize import nnls
+    from workloads import gen
+    g = np.random.default_rng(seed)
+    rows = []
+    for i in range(items):
+        A, k = gen.selector_matrix(seed, i, str(device))
+        m, n = A.shape
+        if k > selector_grid_cap(m, n):
+            continue
+        pts = grid(m, n, k)
+        for j in g.choice(len(pts), size=min(per_item, len(pts)), replace=False):
+            _, p, q = pts[j]
+            sol = RSVD(m, n, k, p, q, dtype="f32", device=device, seed=seed)
+            _timed(sol, A)
+            ms = float(np.median([_timed(sol, A)[0] for _ in range(3)]))
+            rows.append({"item": i, "m": m, "n": n, "k": k, "p": p, "q": q, "ms": ms})
+            del sol
+        del A
+        if log and (i + 1) % 10 == 0:
+            log(f"costfit items {i + 1}/{items}")
+    T = np.array([cost_terms(r["m"], r["n"], r["k"], r["p"], r["q"]) for r in rows])
+    t = np.array([r["ms"] for r in rows])
+    coef, _ = nnls(T / t[:, None], np.ones(len(t)))
+    old = np.array([sum(c * x for c, x in zip(COST_COEF, row)) for row in T])
+    new = T @ coef
+    return {"coef": coef.tolist(), "points": len(rows),
+            "rel_err_old": {"median": float(np.median(np.abs(old / t - 1))), "max": float(np.max(np.abs(old / t - 1)))},
+            "rel_err_new": {"median": float(np.median(np.abs(new / t - 1))), "max": float(np.max(np.abs(new / t - 1)))},
+            "rows": rows}
+
+
+def retune(theta: np.ndarray, val: int, start: int, device, log=None):
+    """The threshold tau of least modelled time on labelled validation items of the training stream (items
+    start .. start+val-1), under the current cost model."""
+    Xv, Yv, Mv, metav = make_dataset(SEED_TRAIN, val, device, log, start=start)
+    tr = Trainer(theta, device)
+    Zv = tr.forward(torch.from_numpy(Xv).to(torch.device(device))).cpu().numpy()
+    pv = 1.0 / (1.0 + np.exp(-Zv))
+    taus = [0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8]
+    sim = {t: simulated_time(pv, Yv, Mv, metav, t) for t in taus}
+    return min(sim, key=sim.get), sim, len(Xv)
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("cmd", choices=["train", "eval", "costfit", "retune"])
+    ap.add_argument("--start", type=int, default=0, help="first item of the stream (eval, retune)")
     ap.add_argument("--items", type=int, default=1500)
     ap.add_argument("--val", type=int, default=150)
     ap.add_argument("--epochs", type=int, default=400)
@@ -328,10 +391,25 @@ def main(argv=None):
         log(json.dumps(res))
         if args.json:
             json.dump({"summary": res, "loss": hist}, open(args.json, "w"))
+    elif args.cmd == "costfit":
+        res = costfit(SEED_COST, args.items, dev, log=log)
+        log(json.dumps({k: v for k, v in res.items() if k != "rows"}))
+        if args.json:
+            json.dump(res, open(args.json, "w"))
+    elif args.cmd == "retune":
+        th, _ = load_weights(args.weights)
+        tau, sim, nval = retune(th, args.val, args.start, dev, log)
+        meta_path = args.weights[:-4] + ".json"
+        meta = json.load(open(meta_path)) if os.path.exists(meta_path) else {}
+        meta.update({"tau": tau, "val_modelled_ms": {str(t): v for t, v in sim.items()}, "val_items": nval,
+                     "cost_coef": list(COST_COEF)})
+        json.dump(meta, open(args.out[:-4] + ".json", "w"), indent=1)
+        log(json.dumps({"tau": tau, "val_modelled_ms": sim, "val_items": nval}))
     else:
         th, tau = load_weights(args.weights)
         theta = torch.from_numpy(th).to(dev)
-        rows = evaluate(theta, SEED_TEST, args.items, dev, tau if args.tau is None else args.tau, log=log)
+        rows = evaluate(theta, SEED_TEST, args.items, dev, tau if args.tau is None else args.tau, start=args.start,
+                        log=log)
         summ = summarize(rows)
         log(json.dumps(summ))
         if args.json:
