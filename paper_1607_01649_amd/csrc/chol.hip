@@ -241,8 +241,15 @@ __global__ __launch_bounds__(kCholThreads) void chol_blk_kernel(const double* __
                                                                  int LP, double tau_rel, TQ* __restrict__ rinv_p,
                                                                  double* __restrict__ r_out,
                                                                  const double* __restrict__ r_prev,
-                                                                 int* __restrict__ flags) {
+                                                                 int* __restrict__ flags,
+                                                                 const int* __restrict__ skip_in,
+                                                                 int* __restrict__ skip_out, double kappa2_max) {
   extern __shared__ __align__(16) double chol_lds[];
+  if (skip_in && *skip_in) {   // a skipped second CholeskyQR pass: R^-1 = I (uniform: every thread reads the flag)
+    for (int e = threadIdx.x; e < LP * LP; e += kCholThreads)
+      rinv_p[e] = static_cast<TQ>((e / LP) == (e - (e / LP) * LP) ? 1.0 : 0.0);
+    return;
+  }
   const int MP = LP + 1;
   const int nb = LP / kCholB;
   double* M = chol_lds;                    // LP x MP
@@ -287,6 +294,31 @@ __global__ __launch_bounds__(kCholThreads) void chol_blk_kernel(const double* __
   if (wv == 0 && lane == 0) {
     if (bad) atomicAdd(&flags[0], bad);
     if (dropped) atomicAdd(&flags[1], dropped);
+  }
+  if (skip_out) {
+    // Condition bound of the panel X with columns scaled to unit norm (S = diag(G_jj)^-1/2): kappa_2(X S) <=
+    // ||R S||_F ||S^-1 R^-1||_F, with ||R S||_F^2 = l (column j of R has squared norm G_jj) and
+    // ||S^-1 R^-1||_F^2 = sum_i G_ii ||column i of R^-T||^2.  One pass of CholeskyQR then leaves X R^-1
+    // orthonormal to about kappa^2 u (the FP64 Gram) plus kappa times the panel's rounding.
+    __shared__ double kpart[kCholWaves];
+    double f = 0.0;
+    for (int i = tid; i < l; i += kCholThreads) {
+      const int bi = i >> 4;
+      double cs = 0.0;
+      for (int c = i; c < l; ++c) {
+        const double v = (c >> 4) == bi ? Wd[bi * kCholB * kWdPitch + (c & 15) * kWdPitch + (i & 15)] : M[c * MP + i];
+        cs = fma(v, v, cs);
+      }
+      f = fma(gdiag[i], cs, f);
+    }
+    f = wave_sum(f);
+    if (lane == 0) kpart[wv] = f;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kCholWaves; ++w) t += kpart[w];
+      *skip_out = (bad == 0 && dropped == 0 && (double)l * t <= kappa2_max) ? 1 : 0;
+    }
   }
   // R^-1 in panel layout: rinv_p[c*LP + k] = R^-T(c, k); identity on padding.  A thread writes four
   // consecutive entries (one block).
@@ -399,8 +431,15 @@ hipError_t launch_chol_diag64(double* M, int LB, int j0, int l, const double* gd
 
 template <typename TQ>
 hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_rel, TQ* rinv_p, double* r_out,
-                       const double* r_prev, double* scratch, int* flags, hipStream_t s) {
+                       const double* r_prev, double* scratch, int* flags, hipStream_t s, int* skip_out,
+                       double kappa_max, const int* skip_in) {
   if (l < 1 || l > 1024) return hipErrorInvalidValue;
+  if (skip_in && (LP > 128 || r_out)) return hipErrorInvalidValue;   // a skippable pass: l <= 128, only R^-1
+  if (LP > 128 && skip_out) {
+    hipError_t e = launch_fill_int(skip_out, 1, 0, s);   // the blocked form gives no bound: never skip
+    if (e != hipSuccess) return e;
+    skip_out = nullptr;
+  }
   if (LP <= 128) {
     if (LP % kCholB != 0) return hipErrorInvalidValue;
     static bool attr_set = false;
@@ -413,7 +452,7 @@ hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_r
     }
     const size_t sh = ((size_t)LP * (LP + 1) + (size_t)(LP / kCholB) * kCholB * kWdPitch) * sizeof(double);
     hipLaunchKernelGGL((chol_blk_kernel<TQ>), dim3(1), dim3(kCholThreads), sh, s, g, ldg, l, LP, tau_rel, rinv_p,
-                       r_out, r_prev, flags);
+                       r_out, r_prev, flags, skip_in, skip_out, kappa_max * kappa_max);
   } else {
     if (!scratch) return hipErrorInvalidValue;
     return launch_chol_blocked<TQ>(g, ldg, l, LP, tau_rel, rinv_p, r_out, r_prev, scratch, flags, s);
@@ -422,8 +461,8 @@ hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_r
 }
 
 template hipError_t launch_chol<float>(const double*, int64_t, int, int, double, float*, double*, const double*,
-                                       double*, int*, hipStream_t);
+                                       double*, int*, hipStream_t, int*, double, const int*);
 template hipError_t launch_chol<double>(const double*, int64_t, int, int, double, double*, double*, const double*,
-                                        double*, int*, hipStream_t);
+                                        double*, int*, hipStream_t, int*, double, const int*);
 
 }  // namespace rsvd

@@ -204,7 +204,8 @@ __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64
 template <typename TP, typename TO>
 __global__ __launch_bounds__(256) void reduce_kernel(const TP* __restrict__ part, int S, int Stot, int64_t pstride,
                                                      int64_t ldp, int64_t rows, int ncols, TO* __restrict__ out,
-                                                     int64_t ldo, int64_t ostride) {
+                                                     int64_t ldo, int64_t ostride, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   int64_t nq = (rows + 3) / 4;
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= nq * ncols) return;
@@ -243,7 +244,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const TP* __restrict__ part
 template <typename TP>
 __global__ __launch_bounds__(1024) void reduce_tree_kernel(const TP* __restrict__ part, int S, int64_t pstride,
                                                            int64_t ldp, int64_t rows, int ncols,
-                                                           TP* __restrict__ out, int64_t ldo) {
+                                                           TP* __restrict__ out, int64_t ldo,
+                                                           const int* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ TP red[16][64];
   const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int64_t n = rows * ncols;
@@ -506,11 +509,11 @@ hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P
 
 template <typename TP, typename TO>
 hipError_t launch_reduce(const TP* part, int S, int64_t pstride, int64_t ldp, int64_t rows, int ncols, TO* out,
-                         int64_t ldo, hipStream_t s) {
+                         int64_t ldo, hipStream_t s, const int* skip) {
   int64_t work = ((rows + 3) / 4) * ncols;
   if (work <= 0) return hipSuccess;
   hipLaunchKernelGGL((reduce_kernel<TP, TO>), dim3((unsigned)((work + 255) / 256), 1), dim3(256), 0, s, part, S, S,
-                     pstride, ldp, rows, ncols, out, ldo, (int64_t)0);
+                     pstride, ldp, rows, ncols, out, ldo, (int64_t)0, skip);
   return hipGetLastError();
 }
 
@@ -519,13 +522,13 @@ hipError_t launch_reduce(const TP* part, int S, int64_t pstride, int64_t ldp, in
 // 6.6 us for a two-level sum through tmp, which is no longer used).
 template <typename TP>
 hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int64_t ldp, int64_t rows, int ncols,
-                          TP* tmp, TP* out, int64_t ldo, hipStream_t s) {
+                          TP* tmp, TP* out, int64_t ldo, hipStream_t s, const int* skip) {
   (void)tmp;
-  if (S <= 2 * group) return launch_reduce<TP, TP>(part, S, pstride, ldp, rows, ncols, out, ldo, s);
+  if (S <= 2 * group) return launch_reduce<TP, TP>(part, S, pstride, ldp, rows, ncols, out, ldo, s, skip);
   const int64_t n = rows * ncols;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL((reduce_tree_kernel<TP>), dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, s, part, S, pstride,
-                     ldp, rows, ncols, out, ldo);
+                     ldp, rows, ncols, out, ldo, skip);
   return hipGetLastError();
 }
 
@@ -570,10 +573,10 @@ template hipError_t launch_tn<float, double, double, double>(const float*, int64
                                                              const double*, int64_t, int, double*, int64_t,
                                                              int64_t, int, bool, hipStream_t);
 template hipError_t launch_reduce<float, float>(const float*, int, int64_t, int64_t, int64_t, int, float*, int64_t,
-                                                hipStream_t);
+                                                hipStream_t, const int*);
 template hipError_t launch_reduce<double, double>(const double*, int, int64_t, int64_t, int64_t, int, double*,
-                                                  int64_t, hipStream_t);
+                                                  int64_t, hipStream_t, const int*);
 template hipError_t launch_reduce2<double>(const double*, int, int, int64_t, int64_t, int64_t, int, double*, double*,
-                                           int64_t, hipStream_t);
+                                           int64_t, hipStream_t, const int*);
 
 }  // namespace rsvd

@@ -220,7 +220,8 @@ __global__ __launch_bounds__(256) void gram_kernel(const TI* __restrict__ Y, int
 template <typename TI, int NCB>
 __global__ __launch_bounds__(256) void gram_sym_kernel(const TI* __restrict__ Y, int64_t ld, int64_t K, int nc,
                                                        double* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                       int64_t kchunk) {
+                                                       int64_t kchunk, const int* __restrict__ skip) {
+  if (skip && *skip) return;   // a skipped second CholeskyQR pass (uniform: every thread reads the flag)
   typedef GramFmt<TI> F;
   typedef typename F::V V;
   constexpr int KC = F::KC;
@@ -341,8 +342,9 @@ __global__ __launch_bounds__(256) void gram_sym_kernel(const TI* __restrict__ Y,
 // a count normalised by nn_splits_used (ranges in multiples of 64 rows), so exactly `splits` partials are written.
 template <typename TI>
 hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, int64_t ldo, int64_t part_stride,
-                       int splits, hipStream_t s) {
+                       int splits, hipStream_t s, const int* skip) {
   if (nc <= 0 || K <= 0) return hipSuccess;
+  if (skip && nc > 128) return hipErrorInvalidValue;   // the skip serves the one-tile (l <= 128) form only
   if (ld < K || (ld % 64) != 0 || (reinterpret_cast<uintptr_t>(Y) & 15) != 0) return hipErrorInvalidValue;
   if (splits < 1) splits = 1;
   int64_t kchunk = ((K + splits - 1) / splits + 63) / 64 * 64;
@@ -361,7 +363,8 @@ hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, 
   if (ntile == 1) {
 #define RSVD_GRAM_SYM_CASE(N)                                                                                    \
   case N:                                                                                                      \
-    hipLaunchKernelGGL((gram_sym_kernel<TI, N>), grid, dim3(256), 0, s, Y, ld, K, nc, out, ldo, part_stride, kchunk); \
+    hipLaunchKernelGGL((gram_sym_kernel<TI, N>), grid, dim3(256), 0, s, Y, ld, K, nc, out, ldo, part_stride, kchunk, \
+                       skip);                                                                                     \
     break;
     switch (ncb) {
       RSVD_GRAM_SYM_CASE(1)
@@ -396,8 +399,8 @@ int gram_tile_pairs(int nc) {
 }
 
 template hipError_t launch_gram<float>(const float*, int64_t, int64_t, int, double*, int64_t, int64_t, int,
-                                       hipStream_t);
+                                       hipStream_t, const int*);
 template hipError_t launch_gram<double>(const double*, int64_t, int64_t, int, double*, int64_t, int64_t, int,
-                                        hipStream_t);
+                                        hipStream_t, const int*);
 
 }  // namespace rsvd

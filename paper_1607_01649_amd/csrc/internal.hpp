@@ -33,15 +33,18 @@ hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P
 int nn_splits_used(int64_t K, int splits);
 template <typename TP, typename TO>
 hipError_t launch_reduce(const TP* part, int S, int64_t pstride, int64_t ldp, int64_t rows, int ncols, TO* out,
-                         int64_t ldo, hipStream_t s);
+                         int64_t ldo, hipStream_t s, const int* skip = nullptr);
 template <typename TP>
 hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int64_t ldp, int64_t rows, int ncols,
-                          TP* tmp, TP* out, int64_t ldo, hipStream_t s);
+                          TP* tmp, TP* out, int64_t ldo, hipStream_t s, const int* skip = nullptr);
 
-// chol.hip
+// chol.hip.  skip_out (optional, l <= 128 only; written 0 otherwise): 1 when the factor shows the panel well
+// enough conditioned that one CholeskyQR pass suffices (scaled Frobenius condition bound at most kappa_max);
+// skip_in (optional): when *skip_in is set the call only writes R^-1 = I (a skipped second pass).
 template <typename TQ>
 hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_rel, TQ* rinv_p, double* r_out,
-                       const double* r_prev, double* scratch, int* flags, hipStream_t s);
+                       const double* r_prev, double* scratch, int* flags, hipStream_t s, int* skip_out = nullptr,
+                       double kappa_max = 0.0, const int* skip_in = nullptr);
 
 // blocked.hip -- the same factorisations for l > 128, spread over many workgroups.
 size_t chol_blocked_scratch_doubles(int LP);
@@ -75,7 +78,7 @@ hipError_t launch_to_fp8_tiled(const float* A, int64_t lda, int64_t m, int64_t n
 int gram_tile_pairs(int nc);
 template <typename TI>
 hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, int64_t ldo, int64_t part_stride,
-                       int splits, hipStream_t s);
+                       int splits, hipStream_t s, const int* skip = nullptr);
 // `scratch` (lp_scratch_bytes); output as launch_nn (split-K partials).
 size_t lp_scratch_bytes(int kind, int64_t K, int ncols);
 int lp_splits_used(int64_t K, int splits);

@@ -18,6 +18,10 @@ using namespace rsvd;
 namespace {
 
 constexpr int kRedGroup = 16;   // partials summed per first-level reduction group
+constexpr int kSkipFlag = 16;   // flags word: the current orthonormalisation may skip its second pass
+// Column-scaled condition bound below which an intermediate basis takes one CholeskyQR pass: orthogonal to
+// about 1e6 u in FP64 and 1e3 u in the FP32 panel product, ample for a basis that is multiplied again.
+constexpr double kOrthSkipKappa = 1e3;
 // device status words: [0] non-finite pivot, [1] dropped columns, [2] Jacobi
 // not converged, [3] Jacobi sweeps, [4] non-finite entry of A (conversion),
 // [8] and [9] non-finite and dropped pivots of the Nystrom core factor B2 = C^T C
@@ -338,12 +342,13 @@ template <typename T> struct Path {
   void gemm_end(int i) { if (i >= 0) (void)hipEventRecord(P.gev[2 * i + 1], st); }
 
   // G (nc x nc, column-major, ld lp16(nc)) = X^T X for a nc-column panel X with `rows` rows, FP64 accumulation.
-  rsvd_status gram(const T* X, int64_t ldx, int64_t rows, int nc, int splits, double* G) {
+  // With `skip`, both launches return at once when *skip is set (a skipped second CholeskyQR pass).
+  rsvd_status gram(const T* X, int64_t ldx, int64_t rows, int nc, int splits, double* G, const int* skip = nullptr) {
     const int LPc = lp16(nc);
     double* gp = P.at<double>(L.gpart);
-    HIP_TRY(launch_gram<T>(X, ldx, rows, nc, gp, LPc, (int64_t)LPc * LPc, splits, st));
+    HIP_TRY(launch_gram<T>(X, ldx, rows, nc, gp, LPc, (int64_t)LPc * LPc, splits, st, skip));
     HIP_TRY(launch_reduce2<double>(gp, splits, kRedGroup, (int64_t)LPc * LPc, LPc, nc, nc, P.at<double>(L.gpart2), G,
-                                   LPc, st));
+                                   LPc, st, skip));
     return RSVD_OK;
   }
 
@@ -353,18 +358,23 @@ template <typename T> struct Path {
   }
 
   // out = orth(X) for an nc-column panel: CholeskyQR2 (two passes of G = X^T X = R^T R, X <- X R^-1).
-  rsvd_status orth(const T* X, int64_t ld, int64_t rows, int nc, int splits, T* out) {
+  // may_skip (a basis that is multiplied again, not the one Stage B uses; nc <= 128): the second pass is
+  // skipped on the device when the first pass's factor bounds the column-scaled condition number of X by
+  // kOrthSkipKappa (its Gram, sum and Cholesky return at once, the apply multiplies by I), since one pass
+  // then leaves a basis orthonormal to about kappa^2 u plus kappa times the panel's rounding.
+  rsvd_status orth(const T* X, int64_t ld, int64_t rows, int nc, int splits, T* out, bool may_skip = false) {
     const int LPc = lp16(nc);
     double* G = P.at<double>(L.G);
     T* rinv = P.at<T>(L.rinv);
     T* tmp = P.at<T>(L.T);
     int* flags = P.at<int>(L.flags);
     double* scr = P.at<double>(L.scr_chol);
+    int* skip = (may_skip && LPc <= 128) ? flags + kSkipFlag : nullptr;
     RS_TRY(gram(X, ld, rows, nc, splits, G));
-    HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st));
+    HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st, skip, kOrthSkipKappa));
     HIP_TRY(apply_rinv(X, ld, rows, nc, rinv, LPc, tmp));
-    RS_TRY(gram(tmp, ld, rows, nc, splits, G));
-    HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st));
+    RS_TRY(gram(tmp, ld, rows, nc, splits, G, skip));
+    HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st, nullptr, 0.0, skip));
     HIP_TRY(apply_rinv(tmp, ld, rows, nc, rinv, LPc, out));
     return RSVD_OK;
   }
@@ -597,15 +607,16 @@ template <typename T> struct Path {
         HIP_TRY(launch_gaussian<T>(P.d.seed, 4u, n, l, 0, omega, 1, L.ldn, st));
       RS_TRY(apply_a(A, lda, omega, l, Y, sk));
     }
-    // (2): Q = orth(A Omega).
-    RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q));
+    // (2): Q = orth(A Omega).  Every basis but the last is multiplied again (the second CholeskyQR pass may
+    // be skipped there).
+    RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q, P.d.q > 0));
     mark(1);
     // (3)-(6): q power steps with re-orthonormalisation.
     for (int it = 0; it < P.d.q; ++it) {
       RS_TRY(apply_at(A, lda, Q, l, Z, sk));
-      RS_TRY(orth(Z, L.ldn, n, l, L.s_gn, Wp));
+      RS_TRY(orth(Z, L.ldn, n, l, L.s_gn, Wp, true));
       RS_TRY(apply_a(A, lda, Wp, l, Y, sk));
-      RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q));
+      RS_TRY(orth(Y, L.ldm, m, l, L.s_gm, Q, it + 1 < P.d.q));
     }
     mark(2);
     return RSVD_OK;
