@@ -51,6 +51,123 @@ __device__ __forceinline__ void stage_panel(V4<TC>* ps, const TP* __restrict__ P
   }
 }
 
+// The two halves of stage_panel: this thread's NB values of the chunk into registers, and from there into LDS.
+template <int NB, typename TP>
+__device__ __forceinline__ void panel_load(V4<TP> (&v)[NB], const TP* __restrict__ P, int64_t ldp, int cg0, int ncols,
+                                           int64_t k0, int64_t kend) {
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    int it = threadIdx.x + 256 * u;
+    int cl = it >> 4, jq = it & 15;
+    int c = cg0 + cl;
+    v[u] = (c < ncols) ? load4_guarded<true>(P, ldp, (int64_t)c, k0 + 4 * jq, (int64_t)ncols, kend) : v4_zero<TP>();
+  }
+}
+template <int NB, typename TP, typename TC>
+__device__ __forceinline__ void panel_store(V4<TC>* ps, const V4<TP> (&v)[NB]) {
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    int it = threadIdx.x + 256 * u;
+    int cl = it >> 4, jq = it & 15;
+    int cb = cl >> 4, cli = cl & 15, kq = jq >> 2, g = jq & 3;
+    ps[(cb * 4 + kq) * 64 + cli + 16 * g] = v4_cast<TC>(v[u]);
+  }
+}
+
+// out[split][c][r] = sum_{j in split} A[r][j] * X(j, c)      (X in panel layout: X[c*ldx + j]), FP32 operands:
+// software-pipelined, the next chunk's A values and panel values are loaded into registers while the current
+// chunk is multiplied, the panel going to the spare of two LDS buffers (one barrier per chunk).
+template <typename TX, typename TO, int NB, bool VEC>
+__global__ __launch_bounds__(256) void nn_pipe_kernel(const float* __restrict__ A, int64_t lda, int64_t rows,
+                                                      int64_t K, const TX* __restrict__ X, int64_t ldx, int ncols,
+                                                      TO* __restrict__ out, int64_t ldo, int64_t part_stride,
+                                                      int64_t kchunk) {
+  __shared__ V4<float> xs[2][NB * 4 * 64];
+  typedef Mma<float> M;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t rbase = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int split = blockIdx.y;
+  const int cg0 = blockIdx.z * NB * 16;
+  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kend = min(K, kbeg + kchunk);
+
+  typename M::acc acc[2][NB];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = M::zero();
+
+  V4<float> a[2][4];
+  V4<TX> xr[NB];
+  auto load_a = [&](V4<float> (&dst)[2][4], int64_t k0) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq)
+        dst[rb][kq] = load4_guarded<VEC>(A, lda, rbase + 16 * rb + M::arow(li), k0 + 16 * kq + 4 * g, rows, kend);
+  };
+  if (kbeg < kend) {
+    load_a(a, kbeg);
+    panel_load<NB>(xr, X, ldx, cg0, ncols, kbeg, kend);
+    panel_store<NB, TX, float>(xs[0], xr);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+    const bool more = k0 + KC < kend;   // uniform
+    V4<float> an[2][4];
+    if (more) {
+      load_a(an, k0 + KC);
+      panel_load<NB>(xr, X, ldx, cg0, ncols, k0 + KC, kend);
+    }
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      V4<float> b[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) b[cb] = xs[cur][(cb * 4 + kq) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          const float av = a[rb][kq].x[t];
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) acc[rb][cb] = M::op(av, b[cb].x[t], acc[rb][cb]);
+        }
+    }
+    if (more) panel_store<NB, TX, float>(xs[cur ^ 1], xr);
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) a[rb][kq] = an[rb][kq];
+    }
+    cur ^= 1;
+  }
+
+  TO* o = out + (int64_t)split * part_stride;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      int c = cg0 + cb * 16 + li;
+      if (c >= ncols) continue;
+      int64_t r = rbase + rb * 16 + 4 * g;
+      TO* p = o + (int64_t)c * ldo + r;
+      if (r + 4 <= rows) {
+        V4<TO> v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v.x[e] = static_cast<TO>(acc[rb][cb][e]);
+        v4_store(p, v);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (r + e < rows) p[e] = static_cast<TO>(acc[rb][cb][e]);
+      }
+    }
+}
+
 // out[split][c][r] = sum_{j in split} A[r][j] * X(j, c)      (X in panel layout: X[c*ldx + j])
 template <typename TA, typename TX, typename TC, typename TO, int NB, bool VEC>
 __global__ __launch_bounds__(256) void nn_kernel(const TA* __restrict__ A, int64_t lda, int64_t rows, int64_t K,
@@ -119,6 +236,107 @@ __global__ __launch_bounds__(256) void nn_kernel(const TA* __restrict__ A, int64
           if (r + e < rows) p[e] = static_cast<TO>(acc[rb][cb][e]);
       }
     }
+}
+
+// tn_kernel for FP32 operands, software-pipelined like nn_pipe_kernel: the next chunk's A values (16 loads of
+// four per lane) and panel values are loaded into registers while the current chunk is multiplied.
+template <typename TP, typename TO, int NB, bool VEC, bool OUT_RM>
+__global__ __launch_bounds__(256) void tn_pipe_kernel(const float* __restrict__ A, int64_t lda, int64_t K, int64_t N,
+                                                      const TP* __restrict__ P, int64_t ldp, int ncols,
+                                                      TO* __restrict__ out, int64_t ldo, int64_t part_stride,
+                                                      int64_t kchunk, bool upper) {
+  __shared__ V4<float> ps[2][NB * 4 * 64];
+  typedef Mma<float> M;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t jw = (int64_t)blockIdx.x * 256 + wave * 64;   // this wave's 64 output rows
+  const int split = blockIdx.y;
+  const int cg0 = blockIdx.z * NB * 16;
+  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kend = upper ? min(min(K, kbeg + kchunk), (int64_t)cg0 + NB * 16) : min(K, kbeg + kchunk);
+
+  // acc[bb][cb]: MFMA tile row m <-> output row jw + 4*arow(m) + bb
+  typename M::acc acc[4][NB];
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[bb][cb] = M::zero();
+
+  V4<float> a[4][4];
+  V4<TP> xr[NB];
+  auto load_a = [&](V4<float> (&dst)[4][4], int64_t k0) {
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        dst[kq][t] = load4_guarded<VEC>(A, lda, k0 + 16 * kq + 4 * g + t, jw + 4 * M::arow(li), kend, N);
+  };
+  if (kbeg < kend) {
+    load_a(a, kbeg);
+    panel_load<NB>(xr, P, ldp, cg0, ncols, kbeg, kend);
+    panel_store<NB, TP, float>(ps[0], xr);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KC) {
+    const bool more = k0 + KC < kend;   // uniform
+    V4<float> an[4][4];
+    if (more) {
+      load_a(an, k0 + KC);
+      panel_load<NB>(xr, P, ldp, cg0, ncols, k0 + KC, kend);
+    }
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      V4<float> b[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) b[cb] = ps[cur][(cb * 4 + kq) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+          const float av = a[kq][t].x[bb];
+#pragma unroll
+          for (int cb = 0; cb < NB; ++cb) acc[bb][cb] = M::op(av, b[cb].x[t], acc[bb][cb]);
+        }
+    }
+    if (more) panel_store<NB, TP, float>(ps[cur ^ 1], xr);
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[kq][t] = an[kq][t];
+    }
+    cur ^= 1;
+  }
+
+  TO* o = out + (int64_t)split * part_stride;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    int c = cg0 + cb * 16 + li;
+    if (c >= ncols) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int64_t j = jw + 16 * g + 4 * r;   // rows j .. j+3 <-> bb = 0..3
+      if (OUT_RM) {
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb)
+          if (j + bb < N) o[(j + bb) * ldo + c] = static_cast<TO>(acc[bb][cb][r]);
+      } else {
+        TO* p = o + (int64_t)c * ldo + j;
+        if (j + 4 <= N) {
+          V4<TO> v;
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb) v.x[bb] = static_cast<TO>(acc[bb][cb][r]);
+          v4_store(p, v);
+        } else {
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb)
+            if (j + bb < N) p[bb] = static_cast<TO>(acc[bb][cb][r]);
+        }
+      }
+    }
+  }
 }
 
 // out[split][c][j] = sum_{i in split} A[i][j] * P(i, c)      (P in panel layout: P[c*ldp + i])
@@ -301,14 +519,25 @@ hipError_t launch_nn(const TA* A, int64_t lda, int64_t rows, int64_t K, const TX
   int groups = (ncols + nb * 16 - 1) / (nb * 16);
   dim3 grid((unsigned)((rows + 127) / 128), (unsigned)used, (unsigned)groups);
   bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  RSVD_NB_SWITCH(nb, {
-    if (vec)
-      hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, true>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
-                         ncols, out, ldo, part_stride, kchunk);
-    else
-      hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, false>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
-                         ncols, out, ldo, part_stride, kchunk);
-  });
+  if constexpr (std::is_same<TA, float>::value && std::is_same<TC, float>::value) {
+    RSVD_NB_SWITCH(nb, {
+      if (vec)
+        hipLaunchKernelGGL((nn_pipe_kernel<TX, TO, NB, true>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx, ncols,
+                           out, ldo, part_stride, kchunk);
+      else
+        hipLaunchKernelGGL((nn_pipe_kernel<TX, TO, NB, false>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx, ncols,
+                           out, ldo, part_stride, kchunk);
+    });
+  } else {
+    RSVD_NB_SWITCH(nb, {
+      if (vec)
+        hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, true>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
+                           ncols, out, ldo, part_stride, kchunk);
+      else
+        hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, false>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
+                           ncols, out, ldo, part_stride, kchunk);
+    });
+  }
   return hipGetLastError();
 }
 
@@ -480,23 +709,43 @@ static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, co
   int groups = (ncols + nb * 16 - 1) / (nb * 16);
   dim3 grid((unsigned)((N + 255) / 256), (unsigned)used, (unsigned)groups);
   bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  RSVD_NB_SWITCH(nb, {
-    if (out_rowmajor) {
-      if (vec)
-        hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                           ldp, ncols, out, ldo, part_stride, kchunk, upper);
-      else
-        hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                           ldp, ncols, out, ldo, part_stride, kchunk, upper);
-    } else {
-      if (vec)
-        hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                           ldp, ncols, out, ldo, part_stride, kchunk, upper);
-      else
-        hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                           ldp, ncols, out, ldo, part_stride, kchunk, upper);
-    }
-  });
+  if constexpr (std::is_same<TA, float>::value && std::is_same<TC, float>::value) {
+    RSVD_NB_SWITCH(nb, {
+      if (out_rowmajor) {
+        if (vec)
+          hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
+                             ncols, out, ldo, part_stride, kchunk, upper);
+        else
+          hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
+                             ncols, out, ldo, part_stride, kchunk, upper);
+      } else {
+        if (vec)
+          hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
+                             ncols, out, ldo, part_stride, kchunk, upper);
+        else
+          hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
+                             ncols, out, ldo, part_stride, kchunk, upper);
+      }
+    });
+  } else {
+    RSVD_NB_SWITCH(nb, {
+      if (out_rowmajor) {
+        if (vec)
+          hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper);
+        else
+          hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper);
+      } else {
+        if (vec)
+          hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper);
+        else
+          hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper);
+      }
+    });
+  }
   return hipGetLastError();
 }
 
