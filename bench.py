@@ -257,7 +257,7 @@ def run_path(A, cfg, sketch, proj, steps, warmup, seed, keep_u=True, flags=0):
     else:
         groups = (nt + 11) // 12
         lp_nb = ((nt + groups - 1) // groups + 1) // 2 * 2
-    names = {"f32": ("nn_kernel (Y = A X, FP32 MFMA)", "tn_kernel (Z = A^T Q, FP32 MFMA)"),
+    names = {"f32": ("nn_pipe_kernel (Y = A X, FP32 MFMA)", "tn_pipe_kernel (Z = A^T Q, FP32 MFMA)"),
              "f64": ("nn_kernel (Y = A X, FP64 MFMA)", "tn_kernel (Z = A^T Q, FP64 MFMA)"),
              "bf16": ("lp_nn_kernel<0,%d,4,1,true> (Y = bf16(A) X)" % lp_nb, "lp_nn_kernel<0,%d,4,1,true> (Z = bf16(A)^T Q)" % lp_nb),
              "fp8": ("lp_nn_kernel<1,%d,4,1,true> (Y = fp8(A) X)" % lp_nb, "lp_nn_kernel<1,%d,4,1,true> (Z = fp8(A)^T Q)" % lp_nb)}[sketch]
