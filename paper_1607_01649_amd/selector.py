@@ -224,10 +224,12 @@ class Trainer:
         return hist
 
 
-def _solver(m, n, k, p, q, device, seed, theta=None, tau=0.5):
+def _solver(m, n, k, p, q, device, seed, theta=None, tau=0.5, sketch="f32"):
+    """The stream's solver; sketch = "bf16" takes the sketches A Omega and the power steps' products in bf16 (the
+    projection B = Q^T A stays FP32, so the residual the certificate measures carries no bf16 rounding of A)."""
     cap = selector_grid_cap(m, n)
     s = RSVD(m, n, k, p, q, dtype="f32", device=device, seed=seed, eps=EPS, max_rank=cap, fallback_block=32,
-             flags=RSVD_RETURN_RANK_L)
+             flags=RSVD_RETURN_RANK_L, sketch_dtype=sketch, proj_dtype="f32")
     if theta is not None:
         s.set_selector(theta, tau)
     return s
@@ -242,7 +244,7 @@ def _timed(solver, A):
 
 
 def evaluate(theta: torch.Tensor, seed: int, items: int, device, tau: float = 0.3, start: int = 0, log=None,
-             with_best: bool = True):
+             with_best: bool = True, sketch: str = "f32"):
     """Time-to-eps on the items of a stream under four strategies: the paper's
     defaults (p = 10, q = 2) with fallback, the fallback alone (p = q = 0),
     the learned selector with fallback, and the per-item cheapest certified
@@ -265,7 +267,7 @@ def evaluate(theta: torch.Tensor, seed: int, items: int, device, tau: float = 0.
         for name, (p, q) in strategies.items():
             if k + max(p, 0) > selector_grid_cap(m, n):
                 p = 0
-            sol = _solver(m, n, k, p, q, device, seed, theta if p == -1 else None, tau)
+            sol = _solver(m, n, k, p, q, device, seed, theta if p == -1 else None, tau, sketch)
             if not warm:
                 _timed(sol, A)
             ms, info = _timed(sol, A)
@@ -356,6 +358,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train", "eval", "costfit", "retune"])
     ap.add_argument("--start", type=int, default=0, help="first item of the stream (eval, retune)")
+    ap.add_argument("--sketch", choices=["f32", "bf16"], default="f32",
+                    help="eval: precision of the sketches and power steps (the projection stays FP32)")
     ap.add_argument("--items", type=int, default=1500)
     ap.add_argument("--val", type=int, default=150)
     ap.add_argument("--epochs", type=int, default=400)
@@ -409,7 +413,7 @@ def main(argv=None):
         th, tau = load_weights(args.weights)
         theta = torch.from_numpy(th).to(dev)
         rows = evaluate(theta, SEED_TEST, args.items, dev, tau if args.tau is None else args.tau, start=args.start,
-                        log=log)
+                        log=log, with_best=args.sketch == "f32", sketch=args.sketch)
         summ = summarize(rows)
         log(json.dumps(summ))
         if args.json:
