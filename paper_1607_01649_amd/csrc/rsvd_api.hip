@@ -974,6 +974,12 @@ template <typename T> struct Path {
       RS_TRY(dominant_left_finish(Yr, L.ldn, n, l, k, Cm, Wm, uhat_p_r, Qr, N1));
     }
     mark(2);
+    // The eigendecompositions of the positive semidefinite P1, P2 go through their Cholesky factors: with
+    // P = R^T R, the left singular vectors of R^T are the eigenvectors of P and sigma^2 its eigenvalues (the
+    // Jacobi on R^T as in Stage B: fewer sweeps than on the columns of P, and P's condition halved).  R lands
+    // in M1 / M2^T (free once P and S are formed), R^-1 in N1; pivots dropped here (k above the rank) count
+    // in flags[8..9], not in the sketches' dropped columns.
+    double* chol_scr = P.at<double>(L.scr_chol);
     if (sym) {
       RS_TRY(tprod64(Gc, l, Qc, k, L.ldn, n, L.s_gn, M2t, LPl));
       mark(3);
@@ -981,7 +987,9 @@ template <typename T> struct Path {
       HIP_TRY(launch_small_gemm<double>(k, k, l, M2t, LPl, true, M2t, LPl, false, P1, LPk, false, nullptr, st));
       HIP_TRY(launch_small_gemm<double>(k, k, l, N2t, LPl, true, M2t, LPl, false, Sm, LPk, false, nullptr, st));
       HIP_TRY(launch_small_gemm<double>(k, k, l, M2t, LPl, true, N2t, LPl, false, Sm, LPk, true, nullptr, st));
-      HIP_TRY(launch_jacobi<double>(P1, k, LPk, tol, 60, a1, Z1, (double*)nullptr, (double*)nullptr, scr, flags, st));
+      HIP_TRY(launch_chol<double>(P1, LPk, k, LPk, tau, N1, M1, nullptr, chol_scr, flags + 8, st));
+      HIP_TRY(launch_jacobi<double>(M1, k, LPk, tol, 60, a1, Z1, (double*)nullptr, (double*)nullptr, scr, flags, st));
+      HIP_TRY(launch_square(a1, a1, k, st));
       Z2 = Z1;
       a2 = a1;
     } else {
@@ -993,16 +1001,20 @@ template <typename T> struct Path {
       HIP_TRY(launch_small_gemm<double>(k, k, l, M2t, LPl, true, M2t, LPl, false, P2, LPk, false, nullptr, st));
       HIP_TRY(launch_small_gemm<double>(k, k, l, M1, LPl, true, N1, LPl, false, Sm, LPk, false, nullptr, st));
       HIP_TRY(launch_small_gemm<double>(k, k, l, N2t, LPl, true, M2t, LPl, false, Sm, LPk, true, nullptr, st));
+      HIP_TRY(launch_chol<double>(P1, LPk, k, LPk, tau, N1, M1, nullptr, chol_scr, flags + 8, st));
+      HIP_TRY(launch_chol<double>(P2, LPk, k, LPk, tau, N1, M2t, nullptr, chol_scr, flags + 8, st));
       if (LPk <= 128) {
-        const JacobiProblem<double> p1{P1, a1, Z1, nullptr, nullptr};
-        const JacobiProblem<double> p2{P2, a2, Z2, nullptr, nullptr};
+        const JacobiProblem<double> p1{M1, a1, Z1, nullptr, nullptr};
+        const JacobiProblem<double> p2{M2t, a2, Z2, nullptr, nullptr};
         HIP_TRY(launch_jacobi2<double>(p1, p2, k, LPk, tol, 60, flags, st));
       } else {
-        HIP_TRY(launch_jacobi<double>(P1, k, LPk, tol, 60, a1, Z1, (double*)nullptr, (double*)nullptr, scr, flags,
+        HIP_TRY(launch_jacobi<double>(M1, k, LPk, tol, 60, a1, Z1, (double*)nullptr, (double*)nullptr, scr, flags,
                                       st));
-        HIP_TRY(launch_jacobi<double>(P2, k, LPk, tol, 60, a2, Z2, (double*)nullptr, (double*)nullptr, scr, flags,
+        HIP_TRY(launch_jacobi<double>(M2t, k, LPk, tol, 60, a2, Z2, (double*)nullptr, (double*)nullptr, scr, flags,
                                       st));
       }
+      HIP_TRY(launch_square(a1, a1, k, st));
+      HIP_TRY(launch_square(a2, a2, k, st));
     }
     // P1 C + C P2 = S: C = Z1 [(Z1^T S Z2) ./ (a_i + b_j)] Z2^T
     HIP_TRY(launch_small_gemm<double>(k, k, k, Z1, LPk, true, Sm, LPk, false, T1, LPk, false, nullptr, st));
