@@ -839,8 +839,12 @@ template <typename T> struct Path {
                                                        st)));
     HIP_TRY((launch_reduce<double, double>(gp, L.s_gn, (int64_t)LK * k, LK, k, k, H, LK, st)));
     const double tol = small_tol(k);
-    HIP_TRY(launch_jacobi<double>(H, k, LK, tol, 60, lam, V, (double*)nullptr, (double*)nullptr,
+    // H = R_H^T R_H (Cholesky, R_H into S11, R_H^-1 into T1, both free here); the left singular vectors of
+    // R_H^T are H's eigenvectors and sigma^2 its eigenvalues (fewer sweeps than the Jacobi on H's columns)
+    HIP_TRY(launch_chol<double>(H, LK, k, LK, tau, T1, S11, nullptr, P.at<double>(L.scr_chol), flags + 8, st));
+    HIP_TRY(launch_jacobi<double>(S11, k, LK, tol, 60, lam, V, (double*)nullptr, (double*)nullptr,
                                   P.at<double>(L.scr_jac), flags, st));
+    HIP_TRY(launch_square(lam, lam, k, st));
     HIP_TRY(launch_cut_small(lam, k, tol, st));
     HIP_TRY(launch_small_gemm<double>(k, k, k, M, LK, false, V, LK, false, T1, LK, false, lam, st));
     HIP_TRY(launch_small_gemm<double>(k, k, k, T1, LK, false, V, LK, true, H, LK, false, nullptr, st));
@@ -1382,7 +1386,7 @@ static rsvd_status finish_call(rsvd_plan_t p, rsvd_status s, rsvd_info* h_info) 
   int flags[kFlags];
   HIP_TRY(hipMemcpyAsync(flags, p->ws + p->L.flags, sizeof(flags), hipMemcpyDeviceToHost, p->st));
   HIP_TRY(hipStreamSynchronize(p->st));
-  if (flags[0] > 0 || flags[4] != 0) s = RSVD_E_NONFINITE;
+  if (flags[0] > 0 || flags[4] != 0 || flags[8] > 0) s = RSVD_E_NONFINITE;
   memset(h_info, 0, sizeof(*h_info));
   h_info->p_used = p->d.p;
   h_info->q_used = p->d.q;
