@@ -45,7 +45,8 @@ namespace rsvd {
 constexpr int CB = 64;   // Cholesky block
 
 __global__ void bc_init_kernel(const double* __restrict__ g, int64_t ldg, int l, int LB, double* __restrict__ M,
-                               double* __restrict__ X, double* __restrict__ gdiag) {
+                               double* __restrict__ X, double* __restrict__ gdiag, const int* __restrict__ skip) {
+  if (skip && *skip) return;   // a skipped second CholeskyQR pass
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)LB * LB) return;
   const int a = (int)(t / LB), b = (int)(t - (t / LB) * LB);
@@ -78,7 +79,8 @@ __device__ __forceinline__ void tile64(FA fa, FB fb, double sign, f64x4 (&acc)[4
 // M = blockIdx.x - nr < J.  In place: every product is complete before the workgroup barrier, the stores
 // come after it.
 __global__ __launch_bounds__(256) void bc_panel_kernel(double* __restrict__ M, double* __restrict__ X, int LB, int j0,
-                                                       int nr) {
+                                                       int nr, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const bool erow = (int)blockIdx.x >= nr;
   double* blk = erow ? X + (int64_t)j0 * LB + CB * ((int)blockIdx.x - nr) : M + (int64_t)j0 * LB + j0 + CB * (1 + blockIdx.x);
   const double* S = X + (int64_t)j0 * LB + j0;
@@ -99,7 +101,8 @@ __global__ __launch_bounds__(256) void bc_panel_kernel(double* __restrict__ M, d
 // E_KM -= R_JK^T E_JM for K > J, M <= J (the rest, nr (J + 1) of them; E_JJ = S_JJ^T).  The output block
 // is never an operand.
 __global__ __launch_bounds__(256) void bc_trail_kernel(double* __restrict__ M, double* __restrict__ X, int LB, int j0,
-                                                       int nr) {
+                                                       int nr, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int jb = j0 / CB;
   const int npair = nr * (nr + 1) / 2;
   const double* A;
@@ -142,14 +145,15 @@ __global__ __launch_bounds__(256) void bc_trail_kernel(double* __restrict__ M, d
     for (int e = 0; e < 4; ++e) out[(int64_t)(16 * w + g + 4 * e) * LB + 16 * tb + i] = acc[tb][e];
 }
 
-// rinv_p[c*LP + k] = R^-1(k, c) for c, k < l; the identity on the padding.
+// rinv_p[c*LP + k] = R^-1(k, c) for c, k < l; the identity on the padding (everywhere for a skipped pass).
 template <typename TQ>
-__global__ void bc_rinv_out_kernel(const double* __restrict__ X, int LB, int l, int LP, TQ* __restrict__ rinv_p) {
+__global__ void bc_rinv_out_kernel(const double* __restrict__ X, int LB, int l, int LP, TQ* __restrict__ rinv_p,
+                                   const int* __restrict__ skip) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)LP * LP) return;
   const int c = (int)(t / LP), k = (int)(t - (t / LP) * LP);
   double v;
-  if (c >= l || k >= l) v = (c == k) ? 1.0 : 0.0;
+  if (c >= l || k >= l || (skip && *skip)) v = (c == k) ? 1.0 : 0.0;
   else if (k > c) v = 0.0;
   else v = (k / CB == c / CB) ? X[(int64_t)k * LB + c] : X[(int64_t)c * LB + k];   // S_JJ, or E(c, k)
   rinv_p[t] = static_cast<TQ>(v);
@@ -212,9 +216,49 @@ size_t chol_blocked_scratch_doubles(int LP) {
   return 2 * LB * LB + LB;
 }
 
+// The skip test of the blocked form (as the one-workgroup Cholesky kernel's): *skip_out = 1 when
+// l sum_i G_ii ||row i of R^-1||^2 <= kappa_max^2, never when a pivot was dropped (a zero on the diagonal of
+// R^-1) or a value is not finite.  Each stored entry of X is one entry of R^-1: X(a, b) with a <= b inside a
+// diagonal block is R^-1(a, b) (weight G_aa); X(a, b) below the diagonal blocks is R^-1(b, a) (weight G_bb).
+// So row a of X, read contiguously by one wave, gives part[a]; a zero pivot makes part[a] NaN.
+__global__ __launch_bounds__(256) void bc_bound_part_kernel(const double* __restrict__ X, int LB, int l,
+                                                            const double* __restrict__ gdiag,
+                                                            double* __restrict__ part) {
+  const int lane = threadIdx.x & 63;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a >= l) return;
+  const double* xa = X + (int64_t)a * LB;
+  const int d0 = a / CB * CB;
+  const int bend = min(d0 + CB, l);
+  const double ga = gdiag[a];
+  double f = 0.0;
+  for (int b = lane; b < bend; b += 64) {
+    if (b >= d0 && b < a) continue;   // the unused lower triangle of the diagonal block
+    const double v = xa[b];
+    f = fma(b >= d0 ? ga : gdiag[b], v * v, f);
+  }
+  f = wave_sum(f);
+  if (lane == 0) part[a] = xa[a] != 0.0 ? f : __longlong_as_double(0x7ff8000000000000LL);
+}
+
+__global__ __launch_bounds__(1024) void bc_bound_fin_kernel(const double* __restrict__ part, int l,
+                                                            double kappa2_max, int* __restrict__ skip_out) {
+  __shared__ double w[16];
+  double f = threadIdx.x < l ? part[threadIdx.x] : 0.0;
+  f = wave_sum(f);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 16; ++i) t += w[i];
+    *skip_out = ((double)l * t <= kappa2_max) ? 1 : 0;   // false for NaN
+  }
+}
+
 template <typename TQ>
 hipError_t launch_chol_blocked(const double* g, int64_t ldg, int l, int LP, double tau, TQ* rinv_p, double* r_out,
-                               const double* r_prev, double* scratch, int* flags, hipStream_t s) {
+                               const double* r_prev, double* scratch, int* flags, hipStream_t s, int* skip_out,
+                               double kappa2_max, const int* skip_in) {
   const int LB = (LP + CB - 1) / CB * CB;
   const int nbk = LB / CB;
   double* M = scratch;
@@ -222,32 +266,38 @@ hipError_t launch_chol_blocked(const double* g, int64_t ldg, int l, int LP, doub
   double* gdiag = X + (size_t)LB * LB;
   const int64_t ll = (int64_t)LB * LB;
   hipLaunchKernelGGL(bc_init_kernel, dim3((unsigned)((ll + 255) / 256)), dim3(256), 0, s, g, ldg, l, LB, M, X,
-                     gdiag);
-  // X: S_JJ on the diagonal blocks, E below them; its blocks above the diagonal are never read.
+                     gdiag, skip_in);
+  // X: S_JJ on the diagonal blocks, E below them; its blocks above the diagonal are never read.  With skip_in
+  // set on the device every launch returns at once and R^-1 comes out as the identity.
   for (int jb = 0; jb < nbk; ++jb) {
     const int j0 = jb * CB;
-    hipError_t e = launch_chol_diag64(M, LB, j0, l, gdiag, tau, X, flags, s);
+    hipError_t e = launch_chol_diag64(M, LB, j0, l, gdiag, tau, X, flags, s, skip_in);
     if (e != hipSuccess) return e;
     const int nr = nbk - 1 - jb;
     if (nr + jb > 0)
-      hipLaunchKernelGGL(bc_panel_kernel, dim3((unsigned)(nr + jb)), dim3(256), 0, s, M, X, LB, j0, nr);
+      hipLaunchKernelGGL(bc_panel_kernel, dim3((unsigned)(nr + jb)), dim3(256), 0, s, M, X, LB, j0, nr, skip_in);
     if (nr > 0)
       hipLaunchKernelGGL(bc_trail_kernel, dim3((unsigned)(nr * (nr + 1) / 2 + nr * (jb + 1))), dim3(256), 0, s, M, X,
-                         LB, j0, nr);
+                         LB, j0, nr, skip_in);
   }
   const int64_t lp2 = (int64_t)LP * LP;
   hipLaunchKernelGGL((bc_rinv_out_kernel<TQ>), dim3((unsigned)((lp2 + 255) / 256)), dim3(256), 0, s, X, LB, l, LP,
-                     rinv_p);
+                     rinv_p, skip_in);
   if (r_out)
     hipLaunchKernelGGL(bc_r_out_kernel, dim3((unsigned)(nbk * (nbk + 1) / 2)), dim3(256), 0, s, M, LB, l, LP, r_prev,
                        r_out, nbk);
+  if (skip_out) {   // M is free once R is out: it holds the per-row partials
+    hipLaunchKernelGGL(bc_bound_part_kernel, dim3((unsigned)((l + 3) / 4)), dim3(256), 0, s, X, LB, l, gdiag, M);
+    hipLaunchKernelGGL(bc_bound_fin_kernel, dim3(1), dim3(1024), 0, s, M, l, kappa2_max, skip_out);
+  }
   return hipGetLastError();
 }
 
 template hipError_t launch_chol_blocked<float>(const double*, int64_t, int, int, double, float*, double*,
-                                               const double*, double*, int*, hipStream_t);
+                                               const double*, double*, int*, hipStream_t, int*, double, const int*);
 template hipError_t launch_chol_blocked<double>(const double*, int64_t, int, int, double, double*, double*,
-                                                const double*, double*, int*, hipStream_t);
+                                                const double*, double*, int*, hipStream_t, int*, double,
+                                                const int*);
 
 // ---------------------------------------------------------------------------
 // Block one-sided Jacobi

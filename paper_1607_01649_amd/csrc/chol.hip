@@ -389,7 +389,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_blk_kernel(const double* __
 // original diagonal of G (the drop rule's reference); columns past l are padding.
 __global__ __launch_bounds__(kCholThreads) void chol_diag64_kernel(double* __restrict__ Mg, int LB, int j0, int l,
                                                                  const double* __restrict__ gdiag, double tau_rel,
-                                                                 double* __restrict__ X, int* __restrict__ flags) {
+                                                                 double* __restrict__ X, int* __restrict__ flags,
+                                                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;   // a skipped second CholeskyQR pass
   constexpr int D = 64, MP = D + 1, nb = D / kCholB;
   __shared__ __align__(16) double M[D * MP];
   __shared__ __align__(16) double Wd[nb * kCholB * kWdPitch];
@@ -423,9 +425,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_diag64_kernel(double* __res
 }
 
 hipError_t launch_chol_diag64(double* M, int LB, int j0, int l, const double* gdiag, double tau_rel, double* X,
-                              int* flags, hipStream_t s) {
+                              int* flags, hipStream_t s, const int* skip) {
   if (j0 < 0 || j0 >= l || LB % 64 != 0 || j0 + 64 > LB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_diag64_kernel, dim3(1), dim3(kCholThreads), 0, s, M, LB, j0, l, gdiag, tau_rel, X, flags);
+  hipLaunchKernelGGL(chol_diag64_kernel, dim3(1), dim3(kCholThreads), 0, s, M, LB, j0, l, gdiag, tau_rel, X, flags,
+                     skip);
   return hipGetLastError();
 }
 
@@ -434,12 +437,7 @@ hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_r
                        const double* r_prev, double* scratch, int* flags, hipStream_t s, int* skip_out,
                        double kappa_max, const int* skip_in) {
   if (l < 1 || l > 1024) return hipErrorInvalidValue;
-  if (skip_in && (LP > 128 || r_out)) return hipErrorInvalidValue;   // a skippable pass: l <= 128, only R^-1
-  if (LP > 128 && skip_out) {
-    hipError_t e = launch_fill_int(skip_out, 1, 0, s);   // the blocked form gives no bound: never skip
-    if (e != hipSuccess) return e;
-    skip_out = nullptr;
-  }
+  if (skip_in && r_out) return hipErrorInvalidValue;   // a skippable pass only writes R^-1
   if (LP <= 128) {
     if (LP % kCholB != 0) return hipErrorInvalidValue;
     static bool attr_set = false;
@@ -455,7 +453,8 @@ hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_r
                        r_out, r_prev, flags, skip_in, skip_out, kappa_max * kappa_max);
   } else {
     if (!scratch) return hipErrorInvalidValue;
-    return launch_chol_blocked<TQ>(g, ldg, l, LP, tau_rel, rinv_p, r_out, r_prev, scratch, flags, s);
+    return launch_chol_blocked<TQ>(g, ldg, l, LP, tau_rel, rinv_p, r_out, r_prev, scratch, flags, s, skip_out,
+                                   kappa_max * kappa_max, skip_in);
   }
   return hipGetLastError();
 }

@@ -244,7 +244,9 @@ template <typename TP, typename TO, int NB, bool VEC, bool OUT_RM>
 __global__ __launch_bounds__(256) void tn_pipe_kernel(const float* __restrict__ A, int64_t lda, int64_t K, int64_t N,
                                                       const TP* __restrict__ P, int64_t ldp, int ncols,
                                                       TO* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                      int64_t kchunk, bool upper) {
+                                                      int64_t kchunk, bool upper,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;   // R^-1 = I (a skipped second CholeskyQR pass): copy_on_skip_kernel copies
   __shared__ V4<float> ps[2][NB * 4 * 64];
   typedef Mma<float> M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -346,7 +348,9 @@ template <typename TA, typename TP, typename TC, typename TO, int NB, bool VEC, 
 __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64_t lda, int64_t K, int64_t N,
                                                  const TP* __restrict__ P, int64_t ldp, int ncols,
                                                  TO* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                 int64_t kchunk, bool upper) {
+                                                 int64_t kchunk, bool upper,
+                                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;   // R^-1 = I (a skipped second CholeskyQR pass): copy_on_skip_kernel copies
   __shared__ V4<TC> ps[NB * 4 * 64];
   typedef Mma<TC> M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -689,15 +693,35 @@ hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, con
   return hipGetLastError();
 }
 
+// out(c, j) = A(c, j) (A K x N row-major as in the product, out[c*ldo + j]) when *skip is set: the apply of
+// R^-1 = I after a skipped second CholeskyQR pass, whose product kernel returned at once.
+template <typename T>
+__global__ __launch_bounds__(256) void copy_on_skip_kernel(const T* __restrict__ A, int64_t lda, int64_t N,
+                                                           T* __restrict__ out, int64_t ldo, bool vec,
+                                                           const int* __restrict__ skip) {
+  if (!*skip) return;
+  const int c = blockIdx.y;
+  const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (j >= N) return;
+  const T* a = A + (int64_t)c * lda + j;
+  T* o = out + (int64_t)c * ldo + j;
+  if (vec && j + 4 <= N) {
+    v4_store(o, v4_load(a));
+  } else {
+    for (int e = 0; e < 4; ++e)
+      if (j + e < N) o[e] = a[e];
+  }
+}
+
 template <typename TA, typename TP, typename TC, typename TO>
 static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols,
                               TO* out, int64_t ldo, int64_t part_stride, int splits, bool out_rowmajor, bool upper,
-                              hipStream_t s) {
+                              hipStream_t s, const int* skip = nullptr) {
   if (N <= 0 || ncols <= 0) return hipSuccess;
   if (splits < 1 || out_rowmajor) splits = 1;
   if constexpr (std::is_same<TA, float>::value && std::is_same<TP, float>::value && std::is_same<TO, float>::value &&
                 std::is_same<TC, float>::value) {
-    if (splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
+    if (!skip && splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
         (int64_t)ncols * ldp < (int64_t(1) << 32))
       return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, upper, out_rowmajor, s);
   }
@@ -714,17 +738,17 @@ static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, co
       if (out_rowmajor) {
         if (vec)
           hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper);
+                             ncols, out, ldo, part_stride, kchunk, upper, skip);
         else
           hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper);
+                             ncols, out, ldo, part_stride, kchunk, upper, skip);
       } else {
         if (vec)
           hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper);
+                             ncols, out, ldo, part_stride, kchunk, upper, skip);
         else
           hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper);
+                             ncols, out, ldo, part_stride, kchunk, upper, skip);
       }
     });
   } else {
@@ -732,19 +756,29 @@ static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, co
       if (out_rowmajor) {
         if (vec)
           hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper);
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper, skip);
         else
           hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper);
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper, skip);
       } else {
         if (vec)
           hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper);
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper, skip);
         else
           hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper);
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper, skip);
       }
     });
+  }
+  if (skip) {
+    if constexpr (std::is_same<TA, TO>::value) {
+      if (splits != 1 || out_rowmajor || ncols != K) return hipErrorInvalidValue;
+      const bool cvec = vec && (ldo % 4 == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
+      hipLaunchKernelGGL((copy_on_skip_kernel<TO>), dim3((unsigned)((N + 1023) / 1024), (unsigned)ncols), dim3(256),
+                         0, s, A, lda, N, out, ldo, cvec, skip);
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
@@ -785,8 +819,8 @@ hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int
 // kernel where it applies, otherwise the general product with each column group's contraction cut at its
 // last column.
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const float* P, int64_t ldp,
-                              int ncols, float* out, int64_t ldo, hipStream_t s) {
-  return launch_tn_k<float, float, float, float>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s);
+                              int ncols, float* out, int64_t ldo, hipStream_t s, const int* skip) {
+  return launch_tn_k<float, float, float, float>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s, skip);
 }
 
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
@@ -799,8 +833,9 @@ hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N,
 }
 
 hipError_t launch_apply_upper(const double* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
-                              int ncols, double* out, int64_t ldo, hipStream_t s) {
-  return launch_tn_k<double, double, double, double>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s);
+                              int ncols, double* out, int64_t ldo, hipStream_t s, const int* skip) {
+  return launch_tn_k<double, double, double, double>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s,
+                                                     skip);
 }
 
 // Explicit instantiations used by the host orchestration.

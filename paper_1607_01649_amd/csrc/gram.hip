@@ -90,7 +90,8 @@ __device__ __forceinline__ void lds_barrier_g() {
 template <typename TI, int NCB>
 __global__ __launch_bounds__(256) void gram_kernel(const TI* __restrict__ Y, int64_t ld, int64_t K, int nc, int ntile,
                                                    double* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                   int64_t kchunk) {
+                                                   int64_t kchunk, const int* __restrict__ skip) {
+  if (skip && *skip) return;   // a skipped second CholeskyQR pass (uniform: every thread reads the flag)
   typedef GramFmt<TI> F;
   typedef typename F::V V;
   constexpr int KC = F::KC;
@@ -344,7 +345,6 @@ template <typename TI>
 hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, int64_t ldo, int64_t part_stride,
                        int splits, hipStream_t s, const int* skip) {
   if (nc <= 0 || K <= 0) return hipSuccess;
-  if (skip && nc > 128) return hipErrorInvalidValue;   // the skip serves the one-tile (l <= 128) form only
   if (ld < K || (ld % 64) != 0 || (reinterpret_cast<uintptr_t>(Y) & 15) != 0) return hipErrorInvalidValue;
   if (splits < 1) splits = 1;
   int64_t kchunk = ((K + splits - 1) / splits + 63) / 64 * 64;
@@ -358,7 +358,7 @@ hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, 
 #define RSVD_GRAM_CASE(N)                                                                                    \
   case N:                                                                                                  \
     hipLaunchKernelGGL((gram_kernel<TI, N>), grid, dim3(256), 0, s, Y, ld, K, nc, ntile, out, ldo, part_stride, \
-                       kchunk);                                                                            \
+                       kchunk, skip);                                                                      \
     break;
   if (ntile == 1) {
 #define RSVD_GRAM_SYM_CASE(N)                                                                                    \

@@ -19,13 +19,15 @@ hipError_t launch_gaussian(uint64_t seed, uint32_t stream, int64_t rows, int64_t
 template <typename TA, typename TX, typename TC, typename TO>
 hipError_t launch_nn(const TA* A, int64_t lda, int64_t rows, int64_t K, const TX* X, int64_t ldx, int ncols, TO* out,
                      int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
-// out = A P with P upper triangular (P(i, c) = 0 for i > c); layouts as launch_tn with one range.
+// out = A P with P upper triangular (P(i, c) = 0 for i > c); layouts as launch_tn with one range.  skip
+// (optional, ncols == K): when *skip is set on the device, P is taken as I and A is copied (a skipped second
+// CholeskyQR pass); the product kernels return at once.
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const float* P, int64_t ldp,
-                              int ncols, float* out, int64_t ldo, hipStream_t s);
+                              int ncols, float* out, int64_t ldo, hipStream_t s, const int* skip = nullptr);
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
                               int ncols, double* out, int64_t ldo, hipStream_t s);
 hipError_t launch_apply_upper(const double* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
-                              int ncols, double* out, int64_t ldo, hipStream_t s);
+                              int ncols, double* out, int64_t ldo, hipStream_t s, const int* skip = nullptr);
 // tn: out[s][c][j] = sum_{i in split s} A[i][j] P(i, c); A K x N row-major, P panel (P[c*ldp + i]).
 template <typename TA, typename TP, typename TC, typename TO>
 hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols, TO* out,
@@ -38,9 +40,9 @@ template <typename TP>
 hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int64_t ldp, int64_t rows, int ncols,
                           TP* tmp, TP* out, int64_t ldo, hipStream_t s, const int* skip = nullptr);
 
-// chol.hip.  skip_out (optional, l <= 128 only; written 0 otherwise): 1 when the factor shows the panel well
-// enough conditioned that one CholeskyQR pass suffices (scaled Frobenius condition bound at most kappa_max);
-// skip_in (optional): when *skip_in is set the call only writes R^-1 = I (a skipped second pass).
+// chol.hip.  skip_out (optional): 1 when the factor shows the panel well enough conditioned that one
+// CholeskyQR pass suffices (scaled Frobenius condition bound at most kappa_max); skip_in (optional): when
+// *skip_in is set the call only writes R^-1 = I (a skipped second pass; r_out must be null).
 template <typename TQ>
 hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_rel, TQ* rinv_p, double* r_out,
                        const double* r_prev, double* scratch, int* flags, hipStream_t s, int* skip_out = nullptr,
@@ -50,10 +52,11 @@ hipError_t launch_chol(const double* g, int64_t ldg, int l, int LP, double tau_r
 size_t chol_blocked_scratch_doubles(int LP);
 template <typename TQ>
 hipError_t launch_chol_blocked(const double* g, int64_t ldg, int l, int LP, double tau, TQ* rinv_p, double* r_out,
-                               const double* r_prev, double* scratch, int* flags, hipStream_t s);
+                               const double* r_prev, double* scratch, int* flags, hipStream_t s,
+                               int* skip_out = nullptr, double kappa2_max = 0.0, const int* skip_in = nullptr);
 // 64 x 64 diagonal block of the blocked Cholesky (chol.hip): R_JJ into M, S_JJ = R_JJ^-1 into X.
 hipError_t launch_chol_diag64(double* M, int LB, int j0, int l, const double* gdiag, double tau_rel, double* X,
-                              int* flags, hipStream_t s);
+                              int* flags, hipStream_t s, const int* skip = nullptr);
 size_t jacobi_blocked_scratch_bytes(int LP);
 template <typename TU>
 hipError_t launch_jacobi_blocked(const double* R, int l, int LP, double tol, int max_sweeps, double* sigma,

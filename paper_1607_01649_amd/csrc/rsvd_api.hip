@@ -353,14 +353,17 @@ template <typename T> struct Path {
   }
 
   // out = X R^-1 (R^-1 upper triangular, nc x nc at leading dimension LPc).
-  hipError_t apply_rinv(const T* X, int64_t ld, int64_t rows, int nc, const T* rinv, int LPc, T* out) {
-    return launch_apply_upper(X, ld, nc, rows, rinv, LPc, nc, out, ld, st);
+  // With `skip` (the second pass of a skippable orthonormalisation, nc > 128 only: below that the short apply
+  // is bound by the same panel traffic as a copy), a set *skip turns the product into a copy of X.
+  hipError_t apply_rinv(const T* X, int64_t ld, int64_t rows, int nc, const T* rinv, int LPc, T* out,
+                        const int* skip = nullptr) {
+    return launch_apply_upper(X, ld, nc, rows, rinv, LPc, nc, out, ld, st, nc > 128 ? skip : nullptr);
   }
 
   // out = orth(X) for an nc-column panel: CholeskyQR2 (two passes of G = X^T X = R^T R, X <- X R^-1).
-  // may_skip (a basis that is multiplied again, not the one Stage B uses; nc <= 128): the second pass is
+  // may_skip (a basis that is multiplied again, not the one Stage B uses): the second pass is
   // skipped on the device when the first pass's factor bounds the column-scaled condition number of X by
-  // kOrthSkipKappa (its Gram, sum and Cholesky return at once, the apply multiplies by I), since one pass
+  // kOrthSkipKappa (its Gram, sum and Cholesky return at once, the apply multiplies by I or copies), since one pass
   // then leaves a basis orthonormal to about kappa^2 u plus kappa times the panel's rounding.
   rsvd_status orth(const T* X, int64_t ld, int64_t rows, int nc, int splits, T* out, bool may_skip = false) {
     const int LPc = lp16(nc);
@@ -369,13 +372,13 @@ template <typename T> struct Path {
     T* tmp = P.at<T>(L.T);
     int* flags = P.at<int>(L.flags);
     double* scr = P.at<double>(L.scr_chol);
-    int* skip = (may_skip && LPc <= 128) ? flags + kSkipFlag : nullptr;
+    int* skip = may_skip ? flags + kSkipFlag : nullptr;
     RS_TRY(gram(X, ld, rows, nc, splits, G));
     HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st, skip, kOrthSkipKappa));
     HIP_TRY(apply_rinv(X, ld, rows, nc, rinv, LPc, tmp));
     RS_TRY(gram(tmp, ld, rows, nc, splits, G, skip));
     HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st, nullptr, 0.0, skip));
-    HIP_TRY(apply_rinv(tmp, ld, rows, nc, rinv, LPc, out));
+    HIP_TRY(apply_rinv(tmp, ld, rows, nc, rinv, LPc, out, skip));
     return RSVD_OK;
   }
 
