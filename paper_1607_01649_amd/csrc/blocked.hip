@@ -397,6 +397,7 @@ template <int W>
 struct BjShared {
   double rc[W], rs[W], rt[W];   // the inner round's rotations, one per disjoint pair
   int any_rot;
+  int need;   // a pair of the inner sweep passes the rotation test on G as assembled
   int ok;
 };
 
@@ -475,7 +476,10 @@ __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, i
 #pragma unroll
       for (int r = 0; r < 4; ++r) red[(wave * NTT + t) * 256 + r * 64 + lane] = acc[t][r];
   }
-  if (tid == 0) sh.any_rot = 0;
+  if (tid == 0) {
+    sh.any_rot = 0;
+    sh.need = 0;
+  }
   for (int e = tid; e < NC * NC; e += 512) vm[e] = (e / NC == e % NC) ? 1.0 : 0.0;
   __syncthreads();
   // Wave partials summed in wave order.  Accumulator element r of lane L holds G(L/16 + 4 r, L % 16) of its
@@ -505,7 +509,18 @@ __device__ __forceinline__ void bj_pair_step(double* __restrict__ xs, int ldx, i
       q = W + ((k + ir) & (W - 1));
     }
   };
-  const int nir = full ? NC - 1 : W;
+  // G changes only by rotations, so when no pair the inner sweep visits (every pair in a full sweep, the
+  // cross pairs otherwise) passes the rotation test on G as assembled, no inner round rotates: the sweep is
+  // skipped, with exactly the result of running it.
+  for (int e = tid; e < NC * NC; e += 512) {
+    const int p = e / NC, q = e - (e / NC) * NC;
+    if (p < q && (full || (p < W && q >= W))) {
+      const double al = gb[p * NC + p], be = gb[q * NC + q], ga = gb[p * NC + q];
+      if (al > thr2 && be > thr2 && fabs(ga) > tol * (sqrt(al) * sqrt(be))) sh.need = 1;
+    }
+  }
+  __syncthreads();
+  const int nir = sh.need == 0 ? 0 : full ? NC - 1 : W;
   int cur = 0;
   for (int ir = 0; ir < nir; ++ir) {
     const double* G = gb + cur * NC * NC;

@@ -13,7 +13,8 @@
 // floor(l/2) disjoint pairs, processed in parallel by groups of 16 lanes (64
 // pairs at once in a 1024-thread block); l-1 (or l) rounds make a sweep.
 // Sweeps repeat until no pair needs a rotation (|x_p . x_q| <= tol * ||x_p||
-// ||x_q||).  A column whose norm is at most tol * ||X||_F is numerically zero
+// ||x_q||); after a sweep with few rotations that test is first made on all
+// pairs at once from X^T X, which spares the sweep that would rotate nothing.  A column whose norm is at most tol * ||X||_F is numerically zero
 // (rank deficiency, below what the stopping test can resolve against the
 // other columns): it takes no rotation, and it is returned as sigma = 0 with a
 // zero u_hat column, as an exactly zero column is.  A rotation only ever
@@ -149,6 +150,8 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
   __shared__ double nrm2[1024];   // squared column norms, kept current through the sweep
   __shared__ int rnk[1024];
   __shared__ int rotated;
+  __shared__ int nrot_sh[2];   // rotations of the sweep, by sweep parity
+  __shared__ int need_sh;      // the all-pairs test found a pair to rotate
   __shared__ double thr2_sh;   // tol^2 ||X||_F^2: squared norm at or below which a column is numerically zero
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
@@ -164,10 +167,18 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
   const double tol2 = tol * tol;
   int sweep = 0;
   bool converged = (l < 2);
-  if (tid == 0) thr2_sh = 0.0;
+  if (tid == 0) {
+    thr2_sh = 0.0;
+    nrot_sh[0] = nrot_sh[1] = 0;
+  }
   for (; sweep < max_sweeps && !converged; ++sweep) {
     __syncthreads();
-    if (tid == 0) rotated = 0;
+    const int prev_rot = nrot_sh[(sweep + 1) & 1];   // the previous sweep's rotations
+    if (tid == 0) {
+      rotated = 0;
+      nrot_sh[sweep & 1] = 0;
+      need_sh = 0;
+    }
     for (int p = w; p < l; p += nw) {
       double ss = 0.0;
       for (int i = lane; i < l; i += 64) ss += xs[p * LX + i] * xs[p * LX + i];
@@ -185,6 +196,55 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
       __syncthreads();
     }
     const double thr2 = thr2_sh;
+    // After a sweep that rotated at most a quarter of the pairs, the next one often rotates none.  A sweep
+    // that rotates none tests every pair on the unchanged X, so the same test applied at once to X^T X
+    // (upper 16 x 16 tiles on the FP64 MFMA, the squared norms of this sweep on the diagonal) ends the
+    // iteration without it; the Gram's entries differ from the pair groups' dot products only in the order of
+    // summation.  Lane (ci, g) supplies rows 16 s + 4 g + e of its column for MFMA step e; accumulator
+    // element r of lane L is G(16 ti + L / 16 + 4 r, 16 tj + L % 16).
+    if (sweep > 0 && 4 * prev_rot <= l * (l - 1) / 2) {
+      const int nt16 = (l + 15) / 16;
+      const int ntile = nt16 * (nt16 + 1) / 2;
+      const int ci = lane & 15, g = lane >> 4;
+      const int rows16 = nt16 * 16;   // rows l .. rows16 - 1 of X are zero
+      for (int tix = w; tix < ntile; tix += nw) {
+        int ti = 0, rem = tix;
+        while (rem >= nt16 - ti) {
+          rem -= nt16 - ti;
+          ++ti;
+        }
+        const int tj = ti + rem;
+        const double* xa = xs + min(16 * ti + ci, l - 1) * LX + 4 * g;
+        const double* xb = xs + min(16 * tj + ci, l - 1) * LX + 4 * g;
+        f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int r0 = 0; r0 < rows16; r0 += 16) {
+          const double2 a0 = *reinterpret_cast<const double2*>(xa + r0);
+          const double2 a1 = *reinterpret_cast<const double2*>(xa + r0 + 2);
+          const double2 b0 = *reinterpret_cast<const double2*>(xb + r0);
+          const double2 b1 = *reinterpret_cast<const double2*>(xb + r0 + 2);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b0.x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b0.y, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b1.x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b1.y, acc, 0, 0, 0);
+        }
+        bool need = false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int p = 16 * ti + (lane >> 4) + 4 * r, q = 16 * tj + (lane & 15);
+          if (p < q && q < l) {
+            const double al = nrm2[p], be = nrm2[q], ga = acc[r];
+            need = need || (al > thr2 && be > thr2 && ga * ga > tol2 * (al * be));
+          }
+        }
+        if (need) need_sh = 1;
+      }
+      __syncthreads();
+      if (need_sh == 0) {   // uniform
+        converged = true;
+        break;
+      }
+    }
+    int my_rot = 0;
     for (int round = 0; round < m1; ++round) {
       for (int pi = slot; pi < npairs; pi += nslots) {
         // circle method: position 0 stays, the others advance by one each round
@@ -223,6 +283,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
           }
           if (sub == 0) {
             rotated = 1;
+            ++my_rot;
             nrm2[p] = al - t * ga;
             nrm2[q] = be + t * ga;
           }
@@ -230,6 +291,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
       }
       __syncthreads();
     }
+    if (my_rot) atomicAdd(&nrot_sh[sweep & 1], my_rot);
     converged = (rotated == 0);
   }
   if (tid == 0) {
