@@ -13,7 +13,10 @@
 //     the next pivot p (largest residual, lowest index on ties) and forms
 //     q_{j+1} from y_p by Gram-Schmidt twice.
 // One launch per step; the panel is read once per step (it stays in the
-// last-level cache for the sizes of a sketch).
+// last-level cache for the sizes of a sketch): a block takes 256 columns, a
+// quarter of its threads a quarter of the rows each, every value of a
+// thread's share loaded before any is used, so that the step is bound by the
+// panel's bandwidth rather than by a chain of load latencies.
 //
 // The column ID then needs Z = S11^-1 S with S11 = S(:, J) upper triangular
 // (Z(:, J) = I, Z elsewhere T = S11^-1 S12): one thread per column runs the
@@ -26,8 +29,11 @@ namespace rsvd {
 
 namespace {
 
-constexpr int kCpThreads = 256;     // threads (columns) per block of the step kernel
+constexpr int kCpThreads = 1024;    // threads per block of the step kernel
+constexpr int kCpCols = 256;        // columns per block: 256 threads per quarter of the rows
+constexpr int kCpGroups = kCpThreads / kCpCols;
 constexpr int kCpMaxL = 128;        // rows of the short wide matrix
+constexpr int kCpRows = kCpMaxL / kCpGroups;   // rows per wave at most
 constexpr int kSolveThreads = 64;   // columns per block of the triangular solve
 
 // Block argmax of (v, c): the larger value, the lower index on ties; invalid entries carry v = -1.
@@ -56,6 +62,7 @@ __device__ void elect_and_build(const T* __restrict__ Y, int64_t ld, int l, int 
   const int tid = threadIdx.x;
   __shared__ double vsh[kCpMaxL];
   __shared__ double wsh[kCpMaxL];
+  __shared__ double part[kCpThreads];
   __shared__ int piv;
   double v = -1.0;
   int c = -1;
@@ -69,25 +76,50 @@ __device__ void elect_and_build(const T* __restrict__ Y, int64_t ld, int l, int 
   __syncthreads();
   const int p = piv;
   if (p < 0) return;   // no column left (cannot happen for j1 < min(l, N))
-  // first projection: v = y_p - sum_i q_i S(i, p)
-  if (tid < l) {
-    double x = static_cast<double>(Y[(int64_t)tid * ld + p]);
-    for (int i = 0; i < j1; ++i) x -= Q[(int64_t)i * LQ + tid] * S[(int64_t)i * ldS + p];
-    vsh[tid] = x;
-  }
+  // Q has j1 vectors of l entries (Q(i, t) at Q[i*LQ + t], L2-resident).  The sums over i below take thread
+  // (t = tid % 128, part h = tid / 128) over one of kNh contiguous ranges of i, unrolled so that its loads are
+  // in flight together, and add the parts in order; Q^T v takes one wave per vector.
+  constexpr int kNh = kCpThreads / 128;
+  const int t = tid & 127, h = tid >> 7;
+  const int ib = j1 * h / kNh, ie = j1 * (h + 1) / kNh;
+  auto q_times = [&](const double* coef) {   // part[tid] = sum over this thread's i of Q(i, t) coef[i]
+    double a = 0.0;
+    if (t < l) {
+#pragma unroll 8
+      for (int i = ib; i < ie; ++i) a = fma(Q[(int64_t)i * LQ + t], coef[i], a);
+    }
+    part[tid] = a;
+  };
+  // first projection: v = y_p - Q S(:, p)
+  if (tid < j1) wsh[tid] = S[(int64_t)tid * ldS + p];
+  __syncthreads();
+  q_times(wsh);
+  __syncthreads();
+  auto part_sum = [&]() {
+    double a = 0.0;
+#pragma unroll
+    for (int hh = 0; hh < kNh; ++hh) a += part[tid + 128 * hh];
+    return a;
+  };
+  if (tid < l) vsh[tid] = static_cast<double>(Y[(int64_t)tid * ld + p]) - part_sum();
   __syncthreads();
   // second projection: w = Q^T v, v -= Q w
-  if (tid < j1) {
-    double w = 0.0;
-    for (int t = 0; t < l; ++t) w += Q[(int64_t)tid * LQ + t] * vsh[t];
-    wsh[tid] = w;
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll 4
+    for (int i = wv; i < j1; i += kCpThreads / 64) {
+      double a = 0.0;
+      if (lane < l) a = Q[(int64_t)i * LQ + lane] * vsh[lane];
+      if (lane + 64 < l) a = fma(Q[(int64_t)i * LQ + lane + 64], vsh[lane + 64], a);
+      a = wave_sum(a);
+      if (lane == 0) wsh[i] = a;
+    }
   }
   __syncthreads();
+  q_times(wsh);
+  __syncthreads();
   double x = 0.0;
-  if (tid < l) {
-    x = vsh[tid];
-    for (int i = 0; i < j1; ++i) x -= Q[(int64_t)i * LQ + tid] * wsh[i];
-  }
+  if (tid < l) x = vsh[tid] - part_sum();
   double ss = wave_sum(x * x);
   if ((tid & 63) == 0) sv[tid >> 6] = ss;
   __syncthreads();
@@ -101,7 +133,30 @@ __device__ void elect_and_build(const T* __restrict__ Y, int64_t ld, int l, int 
   }
 }
 
-// Norms of every column and the first pivot.
+// Rows [r0, r0 + nr) of column c (nr <= kCpRows), all loaded before any is used, so that a wave has its
+// whole share of the column in flight at once; rows past the end read as zero.
+template <typename T>
+__device__ __forceinline__ void load_rows(const T* __restrict__ Y, int64_t ld, int64_t c, bool valid, int r0, int nr,
+                                          double (&y)[kCpRows]) {
+#pragma unroll
+  for (int u = 0; u < kCpRows; ++u) y[u] = (valid && u < nr) ? static_cast<double>(Y[(int64_t)(r0 + u) * ld + c]) : 0.0;
+}
+
+// The four waves' partial sums of a column, added in wave order; returned to every thread of the column.
+__device__ __forceinline__ double column_sum(double v, double* red) {
+  const int lane = threadIdx.x & (kCpCols - 1), grp = threadIdx.x / kCpCols;
+  red[grp * kCpCols + lane] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int g = 0; g < kCpGroups; ++g) t += red[g * kCpCols + lane];
+  __syncthreads();
+  return t;
+}
+
+// Norms of every column and the first pivot.  Block b holds columns 256 b .. 256 b + 255 (thread tid: column
+// tid % 256) and threads [256 g, 256 g + 256) rows [g R, g R + R), R = ceil(l / 4).  One block per compute
+// unit at the sizes of a sketch: the election's ticket counter takes one atomic per block.
 template <typename T>
 __global__ __launch_bounds__(kCpThreads) void cpqr_init_kernel(const T* __restrict__ Y, int64_t ld, int64_t N, int l,
                                                                double* Q, int LQ, const double* S, int64_t ldS,
@@ -109,16 +164,21 @@ __global__ __launch_bounds__(kCpThreads) void cpqr_init_kernel(const T* __restri
                                                                int* blkidx, unsigned* counter, int* J) {
   __shared__ double sv[kCpThreads / 64];
   __shared__ int sc[kCpThreads / 64];
+  __shared__ double red[kCpThreads];
   __shared__ bool last;
-  const int64_t c = (int64_t)blockIdx.x * kCpThreads + threadIdx.x;
+  const int lane = threadIdx.x & (kCpCols - 1), grp = threadIdx.x / kCpCols;
+  const int64_t c = (int64_t)blockIdx.x * kCpCols + lane;
+  const int R = (l + kCpGroups - 1) / kCpGroups;
+  const int r0 = grp * R, nr = max(0, min(R, l - r0));
+  double y[kCpRows];
+  load_rows<T>(Y, ld, c, c < N, r0, nr, y);
+  double part = 0.0;
+#pragma unroll
+  for (int u = 0; u < kCpRows; ++u) part = fma(y[u], y[u], part);
+  const double s = column_sum(part, red);
   double v = -1.0;
   int ci = -1;
-  if (c < N) {
-    double s = 0.0;
-    for (int t = 0; t < l; ++t) {
-      const double y = static_cast<double>(Y[(int64_t)t * ld + c]);
-      s += y * y;
-    }
+  if (grp == 0 && c < N) {
     nrm2[c] = s;
     orig[c] = s;
     v = s;
@@ -138,7 +198,8 @@ __global__ __launch_bounds__(kCpThreads) void cpqr_init_kernel(const T* __restri
   if (threadIdx.x == 0) *counter = 0u;
 }
 
-// Step j: row j of S, downdated norms, and (when another step follows) the next pivot and q_{j+1}.
+// Step j: row j of S, downdated norms, and (when another step follows) the next pivot and q_{j+1}.  Layout as
+// the init kernel.
 template <typename T>
 __global__ __launch_bounds__(kCpThreads) void cpqr_step_kernel(const T* __restrict__ Y, int64_t ld, int64_t N, int l,
                                                                int j, int k, double* Q, int LQ, double* S,
@@ -148,45 +209,57 @@ __global__ __launch_bounds__(kCpThreads) void cpqr_step_kernel(const T* __restri
   __shared__ double qs[kCpMaxL];
   __shared__ double sv[kCpThreads / 64];
   __shared__ int sc[kCpThreads / 64];
+  __shared__ double red[kCpThreads];
+  __shared__ int recompute;   // some column of the block takes the norm recomputation
   __shared__ bool last;
   const int tid = threadIdx.x;
+  const int lane = tid & (kCpCols - 1), grp = tid / kCpCols;
+  const int64_t c = (int64_t)blockIdx.x * kCpCols + lane;
+  const bool valid = c < N;
+  const int R = (l + kCpGroups - 1) / kCpGroups;
+  const int r0 = grp * R, nr = max(0, min(R, l - r0));
+  double y[kCpRows];
+  load_rows<T>(Y, ld, c, valid, r0, nr, y);
   if (tid < l) qs[tid] = Q[(int64_t)j * LQ + tid];
+  if (tid == 0) recompute = 0;
   __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * kCpThreads + tid;
-  double v = -1.0;
-  int ci = -1;
-  if (c < N) {
-    // four independent partial sums, so that the column's loads are in flight together
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int t = 0;
-    for (; t + 4 <= l; t += 4) {
-      s0 += qs[t] * static_cast<double>(Y[(int64_t)t * ld + c]);
-      s1 += qs[t + 1] * static_cast<double>(Y[(int64_t)(t + 1) * ld + c]);
-      s2 += qs[t + 2] * static_cast<double>(Y[(int64_t)(t + 2) * ld + c]);
-      s3 += qs[t + 3] * static_cast<double>(Y[(int64_t)(t + 3) * ld + c]);
-    }
-    for (; t < l; ++t) s0 += qs[t] * static_cast<double>(Y[(int64_t)t * ld + c]);
-    const double s = (s0 + s1) + (s2 + s3);
-    S[(int64_t)j * ldS + c] = s;
-    if (j + 1 >= k) return;   // the last step elects no pivot: its norms are not needed
-    double r = nrm2[c];
-    if (r >= 0.0) {
-      r -= s * s;
-      // LAPACK's safeguard: recompute once the residual is below sqrt(eps) of the original norm squared
-      if (r <= 1.4901161193847656e-08 * orig[c]) {
-        r = 0.0;
-        for (int t = 0; t < l; ++t) {
-          double x = static_cast<double>(Y[(int64_t)t * ld + c]);
-          for (int i = 0; i <= j; ++i) x -= Q[(int64_t)i * LQ + t] * S[(int64_t)i * ldS + c];
-          r += x * x;
+  double part = 0.0;
+#pragma unroll
+  for (int u = 0; u < kCpRows; ++u)
+    if (u < nr) part = fma(qs[r0 + u], y[u], part);
+  const double s = column_sum(part, red);
+  if (grp == 0 && valid) S[(int64_t)j * ldS + c] = s;
+  if (j + 1 >= k) return;   // uniform: the last step elects no pivot, its norms are not needed
+  // downdated norm; LAPACK's safeguard recomputes it from the residual once it is below sqrt(eps) of the
+  // original norm squared (every wave its rows, summed as above)
+  double r = valid ? nrm2[c] : -1.0;
+  const bool cand = r >= 0.0;
+  if (cand) r -= s * s;
+  const bool redo = cand && r <= 1.4901161193847656e-08 * orig[c];
+  if (redo && grp == 0) recompute = 1;
+  __syncthreads();
+  if (recompute) {   // uniform
+    double rp = 0.0;
+    if (redo) {
+#pragma unroll
+      for (int u = 0; u < kCpRows; ++u) {
+        if (u < nr) {
+          double x = y[u];
+          for (int i = 0; i <= j; ++i) x -= Q[(int64_t)i * LQ + r0 + u] * S[(int64_t)i * ldS + c];
+          rp = fma(x, x, rp);
         }
       }
-      nrm2[c] = r;
-      v = r;
-      ci = (int)c;
     }
+    const double rr = column_sum(rp, red);
+    if (redo) r = rr;
   }
-  if (j + 1 >= k) return;   // uniform: every thread of every block leaves here on the last step
+  double v = -1.0;
+  int ci = -1;
+  if (grp == 0 && cand) {
+    nrm2[c] = r;
+    v = r;
+    ci = (int)c;
+  }
   block_argmax(v, ci, sv, sc);
   if (tid == 0) {
     blkmax[blockIdx.x] = v;
@@ -268,7 +341,7 @@ __global__ void cut_small_kernel(double* v, int n, double rel) {
 }  // namespace
 
 int cpqr_max_rows() { return kCpMaxL; }
-int64_t cpqr_blocks(int64_t N) { return (N + kCpThreads - 1) / kCpThreads; }
+int64_t cpqr_blocks(int64_t N) { return (N + kCpCols - 1) / kCpCols; }
 
 template <typename T>
 hipError_t launch_cpqr(const T* Y, int64_t ld, int64_t N, int l, int k, double* Q, int LQ, double* S, int64_t ldS,
