@@ -244,9 +244,12 @@ template <typename TP, typename TO, int NB, bool VEC, bool OUT_RM>
 __global__ __launch_bounds__(256) void tn_pipe_kernel(const float* __restrict__ A, int64_t lda, int64_t K, int64_t N,
                                                       const TP* __restrict__ P, int64_t ldp, int ncols,
                                                       TO* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                      int64_t kchunk, bool upper,
+                                                      int64_t kchunk, bool upper, TO* __restrict__ out_skip,
                                                       const int* __restrict__ skip) {
-  if (skip && *skip) return;   // R^-1 = I (a skipped second CholeskyQR pass): copy_on_skip_kernel copies
+  if (skip && *skip) {   // a skipped second CholeskyQR pass (uniform): write elsewhere, or nothing
+    if (!out_skip) return;
+    out = out_skip;
+  }
   __shared__ V4<float> ps[2][NB * 4 * 64];
   typedef Mma<float> M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -348,9 +351,12 @@ template <typename TA, typename TP, typename TC, typename TO, int NB, bool VEC, 
 __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64_t lda, int64_t K, int64_t N,
                                                  const TP* __restrict__ P, int64_t ldp, int ncols,
                                                  TO* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                 int64_t kchunk, bool upper,
+                                                 int64_t kchunk, bool upper, TO* __restrict__ out_skip,
                                                  const int* __restrict__ skip) {
-  if (skip && *skip) return;   // R^-1 = I (a skipped second CholeskyQR pass): copy_on_skip_kernel copies
+  if (skip && *skip) {   // a skipped second CholeskyQR pass (uniform): write elsewhere, or nothing
+    if (!out_skip) return;
+    out = out_skip;
+  }
   __shared__ V4<TC> ps[NB * 4 * 64];
   typedef Mma<TC> M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -577,7 +583,12 @@ template <typename TP, int NCT, bool TRI>
 __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float* __restrict__ A, int64_t lda, int K, int64_t N,
                                                           const TP* __restrict__ P, int64_t ldp, int ncols,
                                                           TP* __restrict__ out, int64_t ldo, bool vec_out,
-                                                          bool rowmajor) {
+                                                          bool rowmajor, TP* __restrict__ out_skip,
+                                                          const int* __restrict__ skip) {
+  if (skip && *skip) {   // a skipped second CholeskyQR pass (uniform): write elsewhere, or nothing
+    if (!out_skip) return;
+    out = out_skip;
+  }
   constexpr int KS = kApplyKMax / 4;   // MFMA k-steps of a task at most
   __shared__ TP ps[kApplyKMax * kApplyPitch];
   typedef Mma<TP> M;
@@ -669,21 +680,23 @@ __global__ __launch_bounds__(kApplyThreads) void apply_small_kernel(const float*
 
 template <typename TP>
 hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, const TP* P, int64_t ldp, int ncols,
-                              TP* out, int64_t ldo, bool tri, bool rowmajor, hipStream_t s) {
+                              TP* out, int64_t ldo, bool tri, bool rowmajor, hipStream_t s, TP* out_skip = nullptr,
+                              const int* skip = nullptr) {
   const int nct = (ncols + 15) / 16;
   const int64_t ntask = (N + 15) / 16;
   const int wpg = kApplyThreads / 64;
   const unsigned grid = (unsigned)std::min<int64_t>((ntask + wpg - 1) / wpg, 256);   // each workgroup stages P once
-  const bool vec = (ldo % 4 == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
+  const bool vec = (ldo % 4 == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(out_skip) & 15) == 0);
   switch (nct) {
 #define RSVD_APPLY_CASE(N_)                                                                                       \
   case N_:                                                                                                        \
     if (tri)                                                                                                      \
       hipLaunchKernelGGL((apply_small_kernel<TP, N_, true>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, P, \
-                         ldp, ncols, out, ldo, vec, rowmajor);                                                    \
+                         ldp, ncols, out, ldo, vec, rowmajor, out_skip, skip);                                    \
     else                                                                                                          \
       hipLaunchKernelGGL((apply_small_kernel<TP, N_, false>), dim3(grid), dim3(kApplyThreads), 0, s, A, lda, K, N, \
-                         P, ldp, ncols, out, ldo, vec, rowmajor);                                                 \
+                         P, ldp, ncols, out, ldo, vec, rowmajor, out_skip, skip);                                 \
     break;
     RSVD_APPLY_CASE(1) RSVD_APPLY_CASE(2) RSVD_APPLY_CASE(3) RSVD_APPLY_CASE(4)
     RSVD_APPLY_CASE(5) RSVD_APPLY_CASE(6) RSVD_APPLY_CASE(7) RSVD_APPLY_CASE(8)
@@ -693,37 +706,17 @@ hipError_t launch_apply_small(const float* A, int64_t lda, int K, int64_t N, con
   return hipGetLastError();
 }
 
-// out(c, j) = A(c, j) (A K x N row-major as in the product, out[c*ldo + j]) when *skip is set: the apply of
-// R^-1 = I after a skipped second CholeskyQR pass, whose product kernel returned at once.
-template <typename T>
-__global__ __launch_bounds__(256) void copy_on_skip_kernel(const T* __restrict__ A, int64_t lda, int64_t N,
-                                                           T* __restrict__ out, int64_t ldo, bool vec,
-                                                           const int* __restrict__ skip) {
-  if (!*skip) return;
-  const int c = blockIdx.y;
-  const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-  if (j >= N) return;
-  const T* a = A + (int64_t)c * lda + j;
-  T* o = out + (int64_t)c * ldo + j;
-  if (vec && j + 4 <= N) {
-    v4_store(o, v4_load(a));
-  } else {
-    for (int e = 0; e < 4; ++e)
-      if (j + e < N) o[e] = a[e];
-  }
-}
-
 template <typename TA, typename TP, typename TC, typename TO>
 static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols,
                               TO* out, int64_t ldo, int64_t part_stride, int splits, bool out_rowmajor, bool upper,
-                              hipStream_t s, const int* skip = nullptr) {
+                              hipStream_t s, const int* skip = nullptr, TO* out_skip = nullptr) {
   if (N <= 0 || ncols <= 0) return hipSuccess;
   if (splits < 1 || out_rowmajor) splits = 1;
   if constexpr (std::is_same<TA, float>::value && std::is_same<TP, float>::value && std::is_same<TO, float>::value &&
                 std::is_same<TC, float>::value) {
-    if (!skip && splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
+    if (splits == 1 && K <= kApplyKMax && ncols <= kApplyKMax && K * lda < (int64_t(1) << 32) &&
         (int64_t)ncols * ldp < (int64_t(1) << 32))
-      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, upper, out_rowmajor, s);
+      return launch_apply_small(A, lda, (int)K, N, P, ldp, ncols, out, ldo, upper, out_rowmajor, s, out_skip, skip);
   }
   int64_t kchunk = ((K + splits - 1) / splits + KC - 1) / KC * KC;
   if (kchunk < KC) kchunk = KC;
@@ -738,17 +731,17 @@ static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, co
       if (out_rowmajor) {
         if (vec)
           hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper, skip);
+                             ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
         else
           hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper, skip);
+                             ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
       } else {
         if (vec)
           hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper, skip);
+                             ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
         else
           hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper, skip);
+                             ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
       }
     });
   } else {
@@ -756,29 +749,19 @@ static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, co
       if (out_rowmajor) {
         if (vec)
           hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper, skip);
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
         else
           hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper, skip);
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
       } else {
         if (vec)
           hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper, skip);
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
         else
           hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper, skip);
+                             ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
       }
     });
-  }
-  if (skip) {
-    if constexpr (std::is_same<TA, TO>::value) {
-      if (splits != 1 || out_rowmajor || ncols != K) return hipErrorInvalidValue;
-      const bool cvec = vec && (ldo % 4 == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
-      hipLaunchKernelGGL((copy_on_skip_kernel<TO>), dim3((unsigned)((N + 1023) / 1024), (unsigned)ncols), dim3(256),
-                         0, s, A, lda, N, out, ldo, cvec, skip);
-    } else {
-      return hipErrorInvalidValue;
-    }
   }
   return hipGetLastError();
 }
@@ -819,8 +802,9 @@ hipError_t launch_reduce2(const TP* part, int S, int group, int64_t pstride, int
 // kernel where it applies, otherwise the general product with each column group's contraction cut at its
 // last column.
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const float* P, int64_t ldp,
-                              int ncols, float* out, int64_t ldo, hipStream_t s, const int* skip) {
-  return launch_tn_k<float, float, float, float>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s, skip);
+                              int ncols, float* out, int64_t ldo, hipStream_t s, const int* skip, float* out_skip) {
+  return launch_tn_k<float, float, float, float>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s, skip,
+                                                 out_skip);
 }
 
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
@@ -833,9 +817,10 @@ hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N,
 }
 
 hipError_t launch_apply_upper(const double* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
-                              int ncols, double* out, int64_t ldo, hipStream_t s, const int* skip) {
+                              int ncols, double* out, int64_t ldo, hipStream_t s, const int* skip,
+                              double* out_skip) {
   return launch_tn_k<double, double, double, double>(A, lda, K, N, P, ldp, ncols, out, ldo, 0, 1, false, true, s,
-                                                     skip);
+                                                     skip, out_skip);
 }
 
 // Explicit instantiations used by the host orchestration.

@@ -20,14 +20,17 @@ template <typename TA, typename TX, typename TC, typename TO>
 hipError_t launch_nn(const TA* A, int64_t lda, int64_t rows, int64_t K, const TX* X, int64_t ldx, int ncols, TO* out,
                      int64_t ldo, int64_t part_stride, int splits, hipStream_t s);
 // out = A P with P upper triangular (P(i, c) = 0 for i > c); layouts as launch_tn with one range.  skip
-// (optional, ncols == K): when *skip is set on the device, P is taken as I and A is copied (a skipped second
-// CholeskyQR pass); the product kernels return at once.
+// (optional): when *skip is set on the device the product goes to out_skip instead of out, or nowhere when
+// out_skip is null (the two applies of a CholeskyQR whose second pass is skipped: the first writes the final
+// basis, the second nothing).
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const float* P, int64_t ldp,
-                              int ncols, float* out, int64_t ldo, hipStream_t s, const int* skip = nullptr);
+                              int ncols, float* out, int64_t ldo, hipStream_t s, const int* skip = nullptr,
+                              float* out_skip = nullptr);
 hipError_t launch_apply_upper(const float* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
                               int ncols, double* out, int64_t ldo, hipStream_t s);
 hipError_t launch_apply_upper(const double* A, int64_t lda, int64_t K, int64_t N, const double* P, int64_t ldp,
-                              int ncols, double* out, int64_t ldo, hipStream_t s, const int* skip = nullptr);
+                              int ncols, double* out, int64_t ldo, hipStream_t s, const int* skip = nullptr,
+                              double* out_skip = nullptr);
 // tn: out[s][c][j] = sum_{i in split s} A[i][j] P(i, c); A K x N row-major, P panel (P[c*ldp + i]).
 template <typename TA, typename TP, typename TC, typename TO>
 hipError_t launch_tn(const TA* A, int64_t lda, int64_t K, int64_t N, const TP* P, int64_t ldp, int ncols, TO* out,

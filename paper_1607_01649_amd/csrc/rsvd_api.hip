@@ -353,17 +353,18 @@ template <typename T> struct Path {
   }
 
   // out = X R^-1 (R^-1 upper triangular, nc x nc at leading dimension LPc).
-  // With `skip` (the second pass of a skippable orthonormalisation, nc > 128 only: below that the short apply
-  // is bound by the same panel traffic as a copy), a set *skip turns the product into a copy of X.
+  // With `skip`, a set *skip on the device sends the product to out_skip instead of out (nowhere when
+  // out_skip is null).
   hipError_t apply_rinv(const T* X, int64_t ld, int64_t rows, int nc, const T* rinv, int LPc, T* out,
-                        const int* skip = nullptr) {
-    return launch_apply_upper(X, ld, nc, rows, rinv, LPc, nc, out, ld, st, nc > 128 ? skip : nullptr);
+                        const int* skip = nullptr, T* out_skip = nullptr) {
+    return launch_apply_upper(X, ld, nc, rows, rinv, LPc, nc, out, ld, st, skip, out_skip);
   }
 
   // out = orth(X) for an nc-column panel: CholeskyQR2 (two passes of G = X^T X = R^T R, X <- X R^-1).
   // may_skip (a basis that is multiplied again, not the one Stage B uses): the second pass is
   // skipped on the device when the first pass's factor bounds the column-scaled condition number of X by
-  // kOrthSkipKappa (its Gram, sum and Cholesky return at once, the apply multiplies by I or copies), since one pass
+  // kOrthSkipKappa (the first apply then writes `out`, which must not alias X, and the second pass's Gram, sum,
+  // Cholesky and apply return at once), since one pass
   // then leaves a basis orthonormal to about kappa^2 u plus kappa times the panel's rounding.
   rsvd_status orth(const T* X, int64_t ld, int64_t rows, int nc, int splits, T* out, bool may_skip = false) {
     const int LPc = lp16(nc);
@@ -372,13 +373,13 @@ template <typename T> struct Path {
     T* tmp = P.at<T>(L.T);
     int* flags = P.at<int>(L.flags);
     double* scr = P.at<double>(L.scr_chol);
-    int* skip = may_skip ? flags + kSkipFlag : nullptr;
+    int* skip = (may_skip && out != X) ? flags + kSkipFlag : nullptr;
     RS_TRY(gram(X, ld, rows, nc, splits, G));
     HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st, skip, kOrthSkipKappa));
-    HIP_TRY(apply_rinv(X, ld, rows, nc, rinv, LPc, tmp));
+    HIP_TRY(apply_rinv(X, ld, rows, nc, rinv, LPc, tmp, skip, out));   // skipped: this is the basis
     RS_TRY(gram(tmp, ld, rows, nc, splits, G, skip));
     HIP_TRY(launch_chol<T>(G, LPc, nc, LPc, tau, rinv, nullptr, nullptr, scr, flags, st, nullptr, 0.0, skip));
-    HIP_TRY(apply_rinv(tmp, ld, rows, nc, rinv, LPc, out, skip));
+    HIP_TRY(apply_rinv(tmp, ld, rows, nc, rinv, LPc, out, skip));      // skipped: nothing to do
     return RSVD_OK;
   }
 
