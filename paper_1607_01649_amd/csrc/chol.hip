@@ -300,16 +300,16 @@ __global__ __launch_bounds__(kCholThreads) void chol_blk_kernel(const double* __
     // ||R S||_F ||S^-1 R^-1||_F, with ||R S||_F^2 = l (column j of R has squared norm G_jj) and
     // ||S^-1 R^-1||_F^2 = sum_i G_ii ||column i of R^-T||^2.  One pass of CholeskyQR then leaves X R^-1
     // orthonormal to about kappa^2 u (the FP64 Gram) plus kappa times the panel's rounding.
+    // Every entry (i, c), c >= i, of R^-1 by its own thread (about a dozen independent LDS reads each).
     __shared__ double kpart[kCholWaves];
     double f = 0.0;
-    for (int i = tid; i < l; i += kCholThreads) {
-      const int bi = i >> 4;
-      double cs = 0.0;
-      for (int c = i; c < l; ++c) {
+    for (int e = tid; e < l * l; e += kCholThreads) {
+      const int i = e / l, c = e - (e / l) * l;
+      if (c >= i) {
+        const int bi = i >> 4;
         const double v = (c >> 4) == bi ? Wd[bi * kCholB * kWdPitch + (c & 15) * kWdPitch + (i & 15)] : M[c * MP + i];
-        cs = fma(v, v, cs);
+        f = fma(gdiag[i] * v, v, f);
       }
-      f = fma(gdiag[i], cs, f);
     }
     f = wave_sum(f);
     if (lane == 0) kpart[wv] = f;

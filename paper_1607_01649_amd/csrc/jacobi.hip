@@ -38,7 +38,8 @@ __device__ __forceinline__ int rr_player(int pos, int round, int le) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (le - 1);
 }
 
-// Lanes per column pair.
+// Lanes per column pair (16: four pairs per wave; eight lanes per pair, which issues the rotation's own
+// arithmetic once per eight pairs, measured 10 % slower at l = 110: fewer waves hide less of its latency).
 constexpr int kPairLanes = 16;
 
 // Value of the lane chosen by a DPP pattern (applied to both halves of the double).
@@ -50,13 +51,13 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Sum over each aligned group of 16 lanes: lane ^ 1, lane ^ 2 (quad permutes), then the mirror images within 8
-// and within 16 lanes, each of which pairs a lane with one of the other half.
+// Sum over each aligned group of kPairLanes lanes: lane ^ 1, lane ^ 2 (quad permutes), then the mirror image
+// within 8 lanes (and within 16 for groups of 16), each of which pairs a lane with one of the other half.
 __device__ __forceinline__ double group_sum(double v) {
   v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
   v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
   v += dpp_f64<0x141>(v);   // row_half_mirror
-  v += dpp_f64<0x140>(v);   // row_mirror
+  if constexpr (kPairLanes == 16) v += dpp_f64<0x140>(v);   // row_mirror
   return v;
 }
 
@@ -142,8 +143,9 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
                                             double* __restrict__ sigma, double* __restrict__ uhat_d,
                                             TU* __restrict__ uhat_p, TU* __restrict__ vhat_p,
                                             int* __restrict__ flags) {
-  // A lane of a pair group holds rows 2 sub + 32 h and the next one, h < NH; LX = 32 NH >= LP.
+  // A lane of a pair group holds rows 2 (sub + kPairLanes h) and the next one, h < NV; LX = 32 NH >= LP.
   constexpr int LX = 32 * NH;
+  constexpr int NV = LX / (2 * kPairLanes);   // double2 of a column per lane
   extern __shared__ double2 smem2[];   // 16-byte aligned: accessed as double2
   double* xs = reinterpret_cast<double*>(smem2);   // column p of X = row p of R, at xs[p*LX + i]; rows l .. LX-1 zero
   __shared__ double nrm[1024];
@@ -257,15 +259,15 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
         if (p >= l || q >= l) continue;   // the bye of an odd l (uniform within the pair group)
         double2* xp = reinterpret_cast<double2*>(xs + p * LX) + sub;
         double2* xq = reinterpret_cast<double2*>(xs + q * LX) + sub;
-        double2 av[NH], bv[NH];
+        double2 av[NV], bv[NV];
         double ga = 0.0;
 #pragma unroll
-        for (int h = 0; h < NH; ++h) {
+        for (int h = 0; h < NV; ++h) {
           av[h] = xp[h * kPairLanes];
           bv[h] = xq[h * kPairLanes];
         }
 #pragma unroll
-        for (int h = 0; h < NH; ++h) ga += av[h].x * bv[h].x + av[h].y * bv[h].y;
+        for (int h = 0; h < NV; ++h) ga += av[h].x * bv[h].x + av[h].y * bv[h].y;
         ga = group_sum(ga);
         const double al = nrm2[p], be = nrm2[q];
         if (al > thr2 && be > thr2 && ga * ga > tol2 * (al * be)) {
@@ -277,7 +279,7 @@ __device__ __forceinline__ void jacobi_body(const double* __restrict__ R, int l,
           const double c = rsq_nr(1.0 + t * t);
           const double s = c * t;
 #pragma unroll
-          for (int h = 0; h < NH; ++h) {
+          for (int h = 0; h < NV; ++h) {
             xp[h * kPairLanes] = make_double2(c * av[h].x - s * bv[h].x, c * av[h].y - s * bv[h].y);
             xq[h * kPairLanes] = make_double2(s * av[h].x + c * bv[h].x, s * av[h].y + c * bv[h].y);
           }
@@ -347,7 +349,7 @@ hipError_t launch_jacobi(const double* R, int l, int LP, double tol, int max_swe
                          TU* uhat_p, TU* vhat_p, double* scratch, int* flags, hipStream_t s) {
   if (l < 1 || l > 1024) return hipErrorInvalidValue;
   if (LP <= 128) {
-    // rows held in LDS padded to a multiple of 32 (two per lane, 16 lanes per pair)
+    // rows held in LDS padded to a multiple of 32 (pairs of rows per lane, kPairLanes lanes per pair)
     const int nh = (LP + 31) / 32;
     static bool attr_set = false;
     if (!attr_set) {
