@@ -1198,10 +1198,13 @@ rsvd_status rsvd_plan(const rsvd_desc* d, void* d_ws, size_t ws_bytes, void* str
   p->timing = (d->flags & RSVD_TIMING) != 0;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return RSVD_E_HIP; }
   if (p->timing) {
+    // Timing-only events (read after the call's stream synchronisation): no system-scope fence, whose cache
+    // write-back and invalidation would otherwise stall the next kernel at every event.
+    constexpr unsigned kEvFlags = hipEventDisableSystemFence;
     for (int i = 0; i < 8; ++i)
-      if (hipEventCreate(&p->ev[i]) != hipSuccess) { delete p; return RSVD_E_HIP; }
+      if (hipEventCreateWithFlags(&p->ev[i], kEvFlags) != hipSuccess) { delete p; return RSVD_E_HIP; }
     for (int i = 0; i < 2 * rsvd_plan_s::kGemmEv; ++i)
-      if (hipEventCreate(&p->gev[i]) != hipSuccess) { delete p; return RSVD_E_HIP; }
+      if (hipEventCreateWithFlags(&p->gev[i], kEvFlags) != hipSuccess) { delete p; return RSVD_E_HIP; }
   }
   RSVD_LOGF("plan m=%lld n=%lld l=%d LP=%d splits nn=%d tn=%d gm=%d gn=%d ws=%zu", (long long)d->m,
             (long long)d->n, L.l, L.LP, L.s_nn, L.s_tn, L.s_gm, L.s_gn, L.total);
