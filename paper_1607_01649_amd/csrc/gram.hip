@@ -89,8 +89,9 @@ __device__ __forceinline__ void lds_barrier_g() {
 
 template <typename TI, int NCB>
 __global__ __launch_bounds__(256) void gram_kernel(const TI* __restrict__ Y, int64_t ld, int64_t K, int nc, int ntile,
-                                                   double* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                   int64_t kchunk, const int* __restrict__ skip) {
+                                                   int jfix, double* __restrict__ out, int64_t ldo,
+                                                   int64_t part_stride, int64_t kchunk,
+                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;   // a skipped second CholeskyQR pass (uniform: every thread reads the flag)
   typedef GramFmt<TI> F;
   typedef typename F::V V;
@@ -101,10 +102,16 @@ __global__ __launch_bounds__(256) void gram_kernel(const TI* __restrict__ Y, int
   __shared__ V xs0[NF][64], xs1[NF][64];
   typedef Mma<double> M;
 
-  // tile pair (I, J), I <= J, from the linear index over the upper triangle
-  int I = 0, rem = blockIdx.x;
-  while (rem >= ntile - I) { rem -= ntile - I; ++I; }
-  const int J = I + rem;
+  // tile pair (I, J), I <= J: from the linear index over the upper triangle of ntile tiles, or (jfix >= 0) the
+  // pair (blockIdx.x, jfix) of the last, partial column tile, whose NCB column blocks are only the live ones
+  int I = 0, J = jfix;
+  if (jfix >= 0) {
+    I = blockIdx.x;
+  } else {
+    int rem = blockIdx.x;
+    while (rem >= ntile - I) { rem -= ntile - I; ++I; }
+    J = I + rem;
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int split = blockIdx.y;
@@ -353,12 +360,13 @@ hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, 
   if (used != splits) return hipErrorInvalidValue;   // the consumer sums exactly `splits` partials
   const int ntile = (nc + 127) / 128;
   const int npair = ntile * (ntile + 1) / 2;
-  const int ncb = ntile == 1 ? (nc + 15) / 16 : 8;   // a single tile is as wide as the panel
+  int ncb = ntile == 1 ? (nc + 15) / 16 : 8;   // a single tile is as wide as the panel
   dim3 grid((unsigned)npair, (unsigned)used);
+  int ntile_launch = ntile, jfix = -1;
 #define RSVD_GRAM_CASE(N)                                                                                    \
   case N:                                                                                                  \
-    hipLaunchKernelGGL((gram_kernel<TI, N>), grid, dim3(256), 0, s, Y, ld, K, nc, ntile, out, ldo, part_stride, \
-                       kchunk, skip);                                                                      \
+    hipLaunchKernelGGL((gram_kernel<TI, N>), grid, dim3(256), 0, s, Y, ld, K, nc, ntile_launch, jfix, out, ldo, \
+                       part_stride, kchunk, skip);                                                         \
     break;
   if (ntile == 1) {
 #define RSVD_GRAM_SYM_CASE(N)                                                                                    \
@@ -379,22 +387,45 @@ hipError_t launch_gram(const TI* Y, int64_t ld, int64_t K, int nc, double* out, 
 #undef RSVD_GRAM_SYM_CASE
     return hipGetLastError();
   }
-  switch (ncb) {
-    RSVD_GRAM_CASE(1)
-    RSVD_GRAM_CASE(2)
-    RSVD_GRAM_CASE(3)
-    RSVD_GRAM_CASE(4)
-    RSVD_GRAM_CASE(5)
-    RSVD_GRAM_CASE(6)
-    RSVD_GRAM_CASE(7)
-    default: RSVD_GRAM_CASE(8)
+  // A last tile with fewer than 8 live column blocks (ncb_last) is left out of the tile pairs of the full tiles,
+  // which then take the same rows in more ranges (gram_tile_pairs counts only them), and its pairs (I, last)
+  // go to a second launch with ncb_last column blocks: at 520 columns 10 full pairs and 5 pairs of one block
+  // instead of 15 full pairs, 5 of them almost all padding.
+  const int nfull = nc / 128;
+  const int ncb_last = (nc - 128 * nfull + 15) / 16;
+  const bool split_last = ntile > 1 && ncb_last > 0 && ncb_last < 8;
+  for (int part = 0; part < (split_last ? 2 : 1); ++part) {
+    if (split_last && part == 0) {
+      ntile_launch = nfull;
+      grid.x = (unsigned)(nfull * (nfull + 1) / 2);
+    } else if (split_last) {
+      ncb = ncb_last;
+      jfix = nfull;
+      grid.x = (unsigned)(nfull + 1);
+    }
+    switch (ncb) {
+      RSVD_GRAM_CASE(1)
+      RSVD_GRAM_CASE(2)
+      RSVD_GRAM_CASE(3)
+      RSVD_GRAM_CASE(4)
+      RSVD_GRAM_CASE(5)
+      RSVD_GRAM_CASE(6)
+      RSVD_GRAM_CASE(7)
+      default: RSVD_GRAM_CASE(8)
+    }
   }
 #undef RSVD_GRAM_CASE
   return hipGetLastError();
 }
 
+// Workgroups per contraction range of the Gram of an nc-column panel, for choosing the number of ranges: the
+// pairs of full 128-column tiles (a partial last tile of fewer than 8 live column blocks goes to a short
+// launch of its own).
 int gram_tile_pairs(int nc) {
   const int ntile = (nc + 127) / 128;
+  const int nfull = nc / 128;
+  const int ncb_last = (nc - 128 * nfull + 15) / 16;
+  if (ntile > 1 && ncb_last > 0 && ncb_last < 8) return nfull * (nfull + 1) / 2;
   return ntile * (ntile + 1) / 2;
 }
 
