@@ -81,14 +81,14 @@ template <typename TX, typename TO, int NB, bool VEC>
 __global__ __launch_bounds__(256) void nn_pipe_kernel(const float* __restrict__ A, int64_t lda, int64_t rows,
                                                       int64_t K, const TX* __restrict__ X, int64_t ldx, int ncols,
                                                       TO* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                      int64_t kchunk) {
+                                                      int64_t kchunk, int cg_off) {
   __shared__ V4<float> xs[2][NB * 4 * 64];
   typedef Mma<float> M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * 128 + wave * 32;
   const int split = blockIdx.y;
-  const int cg0 = blockIdx.z * NB * 16;
+  const int cg0 = cg_off + blockIdx.z * NB * 16;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
 
@@ -173,14 +173,14 @@ template <typename TA, typename TX, typename TC, typename TO, int NB, bool VEC>
 __global__ __launch_bounds__(256) void nn_kernel(const TA* __restrict__ A, int64_t lda, int64_t rows, int64_t K,
                                                  const TX* __restrict__ X, int64_t ldx, int ncols,
                                                  TO* __restrict__ out, int64_t ldo, int64_t part_stride,
-                                                 int64_t kchunk) {
+                                                 int64_t kchunk, int cg_off) {
   __shared__ V4<TC> xs[NB * 4 * 64];
   typedef Mma<TC> M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int64_t rbase = (int64_t)blockIdx.x * 128 + wave * 32;
   const int split = blockIdx.y;
-  const int cg0 = blockIdx.z * NB * 16;
+  const int cg0 = cg_off + blockIdx.z * NB * 16;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = min(K, kbeg + kchunk);
 
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void tn_pipe_kernel(const float* __restrict__ 
                                                       const TP* __restrict__ P, int64_t ldp, int ncols,
                                                       TO* __restrict__ out, int64_t ldo, int64_t part_stride,
                                                       int64_t kchunk, bool upper, TO* __restrict__ out_skip,
-                                                      const int* __restrict__ skip) {
+                                                      const int* __restrict__ skip, int cg_off) {
   if (skip && *skip) {   // a skipped second CholeskyQR pass (uniform): write elsewhere, or nothing
     if (!out_skip) return;
     out = out_skip;
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void tn_pipe_kernel(const float* __restrict__ 
   const int g = lane >> 4, li = lane & 15;
   const int64_t jw = (int64_t)blockIdx.x * 256 + wave * 64;   // this wave's 64 output rows
   const int split = blockIdx.y;
-  const int cg0 = blockIdx.z * NB * 16;
+  const int cg0 = cg_off + blockIdx.z * NB * 16;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = upper ? min(min(K, kbeg + kchunk), (int64_t)cg0 + NB * 16) : min(K, kbeg + kchunk);
 
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64
                                                  const TP* __restrict__ P, int64_t ldp, int ncols,
                                                  TO* __restrict__ out, int64_t ldo, int64_t part_stride,
                                                  int64_t kchunk, bool upper, TO* __restrict__ out_skip,
-                                                 const int* __restrict__ skip) {
+                                                 const int* __restrict__ skip, int cg_off) {
   if (skip && *skip) {   // a skipped second CholeskyQR pass (uniform): write elsewhere, or nothing
     if (!out_skip) return;
     out = out_skip;
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(256) void tn_kernel(const TA* __restrict__ A, int64
   const int g = lane >> 4, li = lane & 15;
   const int64_t jw = (int64_t)blockIdx.x * 256 + wave * 64;   // this wave's 64 output rows
   const int split = blockIdx.y;
-  const int cg0 = blockIdx.z * NB * 16;
+  const int cg0 = cg_off + blockIdx.z * NB * 16;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = upper ? min(min(K, kbeg + kchunk), (int64_t)cg0 + NB * 16) : min(K, kbeg + kchunk);
 
@@ -525,28 +525,37 @@ hipError_t launch_nn(const TA* A, int64_t lda, int64_t rows, int64_t K, const TX
   if (kchunk < KC) kchunk = KC;
   int used = (int)((K + kchunk - 1) / kchunk);
   if (used < 1) used = 1;
-  int nb = nb_for(ncols);
-  int groups = (ncols + nb * 16 - 1) / (nb * 16);
+  const int nb = nb_for(ncols);
+  const int groups = (ncols + nb * 16 - 1) / (nb * 16);
   dim3 grid((unsigned)((rows + 127) / 128), (unsigned)used, (unsigned)groups);
   bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  if constexpr (std::is_same<TA, float>::value && std::is_same<TC, float>::value) {
-    RSVD_NB_SWITCH(nb, {
-      if (vec)
-        hipLaunchKernelGGL((nn_pipe_kernel<TX, TO, NB, true>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx, ncols,
-                           out, ldo, part_stride, kchunk);
-      else
-        hipLaunchKernelGGL((nn_pipe_kernel<TX, TO, NB, false>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx, ncols,
-                           out, ldo, part_stride, kchunk);
-    });
-  } else {
-    RSVD_NB_SWITCH(nb, {
-      if (vec)
-        hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, true>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
-                           ncols, out, ldo, part_stride, kchunk);
-      else
-        hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, false>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
-                           ncols, out, ldo, part_stride, kchunk);
-    });
+  // a last column group with fewer live blocks than the others goes to a launch of its own with only those
+  // blocks (at 520 columns: four groups of 8 blocks, then one of 1, instead of five of 8)
+  const int nb_last = (ncols - 16 * nb * (groups - 1) + 15) / 16;
+  const bool split_last = groups > 1 && nb_last < nb;
+  for (int part = 0; part < (split_last ? 2 : 1); ++part) {
+    const int nbv = part == 1 ? nb_last : nb;
+    const int cg_off = part == 1 ? 16 * nb * (groups - 1) : 0;
+    grid.z = (unsigned)(part == 1 ? 1 : split_last ? groups - 1 : groups);
+    if constexpr (std::is_same<TA, float>::value && std::is_same<TC, float>::value) {
+      RSVD_NB_SWITCH(nbv, {
+        if (vec)
+          hipLaunchKernelGGL((nn_pipe_kernel<TX, TO, NB, true>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
+                             ncols, out, ldo, part_stride, kchunk, cg_off);
+        else
+          hipLaunchKernelGGL((nn_pipe_kernel<TX, TO, NB, false>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
+                             ncols, out, ldo, part_stride, kchunk, cg_off);
+      });
+    } else {
+      RSVD_NB_SWITCH(nbv, {
+        if (vec)
+          hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, true>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
+                             ncols, out, ldo, part_stride, kchunk, cg_off);
+        else
+          hipLaunchKernelGGL((nn_kernel<TA, TX, TC, TO, NB, false>), grid, dim3(256), 0, s, A, lda, rows, K, X, ldx,
+                             ncols, out, ldo, part_stride, kchunk, cg_off);
+      });
+    }
   }
   return hipGetLastError();
 }
@@ -722,46 +731,54 @@ static hipError_t launch_tn_k(const TA* A, int64_t lda, int64_t K, int64_t N, co
   if (kchunk < KC) kchunk = KC;
   int used = (int)((K + kchunk - 1) / kchunk);
   if (used < 1) used = 1;
-  int nb = nb_for(ncols);
-  int groups = (ncols + nb * 16 - 1) / (nb * 16);
+  const int nb = nb_for(ncols);
+  const int groups = (ncols + nb * 16 - 1) / (nb * 16);
   dim3 grid((unsigned)((N + 255) / 256), (unsigned)used, (unsigned)groups);
   bool vec = (lda % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  if constexpr (std::is_same<TA, float>::value && std::is_same<TC, float>::value) {
-    RSVD_NB_SWITCH(nb, {
-      if (out_rowmajor) {
-        if (vec)
-          hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
-        else
-          hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
-      } else {
-        if (vec)
-          hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
-        else
-          hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
-                             ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
-      }
-    });
-  } else {
-    RSVD_NB_SWITCH(nb, {
-      if (out_rowmajor) {
-        if (vec)
-          hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
-        else
-          hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
-      } else {
-        if (vec)
-          hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
-        else
-          hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
-                             ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip);
-      }
-    });
+  // a last column group with fewer live blocks than the others: a launch of its own with only those blocks
+  const int nb_last = (ncols - 16 * nb * (groups - 1) + 15) / 16;
+  const bool split_last = groups > 1 && nb_last < nb;
+  for (int part = 0; part < (split_last ? 2 : 1); ++part) {
+    const int nbv = part == 1 ? nb_last : nb;
+    const int cg_off = part == 1 ? 16 * nb * (groups - 1) : 0;
+    grid.z = (unsigned)(part == 1 ? 1 : split_last ? groups - 1 : groups);
+    if constexpr (std::is_same<TA, float>::value && std::is_same<TC, float>::value) {
+      RSVD_NB_SWITCH(nbv, {
+        if (out_rowmajor) {
+          if (vec)
+            hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
+                               ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip, cg_off);
+          else
+            hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
+                               ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip, cg_off);
+        } else {
+          if (vec)
+            hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
+                               ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip, cg_off);
+          else
+            hipLaunchKernelGGL((tn_pipe_kernel<TP, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P, ldp,
+                               ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip, cg_off);
+        }
+      });
+    } else {
+      RSVD_NB_SWITCH(nbv, {
+        if (out_rowmajor) {
+          if (vec)
+            hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                               ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip, cg_off);
+          else
+            hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, true>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                               ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip, cg_off);
+        } else {
+          if (vec)
+            hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, true, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                               ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip, cg_off);
+          else
+            hipLaunchKernelGGL((tn_kernel<TA, TP, TC, TO, NB, false, false>), grid, dim3(256), 0, s, A, lda, K, N, P,
+                               ldp, ncols, out, ldo, part_stride, kchunk, upper, out_skip, skip, cg_off);
+        }
+      });
+    }
   }
   return hipGetLastError();
 }
