@@ -468,7 +468,8 @@ def main():
         traffic_summary(fd, wd, int(cb), sk, wl)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the factorisation runs on one GPU (its multi-GPU sharding is not implemented); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
     if args.workload == "kernel_blocks_4096":
         run_batched(args)

@@ -7,7 +7,7 @@ random diagonal D, a fast unitary transform F and a column subsampling S,
 so that Y = A Omega costs O(m n log l) instead of O(m n l); Section 14,
 item (1), pairs it with the Gaussian-probe certificate.  The paper states
 the transform as the complex DFT and allows other fast transforms.  The
-reading here, in real arithmetic (all matrices of this build are real):
+reading here, in real arithmetic (the library handles real matrices only):
 
   N      = 2^ceil(log2 n)  (rows of A's row space padded with zeros to N)
   D      = diag(d_0 .. d_{N-1}), d_i = +1 or -1 (the real unit circle)
