@@ -140,6 +140,29 @@ def test_factor_f32_matches_the_f64_oracle(m, n, rank, alpha, k, p, q, pad):
     assert orth_error(U) <= 1e-5 and orth_error(V) <= 1e-5
 
 
+def test_factor_f32_with_one_pass_bases_past_128_columns():
+    """Figure 5 at l = 200 (q = 3) on a spectrum with a gap at k and a flat tail past it: every intermediate
+    basis is well conditioned (the column-scaled Frobenius condition bound of the six panels is 204 to 289 in
+    FP64, below the 1e3 of the one-pass test), so each takes a single CholeskyQR pass, with the bound formed
+    from the blocked factor and the first apply writing the basis.  The factors match the FP64 oracle, which
+    orthonormalises every basis fully, to the FP32 bar of the other cases."""
+    m, n, k, p, q = 3000, 2000, 180, 20, 3
+    sigma = np.concatenate([np.ones(k), np.full(300, 0.5)])
+    A64 = gen.low_rank_matrix(m, n, sigma, 1e-3 / math.sqrt(n), seed=91)
+    A32 = A64.astype(np.float32)
+    G = gen.gaussian_matrix(n, k + p, seed=92)
+    ref = orc.rsvd(A32.astype(np.float64), G, q)
+    refk = ref.truncate(k)
+    U, S, V, info = run_factor(A32, k, p, q, "f32", omega=G)
+    assert info.status == 0
+    assert max_rel_sigma(S, refk.D, k) <= 1e-4
+    relgap = (ref.D[k - 1] - ref.D[k]) / ref.D[0]
+    tol = 50 * math.sqrt(max(m, n)) * U32 / relgap
+    assert subspace_sin(U, refk.U) <= tol
+    assert subspace_sin(V, refk.V) <= tol
+    assert orth_error(U) <= 1e-5 and orth_error(V) <= 1e-5
+
+
 def test_exact_low_rank_input_drops_dependent_directions():
     """rank(A) = 5 < l = 16: the leading five triplets are exact (Section 4),
     the remaining singular values are zero or at rounding level."""
