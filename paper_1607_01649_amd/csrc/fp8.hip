@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void to_fp8_kernel(const float* __restrict__ A
                                                      uint8_t* __restrict__ A8, int64_t ld8, uint8_t* __restrict__ A8T,
                                                      int64_t ldT, float* __restrict__ scale, int ntc,
                                                      int* __restrict__ flag) {
-  __shared__ uint8_t tile[128][132];
+  __shared__ __align__(16) uint8_t tile[128][132];
   __shared__ float wmax[4];
   const int t = threadIdx.x;
   const int c4 = t & 31, rg = t >> 5;
@@ -71,13 +71,9 @@ __global__ __launch_bounds__(256) void to_fp8_kernel(const float* __restrict__ A
   for (int rr = 0; rr < 16; ++rr) {
     const int ii = rg + 8 * rr;
     const int64_t i = i0 + ii;
-    uint32_t w = 0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t c = f32_to_e4m3(ldexpf(v[rr][e], -ex));
-      tile[ii][4 * c4 + e] = (uint8_t)c;
-      w |= c << (8 * e);
-    }
+    const uint32_t w = f32x4_to_e4m3(ldexpf(v[rr][0], -ex), ldexpf(v[rr][1], -ex), ldexpf(v[rr][2], -ex),
+                                     ldexpf(v[rr][3], -ex));
+    *reinterpret_cast<uint32_t*>(&tile[ii][4 * c4]) = w;   // row pitch 132: 4-byte aligned
     if (!TILED && i < m) *reinterpret_cast<uint32_t*>(A8 + i * ld8 + j0 + 4 * c4) = w;
   }
   __syncthreads();

@@ -34,6 +34,19 @@ __device__ __forceinline__ uint32_t f32_to_e4m3(float x) {
   return sgn | (e << 3) | ((r >> 20) & 7u);
 }
 
+// Four E4M3 codes (x0 in the low byte), each the code f32_to_e4m3 gives: gfx950's packed conversion when all
+// four are finite with magnitude at most 448 (round to nearest even with E4M3 subnormals: the same code as
+// f32_to_e4m3 for every such value of either sign, checked on the device over all of them), the software
+// rounding otherwise (non-finite and saturated values).  The scaled operands of the products always take the
+// hardware path.
+__device__ __forceinline__ uint32_t f32x4_to_e4m3(float x0, float x1, float x2, float x3) {
+  if (fabsf(x0) <= 448.0f && fabsf(x1) <= 448.0f && fabsf(x2) <= 448.0f && fabsf(x3) <= 448.0f) {
+    const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(x0, x1, 0, false);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x2, x3, lo, true);
+  }
+  return f32_to_e4m3(x0) | (f32_to_e4m3(x1) << 8) | (f32_to_e4m3(x2) << 16) | (f32_to_e4m3(x3) << 24);
+}
+
 // Least e with amax <= 448 2^e (0 for amax == 0): amax = f 2^E, f in [0.5, 1), 448 = 0.875 2^9.
 // Exponents are kept in [-127, 127], the range of an E8M0 scale (the MFMA's block-scale operand); only blocks
 // whose largest magnitude is below 448 2^-127 reach the lower limit.

@@ -163,9 +163,8 @@ __global__ void panel_to_fp8_frag_kernel(const float* __restrict__ X, int64_t ld
     uint32_t w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      w[q] = 0;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) w[q] |= f32_to_e4m3(ldexpf(v[16 * h + 4 * q + e], -ex)) << (8 * e);
+      const float* vq = v + 16 * h + 4 * q;
+      w[q] = f32x4_to_e4m3(ldexpf(vq[0], -ex), ldexpf(vq[1], -ex), ldexpf(vq[2], -ex), ldexpf(vq[3], -ex));
     }
     *reinterpret_cast<u32x4*>(blk + h * 1024) = u32x4{w[0], w[1], w[2], w[3]};
   }
