@@ -79,11 +79,13 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // Norms, order, signs and outputs of the converged columns: sigma descending, u_hat = x / sigma signed so
 // that its entry of largest magnitude (lowest index on ties) is positive, v_hat = u_hat / sigma; a column
 // with squared norm at most thr2 (numerically zero) gives sigma = 0 and zero vectors.  Column p of X is at
-// xs[p*LX + i]; the outputs have leading dimension LP.
+// xs[p*LX + i]; the outputs have leading dimension LP.  Columns p0 .. p1-1 are written (all by default); every
+// caller computes all norms and ranks the same way, so workgroups that split the columns agree on them.
 template <typename TU>
 __device__ void jacobi_epilogue(const double* xs, int LX, int l, int LP, double thr2, double* nrm, int* rnk,
                                 double* __restrict__ sigma, double* __restrict__ uhat_d, TU* __restrict__ uhat_p,
-                                TU* __restrict__ vhat_p) {
+                                TU* __restrict__ vhat_p, int p0 = 0, int p1 = -1) {
+  if (p1 < 0) p1 = LP;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, w = tid >> 6, nw = nt >> 6;
   for (int p = w; p < l; p += nw) {
@@ -100,7 +102,7 @@ __device__ void jacobi_epilogue(const double* xs, int LX, int l, int LP, double 
     rnk[p] = r;
   }
   __syncthreads();
-  for (int p = w; p < LP; p += nw) {
+  for (int p = p0 + w; p < p1; p += nw) {
     if (p >= l) {   // padding: zero column at the same index
       for (int i = lane; i < LP; i += 64) {
         uhat_d[(int64_t)p * LP + i] = 0.0;
@@ -321,6 +323,10 @@ __global__ __launch_bounds__(1024) void jacobi2_kernel(JacobiProblem<TU> a, Jaco
   jacobi_body<TU, NH>(p.R, l, LP, tol, max_sweeps, p.sigma, p.uhat_d, p.uhat_p, p.vhat_p, flags);
 }
 
+// Columns per workgroup of the epilogue of the block form (one per wave of 1024 threads); each workgroup
+// recomputes all norms and ranks (a read of X from L2) and writes its own columns.
+constexpr int kFinishCols = 16;
+
 template <typename TU>
 __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* __restrict__ xs, int l, int LP,
                                                               const double* __restrict__ thr2,
@@ -328,15 +334,16 @@ __global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* __res
                                                               TU* __restrict__ uhat_p, TU* __restrict__ vhat_p) {
   __shared__ double nrm[1024];
   __shared__ int rnk[1024];
-  jacobi_epilogue<TU>(xs, LP, l, LP, *thr2, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p);
+  const int p0 = blockIdx.x * kFinishCols;   // this workgroup's columns (one per wave)
+  jacobi_epilogue<TU>(xs, LP, l, LP, *thr2, nrm, rnk, sigma, uhat_d, uhat_p, vhat_p, p0, min(LP, p0 + kFinishCols));
 }
 
 template <typename TU>
 hipError_t jacobi_epilogue_launch(const double* xs, int ldx, int l, int LP, const double* thr2, double* sigma,
                                   double* uhat_d, TU* uhat_p, TU* vhat_p, hipStream_t s) {
   if (ldx != LP) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((jacobi_finish_kernel<TU>), dim3(1), dim3(1024), 0, s, xs, l, LP, thr2, sigma, uhat_d, uhat_p,
-                     vhat_p);
+  hipLaunchKernelGGL((jacobi_finish_kernel<TU>), dim3((unsigned)((LP + kFinishCols - 1) / kFinishCols)), dim3(1024), 0,
+                     s, xs, l, LP, thr2, sigma, uhat_d, uhat_p, vhat_p);
   return hipGetLastError();
 }
 template hipError_t jacobi_epilogue_launch<float>(const double*, int, int, int, const double*, double*, double*,
